@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the RSM hot path on one MI355X.
+
+One step = one whole decomposition (steps a0..a7: mask packing, subset draw, row
+qualification + Gram, minor vectors + N, V-hat, U-hat) of the paper-scale problem
+131072 x 1024, r = 8, l = 9, rho = 0.8, 8192 sub-matrices, FP32 data and Gram, FP64
+eigen-solves — with Y and W already resident in HBM.  Prints one JSON line.
+
+Also reported:
+  * latency p50 / p99 of one decomposition (HIP events on the launch stream);
+  * the roofline of the dominant kernel (row qualification + Gram) against HBM, from its
+    algorithmic bytes (the l mask bit-columns and the l values of every qualifying row, per
+    trial) over its event-timed duration;
+  * parity of the measured run against the FP64 oracle (largest principal angle of V-hat,
+    relative RMS of U V^T on a sample of rows);
+  * the oracle itself timed on the host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decompositions/s + p99 latency, batched/served vs plain RSM on 1 GPU, ≤1e-4 rad"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="paper_scale",
+                    choices=["paper_scale", "plain_fp64", "precision"])
+    ap.add_argument("--plain-gram", action="store_true",
+                    help="per-trial column-streaming Gram kernel instead of the tiled one")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--cpu-sample-trials", type=int, default=256)
+    ap.add_argument("--cpu-sample-rows", type=int, default=2048)
+    return ap.parse_args()
+
+
+def make_workload(name):
+    import synth
+    if name == "paper_scale":
+        return synth.paper_scale()
+    if name == "plain_fp64":
+        return synth.plain_fp64()
+    return synth.precision_stress()
+
+
+def _oracle_chunk(args):
+    """N over a trial range (worker process; inherits the problem through fork)."""
+    from oracle import rsm
+    lo, hi = args
+    p = _G["p"]
+    return rsm.accumulate_N(p.Y, p.W, _G["subsets"][lo:hi], p.r, p.l - p.r, p.r)[0]
+
+
+_G = {}
+
+
+def oracle_parity(p, V_gpu, U_gpu, sample_rows, workers):
+    """theta_max of V-hat and rel RMS of U V^T (sampled rows) against the FP64 oracle."""
+    import multiprocessing as mp
+
+    from oracle import metrics, rng, rsm
+    subsets = rng.draw_subsets(p.seed_rsm, p.n, p.l, p.num_submatrices)
+    _G.update(p=p, subsets=subsets)
+    t0 = time.perf_counter()
+    chunks = np.array_split(np.arange(p.num_submatrices), workers * 4)
+    ranges = [(int(c[0]), int(c[-1]) + 1) for c in chunks if len(c)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_oracle_chunk, ranges)
+    N = np.sum(parts, axis=0)
+    V_ora, _ = rsm.solve_V(N, p.r)
+    rows = np.linspace(0, p.m - 1, sample_rows).astype(np.int64)
+    U_ora, _ = rsm.solve_U(p.Y, p.W, V_ora, rows=rows)
+    t_oracle = time.perf_counter() - t0
+    theta = metrics.principal_angle_max(V_gpu, V_ora)
+    rms = metrics.rel_rms_known(p.W[rows], U_gpu[rows], V_gpu, U_ora[rows], V_ora)
+    return theta, rms, t_oracle
+
+
+def cpu_baseline(p, n_trials, n_rows):
+    """The oracle on one host core over a bounded sample, scaled to one decomposition."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import rng, rsm
+    with threadpool_limits(limits=1):
+        subsets = rng.draw_subsets(p.seed_rsm, p.n, p.l, n_trials)
+        t0 = time.perf_counter()
+        N, _, _ = rsm.accumulate_N(p.Y, p.W, subsets, p.r, p.l - p.r, p.r)
+        t_trials = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        N = N + np.eye(p.n) * 1e-3
+        V, _ = rsm.solve_V(N, p.r)
+        t_eig = time.perf_counter() - t0
+        rows = np.arange(n_rows)
+        t0 = time.perf_counter()
+        rsm.solve_U(p.Y, p.W, V, rows=rows)
+        t_u = time.perf_counter() - t0
+    est = t_trials * (p.num_submatrices / n_trials) + t_eig + t_u * (p.m / n_rows)
+    return {
+        "value": 1.0 / est, "unit": "decompositions/s", "cores": 1, "kind": "oracle",
+        "sample": (f"{n_trials} of {p.num_submatrices} trials, {n_rows} of {p.m} rows of U, "
+                   f"one n x n eigh; scaled to one decomposition ({est:.1f} s estimated)"),
+        "measured_s": round(t_trials + t_eig + t_u, 2),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_1411_0814_amd import _lib, decompose, workspace_bytes, Request
+
+    t_gen = time.perf_counter()
+    p = make_workload(args.workload)
+    t_gen = time.perf_counter() - t_gen
+    dev = torch.device("cuda:0")
+    Y = torch.from_numpy(p.Yt).to(dev).T
+    W = torch.from_numpy(p.Wt.view(bool)).to(dev).T
+    gram = p.gram
+    flags = _lib.PLAIN_GRAM if args.plain_gram else 0
+    stream = torch.cuda.current_stream(dev)
+    req = Request(Y=Y, W=W, r=p.r, num_submatrices=p.num_submatrices, seed=p.seed_rsm, l=p.l,
+                  gram=gram, flags=flags)
+    ws_need = workspace_bytes([req])
+    ws = torch.empty(ws_need + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off:off + ws_need]
+    nev = 2 * len(_lib.STEPS)
+
+    def new_events():
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(nev)]
+        for e in evs:
+            e.record(stream)  # materialise the handle
+        return evs
+
+    def run(evs):
+        return decompose(Y, W, p.r, p.num_submatrices, p.seed_rsm, l=p.l, gram=gram,
+                         flags=flags, workspace=ws, events=evs, stream=stream)
+
+    for _ in range(args.warmup):
+        res = run(new_events())
+    torch.cuda.synchronize()
+    events = [new_events() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [run(events[k]) for k in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    steps = _lib.STEPS
+    per_step = {name: [] for name in steps}
+    latency = []
+    for evs in events:
+        for k, name in enumerate(steps):
+            if name == "error":
+                continue
+            per_step[name].append(evs[2 * k].elapsed_time(evs[2 * k + 1]))
+        latency.append(evs[0].elapsed_time(evs[2 * steps.index("usolve") + 1]))
+    last = results[-1]
+    info = last.info()
+    gram_ms = float(np.mean(per_step["gram"]))
+    elem = 4 if p.Yt.dtype == np.float32 else 8
+    b_alg = p.num_submatrices * p.l * ((p.m + 7) // 8) + info["rows_total"] * p.l * elem
+    achieved = b_alg / (gram_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / elapsed, 3),
+        "unit": "decompositions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if gram == "f32" else gram,
+        "data": "synthetic",
+        "config": {"workload": p.name, "m": p.m, "n": p.n, "r": p.r, "l": p.l,
+                   "num_submatrices": p.num_submatrices, "rho": p.rho, "gram": gram,
+                   "gram_kernel": "plain" if args.plain_gram else "tiled",
+                   "eig_solves": "f64"},
+        "latency_ms": {"p50": round(float(np.percentile(latency, 50)), 4),
+                       "p99": round(float(np.percentile(latency, 99)), 4)},
+        "step_ms": {k: round(float(np.mean(v)), 4) for k, v in per_step.items() if v},
+        "roofline": {"bound": "hbm", "kernel": "gram (row qualification + Gram)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_alg_per_launch": int(b_alg), "launch_ms": round(gram_ms, 4)},
+        "info": {"accepted": info["accepted"], "mean_rows": info["rows_total"] / max(1, p.num_submatrices),
+                 "warnings": info["warnings"], "residual": info["residual"],
+                 "lambda_r": info["lambda"][p.r - 1], "lambda_r1": info["lambda"][p.r]},
+        "gen_s": round(t_gen, 1),
+    }
+    if not args.no_parity:
+        workers = min(16, os.cpu_count() or 4)
+        theta, rms, t_or = oracle_parity(p, last.V.cpu().numpy(), last.U.cpu().numpy(),
+                                         args.cpu_sample_rows, workers)
+        out["parity"] = {"theta_max_rad": theta, "rel_rms_known": rms,
+                         "rows_sampled_for_rms": args.cpu_sample_rows,
+                         "oracle_s": round(t_or, 1), "oracle_workers": workers,
+                         "pass": bool(theta <= 1e-4 and rms <= 1e-5)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample_trials, args.cpu_sample_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

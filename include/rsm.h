@@ -1,0 +1,219 @@
+/*
+ * rsm.h — C ABI of librsm, the MI355X (gfx950) implementation of the hot path of the
+ * Random SubMatrix method (RSM) for low-rank decomposition with missing entries:
+ *
+ *   Y. Liu, "A random algorithm for low-rank decomposition of large-scale matrices with
+ *   missing entries", arXiv:1411.0814.
+ *
+ * The problem (eq.(problem)): given Y (m x n) and a mask W (w_ij = 1 where y_ij is known),
+ * find U (m x r) and V (n x r) minimising ||W o (Y - U V^T)||.  The library runs the
+ * paper's three steps (Section IV-A) with method M1 and the L2 norm:
+ *
+ *   a1  draw I random l-column subsets C_t (l = r + 1 by default)             [step 1-2, M1]
+ *   a2  keep the rows R_t whose entries at C_t are all known                  [M1]
+ *   a3  form the l x l Gram G_t = Z_t^T Z_t of Z_t = Y[R_t, C_t]
+ *   a4  its nvec = l - r eigenvectors of the smallest eigenvalues, i.e. the minor right
+ *       singular vectors zeta of Z_t                                           [Section III]
+ *   a5  N += e(zeta) e(zeta)^T, N = Xi Xi^T                     [eq.(get_xi), eq.(XI)]
+ *   a6  V-hat = the r eigenvectors of N with the smallest eigenvalues
+ *                                                              [eq.(solve.barV_L2_norm)]
+ *   a7  U-hat row by row: u_i = argmin_u sum_j w_ij (y_ij - u^T v_j)^2      [eq.(solve.barU)]
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller; the library never allocates
+ *     device memory.  Scratch memory is the caller's `workspace` (size from
+ *     rsm_workspace_bytes).  Structs themselves (rsm_problem, rsm_input, rsm_output) are
+ *     host memory, read during the call only.
+ *   - Work is enqueued asynchronously on the caller's HIP stream (`hip_stream`, a
+ *     hipStream_t; NULL = the default stream).  Results are valid once the stream has
+ *     reached that point.  Inputs must stay valid and unmodified until then.
+ *   - Every argument is validated on the host before anything is enqueued: a negative
+ *     return (RSM_E_*) means nothing was launched.  RSM_E_DEVICE means a launch failed
+ *     part-way; the outputs are then undefined.
+ *   - Data-dependent conditions are reported in the device-side rsm_info (`warn` bit
+ *     flags RSM_W_*), never as a return value.
+ *   - Outputs are FP64, column-major.  V-hat (n x r) has orthonormal columns ordered by
+ *     ascending eigenvalue of N; U-hat is m x r with leading dimension m.  Only the
+ *     subspace of V-hat (and the product U-hat V-hat^T) is unique.
+ *   - Calls on different streams that use different workspaces and outputs may overlap.
+ */
+#ifndef RSM_H
+#define RSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSM_ABI_VERSION 1
+
+/* Size limits of this build. */
+#define RSM_MAX_R 16          /* rank r */
+#define RSM_MAX_L 17          /* columns per sub-matrix l (r < l <= RSM_MAX_L) */
+#define RSM_MAX_N 4096        /* columns of Y */
+
+/* Return values.  Negative: error, nothing (or, for RSM_E_DEVICE, not everything) was
+ * enqueued.  Warnings are never returned; they are bits of rsm_info.warn. */
+enum {
+  RSM_OK = 0,
+  RSM_E_ARG = -1,          /* a NULL pointer, a size out of range, an inconsistent field */
+  RSM_E_WORKSPACE = -2,    /* ws_bytes below rsm_workspace_bytes(), or workspace misaligned */
+  RSM_E_DEVICE = -3,       /* a HIP launch or query failed */
+  RSM_E_UNSUPPORTED = -4   /* valid request outside this build's limits (RSM_MAX_*) */
+};
+
+/* Bits of rsm_info.warn (per problem, written by the device). */
+enum {
+  RSM_W_NO_CONSTRAINTS = 1,      /* no trial was accepted: N == 0, V-hat arbitrary */
+  RSM_W_RANK_DEFICIENT = 2,      /* a column of Y was never sampled (N_jj == 0), or
+                                    lambda_{r+1}(N) <= 1e-12 lambda_max(N): V-hat not unique */
+  RSM_W_ROWS_UNDERDETERMINED = 4,/* some rows have fewer than r known entries: u_i = 0 */
+  RSM_W_NOT_CONVERGED = 8,       /* eigen-solver residual of N above its tolerance */
+  RSM_W_BAD_SUBSET = 16,         /* a caller-supplied subset was out of range or unsorted;
+                                    that trial was rejected */
+  RSM_W_PIVOT = 32               /* a Cholesky pivot of N + mu I was clamped */
+};
+
+/* Element type of Y. */
+enum { RSM_F32 = 0, RSM_F64 = 1 };
+
+/* Storage order of Y and W.  RSM_COL_MAJOR: element (i, j) at [i + j * ld] (the paper's
+ * Matlab order; read in place).  RSM_ROW_MAJOR: at [i * ld + j] (repacked once into the
+ * workspace). */
+enum { RSM_COL_MAJOR = 0, RSM_ROW_MAJOR = 1 };
+
+/* Arithmetic of the Gram step a3.  The l x l eigen-solves (a4), the n x n eigen-solve
+ * (a6) and the r x r solves (a7) are FP64 in every mode. */
+enum {
+  RSM_GRAM_F64 = 0,        /* FP64 products and sums */
+  RSM_GRAM_F32 = 1,        /* FP32 products, FP32 sums over row chunks, FP64 across chunks */
+  RSM_GRAM_BF16X2 = 2      /* split-BF16 (hi + lo) products on MFMA, FP32 accumulate */
+};
+
+/* rsm_problem.flags */
+enum {
+  RSM_ACCUMULATE_ONLY = 1u << 0, /* stop after a5: N only (no V-hat, no U-hat) */
+  RSM_FINALIZE_ONLY = 1u << 1,   /* skip a1..a5: take N from out->N, run a6 and a7 */
+  RSM_N_ACCUMULATE = 1u << 2,    /* add this call's trials onto the N passed in out->N
+                                    instead of starting from zero (resume / sharding) */
+  RSM_COMPUTE_ERROR = 1u << 3,   /* fill rsm_info.e (eq.(ep)) with an extra pass over Y */
+  RSM_PLAIN_GRAM = 1u << 4       /* use the per-trial column-streaming Gram kernel
+                                    (the unblocked baseline) instead of the tiled one */
+};
+
+typedef struct rsm_problem {
+  int64_t m, n;              /* Y is m x n; 1 <= r < min(m, n); n <= RSM_MAX_N */
+  int32_t r;                 /* target rank */
+  int32_t l;                 /* columns per sub-matrix; 0 => r + 1; r < l <= min(n, RSM_MAX_L) */
+  int32_t nvec;              /* minor vectors per accepted sub-matrix; 0 => l - r; 1..l-r */
+  int32_t min_rows;          /* accept trial t iff |R_t| >= min_rows; 0 => r */
+  int64_t num_submatrices;   /* I: trials drawn (rejected ones included); >= 0 */
+  int64_t trial_begin;       /* counter of the first trial (resume / sharding); >= 0 */
+  uint64_t seed;             /* key of the subset generator */
+  int32_t gram_prec;         /* RSM_GRAM_* */
+  uint32_t flags;            /* RSM_* flags above */
+  int32_t y_dtype;           /* RSM_F32 | RSM_F64: element type of Y */
+  int32_t y_layout;          /* RSM_COL_MAJOR | RSM_ROW_MAJOR: storage order of Y */
+  int32_t w_layout;          /* RSM_COL_MAJOR | RSM_ROW_MAJOR: storage order of W */
+  int32_t reserved;          /* must be 0 */
+} rsm_problem;
+
+/* Subset generator (a1), identical on every implementation: trial t's column subset is
+ * Floyd's sampling (Bentley & Floyd, CACM 1987) driven by the 64-bit words of
+ * Philox4x64-10 (Salmon et al., SC'11) with key (seed, 0) and counter (b, t, 0, 0), words
+ * taken block b = 0, 1, ... in order: for i = 0..l-1, j = n-l+i, x = mulhi64(u_i, j+1);
+ * insert j if x is taken, else x.  The subset is sorted ascending. */
+
+typedef struct rsm_input {
+  const void* Y;             /* device, m x n of y_dtype in y_layout, leading dimension ldy:
+                                col-major ldy >= m, row-major ldy >= n */
+  int64_t ldy;
+  const uint8_t* W;          /* device, m x n bytes in w_layout, nonzero = known;
+                                col-major ldw >= m, row-major ldw >= n */
+  int64_t ldw;
+  const int32_t* subsets;    /* optional device I x l row-major column indices replacing the
+                                generator (each row sorted ascending, in [0, n)); NULL = draw */
+} rsm_input;
+
+/* Device-side report, one per problem (device memory, written by the library). */
+typedef struct rsm_info {
+  uint32_t warn;             /* RSM_W_* bits */
+  int32_t uncovered;         /* columns j with N_jj == 0 */
+  int64_t accepted;          /* trials with |R_t| >= min_rows */
+  int64_t rows_total;        /* sum over all trials of |R_t| */
+  int64_t rows_underdetermined; /* rows with fewer than r known entries */
+  int64_t known;             /* sum of w_ij (numerator of rho, eq.(def.rho)) */
+  int32_t eig_iterations;    /* inverse-iteration steps taken for V-hat */
+  int32_t reserved;
+  double lambda[RSM_MAX_R + 1]; /* Ritz values of N on the final subspace, ascending:
+                                lambda_1..lambda_r (converged with V-hat) and an upper
+                                bound on lambda_{r+1} (rest zero) */
+  double residual;           /* max_k ||N v_k - lambda_k v_k|| / lambda_max(N) */
+  double mu;                 /* shift used for the factorisation of N */
+  double e;                  /* eq.(ep) if RSM_COMPUTE_ERROR, else NaN */
+} rsm_info;
+
+/* Steps of one decomposition, in launch order (for the optional step events below). */
+enum {
+  RSM_STEP_PACK = 0,     /* a0: mask bit-planes (and Y repack) */
+  RSM_STEP_SUBSETS = 1,  /* a1 */
+  RSM_STEP_GRAM = 2,     /* a2 + a3 */
+  RSM_STEP_MINOR = 3,    /* a4 + a5 */
+  RSM_STEP_EIG = 4,      /* a6 */
+  RSM_STEP_USOLVE = 5,   /* a7 */
+  RSM_STEP_ERROR = 6,    /* eq.(ep), only with RSM_COMPUTE_ERROR */
+  RSM_NUM_STEPS = 7
+};
+
+typedef struct rsm_output {
+  double* V;                 /* device n x r (ld n); required unless RSM_ACCUMULATE_ONLY */
+  double* U;                 /* device m x r (ld m); required unless RSM_ACCUMULATE_ONLY */
+  double* N;                 /* device n x n (ld n) or NULL (then kept in the workspace).
+                                Written: the lower triangle and the diagonal (the upper
+                                triangle is not touched).  Read when RSM_FINALIZE_ONLY or
+                                RSM_N_ACCUMULATE is set. */
+  rsm_info* info;            /* device, required */
+  /* Optional per-trial taps (device, NULL = not written), trial index k = 0..I-1: */
+  int32_t* trial_cols;       /* I x l: C_t */
+  int32_t* trial_rows;       /* I: |R_t| */
+  double* trial_gram;        /* I x l x l: G_t (as reduced in FP64) */
+  double* trial_vecs;        /* I x nvec x l: minor vectors (zero for rejected trials) */
+  double* trial_eigs;        /* I x l: eigenvalues of G_t, ascending */
+  /* Optional host array of 2 * RSM_NUM_STEPS hipEvent_t created by the caller (NULL = none):
+     element 2k is recorded on the stream just before step k, element 2k + 1 just after
+     it.  Events of steps that do not run are left untouched. */
+  void* const* step_events;
+} rsm_output;
+
+/* Library ABI version (RSM_ABI_VERSION of the build). */
+int32_t rsm_abi_version(void);
+
+/* Static text for a return value or a single RSM_W_* bit. */
+const char* rsm_status_string(int32_t status);
+
+/* Bytes of workspace rsm_decompose (nprob == 1) or rsm_decompose_batched needs for these
+ * problems.  Host only: no device call.  Returns RSM_E_ARG / RSM_E_UNSUPPORTED for a
+ * problem the decomposition would reject. */
+int32_t rsm_workspace_bytes(const rsm_problem* problems, int32_t nprob, size_t* bytes);
+
+/* One decomposition (steps a1..a7, Section IV-A).  `workspace` is device memory of at
+ * least rsm_workspace_bytes(p, 1) bytes, 256-byte aligned; its contents on entry do not
+ * matter and on exit are undefined.  The call returns after enqueueing. */
+int32_t rsm_decompose(const rsm_problem* p, const rsm_input* in, const rsm_output* out,
+                      void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Several independent decompositions (uneven sizes allowed) fused into shared launches.
+ * problems/inputs/outputs are host arrays of nprob entries; each problem's results equal
+ * those of rsm_decompose on it alone, up to the order of floating-point accumulation
+ * into N.  workspace: rsm_workspace_bytes(problems, nprob) bytes. */
+int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
+                              const rsm_input* inputs, const rsm_output* outputs,
+                              void* workspace, size_t ws_bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSM_H */

@@ -69,7 +69,10 @@ def minor_right_singular_vectors(Z: np.ndarray, nvec: int) -> np.ndarray:
     The full right basis is used, so when Z has fewer rows than columns the null space
     (singular values that count as zero) is part of it, ordered last.
     """
-    _, _, vt = np.linalg.svd(np.asarray(Z, dtype=np.float64), full_matrices=True)
+    Z = np.asarray(Z, dtype=np.float64)
+    # the right basis is complete (l x l) either way; the full left basis is only needed
+    # (and cheap) when there are fewer rows than columns
+    _, _, vt = np.linalg.svd(Z, full_matrices=Z.shape[0] < Z.shape[1])
     return vt[vt.shape[0] - nvec:, :].T.copy()
 
 

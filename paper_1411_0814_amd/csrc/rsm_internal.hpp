@@ -1,0 +1,89 @@
+// Internal declarations of librsm: the execution plan of one problem, the workspace
+// layout, and the host-side launchers of every kernel (one source file per step).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "rsm.h"
+
+namespace rsm {
+
+constexpr int kWave = 64;                 // CDNA wavefront width
+constexpr int kCholNB = 64;               // tile of the blocked Cholesky of N
+constexpr int kEigPad = 4;                // extra vectors in the subspace iteration for V-hat
+constexpr int kEigMaxB = RSM_MAX_R + kEigPad + 1;
+constexpr int kEigIters = 3;              // inverse-iteration steps
+constexpr int kTileRows = 32;             // rows per LDS tile of the tiled Gram kernel
+constexpr size_t kTileLdsBytes = 144 * 1024;  // LDS budget of one tiled-Gram workgroup
+constexpr int kTileThreads = 1024;        // trials per tiled-Gram workgroup (one per thread)
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Scalars the device passes between steps of one problem (lives in the workspace).
+struct DevScalars {
+  double mu;            // shift of the factorisation
+  double lam_max;       // Gershgorin bound on lambda_max(N)
+  double err_acc;       // sum of squared residuals for eq.(ep)
+  int32_t pivots;       // clamped Cholesky pivots
+  int32_t pad;
+};
+
+// How one problem is executed and where its scratch lives in the workspace.
+struct Plan {
+  // problem (defaults resolved)
+  int64_t m = 0, n = 0;
+  int r = 0, l = 0, nvec = 0, min_rows = 0;
+  int64_t I = 0, t0 = 0;
+  uint64_t seed = 0;
+  int prec = RSM_GRAM_F32;
+  uint32_t flags = 0;
+  int y_dtype = RSM_F32, y_layout = RSM_COL_MAJOR, w_layout = RSM_COL_MAJOR;
+  // derived
+  int64_t mw = 0;        // 64-row words per column of the mask bit-planes
+  int ng = 0;            // l (l + 1) / 2 unique Gram entries
+  bool tiled = false;    // tiled (LDS-reuse) Gram kernel instead of the per-trial streamer
+  int splits = 1;        // row splits of the Gram step (partial Grams per trial)
+  int64_t words_per_split = 0;  // 64-row mask words per split
+  int eig_b = 0;         // subspace width of the V-hat iteration
+  int nb = 0;            // Cholesky tiles per dimension
+  size_t part_elem = 4;  // bytes of one partial-Gram element
+  // workspace offsets (bytes from the workspace base); ~0 = unused
+  size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0;
+  size_t off_N = 0, off_Nsym = 0, off_L = 0, off_Lt = 0, off_Dinv = 0, off_X = 0, off_Z = 0,
+         off_NX = 0;
+  size_t off_scal = 0;
+  size_t total = 0;
+};
+
+// Fills `plan` from `p` (defaults resolved, sizes checked).  Returns RSM_OK or an error.
+int32_t make_plan(const rsm_problem& p, Plan& plan);
+
+// Host launchers (each enqueues on `s`; errors surface through hipGetLastError).
+void launch_init_info(rsm_info* info, DevScalars* scal, hipStream_t s);
+void launch_pack_mask(const uint8_t* W, int layout, int64_t ldw, int64_t m, int64_t n,
+                      uint64_t* wbits, int64_t mw, hipStream_t s);
+void launch_pack_y(const void* Y, int dtype, int64_t ldy, int64_t m, int64_t n, void* ycm,
+                   int64_t ldc, hipStream_t s);
+void launch_subsets(const Plan& P, const int32_t* user, int32_t* cols, rsm_info* info,
+                    hipStream_t s);
+void launch_fill_zero(double* x, int64_t count, hipStream_t s);
+void launch_gram(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
+                 const uint64_t* wbits, const int32_t* cols, void* part, int32_t* prow,
+                 hipStream_t s);
+void launch_minor(const Plan& P, const void* part, const int32_t* prow, const int32_t* cols,
+                  double* N, rsm_info* info, const rsm_output& out, hipStream_t s);
+void launch_solve_v(const Plan& P, const double* N, double* Nsym, double* Lf, double* Lt,
+                    double* Dinv, double* X, double* Z, double* NX, DevScalars* scal, double* V,
+                    rsm_info* info, hipStream_t s);
+void launch_solve_u(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
+                    const uint64_t* wbits, const double* V, double* U, rsm_info* info,
+                    hipStream_t s);
+void launch_error(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
+                  const uint64_t* wbits, const double* U, const double* V, DevScalars* scal,
+                  rsm_info* info, hipStream_t s);
+
+}  // namespace rsm

@@ -1,0 +1,174 @@
+"""The C ABI: symbols, struct layouts, and host-side argument validation (no GPU needed)."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1411_0814_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rsm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int32_t|const char\*)\s+(rsm_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    declared = _declared_functions()
+    assert declared == sorted(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+    assert L.rsm_abi_version() == _lib.ABI_VERSION
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for name in declared:
+        assert re.search(rf"\bT {name}$", out, re.M), name
+
+
+_PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "rsm.h"
+#define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("rsm_problem %zu\nrsm_input %zu\nrsm_info %zu\nrsm_output %zu\n",
+         sizeof(rsm_problem), sizeof(rsm_input), sizeof(rsm_info), sizeof(rsm_output));
+  F(rsm_problem, m) F(rsm_problem, r) F(rsm_problem, num_submatrices) F(rsm_problem, seed)
+  F(rsm_problem, gram_prec) F(rsm_problem, flags) F(rsm_problem, y_dtype) F(rsm_problem, reserved)
+  F(rsm_input, Y) F(rsm_input, ldy) F(rsm_input, W) F(rsm_input, ldw) F(rsm_input, subsets)
+  F(rsm_info, warn) F(rsm_info, accepted) F(rsm_info, known) F(rsm_info, eig_iterations)
+  F(rsm_info, lambda) F(rsm_info, residual) F(rsm_info, mu) F(rsm_info, e)
+  F(rsm_output, V) F(rsm_output, info) F(rsm_output, trial_cols) F(rsm_output, trial_eigs)
+  F(rsm_output, step_events)
+  printf("STEPS %d\n", RSM_NUM_STEPS);
+  printf("MAX %d %d %d %d\n", RSM_MAX_R, RSM_MAX_L, RSM_MAX_N, RSM_ABI_VERSION);
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_header():
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(src, "w").write(_PROBE)
+        subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", f"-I{os.path.dirname(HEADER)}",
+                        src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = {}
+    for line in out.strip().splitlines():
+        k, *v = line.split()
+        got[k] = v
+    assert int(got["rsm_problem"][0]) == C.sizeof(_lib.Problem)
+    assert int(got["rsm_input"][0]) == C.sizeof(_lib.Input)
+    assert int(got["rsm_info"][0]) == C.sizeof(_lib.Info)
+    assert int(got["rsm_output"][0]) == C.sizeof(_lib.Output)
+    pyname = {"lambda": "lambda_"}
+    structs = {"rsm_problem": _lib.Problem, "rsm_input": _lib.Input, "rsm_info": _lib.Info,
+               "rsm_output": _lib.Output}
+    for k, v in got.items():
+        if "." in k and k != "STEPS":
+            s, f = k.split(".")
+            assert getattr(structs[s], pyname.get(f, f)).offset == int(v[0]), k
+    assert [int(x) for x in got["MAX"]] == [_lib.MAX_R, _lib.MAX_L, _lib.MAX_N, _lib.ABI_VERSION]
+    assert int(got["STEPS"][0]) == len(_lib.STEPS)
+
+
+def _prob(**kw):
+    p = _lib.Problem()
+    p.m, p.n, p.r, p.num_submatrices, p.seed = 2000, 200, 5, 800, 1
+    p.gram_prec = _lib.GRAM_F64
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ws(p):
+    out = C.c_size_t(0)
+    code = _lib.lib().rsm_workspace_bytes(C.byref(p), 1, C.byref(out))
+    return code, out.value
+
+
+def test_workspace_bytes_valid_and_monotone():
+    code, small = _ws(_prob())
+    assert code == _lib.OK and small > 0
+    code, big = _ws(_prob(num_submatrices=8000))
+    assert code == _lib.OK and big > small
+    code, rm = _ws(_prob(y_layout=_lib.ROW_MAJOR))
+    assert code == _lib.OK and rm >= small + 2000 * 200 * 4
+    # batched: the sum of the parts (each aligned)
+    arr = (_lib.Problem * 2)(_prob(), _prob(num_submatrices=8000))
+    out = C.c_size_t(0)
+    assert _lib.lib().rsm_workspace_bytes(arr, 2, C.byref(out)) == _lib.OK
+    assert out.value == small + big
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(r=0), _lib.E_ARG),
+    (dict(r=200), _lib.E_ARG),                 # r >= min(m, n)
+    (dict(l=5), _lib.E_ARG),                   # l <= r
+    (dict(l=201), _lib.E_ARG),                 # l > n
+    (dict(nvec=2), _lib.E_ARG),                # nvec > l - r
+    (dict(num_submatrices=-1), _lib.E_ARG),
+    (dict(trial_begin=-5), _lib.E_ARG),
+    (dict(m=0), _lib.E_ARG),
+    (dict(gram_prec=7), _lib.E_ARG),
+    (dict(y_dtype=3), _lib.E_ARG),
+    (dict(flags=1 << 20), _lib.E_ARG),
+    (dict(flags=_lib.ACCUMULATE_ONLY | _lib.FINALIZE_ONLY), _lib.E_ARG),
+    (dict(reserved=1), _lib.E_ARG),
+    (dict(r=17, n=300, m=5000), _lib.E_UNSUPPORTED),
+    (dict(l=18, r=5), _lib.E_UNSUPPORTED),
+    (dict(n=5000, m=6000), _lib.E_UNSUPPORTED),
+])
+def test_invalid_problems_rejected_on_host(kw, code):
+    assert _ws(_prob(**kw))[0] == code
+
+
+def _decompose_raw(p, inp, out, ws_ptr, ws_bytes):
+    return _lib.lib().rsm_decompose(C.byref(p), C.byref(inp), C.byref(out), C.c_void_p(ws_ptr),
+                                    C.c_size_t(ws_bytes), None)
+
+
+def test_decompose_validates_before_any_launch():
+    # Fake (never dereferenced) device addresses: every case below must be rejected on the
+    # host before anything touches the device.
+    fake = 1 << 40
+    p = _prob()
+    _, need = _ws(p)
+    inp = _lib.Input(Y=fake, ldy=2000, W=fake, ldw=2000, subsets=None)
+    out = _lib.Output(V=fake, U=fake, N=None, info=fake)
+    assert _decompose_raw(p, inp, out, fake, need - 1) == _lib.E_WORKSPACE
+    assert _decompose_raw(p, inp, out, fake + 8, need) == _lib.E_WORKSPACE      # misaligned
+    assert _decompose_raw(p, inp, out, None, need) == _lib.E_WORKSPACE
+    bad = _lib.Input(Y=fake, ldy=1999, W=fake, ldw=2000)                       # ldy < m
+    assert _decompose_raw(p, bad, out, fake, need) == _lib.E_ARG
+    bad = _lib.Input(Y=None, ldy=2000, W=fake, ldw=2000)
+    assert _decompose_raw(p, bad, out, fake, need) == _lib.E_ARG
+    assert _decompose_raw(p, inp, _lib.Output(V=fake, U=fake, info=None), fake, need) == _lib.E_ARG
+    assert _decompose_raw(p, inp, _lib.Output(V=None, U=fake, info=fake), fake, need) == _lib.E_ARG
+    # accumulate-only / finalize-only need N
+    p2 = _prob(flags=_lib.ACCUMULATE_ONLY)
+    _, need2 = _ws(p2)
+    assert _decompose_raw(p2, inp, _lib.Output(info=fake), fake, need2) == _lib.E_ARG
+    p3 = _prob(flags=_lib.FINALIZE_ONLY)
+    assert _decompose_raw(p3, inp, out, fake, need2) == _lib.E_ARG
+    # row-major W needs ldw >= n
+    p4 = _prob(w_layout=_lib.ROW_MAJOR)
+    _, need4 = _ws(p4)
+    assert _decompose_raw(p4, _lib.Input(Y=fake, ldy=2000, W=fake, ldw=199), out, fake, need4) == _lib.E_ARG
+    assert _lib.lib().rsm_decompose_batched(0, None, None, None, None, 0, None) == _lib.E_ARG
+
+
+def test_status_strings():
+    for code in [_lib.OK, _lib.E_ARG, _lib.E_WORKSPACE, _lib.E_DEVICE, _lib.E_UNSUPPORTED,
+                 *_lib.WARNINGS]:
+        s = _lib.status_string(code)
+        assert s and s != "unknown status"
+    assert _lib.status_string(12345) == "unknown status"
