@@ -1,16 +1,24 @@
 // Step a6: V-hat = the r eigenvectors of N = Xi Xi^T with the smallest eigenvalues
 // (eq.(solve.barV_L2_norm); "||V|| = 1" read as V^T V = I_r).  FP64 throughout.
 //
-// N is symmetric positive semidefinite with (near-)null space of dimension r, so its
-// smallest eigenvalues are the dominant ones of (N + mu I)^{-1}:
-//   1. N (lower triangle) -> full symmetric copy; Gershgorin bound lam_max; uncovered
-//      columns (N_jj == 0).
-//   2. mu = 8 n eps lam_max (above the backward error of the factorisation) and the
-//      blocked right-looking Cholesky N + mu I = L L^T (64 x 64 tiles).
-//   3. Block inverse iteration on b = r + 4 vectors: X <- orth(L^{-T} L^{-1} X), with
-//      backward-stable triangular solves and classical Gram-Schmidt applied twice.
-//   4. Rayleigh-Ritz: H = X^T N X, H = Q Theta Q^T (Jacobi), V-hat = X Q[:, :r],
-//      lambda_1..lambda_{r+1} = Theta, residual max_k ||N v_k - theta_k v_k|| / lam_max.
+// N is symmetric positive semidefinite and its wanted eigenvalues are the smallest ones,
+// i.e. the dominant ones of (N + mu I)^{-1}.  The solver:
+//   1. Nsym = N with the upper triangle mirrored; Gershgorin bound lam_max of lambda_max(N);
+//      the count of uncovered columns (N_jj == 0).
+//   2. mu = 1e-8 lam_max, so cond(N + mu I) <= 1e8 and cond(L) <= 1e4: the factor and its
+//      explicit inverse stay accurate to ~1e-12 relative, while one step of inverse
+//      iteration still shrinks the unwanted components by (lambda_r + mu) /
+//      (lambda_{b+1} + mu).  Blocked right-looking Cholesky N + mu I = L L^T in 64 x 64
+//      tiles; each diagonal tile's inverse is formed with its factor, so the panel solve
+//      is a product.
+//   3. M = L^{-1} by recursive doubling over the tile structure:
+//      [A 0; C B]^{-1} = [A^{-1} 0; -B^{-1} C A^{-1}  B^{-1}], log2(tiles) levels of
+//      products (the matrix is padded to a power-of-two number of tiles with identity).
+//   4. b = r + 4 vectors: X <- orth(M^T M X), a fixed number of steps, with classical
+//      Gram-Schmidt applied twice (rows held in registers of one workgroup).
+//   5. Rayleigh-Ritz: H = X^T N X, H = Q Theta Q^T by parallel-ordering Jacobi,
+//      V-hat = X Q[:, :r]; lambda_1..lambda_{r+1} = Theta; residual
+//      max_k ||N v_k - theta_k v_k|| / lam_max.
 #include <cmath>
 
 #include "device_util.hpp"
@@ -21,139 +29,177 @@ namespace rsm {
 namespace {
 
 constexpr int NB = kCholNB;
-constexpr double kEps = 1.1102230246251565e-16;  // 2^-53
+constexpr double kShiftRel = 1e-8;
 
 __device__ __forceinline__ void atomic_max_pos_f64(double* addr, double v) {
   // non-negative doubles order like their bit patterns
-  atomicMax(reinterpret_cast<unsigned long long*>(addr), static_cast<unsigned long long>(__double_as_longlong(v)));
+  atomicMax(reinterpret_cast<unsigned long long*>(addr),
+            static_cast<unsigned long long>(__double_as_longlong(v)));
 }
 
-// Nsym = N with the upper triangle mirrored from the lower one.
-__global__ void k_symmetrize(const double* __restrict__ N, int64_t n, double* __restrict__ Ns) {
+__device__ __forceinline__ double shift_of(const DevScalars* scal) {
+  const double lam = scal->lam_max;
+  // N == 0 (no accepted trial): factor I instead; V-hat is then an arbitrary basis
+  return lam > 0.0 ? kShiftRel * lam : 1.0;
+}
+
+// ------------------------------------------------------------------ 1. preparation
+
+// Nsym (full), Lf = lower(N) (the shift is added when a diagonal tile is factored),
+// uncovered columns.
+__global__ void k_eig_prep(const double* __restrict__ N, int64_t n, double* __restrict__ Ns,
+                           double* __restrict__ Lf, double* __restrict__ rowsum, rsm_info* info) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx < n) rowsum[idx] = 0.0;
   if (idx >= n * n) return;
   const int64_t j = idx / n, i = idx - j * n;
-  Ns[idx] = (i >= j) ? N[i + j * n] : N[j + i * n];
+  const double v = (i >= j) ? N[i + j * n] : N[j + i * n];
+  Ns[idx] = v;
+  Lf[idx] = (i >= j) ? v : 0.0;
+  if (i == j && v == 0.0) atomicAdd(&info->uncovered, 1);
 }
 
-// Thread per row: Gershgorin bound max_i sum_j |N_ij| and the count of zero diagonals.
-__global__ void k_norm_stats(const double* __restrict__ Ns, int64_t n, DevScalars* scal,
-                             rsm_info* info) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+// Row sums of |N| over a column chunk (rows in 64-row blocks, columns split in chunks):
+// rowsum_i += sum_{j in chunk} |N_ij|.  max_i rowsum_i >= lambda_max(N) (Gershgorin).
+__global__ __launch_bounds__(256) void k_rowsum(const double* __restrict__ Ns, int64_t n,
+                                                int64_t cols_per_chunk,
+                                                double* __restrict__ rowsum) {
+  __shared__ double red[4][64];
+  const int rr = threadIdx.x % 64, g = threadIdx.x / 64;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + rr;
+  const int64_t j0 = static_cast<int64_t>(blockIdx.y) * cols_per_chunk;
+  const int64_t j1 = (j0 + cols_per_chunk < n) ? (j0 + cols_per_chunk) : n;
   double s = 0.0;
-  int zero = 0;
-  if (i < n) {
-    for (int64_t j = 0; j < n; ++j) s += fabs(Ns[i + j * n]);
-    zero = (Ns[i + i * n] == 0.0);
-  }
-  const double smax = [&] {
-    double v = s;
+  if (i < n)
+    for (int64_t j = j0 + g; j < j1; j += 4) s += fabs(Ns[i + j * n]);
+  red[g][rr] = s;
+  __syncthreads();
+  if (g == 0 && i < n) atomic_add_f64(&rowsum[i], red[0][rr] + red[1][rr] + red[2][rr] + red[3][rr]);
+}
+
+// ------------------------------------------------------------------ 2. Cholesky
+
+// Factor tile (k, k) of N + mu I (one workgroup), write L_kk and its inverse Dinv_kk
+// (a ragged last tile is completed with the identity).
+__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ Lf, int64_t n, int k,
+                                                   double* __restrict__ Dinv,
+                                                   const double* __restrict__ rowsum,
+                                                   DevScalars* scal, rsm_info* info) {
+  __shared__ double A[NB][NB + 1];
+  __shared__ double X[NB][NB + 1];
+  __shared__ int npiv;
+  const int tid = threadIdx.x;
+  const int64_t k0 = static_cast<int64_t>(k) * NB;
+  const int kb = static_cast<int>((n - k0) < NB ? (n - k0) : NB);
+  __shared__ double wmax[4];
+  if (k == 0) {  // Gershgorin bound from the row sums, once
+    double v = 0.0;
+    for (int64_t i = tid; i < n; i += blockDim.x) v = fmax(v, rowsum[i]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-  }();
-  const int zsum = wave_sum(zero);
-  if ((threadIdx.x & 63) == 0) {
-    atomic_max_pos_f64(&scal->lam_max, smax);
-    if (zsum) atomicAdd(&info->uncovered, zsum);
+    if ((tid & 63) == 0) wmax[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) scal->lam_max = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    __syncthreads();
   }
-}
-
-// L <- lower(Nsym) + mu I.
-__global__ void k_chol_init(const double* __restrict__ Ns, int64_t n, double* __restrict__ Lf,
-                            DevScalars* scal, rsm_info* info) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const double lam = scal->lam_max;
-  // N == 0 (no accepted trial): factor I instead; V-hat is then an arbitrary orthonormal basis
-  const double mu = lam > 0.0 ? fmax(8.0 * static_cast<double>(n) * kEps * lam, 1e-290) : 1.0;
-  if (idx == 0) {
-    scal->mu = mu;
-    info->mu = mu;
+  const double mu = shift_of(scal);
+  if (tid == 0) {
+    npiv = 0;
+    if (k == 0) {
+      scal->mu = mu;
+      info->mu = mu;
+    }
   }
-  if (idx >= n * n) return;
-  const int64_t j = idx / n, i = idx - j * n;
-  Lf[idx] = (i > j) ? Ns[idx] : (i == j ? Ns[idx] + mu : 0.0);
-}
-
-// Unblocked Cholesky of the kb x kb lower block held in LDS (ld NB+1), 256 threads.
-__device__ void potrf_lds(double (*A)[NB + 1], int kb, double mu, int* npiv) {
-  const int tid = threadIdx.x;
-  for (int j = 0; j < kb; ++j) {
+  for (int e = tid; e < NB * NB; e += blockDim.x) {
+    const int ii = e % NB, jj = e / NB;
+    double v;
+    if (ii < kb && jj < kb)
+      v = (jj <= ii) ? Lf[(k0 + ii) + (k0 + jj) * n] + (ii == jj ? mu : 0.0) : 0.0;
+    else
+      v = (ii == jj) ? 1.0 : 0.0;
+    A[ii][jj] = v;
+    X[ii][jj] = (ii == jj) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // right-looking unblocked factorisation
+  for (int j = 0; j < NB; ++j) {
     if (tid == 0) {
       double d = A[j][j];
       if (!(d > 0.0) || !isfinite(d)) {
         d = mu;
-        ++*npiv;
+        ++npiv;
       }
       A[j][j] = sqrt(d);
     }
     __syncthreads();
     const double ljj = A[j][j];
-    for (int i = j + 1 + tid; i < kb; i += blockDim.x) A[i][j] /= ljj;
+    for (int i = j + 1 + tid; i < NB; i += blockDim.x) A[i][j] /= ljj;
     __syncthreads();
-    const int rem = kb - j - 1;
+    const int rem = NB - j - 1;
     for (int e = tid; e < rem * rem; e += blockDim.x) {
-      const int ii = j + 1 + e / rem, kk = j + 1 + e % rem;
-      if (kk <= ii) A[ii][kk] -= A[ii][j] * A[kk][j];
+      const int ii = j + 1 + e / rem, cc = j + 1 + e % rem;
+      if (cc <= ii) A[ii][cc] -= A[ii][j] * A[cc][j];
     }
     __syncthreads();
   }
-}
-
-// Panel step k, part 1: factor tile (k, k) in place (one workgroup).
-__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ Lf, int64_t n, int k,
-                                                   DevScalars* scal) {
-  __shared__ double D[NB][NB + 1];
-  __shared__ int npiv;
-  const int tid = threadIdx.x;
-  const int64_t k0 = static_cast<int64_t>(k) * NB;
-  const int kb = static_cast<int>((n - k0) < NB ? (n - k0) : NB);
-  if (tid == 0) npiv = 0;
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int ii = e % NB, jj = e / NB;
-    D[ii][jj] = (ii < kb && jj < kb && jj <= ii) ? Lf[(k0 + ii) + (k0 + jj) * n] : 0.0;
+  // inverse of the lower-triangular factor: L X = I, row j of X finished at step j
+  for (int j = 0; j < NB; ++j) {
+    const double ljj = A[j][j];
+    if (tid < NB) X[j][tid] /= ljj;
+    __syncthreads();
+    const int rem = NB - j - 1;
+    for (int e = tid; e < rem * NB; e += blockDim.x) {
+      const int ii = j + 1 + e / NB, cc = e % NB;
+      X[ii][cc] -= A[ii][j] * X[j][cc];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  potrf_lds(D, kb, scal->mu, &npiv);
   for (int e = tid; e < NB * NB; e += blockDim.x) {
     const int ii = e % NB, jj = e / NB;
-    if (ii < kb && jj < kb && jj <= ii) Lf[(k0 + ii) + (k0 + jj) * n] = D[ii][jj];
+    if (ii < kb && jj < kb && jj <= ii) Lf[(k0 + ii) + (k0 + jj) * n] = A[ii][jj];
+    Dinv[static_cast<int64_t>(k) * NB * NB + e] = (jj <= ii) ? X[ii][jj] : 0.0;
   }
   if (tid == 0 && npiv) atomicAdd(&scal->pivots, npiv);
 }
 
-// Panel step k, part 2: workgroup i solves tile (k+1+i, k): L_ik = A_ik L_kk^{-T}.
-__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Lf, int64_t n, int k) {
-  __shared__ double D[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
+// Panel: tile (k+1+bid, k) becomes L_ik = A_ik L_kk^{-T} = A_ik Dinv_kk^T.
+__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Lf, int64_t n, int k,
+                                                    const double* __restrict__ Dinv) {
+  __shared__ double Xs[NB][NB + 1];
+  __shared__ double Ds[NB][NB + 1];
   const int tid = threadIdx.x;
   const int64_t k0 = static_cast<int64_t>(k) * NB;
   const int kb = static_cast<int>((n - k0) < NB ? (n - k0) : NB);
   const int64_t i0 = k0 + static_cast<int64_t>(blockIdx.x + 1) * NB;
-  if (i0 >= n) return;
   const int ib = static_cast<int>((n - i0) < NB ? (n - i0) : NB);
+  const double* dk = Dinv + static_cast<int64_t>(k) * NB * NB;
   for (int e = tid; e < NB * NB; e += blockDim.x) {
     const int ii = e % NB, jj = e / NB;
-    D[ii][jj] = (ii < kb && jj < kb && jj <= ii) ? Lf[(k0 + ii) + (k0 + jj) * n] : 0.0;
-    X[ii][jj] = (ii < ib && jj < kb) ? Lf[(i0 + ii) + (k0 + jj) * n] : 0.0;
+    Xs[ii][jj] = (ii < ib && jj < kb) ? Lf[(i0 + ii) + (k0 + jj) * n] : 0.0;
+    Ds[ii][jj] = dk[e];
   }
   __syncthreads();
-  // X L^T = A  ->  column j: x_j = (a_j - sum_{p<j} x_p L_jp) / L_jj, column-oriented
-  for (int j = 0; j < kb; ++j) {
-    const double ljj = D[j][j];
-    for (int ii = tid; ii < ib; ii += blockDim.x) X[ii][j] /= ljj;
-    __syncthreads();
-    const int rem = kb - j - 1;
-    for (int e = tid; e < ib * rem; e += blockDim.x) {
-      const int ii = e % ib, jj = j + 1 + e / ib;
-      X[ii][jj] -= X[ii][j] * D[jj][j];
+  const int tx = tid % 16, ty = tid / 16;
+  double acc[4][4] = {};
+  for (int p = 0; p < NB; ++p) {
+    double a[4], d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = Xs[ty * 4 + u][p];
+      d[u] = Ds[tx * 4 + u][p];  // (Dinv^T)[p][c] = Dinv[c][p]
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * d[v];
   }
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int ii = e % NB, jj = e / NB;
-    if (ii < ib && jj < kb) Lf[(i0 + ii) + (k0 + jj) * n] = X[ii][jj];
-  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rr = ty * 4 + u, cc = tx * 4 + v;
+      if (rr < ib && cc < kb) Lf[(i0 + rr) + (k0 + cc) * n] = acc[u][v];
+    }
 }
 
 // Trailing update after panel k: tile (i, j), k < j <= i:  A_ij -= L_ik L_jk^T.
@@ -161,7 +207,6 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ Lf, in
                                                      int nb) {
   __shared__ double Li[NB][NB + 1];
   __shared__ double Lj[NB][NB + 1];
-  // tile index -> (i, j)
   int b = blockIdx.x;
   int ti = k + 1, tj = k + 1;
   for (int i = k + 1; i < nb; ++i) {
@@ -208,6 +253,120 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ Lf, in
   }
 }
 
+// ------------------------------------------------------------------ 3. M = L^{-1}
+
+// M (npad x npad, ld npad): diagonal tiles = Dinv (identity past the last tile), and the
+// strictly lower tiles of L copied in (zero past n) as the blocks C of the recursion.
+__global__ void k_inv_init(const double* __restrict__ Lf, const double* __restrict__ Dinv,
+                           int64_t n, int nb, int64_t npad, double* __restrict__ M) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= npad * npad) return;
+  const int64_t c = idx / npad, rr = idx - c * npad;
+  const int64_t ti = rr / NB, tj = c / NB;
+  double v = 0.0;
+  if (ti == tj) {
+    if (ti < nb)
+      v = Dinv[ti * NB * NB + (rr - ti * NB) + (c - tj * NB) * NB];
+    else
+      v = (rr == c) ? 1.0 : 0.0;
+  } else if (ti > tj && rr < n && c < n) {
+    v = Lf[rr + c * n];
+  }
+  M[idx] = v;
+}
+
+// Level with inverted diagonal blocks of size bs: for every pair of consecutive blocks,
+// T = C A^{-1} where C = M[block2, block1] (still the L entries) and A^{-1} = M[block1,
+// block1] (lower triangular).  One 64 x 64 output tile per workgroup.
+__global__ __launch_bounds__(256) void k_inv_stage1(const double* __restrict__ M, int64_t npad,
+                                                    int64_t bs, double* __restrict__ T) {
+  __shared__ double As[NB][NB + 1];
+  __shared__ double Bs[NB][NB + 1];
+  const int64_t tpb = bs / NB;                       // tiles per block side
+  const int64_t pair = blockIdx.x / (tpb * tpb);
+  const int64_t rem = blockIdx.x - pair * tpb * tpb;
+  const int64_t ti = rem / tpb, tj = rem % tpb;      // output tile inside the pair
+  const int64_t r1 = pair * 2 * bs;                  // block 1 origin
+  const int64_t r2 = r1 + bs;                        // block 2 origin
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  double acc[4][4] = {};
+  // T[ti, tj] = sum_q C[ti, q] Ainv[q, tj], q >= tj (Ainv lower)
+  for (int64_t q = tj; q < tpb; ++q) {
+    for (int e = tid; e < NB * NB; e += blockDim.x) {
+      const int a = e % NB, c = e / NB;
+      As[a][c] = M[(r2 + ti * NB + a) + (r1 + q * NB + c) * npad];  // C tile
+      Bs[a][c] = M[(r1 + q * NB + a) + (r1 + tj * NB + c) * npad];  // Ainv tile
+    }
+    __syncthreads();
+    for (int p = 0; p < NB; ++p) {
+      double x[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = As[ty * 4 + u][p];
+        y[u] = Bs[p][tx * 4 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += x[u] * y[v];
+    }
+    __syncthreads();
+  }
+  const int64_t ldt = npad / 2;
+  const int64_t base = (pair * bs + ti * NB) + (tj * NB) * ldt;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      T[base + (ty * 4 + u) + static_cast<int64_t>(tx * 4 + v) * ldt] = acc[u][v];
+}
+
+// M[block2, block1] = -B^{-1} T with B^{-1} = M[block2, block2] (lower triangular).
+__global__ __launch_bounds__(256) void k_inv_stage2(double* __restrict__ M, int64_t npad,
+                                                    int64_t bs, const double* __restrict__ T) {
+  __shared__ double As[NB][NB + 1];
+  __shared__ double Bs[NB][NB + 1];
+  const int64_t tpb = bs / NB;
+  const int64_t pair = blockIdx.x / (tpb * tpb);
+  const int64_t rem = blockIdx.x - pair * tpb * tpb;
+  const int64_t ti = rem / tpb, tj = rem % tpb;
+  const int64_t r1 = pair * 2 * bs;
+  const int64_t r2 = r1 + bs;
+  const int64_t ldt = npad / 2;
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  double acc[4][4] = {};
+  for (int64_t q = 0; q <= ti; ++q) {
+    for (int e = tid; e < NB * NB; e += blockDim.x) {
+      const int a = e % NB, c = e / NB;
+      As[a][c] = M[(r2 + ti * NB + a) + (r2 + q * NB + c) * npad];      // Binv tile
+      Bs[a][c] = T[(pair * bs + q * NB + a) + (tj * NB + c) * ldt];     // T tile
+    }
+    __syncthreads();
+    for (int p = 0; p < NB; ++p) {
+      double x[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = As[ty * 4 + u][p];
+        y[u] = Bs[p][tx * 4 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += x[u] * y[v];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      M[(r2 + ti * NB + ty * 4 + u) + (r1 + tj * NB + tx * 4 + v) * npad] = -acc[u][v];
+}
+
+// ------------------------------------------------------------------ 4. subspace iteration
+
 // Deterministic start block: entries uniform in [-1, 1) from Philox (key = seed, 1).
 __global__ void k_start_vectors(double* __restrict__ X, int64_t n, int b, uint64_t seed) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -217,383 +376,449 @@ __global__ void k_start_vectors(double* __restrict__ X, int64_t n, int b, uint64
   X[idx] = static_cast<double>(static_cast<int64_t>(c[0]) >> 11) * (1.0 / 4503599627370496.0);
 }
 
-// Transposed copy of the factor: Lt[i + j n] = L[j + i n] (upper triangle = L^T), so that
-// the backward solve reads rows of L^T contiguously.
-__global__ void k_transpose_lower(const double* __restrict__ Lf, int64_t n,
-                                  double* __restrict__ Lt) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= n * n) return;
-  const int64_t j = idx / n, i = idx - j * n;
-  Lt[idx] = (i <= j) ? Lf[j + i * n] : 0.0;
+__global__ void k_zero(double* __restrict__ x, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) x[i] = 0.0;
 }
 
-// Inverse of every 64 x 64 diagonal tile of L (one workgroup per tile, one thread per
-// column of the inverse: L_kk x = e_c by forward substitution).  Dinv[k][i + 64 j].
-__global__ __launch_bounds__(64) void k_diag_inverse(const double* __restrict__ Lf, int64_t n,
-                                                     double* __restrict__ Dinv) {
-  __shared__ double D[NB][NB + 1];
-  __shared__ double Xs[NB][NB + 1];
-  const int kb = blockIdx.x;
-  const int64_t k0 = static_cast<int64_t>(kb) * NB;
-  const int kk = static_cast<int>((n - k0) < NB ? (n - k0) : NB);
+// Z += op(M)[row tile, col tile] X[col tile]  (one tile pair per workgroup; FP64 atomics).
+// trans = 0: Z = M X with M lower;  trans = 1: Z = M^T X.
+__global__ __launch_bounds__(256) void k_trmm(const double* __restrict__ M, int64_t npad,
+                                              int64_t n, int b, const double* __restrict__ X,
+                                              double* __restrict__ Z, int trans) {
+  __shared__ double Ms[NB][NB + 1];
+  __shared__ double Xs[NB][kEigMaxB + 1];
+  const int nt = static_cast<int>(ceil_div(n, NB));
+  // enumerate the tiles (i, k), k <= i, of the lower triangle of M
+  int bidx = blockIdx.x;
+  int ti = 0, tk = 0;
+  for (int i = 0; i < nt; ++i) {
+    if (bidx <= i) {
+      ti = i;
+      tk = bidx;
+      break;
+    }
+    bidx -= i + 1;
+  }
+  if (trans) {  // M tile (ti, tk) feeds output rows tk of M^T X
+    const int t = ti;
+    ti = tk;
+    tk = t;
+  }
   const int tid = threadIdx.x;
+  const int64_t r0 = static_cast<int64_t>(ti) * NB, k0 = static_cast<int64_t>(tk) * NB;
   for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int ii = e % NB, jj = e / NB;
-    D[ii][jj] = (ii < kk && jj < kk && jj <= ii) ? Lf[(k0 + ii) + (k0 + jj) * n] : (ii == jj ? 1.0 : 0.0);
+    const int a = e % NB, c = e / NB;
+    // element (r0 + a, k0 + c) of op(M); loads run along the first index of M
+    double v;
+    if (!trans) {
+      v = (r0 + a < n && k0 + c < n) ? M[(r0 + a) + (k0 + c) * npad] : 0.0;
+      Ms[a][c] = v;
+    } else {
+      v = (k0 + a < n && r0 + c < n) ? M[(k0 + a) + (r0 + c) * npad] : 0.0;
+      Ms[c][a] = v;
+    }
+  }
+  for (int e = tid; e < NB * b; e += blockDim.x) {
+    const int a = e % NB, c = e / NB;
+    Xs[a][c] = (k0 + a < n) ? X[(k0 + a) + static_cast<int64_t>(c) * n] : 0.0;
   }
   __syncthreads();
-  const int c = tid;
-  for (int i = 0; i < NB; ++i) {
-    double v = (i == c) ? 1.0 : 0.0;
-    for (int p = c; p < i; ++p) v -= D[i][p] * Xs[p][c];
-    Xs[i][c] = (i < c) ? 0.0 : v / D[i][i];
+  const int rr = tid % NB;
+  const int cg = tid / NB;  // 4 column groups
+  if (r0 + rr < n) {
+    for (int c = cg; c < b; c += 4) {
+      double s = 0.0;
+#pragma unroll 8
+      for (int p = 0; p < NB; ++p) s += Ms[rr][p] * Xs[p][c];
+      atomic_add_f64(&Z[(r0 + rr) + static_cast<int64_t>(c) * n], s);
+    }
   }
-  __syncthreads();
-  double* out = Dinv + static_cast<int64_t>(kb) * NB * NB;
-  for (int e = tid; e < NB * NB; e += blockDim.x) out[e] = Xs[e % NB][e / NB];
 }
 
-// Single-workgroup blocked triangular solve with b right-hand sides (n x b, ld n):
-//   upper = 0:  L Z = X with T = L (lower);   upper = 1:  L^T Z = X with T = L^T (upper).
-// Per 64-row tile: acc = X_k - sum over solved tiles T_kj Z_j (four wavefronts split the
-// inner index), then z = D^{-1} acc followed by one step of iterative refinement
-// z += D^{-1} (acc - D z) with the stored tile inverse.  Z may alias X.
-__global__ __launch_bounds__(256) void k_trsm(const double* __restrict__ T, int64_t n, int b,
-                                              const double* __restrict__ Dinv, const double* X,
-                                              double* Z, int upper) {
-  __shared__ double acc[NB][kEigMaxB];
-  __shared__ double zs[NB][kEigMaxB];
-  __shared__ double Dm[NB][NB + 1];
-  __shared__ double Di[NB][NB + 1];
-  __shared__ double red[3][NB][kEigMaxB];
+// X = orth(Z): classical Gram-Schmidt applied twice per column, one workgroup of 1024
+// threads, thread t owning rows t, t + 1024, ... (RPT rows) in registers.
+template <int RPT>
+__global__ __launch_bounds__(1024) void k_orth(const double* __restrict__ Z, int64_t n, int b,
+                                               double* __restrict__ X) {
+  __shared__ double red[16][kEigMaxB];
+  __shared__ double h[kEigMaxB];
   const int tid = threadIdx.x;
-  const int rr = tid % NB;
-  const int g = tid / NB;  // 0..3
-  const int nb = static_cast<int>(ceil_div(n, NB));
-  for (int s = 0; s < nb; ++s) {
-    const int kb = upper ? (nb - 1 - s) : s;
-    const int64_t k0 = static_cast<int64_t>(kb) * NB;
-    const int kk = static_cast<int>((n - k0) < NB ? (n - k0) : NB);
-    const double* dinv = Dinv + static_cast<int64_t>(kb) * NB * NB;
-    for (int e = tid; e < NB * NB; e += blockDim.x) {
-      const int ii = e % NB, jj = e / NB;
-      const bool in = ii < kk && jj < kk;
-      Dm[ii][jj] = in ? T[(k0 + ii) + (k0 + jj) * n] : 0.0;
-      // inverse of L_kk^T is (L_kk^{-1})^T
-      Di[ii][jj] = in ? (upper ? dinv[jj + NB * ii] : dinv[ii + NB * jj]) : 0.0;
-    }
-    // off-diagonal contribution: rows k0..k0+kk of T times the solved part of Z
-    double part[kEigMaxB];
+  const int lane = tid & 63, wid = tid >> 6;
+  double x[RPT][kEigMaxB];
 #pragma unroll
-    for (int c = 0; c < kEigMaxB; ++c) part[c] = 0.0;
-    const int64_t p_begin = upper ? (k0 + kk) : 0;
-    const int64_t p_end = upper ? n : k0;
-    if (rr < kk) {
-      for (int64_t p = p_begin + g; p < p_end; p += 4) {
-        const double tv = T[(k0 + rr) + p * n];
+  for (int s = 0; s < RPT; ++s) {
+    const int64_t i = tid + static_cast<int64_t>(s) * 1024;
 #pragma unroll
-        for (int c = 0; c < kEigMaxB; ++c)
-          if (c < b) part[c] += tv * Z[p + c * n];
+    for (int c = 0; c < kEigMaxB; ++c) x[s][c] = (i < n && c < b) ? Z[i + c * n] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < kEigMaxB; ++k) {
+    if (k < b) {
+      for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+        for (int j = 0; j < k; ++j) {
+          double p = 0.0;
+#pragma unroll
+          for (int s = 0; s < RPT; ++s) p += x[s][j] * x[s][k];
+          p = wave_sum(p);
+          if (lane == 0) red[wid][j] = p;
+        }
+        __syncthreads();
+        if (tid < k) {
+          double s = 0.0;
+          for (int w = 0; w < 16; ++w) s += red[w][tid];
+          h[tid] = s;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < k; ++j) {
+          const double hj = h[j];
+#pragma unroll
+          for (int s = 0; s < RPT; ++s) x[s][k] -= hj * x[s][j];
+        }
+        __syncthreads();
       }
-    }
-    if (g > 0) {
+      double p = 0.0;
 #pragma unroll
-      for (int c = 0; c < kEigMaxB; ++c) red[g - 1][rr][c] = part[c];
+      for (int s = 0; s < RPT; ++s) p += x[s][k] * x[s][k];
+      p = wave_sum(p);
+      if (lane == 0) red[wid][0] = p;
+      __syncthreads();
+      if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < 16; ++w) s += red[w][0];
+        h[0] = s;
+      }
+      __syncthreads();
+      const double nrm = sqrt(h[0]);
+      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) x[s][k] *= inv;
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int64_t i = tid + static_cast<int64_t>(s) * 1024;
+    if (i < n)
+#pragma unroll
+      for (int c = 0; c < kEigMaxB; ++c)
+        if (c < b) X[i + c * n] = x[s][c];
+  }
+}
+
+// NX += Nsym[row block, column chunk] X[column chunk] (NX zeroed beforehand; FP64
+// atomics).  Thread per row, X staged through LDS.
+__global__ __launch_bounds__(256) void k_symm_mult(const double* __restrict__ Ns, int64_t n,
+                                                   int b, const double* __restrict__ X,
+                                                   int64_t cols_per_chunk,
+                                                   double* __restrict__ NX) {
+  __shared__ double Xs[NB][kEigMaxB + 1];
+  const int tid = threadIdx.x;
+  const int rr = tid % 64, cg = tid / 64;  // 4 column groups
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + rr;
+  const int64_t j0 = static_cast<int64_t>(blockIdx.y) * cols_per_chunk;
+  const int64_t j1 = (j0 + cols_per_chunk < n) ? (j0 + cols_per_chunk) : n;
+  double acc[6] = {};
+  for (int64_t p0 = j0; p0 < j1; p0 += NB) {
+    __syncthreads();
+    for (int e = tid; e < NB * b; e += blockDim.x) {
+      const int a = e % NB, c = e / NB;
+      Xs[a][c] = (p0 + a < j1) ? X[(p0 + a) + static_cast<int64_t>(c) * n] : 0.0;
     }
     __syncthreads();
-    if (g == 0) {
+    if (i < n) {
+      const int pe = static_cast<int>((j1 - p0) < NB ? (j1 - p0) : NB);
+      for (int p = 0; p < pe; ++p) {
+        const double a = Ns[i + (p0 + p) * n];
 #pragma unroll
-      for (int c = 0; c < kEigMaxB; ++c) {
-        if (c < b) {
-          const double x = (rr < kk) ? X[(k0 + rr) + c * n] : 0.0;
-          acc[rr][c] = x - (part[c] + red[0][rr][c] + red[1][rr][c] + red[2][rr][c]);
+        for (int u = 0; u < 6; ++u) {
+          const int c = cg + 4 * u;
+          if (c < b) acc[u] += a * Xs[p][c];
         }
       }
     }
-    __syncthreads();
-    // z = Dinv acc, then one refinement step
-    for (int e = tid; e < NB * b; e += blockDim.x) {
-      const int i = e % NB, c = e / NB;
-      double v = 0.0;
-      for (int p = 0; p < NB; ++p) v += Di[i][p] * acc[p][c];
-      zs[i][c] = v;
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * b; e += blockDim.x) {
-      const int i = e % NB, c = e / NB;
-      double v = acc[i][c];
-      for (int p = 0; p < NB; ++p) v -= Dm[i][p] * zs[p][c];
-      red[0][i][c] = v;  // residual
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * b; e += blockDim.x) {
-      const int i = e % NB, c = e / NB;
-      double v = 0.0;
-      for (int p = 0; p < NB; ++p) v += Di[i][p] * red[0][p][c];
-      if (i < kk) Z[(k0 + i) + c * n] = zs[i][c] + v;
-    }
-    __threadfence();
-    __syncthreads();
   }
-}
-
-// Block reduction of `cnt` per-thread values into red[0..cnt) (1024 threads).
-__device__ void block_sum(double* vals, int cnt, double* red /* [16][kEigMaxB] */,
-                          double* out) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int j = 0; j < cnt; ++j) {
-    const double s = wave_sum(vals[j]);
-    if (lane == 0) red[wid * kEigMaxB + j] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < cnt) {
-    double s = 0.0;
-    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) s += red[w * kEigMaxB + threadIdx.x];
-    out[threadIdx.x] = s;
-  }
-  __syncthreads();
-}
-
-// X = orth(Z): classical Gram-Schmidt applied twice per column (one workgroup).
-__global__ __launch_bounds__(1024) void k_orth(const double* __restrict__ Z, int64_t n, int b,
-                                               double* __restrict__ X) {
-  __shared__ double red[16 * kEigMaxB];
-  __shared__ double h[kEigMaxB];
-  const int tid = threadIdx.x;
-  for (int64_t i = tid; i < n; i += blockDim.x)
-    for (int c = 0; c < b; ++c) X[i + c * n] = Z[i + c * n];
-  __threadfence();
-  __syncthreads();
-  for (int k = 0; k < b; ++k) {
-    for (int pass = 0; pass < 2; ++pass) {
-      double part[kEigMaxB];
-      for (int j = 0; j < k; ++j) part[j] = 0.0;
-      for (int64_t i = tid; i < n; i += blockDim.x) {
-        const double xk = X[i + k * n];
-        for (int j = 0; j < k; ++j) part[j] += X[i + j * n] * xk;
-      }
-      block_sum(part, k, red, h);
-      for (int64_t i = tid; i < n; i += blockDim.x) {
-        double v = X[i + k * n];
-        for (int j = 0; j < k; ++j) v -= h[j] * X[i + j * n];
-        X[i + k * n] = v;
-      }
-      __threadfence();
-      __syncthreads();
-    }
-    double part1[1] = {0.0};
-    for (int64_t i = tid; i < n; i += blockDim.x) {
-      const double v = X[i + k * n];
-      part1[0] += v * v;
-    }
-    block_sum(part1, 1, red, h);
-    const double nrm = sqrt(h[0]);
-    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int64_t i = tid; i < n; i += blockDim.x) X[i + k * n] *= inv;
-    __threadfence();
-    __syncthreads();
-  }
-}
-
-// NX = Nsym X (n x b), one 64-row block per workgroup, 256 threads.
-__global__ __launch_bounds__(256) void k_symm_mult(const double* __restrict__ Ns, int64_t n,
-                                                   int b, const double* __restrict__ X,
-                                                   double* __restrict__ NX) {
-  const int rr = threadIdx.x % 64;
-  const int cg = threadIdx.x / 64;  // 4 column groups
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + rr;
-  double acc[6] = {};
   if (i < n) {
-    for (int64_t p = 0; p < n; ++p) {
-      const double a = Ns[i + p * n];
-#pragma unroll
-      for (int u = 0; u < 6; ++u) {
-        const int c = cg + 4 * u;
-        if (c < b) acc[u] += a * X[p + c * n];
-      }
-    }
 #pragma unroll
     for (int u = 0; u < 6; ++u) {
       const int c = cg + 4 * u;
-      if (c < b) NX[i + c * n] = acc[u];
+      if (c < b) atomic_add_f64(&NX[i + c * n], acc[u]);
     }
   }
 }
 
-// Cyclic Jacobi on the b x b symmetric H (row-major, LDS) by one wavefront; the lanes
-// apply each rotation's row/column updates in parallel.  Q accumulates the rotations.
-__device__ void jacobi_wave(double* H, double* Q, int b) {
-  const int lane = threadIdx.x & 63;
-  for (int i = lane; i < b * b; i += 64) Q[i] = ((i / b) == (i % b)) ? 1.0 : 0.0;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    bool rotated = false;
-    for (int p = 0; p < b - 1; ++p) {
-      for (int q = p + 1; q < b; ++q) {
-        const double apq = H[p * b + q];
-        const double app = H[p * b + p];
-        const double aqq = H[q * b + q];
-        if (!(fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq)))) continue;
-        rotated = true;
-        const double tau = (aqq - app) / (2.0 * apq);
-        double t;
-        if (fabs(tau) > 1e150) {
-          t = 0.5 / tau;
-        } else {
-          t = 1.0 / (fabs(tau) + sqrt(1.0 + tau * tau));
-          if (tau < 0.0) t = -t;
-        }
-        const double c = 1.0 / sqrt(1.0 + t * t);
-        const double s = t * c;
-        const int k = lane;
-        double akp = 0.0, akq = 0.0, qkp = 0.0, qkq = 0.0;
-        if (k < b) {
-          akp = H[k * b + p];
-          akq = H[k * b + q];
-          qkp = Q[k * b + p];
-          qkq = Q[k * b + q];
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (k < b) {
-          if (k != p && k != q) {
-            const double nkp = c * akp - s * akq;
-            const double nkq = s * akp + c * akq;
-            H[k * b + p] = nkp;
-            H[p * b + k] = nkp;
-            H[k * b + q] = nkq;
-            H[q * b + k] = nkq;
-          }
-          Q[k * b + p] = c * qkp - s * qkq;
-          Q[k * b + q] = s * qkp + c * qkq;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) {
-          H[p * b + p] = app - t * apq;
-          H[q * b + q] = aqq + t * apq;
-          H[p * b + q] = 0.0;
-          H[q * b + p] = 0.0;
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
-    if (!rotated) break;
-  }
-}
-
-// Rayleigh-Ritz on span(X), then V-hat, lambda_1..lambda_{r+1}, residual and flags.
-__global__ __launch_bounds__(256) void k_rayleigh_ritz(const double* __restrict__ X,
-                                                       const double* __restrict__ NX, int64_t n,
-                                                       int b, int r, double* __restrict__ V,
-                                                       DevScalars* scal, rsm_info* info,
-                                                       int check_accepted) {
-  __shared__ double H[kEigMaxB * kEigMaxB];
-  __shared__ double Q[kEigMaxB * kEigMaxB];
-  __shared__ int order[kEigMaxB];
-  __shared__ double theta[kEigMaxB];
-  __shared__ double resid[RSM_MAX_R];
+// H += X[rows]^T NX[rows] over one 64-row block (H zeroed beforehand).
+__global__ __launch_bounds__(256) void k_xtnx(const double* __restrict__ X,
+                                              const double* __restrict__ NX, int64_t n, int b,
+                                              double* __restrict__ H) {
+  __shared__ double xs[NB][kEigMaxB + 1];
+  __shared__ double ys[NB][kEigMaxB + 1];
   const int tid = threadIdx.x;
-  // H = X^T NX, one thread per entry (b <= 21 -> at most 441 entries)
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * NB;
+  for (int e = tid; e < NB * b; e += blockDim.x) {
+    const int a = e % NB, c = e / NB;
+    const bool in = r0 + a < n;
+    xs[a][c] = in ? X[(r0 + a) + static_cast<int64_t>(c) * n] : 0.0;
+    ys[a][c] = in ? NX[(r0 + a) + static_cast<int64_t>(c) * n] : 0.0;
+  }
+  __syncthreads();
   for (int e = tid; e < b * b; e += blockDim.x) {
     const int i = e / b, j = e % b;
     double s = 0.0;
-    for (int64_t p = 0; p < n; ++p) s += X[p + i * n] * NX[p + j * n];
-    H[e] = s;
+    for (int a = 0; a < NB; ++a) s += xs[a][i] * ys[a][j];
+    atomic_add_f64(&H[e], s);
   }
+}
+
+// ------------------------------------------------------------------ 5. Rayleigh-Ritz
+
+typedef double SmallMat[kEigMaxB + 1];
+
+// Parallel-ordering (round-robin) Jacobi on the symmetric b x b matrix H (LDS), one
+// workgroup.  Each round rotates floor(b/2) disjoint index pairs: the rotations are
+// computed in parallel, then applied as H <- J^T H J and Q <- Q J.  For a pair (p, q),
+// p < q, with c, s from the usual tau formula, column p becomes c col_p - s col_q and
+// column q becomes s col_p + c col_q (rows likewise); storing sn[q] = -s makes both
+// "cs[j] col_j - sn[j] col_partner".
+__device__ void jacobi_rounds(SmallMat* H, SmallMat* Q, int b, SmallMat* tmp, int* perm,
+                              double* cs, double* sn, int* partner, int* flag) {
+  const int tid = threadIdx.x;
+  const int bb = b + (b & 1);  // even number of players (one idle slot if b is odd)
+  for (int e = tid; e < b * b; e += blockDim.x) Q[e / b][e % b] = ((e / b) == (e % b)) ? 1.0 : 0.0;
+  if (tid < bb) perm[tid] = tid;
   __syncthreads();
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int round = 0; round < bb - 1; ++round) {
+      if (tid < bb) partner[tid] = -1;
+      __syncthreads();
+      if (tid < bb / 2) {
+        int p = perm[tid], q = perm[bb - 1 - tid];
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        if (q < b) {
+          double c = 1.0, s = 0.0;
+          const double apq = H[p][q], app = H[p][p], aqq = H[q][q];
+          if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq))) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            double t;
+            if (fabs(tau) > 1e150) {
+              t = 0.5 / tau;
+            } else {
+              t = 1.0 / (fabs(tau) + sqrt(1.0 + tau * tau));
+              if (tau < 0.0) t = -t;
+            }
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            *flag = 1;
+          }
+          partner[p] = q;
+          partner[q] = p;
+          cs[p] = c;
+          sn[p] = s;
+          cs[q] = c;
+          sn[q] = -s;
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < b * b; e += blockDim.x) {  // tmp = H J
+        const int i = e / b, j = e % b;
+        const int pj = partner[j];
+        tmp[i][j] = (pj >= 0) ? cs[j] * H[i][j] - sn[j] * H[i][pj] : H[i][j];
+      }
+      __syncthreads();
+      for (int e = tid; e < b * b; e += blockDim.x) {  // H = J^T tmp
+        const int i = e / b, j = e % b;
+        const int pi = partner[i];
+        H[i][j] = (pi >= 0) ? cs[i] * tmp[i][j] - sn[i] * tmp[pi][j] : tmp[i][j];
+      }
+      __syncthreads();
+      for (int e = tid; e < b * b; e += blockDim.x) {  // tmp = Q J
+        const int i = e / b, j = e % b;
+        const int pj = partner[j];
+        tmp[i][j] = (pj >= 0) ? cs[j] * Q[i][j] - sn[j] * Q[i][pj] : Q[i][j];
+      }
+      __syncthreads();
+      for (int e = tid; e < b * b; e += blockDim.x) {
+        const int i = e / b, j = e % b;
+        Q[i][j] = tmp[i][j];
+        if (i < j) {  // keep H exactly symmetric
+          const double avg = 0.5 * (H[i][j] + H[j][i]);
+          H[i][j] = avg;
+          H[j][i] = avg;
+        }
+      }
+      if (tid == 0) {  // circle method: player 0 fixed, the others rotate
+        const int last = perm[bb - 1];
+        for (int k = bb - 1; k > 1; --k) perm[k] = perm[k - 1];
+        perm[1] = last;
+      }
+      __syncthreads();
+    }
+    if (*flag == 0) break;
+    __syncthreads();
+  }
+}
+
+// Small part of Rayleigh-Ritz (one workgroup): Jacobi of H, eigenvalues sorted ascending;
+// writes Qs = Q with its columns in that order and theta.
+__global__ __launch_bounds__(256) void k_rr_small(const double* __restrict__ Hg, int b,
+                                                  double* __restrict__ Qs,
+                                                  double* __restrict__ theta_out) {
+  __shared__ SmallMat H[kEigMaxB];
+  __shared__ SmallMat Q[kEigMaxB];
+  __shared__ SmallMat tmp[kEigMaxB];
+  __shared__ int perm[kEigMaxB + 1];
+  __shared__ double cs[kEigMaxB + 1];
+  __shared__ double sn[kEigMaxB + 1];
+  __shared__ int partner[kEigMaxB + 1];
+  __shared__ int flag;
+  __shared__ int order[kEigMaxB];
+  const int tid = threadIdx.x;
   for (int e = tid; e < b * b; e += blockDim.x) {
     const int i = e / b, j = e % b;
-    if (i < j) {
-      const double avg = 0.5 * (H[i * b + j] + H[j * b + i]);
-      H[i * b + j] = avg;
-      H[j * b + i] = avg;
-    }
+    H[i][j] = 0.5 * (Hg[i * b + j] + Hg[j * b + i]);
   }
   __syncthreads();
-  if (tid < 64) jacobi_wave(H, Q, b);
+  jacobi_rounds(H, Q, b, tmp, perm, cs, sn, partner, &flag);
   __syncthreads();
   if (tid < b) {
-    const double dk = H[tid * b + tid];
+    const double dk = H[tid][tid];
     int rk = 0;
     for (int j = 0; j < b; ++j) {
-      const double dj = H[j * b + j];
+      const double dj = H[j][j];
       rk += (dj < dk) || (dj == dk && j < tid);
     }
     order[rk] = tid;
-    theta[rk] = dk;
+    theta_out[rk] = dk;
   }
   __syncthreads();
-  // V-hat = X Q[:, order[0..r)]
-  for (int64_t e = tid; e < n * r; e += blockDim.x) {
-    const int64_t i = e % n;
-    const int k = static_cast<int>(e / n);
-    const int col = order[k];
-    double s = 0.0;
-    for (int j = 0; j < b; ++j) s += X[i + j * n] * Q[j * b + col];
-    V[i + static_cast<int64_t>(k) * n] = s;
+  for (int e = tid; e < b * b; e += blockDim.x) {
+    const int j = e / b, k = e % b;  // Qs[j][k] = Q[j][order[k]]
+    Qs[e] = Q[j][order[k]];
   }
-  // residual of each Ritz pair: ||NX q - theta X q||
-  if (tid < 64) {
-    for (int k = 0; k < r; ++k) {
-      const int col = order[k];
-      double part = 0.0;
-      for (int64_t i = tid; i < n; i += 64) {
-        double s = 0.0;
-        for (int j = 0; j < b; ++j) s += (NX[i + j * n] - theta[k] * X[i + j * n]) * Q[j * b + col];
-        part += s * s;
+}
+
+// V-hat = X Qs[:, :r] and the squared residual norms ||NX q_k - theta_k X q_k||^2 (per
+// 64-row block, accumulated into res2[k]).
+__global__ __launch_bounds__(256) void k_rr_apply(const double* __restrict__ X,
+                                                  const double* __restrict__ NX, int64_t n,
+                                                  int b, int r, const double* __restrict__ Qs,
+                                                  const double* __restrict__ theta,
+                                                  double* __restrict__ V,
+                                                  double* __restrict__ res2) {
+  __shared__ double q[kEigMaxB * kEigMaxB];
+  __shared__ double red[4][RSM_MAX_R];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < b * b; e += blockDim.x) q[e] = Qs[e];
+  __syncthreads();
+  const int rr = tid % 64, g = tid / 64;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + rr;
+  for (int k = g; k < r; k += 4) {
+    double v = 0.0, res = 0.0;
+    if (i < n) {
+      for (int j = 0; j < b; ++j) {
+        const double x = X[i + static_cast<int64_t>(j) * n];
+        const double y = NX[i + static_cast<int64_t>(j) * n];
+        v += x * q[j * b + k];
+        res += (y - theta[k] * x) * q[j * b + k];
       }
-      part = wave_sum(part);
-      if (tid == 0) resid[k] = sqrt(part);
+      V[i + static_cast<int64_t>(k) * n] = v;
     }
+    const double s2 = wave_sum(res * res);
+    if (rr == 0) atomic_add_f64(&res2[k], s2);
   }
-  __syncthreads();
-  if (tid == 0) {
-    const double lam_max = scal->lam_max;
-    double rmax = 0.0;
-    for (int k = 0; k < r; ++k) rmax = fmax(rmax, resid[k]);
-    const double rel = lam_max > 0.0 ? rmax / lam_max : rmax;
-    info->residual = rel;
-    for (int k = 0; k <= r && k < b; ++k) info->lambda[k] = theta[k];
-    uint32_t warn = 0;
-    if (info->uncovered > 0) warn |= RSM_W_RANK_DEFICIENT;
-    if (b > r && !(theta[r] > 1e-12 * lam_max)) warn |= RSM_W_RANK_DEFICIENT;
-    if (rel > 1e-6) warn |= RSM_W_NOT_CONVERGED;
-    if (scal->pivots > 0) warn |= RSM_W_PIVOT;
-    if (check_accepted && info->accepted == 0) warn |= RSM_W_NO_CONSTRAINTS;
-    atomicOr(&info->warn, warn);
-    info->eig_iterations = kEigIters;
-  }
+}
+
+__global__ void k_rr_finish(int b, int r, const double* __restrict__ theta,
+                            const double* __restrict__ res2, DevScalars* scal, rsm_info* info,
+                            int check_accepted) {
+  if (threadIdx.x != 0) return;
+  const double lam_max = scal->lam_max;
+  double rmax = 0.0;
+  for (int k = 0; k < r; ++k) rmax = fmax(rmax, sqrt(res2[k]));
+  const double rel = lam_max > 0.0 ? rmax / lam_max : rmax;
+  info->residual = rel;
+  for (int k = 0; k <= r && k < b; ++k) info->lambda[k] = theta[k];
+  uint32_t warn = 0;
+  if (info->uncovered > 0) warn |= RSM_W_RANK_DEFICIENT;
+  if (b > r && !(theta[r] > 1e-12 * lam_max)) warn |= RSM_W_RANK_DEFICIENT;
+  if (rel > 1e-6) warn |= RSM_W_NOT_CONVERGED;
+  if (scal->pivots > 0) warn |= RSM_W_PIVOT;
+  if (check_accepted && info->accepted == 0) warn |= RSM_W_NO_CONSTRAINTS;
+  atomicOr(&info->warn, warn);
+  info->eig_iterations = kEigIters;
 }
 
 }  // namespace
 
-void launch_solve_v(const Plan& P, const double* N, double* Nsym, double* Lf, double* Lt,
-                    double* Dinv, double* X, double* Z, double* NX, DevScalars* scal, double* V,
-                    rsm_info* info, hipStream_t s) {
+void launch_solve_v(const Plan& P, const double* N, double* Nsym, double* Lf, double* Mi,
+                    double* T, double* Dinv, double* X, double* Z, double* NX, DevScalars* scal,
+                    double* V, rsm_info* info, hipStream_t s) {
   const int64_t n = P.n;
   const int b = P.eig_b;
-  const unsigned g_nn = static_cast<unsigned>(ceil_div(n * n, 256));
-  k_symmetrize<<<g_nn, 256, 0, s>>>(N, n, Nsym);
-  k_norm_stats<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(Nsym, n, scal, info);
-  k_chol_init<<<g_nn, 256, 0, s>>>(Nsym, n, Lf, scal, info);
   const int nb = P.nb;
+  const int64_t npad = P.npad;
+  const unsigned g_nn = static_cast<unsigned>(ceil_div(n * n, 256));
+  const unsigned g_rows = static_cast<unsigned>(ceil_div(n, 64));
+  const int64_t chunk_cols = ceil_div(n, 16);
+  // small scratch carved from T (its first use, by the inverse, is over by then)
+  double* rowsum = Z;              // n values, before the iteration uses Z
+  double* Hb = T;                  // b x b
+  double* Qs = T + kEigMaxB * kEigMaxB;
+  double* theta = Qs + kEigMaxB * kEigMaxB;
+  double* res2 = theta + kEigMaxB;
+  k_eig_prep<<<g_nn, 256, 0, s>>>(N, n, Nsym, Lf, rowsum, info);
+  k_rowsum<<<dim3(g_rows, 16), 256, 0, s>>>(Nsym, n, chunk_cols, rowsum);
   for (int k = 0; k < nb; ++k) {
-    k_chol_diag<<<1, 256, 0, s>>>(Lf, n, k, scal);
-    if (nb - k - 1 > 0) k_chol_panel<<<static_cast<unsigned>(nb - k - 1), 256, 0, s>>>(Lf, n, k);
-    const int tiles = (nb - k - 1) * (nb - k) / 2;
-    if (tiles > 0) k_chol_update<<<static_cast<unsigned>(tiles), 256, 0, s>>>(Lf, n, k, nb);
+    k_chol_diag<<<1, 256, 0, s>>>(Lf, n, k, Dinv, rowsum, scal, info);
+    if (nb - k - 1 > 0) {
+      k_chol_panel<<<static_cast<unsigned>(nb - k - 1), 256, 0, s>>>(Lf, n, k, Dinv);
+      const int tiles = (nb - k - 1) * (nb - k) / 2;
+      k_chol_update<<<static_cast<unsigned>(tiles), 256, 0, s>>>(Lf, n, k, nb);
+    }
   }
-  // Nsym is not needed past this point except for the Rayleigh-Ritz product; the
-  // transposed factor goes to Lt and the tile inverses to Dinv.
-  k_transpose_lower<<<g_nn, 256, 0, s>>>(Lf, n, Lt);
-  k_diag_inverse<<<static_cast<unsigned>(nb), 64, 0, s>>>(Lf, n, Dinv);
-  k_start_vectors<<<static_cast<unsigned>(ceil_div(n * b, 256)), 256, 0, s>>>(X, n, b, P.seed ^ 0x9E3779B97F4A7C15ull);
+  k_inv_init<<<static_cast<unsigned>(ceil_div(npad * npad, 256)), 256, 0, s>>>(Lf, Dinv, n, nb,
+                                                                                npad, Mi);
+  for (int64_t bs = NB; bs < npad; bs *= 2) {
+    const int64_t tpb = bs / NB;
+    const unsigned grid = static_cast<unsigned>((npad / (2 * bs)) * tpb * tpb);
+    k_inv_stage1<<<grid, 256, 0, s>>>(Mi, npad, bs, T);
+    k_inv_stage2<<<grid, 256, 0, s>>>(Mi, npad, bs, T);
+  }
+  k_start_vectors<<<static_cast<unsigned>(ceil_div(n * b, 256)), 256, 0, s>>>(
+      X, n, b, P.seed ^ 0x9E3779B97F4A7C15ull);
+  const int nt = static_cast<int>(ceil_div(n, NB));
+  const unsigned tri = static_cast<unsigned>(nt * (nt + 1) / 2);
+  const unsigned gz = static_cast<unsigned>(ceil_div(n * b, 256));
   for (int it = 0; it < kEigIters; ++it) {
-    k_trsm<<<1, 256, 0, s>>>(Lf, n, b, Dinv, X, Z, 0);
-    k_trsm<<<1, 256, 0, s>>>(Lt, n, b, Dinv, Z, Z, 1);
-    k_orth<<<1, 1024, 0, s>>>(Z, n, b, X);
+    k_zero<<<gz, 256, 0, s>>>(Z, n * b);
+    k_trmm<<<tri, 256, 0, s>>>(Mi, npad, n, b, X, Z, 0);
+    k_zero<<<gz, 256, 0, s>>>(NX, n * b);
+    k_trmm<<<tri, 256, 0, s>>>(Mi, npad, n, b, Z, NX, 1);
+    if (n <= 1024)
+      k_orth<1><<<1, 1024, 0, s>>>(NX, n, b, X);
+    else if (n <= 2048)
+      k_orth<2><<<1, 1024, 0, s>>>(NX, n, b, X);
+    else
+      k_orth<4><<<1, 1024, 0, s>>>(NX, n, b, X);
   }
-  k_symm_mult<<<static_cast<unsigned>(ceil_div(n, 64)), 256, 0, s>>>(Nsym, n, b, X, NX);
-  k_rayleigh_ritz<<<1, 256, 0, s>>>(X, NX, n, b, P.r, V, scal, info,
-                                    (P.flags & RSM_FINALIZE_ONLY) ? 0 : 1);
+  // Rayleigh-Ritz with the true N
+  k_zero<<<gz, 256, 0, s>>>(NX, n * b);
+  const int64_t small = kEigMaxB * kEigMaxB * 2 + 2 * kEigMaxB;
+  k_zero<<<static_cast<unsigned>(ceil_div(small, 256)), 256, 0, s>>>(Hb, small);
+  k_symm_mult<<<dim3(g_rows, 16), 256, 0, s>>>(Nsym, n, b, X, chunk_cols, NX);
+  k_xtnx<<<g_rows, 256, 0, s>>>(X, NX, n, b, Hb);
+  k_rr_small<<<1, 256, 0, s>>>(Hb, b, Qs, theta);
+  k_rr_apply<<<g_rows, 256, 0, s>>>(X, NX, n, b, P.r, Qs, theta, V, res2);
+  k_rr_finish<<<1, 64, 0, s>>>(b, P.r, theta, res2, scal, info,
+                               (P.flags & RSM_FINALIZE_ONLY) ? 0 : 1);
 }
 
 }  // namespace rsm

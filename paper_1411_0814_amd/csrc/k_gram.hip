@@ -6,9 +6,10 @@
 // The minor right singular vectors of Z_t = Y[R_t, C_t] are the eigenvectors of G_t for its
 // smallest eigenvalues (Section III; they are computed in k_minor.hip).
 //
-// Output: partial Grams over row splits, part[split][trial][g] with g enumerating
+// Output: partial Grams over row splits, part[split][g][trial] with g enumerating
 // (a, b), b <= a, row-major over the lower triangle, and partial row counts
-// prow[split][trial].  k_minor sums the splits in FP64.
+// prow[split][trial].  k_minor sums the splits in FP64.  A split is a range of 64-row
+// mask words [split * words_per_split, ...).
 //
 // Two kernels:
 //  * k_gram_plain  — one wavefront per (trial, row split).  Each 64-row word ANDs l mask
@@ -82,11 +83,11 @@ __global__ __launch_bounds__(256) void k_gram_plain(
     }
   }
 
-  TA* dst = part + (static_cast<int64_t>(split) * I + t) * NG;
+  TA* dst = part + static_cast<int64_t>(split) * NG * I + t;
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     const TA v = wave_sum(acc[g]);
-    if (lane == 0) dst[g] = v;
+    if (lane == 0) dst[static_cast<int64_t>(g) * I] = v;
   }
   if (lane == 0) prow[static_cast<int64_t>(split) * I + t] = count;
 }
@@ -100,17 +101,232 @@ void run_plain(const Plan& P, const void* ycm, int64_t ldy, const uint64_t* wbit
                                                static_cast<TA*>(part), prow);
 }
 
+// ------------------------------------------------------------------ LDS-tiled kernel
+//
+// Workgroup (trial group g, row split s): NT threads, thread = trial.  The split's rows are
+// walked in chunks of 32: the chunk's Y values for ALL n columns (column-major, 32 per
+// column) and its 32-bit mask words (one per column) are staged in LDS; every thread ANDs
+// its l mask words and, for each set bit, gathers its l values from LDS and accumulates
+// the l(l+1)/2 products.  The next chunk is loaded into registers (16-byte vectors) while
+// the current one is processed.  Global traffic is (trial groups) x (m n) elements instead
+// of I l m; the rest is LDS traffic proportional to the qualifying rows only.
+
+constexpr int kChunk = 32;
+
+// LDS column stride of the tile, in elements: the chunk's 32 rows plus padding that keeps
+// 16-byte alignment and spreads different columns over different LDS banks.
+template <typename T>
+struct TileStride;
+template <>
+struct TileStride<float> {
+  static constexpr int kValue = 36;
+};
+template <>
+struct TileStride<double> {
+  static constexpr int kValue = 34;
+};
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int kN = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int kN = 2;
+};
+
+template <int L, typename T, int NT>
+__global__ __launch_bounds__(NT) void k_gram_tile(
+    const T* __restrict__ Y, int64_t ldy, const uint32_t* __restrict__ mask32,
+    int64_t mw32, int64_t m, int n, int n_pad, int m_pad, const int32_t* __restrict__ cols,
+    int64_t I,
+    int64_t chunks_per_split, int64_t chunks, int groups, int xcd_map, T* __restrict__ part,
+    int32_t* __restrict__ prow) {
+  constexpr int NG = L * (L + 1) / 2;
+  using V = typename Vec16<T>::type;
+  constexpr int kVN = Vec16<T>::kN;                 // elements per 16-byte vector
+  constexpr int kVPC = kChunk / kVN;                // vectors per column of a chunk
+  constexpr int kS = TileStride<T>::kValue;           // LDS elements per column
+  constexpr int kVPS = kS / kVN;                      // 16-byte vectors per column stride
+  constexpr int kMaxCols = static_cast<int>(kTileLdsBytes / (kS * sizeof(T)));
+  constexpr int kMaxV = (kMaxCols * kVPC + NT - 1) / NT;
+  constexpr int kMaxM = (kMaxCols + NT - 1) / NT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);                                   // [n_pad][kS]
+  uint32_t* msk = reinterpret_cast<uint32_t*>(tile + static_cast<int64_t>(n_pad) * kS);  // [m_pad]
+
+  // Workgroup -> (trial group, row split).  Workgroups are dispatched to the 8 XCDs
+  // round-robin by id, so with xcd_map the ids id = 8 k + x of XCD x enumerate all trial
+  // groups of split 8 (k / groups) + x before the next split: the groups reading the same
+  // rows share that XCD's L2.
+  const int id = blockIdx.x;
+  int group, split;
+  if (xcd_map) {
+    const int x = id & 7, k = id >> 3;
+    const int sl = k / groups;
+    group = k - sl * groups;
+    split = sl * 8 + x;
+  } else {
+    group = id % groups;
+    split = id / groups;
+  }
+  const int tid = threadIdx.x;
+  const int64_t t = static_cast<int64_t>(group) * NT + tid;
+  const bool active = t < I;
+  const int64_t ch0 = static_cast<int64_t>(split) * chunks_per_split;
+  const int64_t ch1 = (ch0 + chunks_per_split < chunks) ? (ch0 + chunks_per_split) : chunks;
+
+  int mc[L];  // column index; its tile values start at mc * kChunk
+  bool valid = active;
+#pragma unroll
+  for (int a = 0; a < L; ++a) {
+    int c = active ? cols[t * L + a] : 0;
+    valid &= (c >= 0);
+    mc[a] = c < 0 ? 0 : c;
+  }
+  T acc[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) acc[g] = T(0);
+  int count = 0;
+
+  // Chunk staging.  The tile holds n_pad >= n columns (n_pad a multiple of NT / kVPC) and
+  // the mask row m_pad >= n words (a multiple of NT), so every thread moves exactly kv
+  // vectors and km mask words per chunk: uniform trip counts, loads issued back to back.
+  // Columns past n repeat column n - 1 (valid addresses, never read back).  Vector k of
+  // thread tid is column tid / kVPC + k * (NT / kVPC), rows kVN * (tid % kVPC) + [0, kVN).
+  static_assert(NT % kVPC == 0, "threads must cover whole columns");
+  const int kv = n_pad * kVPC / NT;
+  const int km = m_pad / NT;
+  const int c0 = tid / kVPC;
+  const int vpart = (tid % kVPC) * kVN;
+  V vreg[kMaxV];
+  uint32_t mreg[kMaxM];
+  auto load_chunk = [&](int64_t ch) {
+    const int64_t r0 = ch * kChunk;
+    if (r0 + kChunk <= m) {
+#pragma unroll
+      for (int k = 0; k < kMaxV; ++k) {
+        if (k < kv) {
+          const int c = min(c0 + k * (NT / kVPC), n - 1);
+          vreg[k] = *reinterpret_cast<const V*>(Y + static_cast<int64_t>(c) * ldy + r0 + vpart);
+        }
+      }
+    } else {  // ragged last chunk: rows past m read as zero
+#pragma unroll
+      for (int k = 0; k < kMaxV; ++k) {
+        if (k < kv) {
+          const int c = min(c0 + k * (NT / kVPC), n - 1);
+          const T* src = Y + static_cast<int64_t>(c) * ldy + r0 + vpart;
+          T tmp[kVN];
+#pragma unroll
+          for (int u = 0; u < kVN; ++u) tmp[u] = (r0 + vpart + u < m) ? src[u] : T(0);
+          V v;
+          __builtin_memcpy(&v, tmp, sizeof(V));
+          vreg[k] = v;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxM; ++k) {
+      if (k < km) {
+        const int c = min(tid + k * NT, n - 1);
+        mreg[k] = mask32[static_cast<int64_t>(c) * mw32 + ch];
+      }
+    }
+  };
+  auto store_chunk = [&]() {
+    V* tv = reinterpret_cast<V*>(tile) + c0 * kVPS + (tid % kVPC);
+#pragma unroll
+    for (int k = 0; k < kMaxV; ++k)
+      if (k < kv) tv[k * (NT / kVPC) * kVPS] = vreg[k];
+#pragma unroll
+    for (int k = 0; k < kMaxM; ++k)
+      if (k < km) msk[tid + k * NT] = mreg[k];
+  };
+
+  if (ch0 < ch1) load_chunk(ch0);
+  for (int64_t ch = ch0; ch < ch1; ++ch) {
+    __syncthreads();
+    store_chunk();
+    __syncthreads();
+    if (ch + 1 < ch1) load_chunk(ch + 1);
+    if (valid) {
+      uint32_t q = 0xffffffffu;
+#pragma unroll
+      for (int a = 0; a < L; ++a) q &= msk[mc[a]];
+      count += __popc(q);
+      // walk the set bits starting at a lane-dependent row, so that the lanes of a
+      // wavefront read different rows (and LDS banks) in the same step
+      const int rot = (tid * 13) & (kChunk - 1);
+      q = (q >> rot) | (q << ((kChunk - rot) & (kChunk - 1)));
+      while (q) {
+        const int i = (__ffs(q) - 1 + rot) & (kChunk - 1);
+        q &= q - 1;
+        T y[L];
+#pragma unroll
+        for (int a = 0; a < L; ++a) y[a] = tile[mc[a] * kS + i];
+        int g = 0;
+#pragma unroll
+        for (int a = 0; a < L; ++a)
+#pragma unroll
+          for (int b = 0; b <= a; ++b) acc[g++] += y[a] * y[b];
+      }
+    }
+  }
+  if (active) {
+    T* dst = part + static_cast<int64_t>(split) * NG * I + t;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) dst[static_cast<int64_t>(g) * I] = acc[g];
+    prow[static_cast<int64_t>(split) * I + t] = count;
+  }
+}
+
+template <int L, typename T>
+void run_tile(const Plan& P, const void* ycm, int64_t ldy, const uint64_t* wbits,
+              const int32_t* cols, void* part, int32_t* prow, hipStream_t s) {
+  constexpr int NT = tile_threads(L, sizeof(T));
+  constexpr int kVPC = kChunk / Vec16<T>::kN;
+  const int n = static_cast<int>(P.n);
+  const int n_pad = static_cast<int>(ceil_div(n, NT / kVPC) * (NT / kVPC));
+  const int m_pad = static_cast<int>(ceil_div(n, NT) * NT);
+  const size_t lds = static_cast<size_t>(n_pad) * TileStride<T>::kValue * sizeof(T) +
+                     static_cast<size_t>(m_pad) * sizeof(uint32_t);
+  static bool attr_set = false;  // dynamic LDS above 64 KiB must be allowed explicitly
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_tile<L, T, NT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(kTileLdsBytes + 8192));
+    attr_set = true;
+  }
+  const int64_t chunks = ceil_div(P.m, kChunk);
+  const int groups = static_cast<int>(ceil_div(P.I, NT));
+  const int xcd_map = (P.splits % 8 == 0) ? 1 : 0;
+  const unsigned grid = static_cast<unsigned>(groups) * static_cast<unsigned>(P.splits);
+  k_gram_tile<L, T, NT><<<grid, NT, lds, s>>>(
+      static_cast<const T*>(ycm), ldy, reinterpret_cast<const uint32_t*>(wbits), 2 * P.mw, P.m,
+      n, n_pad, m_pad, cols, P.I, 2 * P.words_per_split, chunks, groups, xcd_map,
+      static_cast<T*>(part), prow);
+}
+
 template <int L>
 void dispatch_types(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
                     const uint64_t* wbits, const int32_t* cols, void* part, int32_t* prow,
-                    hipStream_t s) {
+                    hipStream_t s, bool tiled) {
   if (P.prec == RSM_GRAM_F64) {
-    if (y_dtype == RSM_F32)
+    if (y_dtype == RSM_F64 && tiled)
+      run_tile<L, double>(P, ycm, ldy, wbits, cols, part, prow, s);
+    else if (y_dtype == RSM_F32)
       run_plain<L, float, double>(P, ycm, ldy, wbits, cols, part, prow, s);
     else
       run_plain<L, double, double>(P, ycm, ldy, wbits, cols, part, prow, s);
   } else {
-    if (y_dtype == RSM_F32)
+    if (y_dtype == RSM_F32 && tiled)
+      run_tile<L, float>(P, ycm, ldy, wbits, cols, part, prow, s);
+    else if (y_dtype == RSM_F32)
       run_plain<L, float, float>(P, ycm, ldy, wbits, cols, part, prow, s);
     else
       run_plain<L, double, float>(P, ycm, ldy, wbits, cols, part, prow, s);
@@ -119,14 +335,27 @@ void dispatch_types(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
 
 }  // namespace
 
+bool gram_tiled_ok(const Plan& P, const void* ycm, int64_t ldy, int y_dtype) {
+  if (!P.tiled) return false;
+  const bool same = (P.prec == RSM_GRAM_F64) == (y_dtype == RSM_F64);
+  const size_t elem = (y_dtype == RSM_F64) ? 8 : 4;
+  if (!same) return false;
+  const size_t stride = (y_dtype == RSM_F64) ? TileStride<double>::kValue : TileStride<float>::kValue;
+  if (static_cast<size_t>(ceil_div(P.n, 64) * 64) * stride * elem > kTileLdsBytes) return false;
+  if ((reinterpret_cast<uintptr_t>(ycm) % 16) != 0) return false;
+  if ((static_cast<size_t>(ldy) * elem) % 16 != 0) return false;
+  return true;
+}
+
 void launch_gram(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
                  const uint64_t* wbits, const int32_t* cols, void* part, int32_t* prow,
                  hipStream_t s) {
   if (P.I == 0) return;
+  const bool tiled = gram_tiled_ok(P, ycm, ldy, y_dtype);
   switch (P.l) {
 #define RSM_GRAM_CASE(LL) \
   case LL:                \
-    dispatch_types<LL>(P, ycm, ldy, y_dtype, wbits, cols, part, prow, s); \
+    dispatch_types<LL>(P, ycm, ldy, y_dtype, wbits, cols, part, prow, s, tiled); \
     break;
     RSM_GRAM_CASE(2) RSM_GRAM_CASE(3) RSM_GRAM_CASE(4) RSM_GRAM_CASE(5) RSM_GRAM_CASE(6)
     RSM_GRAM_CASE(7) RSM_GRAM_CASE(8) RSM_GRAM_CASE(9) RSM_GRAM_CASE(10) RSM_GRAM_CASE(11)

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(MinorCfg<L>::kThreads) void k_minor(
       for (int j = 0; j <= i; ++j, ++g) {
         double sum = 0.0;
         for (int s = 0; s < splits; ++s)
-          sum += static_cast<double>(part[(static_cast<int64_t>(s) * I + t) * NG + g]);
+          sum += static_cast<double>(part[(static_cast<int64_t>(s) * NG + g) * I + t]);
         a(i, j) = sum;
         a(j, i) = sum;
       }

@@ -64,13 +64,30 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   P.part_elem = (p.gram_prec == RSM_GRAM_F64) ? sizeof(double) : sizeof(float);
   P.eig_b = static_cast<int>((p.r + kEigPad) < p.n ? (p.r + kEigPad) : p.n);
   P.nb = static_cast<int>(ceil_div(p.n, kCholNB));
+  int64_t nbp = 1;
+  while (nbp < P.nb) nbp *= 2;
+  P.npad = nbp * kCholNB;
 
-  // Gram step: per-trial streamer; split rows so that there are enough wavefronts
-  P.tiled = false;
+  // Gram step.  Tiled kernel (one trial per thread, a 32-row x n tile of Y in LDS): split
+  // the rows so that (trial groups) x (splits) is about one workgroup per CU.  Per-trial
+  // streamer: enough wavefronts of (trial, split).
+  const size_t acc_elem = (p.gram_prec == RSM_GRAM_F64) ? sizeof(double) : sizeof(float);
+  const size_t tile_stride = (acc_elem == sizeof(double)) ? 34 : 36;  // see k_gram_tile
+  P.tiled = !(p.flags & RSM_PLAIN_GRAM) &&
+            static_cast<size_t>(ceil_div(p.n, 64) * 64) * tile_stride * acc_elem <= kTileLdsBytes;
   int64_t splits = 1;
-  if (P.I > 0 && P.I < 8192) splits = ceil_div(8192, P.I);
+  if (P.tiled) {
+    const int64_t groups =
+        ceil_div(P.I > 0 ? P.I : 1, tile_threads(l, static_cast<int>(acc_elem)));
+    splits = kTileTargetGroups / groups;
+    if (splits < 1) splits = 1;
+    if (splits >= 8) splits -= splits % 8;  // whole XCD rounds (see k_gram_tile)
+  } else if (P.I > 0 && P.I < 8192) {
+    splits = ceil_div(8192, P.I);
+  }
   if (splits > P.mw) splits = P.mw;
   P.words_per_split = ceil_div(P.mw, splits);
+  // the splits actually needed to cover mw words (never more than requested)
   P.splits = static_cast<int>(ceil_div(P.mw, P.words_per_split));
 
   // workspace layout
@@ -88,7 +105,9 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   P.off_N = carve(cur, nn);
   P.off_Nsym = carve(cur, nn);
   P.off_L = carve(cur, nn);
-  P.off_Lt = carve(cur, nn);
+  const size_t pp = static_cast<size_t>(P.npad) * P.npad * sizeof(double);
+  P.off_M = carve(cur, pp);
+  P.off_T = carve(cur, pp / 2);
   P.off_Dinv = carve(cur, static_cast<size_t>(P.nb) * kCholNB * kCholNB * sizeof(double));
   const size_t nbv = static_cast<size_t>(P.n) * P.eig_b * sizeof(double);
   P.off_X = carve(cur, nbv);
@@ -171,8 +190,9 @@ void enqueue(const Plan& P, const rsm_input& in, const rsm_output& out, void* ws
   // a6: V-hat
   mark(out, RSM_STEP_EIG, 0, s);
   launch_solve_v(P, N, at<double>(ws, P.off_Nsym), at<double>(ws, P.off_L),
-                 at<double>(ws, P.off_Lt), at<double>(ws, P.off_Dinv), at<double>(ws, P.off_X),
-                 at<double>(ws, P.off_Z), at<double>(ws, P.off_NX), scal, out.V, info, s);
+                 at<double>(ws, P.off_M), at<double>(ws, P.off_T), at<double>(ws, P.off_Dinv),
+                 at<double>(ws, P.off_X), at<double>(ws, P.off_Z), at<double>(ws, P.off_NX), scal,
+                 out.V, info, s);
   mark(out, RSM_STEP_EIG, 1, s);
   // a7: U-hat
   mark(out, RSM_STEP_USOLVE, 0, s);

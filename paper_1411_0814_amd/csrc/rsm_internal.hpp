@@ -16,9 +16,14 @@ constexpr int kCholNB = 64;               // tile of the blocked Cholesky of N
 constexpr int kEigPad = 4;                // extra vectors in the subspace iteration for V-hat
 constexpr int kEigMaxB = RSM_MAX_R + kEigPad + 1;
 constexpr int kEigIters = 3;              // inverse-iteration steps
-constexpr int kTileRows = 32;             // rows per LDS tile of the tiled Gram kernel
-constexpr size_t kTileLdsBytes = 144 * 1024;  // LDS budget of one tiled-Gram workgroup
-constexpr int kTileThreads = 1024;        // trials per tiled-Gram workgroup (one per thread)
+constexpr size_t kTileLdsBytes = 148 * 1024;  // LDS budget of the Y tile of the tiled Gram
+constexpr int64_t kTileTargetGroups = 256;    // tiled Gram: workgroups to aim for (one per CU)
+
+// Threads (= trials) per workgroup of the tiled Gram kernel: as many as the register file
+// allows with l(l+1)/2 accumulators plus the prefetched next tile held per thread.
+__host__ __device__ constexpr int tile_threads(int l, int elem_bytes) {
+  return elem_bytes == 4 ? (l <= 10 ? 512 : 256) : (l <= 6 ? 512 : 256);
+}
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -50,11 +55,12 @@ struct Plan {
   int64_t words_per_split = 0;  // 64-row mask words per split
   int eig_b = 0;         // subspace width of the V-hat iteration
   int nb = 0;            // Cholesky tiles per dimension
+  int64_t npad = 0;      // 64 x (nb rounded up to a power of two): size of L^{-1}
   size_t part_elem = 4;  // bytes of one partial-Gram element
   // workspace offsets (bytes from the workspace base); ~0 = unused
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0;
-  size_t off_N = 0, off_Nsym = 0, off_L = 0, off_Lt = 0, off_Dinv = 0, off_X = 0, off_Z = 0,
-         off_NX = 0;
+  size_t off_N = 0, off_Nsym = 0, off_L = 0, off_M = 0, off_T = 0, off_Dinv = 0, off_X = 0,
+         off_Z = 0, off_NX = 0;
   size_t off_scal = 0;
   size_t total = 0;
 };
@@ -76,9 +82,9 @@ void launch_gram(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
                  hipStream_t s);
 void launch_minor(const Plan& P, const void* part, const int32_t* prow, const int32_t* cols,
                   double* N, rsm_info* info, const rsm_output& out, hipStream_t s);
-void launch_solve_v(const Plan& P, const double* N, double* Nsym, double* Lf, double* Lt,
-                    double* Dinv, double* X, double* Z, double* NX, DevScalars* scal, double* V,
-                    rsm_info* info, hipStream_t s);
+void launch_solve_v(const Plan& P, const double* N, double* Nsym, double* Lf, double* Mi,
+                    double* T, double* Dinv, double* X, double* Z, double* NX, DevScalars* scal,
+                    double* V, rsm_info* info, hipStream_t s);
 void launch_solve_u(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
                     const uint64_t* wbits, const double* V, double* U, rsm_info* info,
                     hipStream_t s);
