@@ -79,87 +79,141 @@ __global__ __launch_bounds__(256) void k_rowsum(const double* __restrict__ Ns, i
 
 // ------------------------------------------------------------------ 2. Cholesky
 
-// Factor tile (k, k) of N + mu I (one workgroup), write L_kk and its inverse Dinv_kk
-// (a ragged last tile is completed with the identity).
-__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ Lf, int64_t n, int k,
-                                                   double* __restrict__ Dinv,
-                                                   const double* __restrict__ rowsum,
-                                                   DevScalars* scal, rsm_info* info) {
-  __shared__ double A[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
-  __shared__ int npiv;
-  const int tid = threadIdx.x;
-  const int64_t k0 = static_cast<int64_t>(k) * NB;
-  const int kb = static_cast<int>((n - k0) < NB ? (n - k0) : NB);
-  __shared__ double wmax[4];
-  if (k == 0) {  // Gershgorin bound from the row sums, once
-    double v = 0.0;
-    for (int64_t i = tid; i < n; i += blockDim.x) v = fmax(v, rowsum[i]);
+// Factor tile (k, k) of N + mu I and invert the factor, by one wavefront: lane i holds
+// row i of the tile in registers (static indices after full unrolling).  Step j of the
+// factorisation broadcasts column j through LDS; step j of the inverse (L X = I, rows of
+// X finished in order) broadcasts row j of X.  Writes L_kk into Lf and Dinv_kk = L_kk^{-1}.
+// A ragged last tile is completed with the identity.
+// Step J of the left-looking (Crout) factorisation, lane = row: column J of L is
+//   l_iJ = (a_iJ - sum_{p<J} l_ip l_Jp) / l_JJ,   l_JJ = sqrt(a_JJ - sum_{p<J} l_Jp^2),
+// with row J of L read from LDS (broadcast) and the lane's own finished entries l[0..J)
+// in registers.  The pivot lane stores 1 / l_JJ (from rsqrt) for the other lanes and for
+// the inverse.  Four partial sums shorten the dependent chain.  The template recursion
+// keeps every index static.
+template <int J>
+__device__ __forceinline__ void crout_steps(double (&l)[NB], const double (*As)[NB + 1],
+                                            double (*Ls)[NB + 1], double* invd, int lane,
+                                            double mu, int& npiv) {
+  if constexpr (J < NB) {
+    double s4[4] = {As[lane][J], 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    if ((tid & 63) == 0) wmax[tid >> 6] = v;
-    __syncthreads();
-    if (tid == 0) scal->lam_max = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
-    __syncthreads();
-  }
-  const double mu = shift_of(scal);
-  if (tid == 0) {
-    npiv = 0;
-    if (k == 0) {
-      scal->mu = mu;
-      info->mu = mu;
+    for (int p0 = 0; p0 < J; p0 += 8) {
+#pragma unroll
+      for (int p = p0; p < p0 + 8 && p < J; ++p) s4[p & 3] -= l[p] * Ls[J][p];
+      __builtin_amdgcn_sched_barrier(0);
     }
-  }
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int ii = e % NB, jj = e / NB;
-    double v;
-    if (ii < kb && jj < kb)
-      v = (jj <= ii) ? Lf[(k0 + ii) + (k0 + jj) * n] + (ii == jj ? mu : 0.0) : 0.0;
-    else
-      v = (ii == jj) ? 1.0 : 0.0;
-    A[ii][jj] = v;
-    X[ii][jj] = (ii == jj) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  // right-looking unblocked factorisation
-  for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      double d = A[j][j];
-      if (!(d > 0.0) || !isfinite(d)) {
-        d = mu;
+    double sum = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    if (lane == J) {
+      if (!(sum > 0.0) || !isfinite(sum)) {
+        sum = mu;
         ++npiv;
       }
-      A[j][j] = sqrt(d);
+      const double inv = rsqrt(sum);
+      l[J] = sum * inv;
+      Ls[J][J] = l[J];
+      invd[J] = inv;
     }
     __syncthreads();
-    const double ljj = A[j][j];
-    for (int i = j + 1 + tid; i < NB; i += blockDim.x) A[i][j] /= ljj;
-    __syncthreads();
-    const int rem = NB - j - 1;
-    for (int e = tid; e < rem * rem; e += blockDim.x) {
-      const int ii = j + 1 + e / rem, cc = j + 1 + e % rem;
-      if (cc <= ii) A[ii][cc] -= A[ii][j] * A[cc][j];
+    if (lane > J) {
+      l[J] = sum * invd[J];
+      Ls[lane][J] = l[J];
     }
     __syncthreads();
+    crout_steps<J + 1>(l, As, Ls, invd, lane, mu, npiv);
   }
-  // inverse of the lower-triangular factor: L X = I, row j of X finished at step j
-  for (int j = 0; j < NB; ++j) {
-    const double ljj = A[j][j];
-    if (tid < NB) X[j][tid] /= ljj;
-    __syncthreads();
-    const int rem = NB - j - 1;
-    for (int e = tid; e < rem * NB; e += blockDim.x) {
-      const int ii = j + 1 + e / NB, cc = e % NB;
-      X[ii][cc] -= A[ii][j] * X[j][cc];
+}
+
+// Step J of X = L^{-1} (lane = row of X): row J of X is final; rows below subtract it.
+template <int J>
+__device__ __forceinline__ void trinv_steps(double (&x)[NB], double* bc, double (*Ls)[NB + 1],
+                                            const double* invd, int lane) {
+  if constexpr (J < NB) {
+    if (lane == J) {
+      const double inv = invd[J];
+#pragma unroll
+      for (int c = 0; c <= J; ++c) {
+        x[c] *= inv;
+        bc[c] = x[c];
+      }
     }
     __syncthreads();
+    if (lane > J) {
+      const double lij = Ls[lane][J];
+#pragma unroll
+      for (int c0 = 0; c0 <= J; c0 += 8) {
+#pragma unroll
+        for (int c = c0; c < c0 + 8 && c <= J; ++c) x[c] -= lij * bc[c];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    __syncthreads();
+    trinv_steps<J + 1>(x, bc, Ls, invd, lane);
   }
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int ii = e % NB, jj = e / NB;
-    if (ii < kb && jj < kb && jj <= ii) Lf[(k0 + ii) + (k0 + jj) * n] = A[ii][jj];
-    Dinv[static_cast<int64_t>(k) * NB * NB + e] = (jj <= ii) ? X[ii][jj] : 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ Lf, int64_t n, int k,
+                                                  double* __restrict__ Dinv,
+                                                  const double* __restrict__ rowsum,
+                                                  DevScalars* scal, rsm_info* info) {
+  __shared__ double bc[NB];
+  __shared__ double invd[NB];
+  __shared__ double As[NB][NB + 1];
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double lam;
+  const int lane = threadIdx.x;
+  const int64_t k0 = static_cast<int64_t>(k) * NB;
+  const int kb = static_cast<int>((n - k0) < NB ? (n - k0) : NB);
+  if (k == 0) {  // Gershgorin bound from the row sums, once
+    double v = 0.0;
+    for (int64_t i = lane; i < n; i += NB) v = fmax(v, rowsum[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if (lane == 0) {
+      scal->lam_max = v;
+      lam = v;
+    }
+  } else if (lane == 0) {
+    lam = scal->lam_max;
   }
-  if (tid == 0 && npiv) atomicAdd(&scal->pivots, npiv);
+  __syncthreads();
+  const double mu = lam > 0.0 ? kShiftRel * lam : 1.0;
+  if (k == 0 && lane == 0) {
+    scal->mu = mu;
+    info->mu = mu;
+  }
+  // stage the tile (coalesced: lane = row), shift on the diagonal, identity past n
+  for (int c = 0; c < NB; ++c) {
+    double v;
+    if (lane < kb && c < kb)
+      v = (c <= lane) ? Lf[(k0 + lane) + (k0 + c) * n] + (c == lane ? mu : 0.0) : 0.0;
+    else
+      v = (lane == c) ? 1.0 : 0.0;
+    As[lane][c] = v;
+    Ls[lane][c] = 0.0;
+  }
+  __syncthreads();
+  int npiv = 0;
+  {
+    double l[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) l[c] = 0.0;
+    crout_steps<0>(l, As, Ls, invd, lane, mu, npiv);
+  }
+  for (int c = 0; c < NB; ++c)  // L back to memory (lower part)
+    if (lane < kb && c < kb && c <= lane) Lf[(k0 + lane) + (k0 + c) * n] = Ls[lane][c];
+  {
+    double x[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) x[c] = (c == lane) ? 1.0 : 0.0;
+    trinv_steps<0>(x, bc, Ls, invd, lane);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Ls[lane][c] = (c <= lane) ? x[c] : 0.0;
+  }
+  __syncthreads();
+  double* out = Dinv + static_cast<int64_t>(k) * NB * NB;
+  for (int c = 0; c < NB; ++c) out[lane + c * NB] = Ls[lane][c];
+  if (npiv) atomicAdd(&scal->pivots, npiv);
 }
 
 // Panel: tile (k+1+bid, k) becomes L_ik = A_ik L_kk^{-T} = A_ik Dinv_kk^T.
@@ -777,7 +831,7 @@ void launch_solve_v(const Plan& P, const double* N, double* Nsym, double* Lf, do
   k_eig_prep<<<g_nn, 256, 0, s>>>(N, n, Nsym, Lf, rowsum, info);
   k_rowsum<<<dim3(g_rows, 16), 256, 0, s>>>(Nsym, n, chunk_cols, rowsum);
   for (int k = 0; k < nb; ++k) {
-    k_chol_diag<<<1, 256, 0, s>>>(Lf, n, k, Dinv, rowsum, scal, info);
+    k_chol_diag<<<1, NB, 0, s>>>(Lf, n, k, Dinv, rowsum, scal, info);
     if (nb - k - 1 > 0) {
       k_chol_panel<<<static_cast<unsigned>(nb - k - 1), 256, 0, s>>>(Lf, n, k, Dinv);
       const int tiles = (nb - k - 1) * (nb - k) / 2;

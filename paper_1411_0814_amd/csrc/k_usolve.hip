@@ -18,6 +18,7 @@ namespace rsm {
 namespace {
 
 constexpr int kUChunk = 256;  // columns of V-hat per LDS stage
+constexpr int kUnroll = 4;    // columns whose loads are issued together
 
 template <int R, typename TY>
 __global__ __launch_bounds__(256) void k_usolve(const TY* __restrict__ Y, int64_t ldy,
@@ -40,6 +41,8 @@ __global__ __launch_bounds__(256) void k_usolve(const TY* __restrict__ Y, int64_
   for (int a = 0; a < R; ++a) bv[a] = 0.0;
   int cnt = 0;
   const bool wave_active = w < mw;
+  // rows past m (last wavefront only) read row m - 1: valid address, zero weight
+  const int64_t iy = active ? i : (m - 1);
   for (int64_t j0 = 0; j0 < n; j0 += kUChunk) {
     const int jn = static_cast<int>((n - j0) < kUChunk ? (n - j0) : kUChunk);
     __syncthreads();
@@ -49,22 +52,40 @@ __global__ __launch_bounds__(256) void k_usolve(const TY* __restrict__ Y, int64_
     }
     __syncthreads();
     if (wave_active) {
-      for (int jj = 0; jj < jn; ++jj) {
-        const int64_t j = j0 + jj;
-        const uint64_t word = wbits[j * mw + w];
-        if ((word >> bit) & 1ull) {
-          const double y = static_cast<double>(Y[j * ldy + i]);
-          double v[R];
+      // groups of kUnroll columns: all loads of a group first, then the products; the
+      // mask bit is a 0/1 weight, so there is no divergent branch
+      for (int jj = 0; jj < jn; jj += kUnroll) {
+        uint64_t word[kUnroll];
+        double y[kUnroll];
 #pragma unroll
-          for (int a = 0; a < R; ++a) v[a] = Vs[jj * R + a];
+        for (int u = 0; u < kUnroll; ++u) {
+          const int64_t j = j0 + jj + u;
+          if (jj + u < jn) {
+            word[u] = wbits[j * mw + w];
+            y[u] = static_cast<double>(Y[j * ldy + iy]);
+          } else {
+            word[u] = 0;
+            y[u] = 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const bool known = ((word[u] >> bit) & 1ull) && active;
+          const double yw = known ? y[u] : 0.0;
+          double v[R], wv[R];
+#pragma unroll
+          for (int a = 0; a < R; ++a) {
+            v[a] = Vs[(jj + u) * R + a];
+            wv[a] = known ? v[a] : 0.0;
+          }
           int g = 0;
 #pragma unroll
           for (int a = 0; a < R; ++a) {
-            bv[a] += y * v[a];
+            bv[a] += yw * v[a];
 #pragma unroll
-            for (int b = 0; b <= a; ++b) A[g++] += v[a] * v[b];
+            for (int b = 0; b <= a; ++b) A[g++] += wv[a] * v[b];
           }
-          ++cnt;
+          cnt += known ? 1 : 0;
         }
       }
     }

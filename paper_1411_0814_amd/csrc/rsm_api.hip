@@ -101,6 +101,8 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   P.off_cols = carve(cur, static_cast<size_t>(P.I) * l * sizeof(int32_t));
   P.off_part = carve(cur, static_cast<size_t>(P.splits) * P.I * P.ng * P.part_elem);
   P.off_prow = carve(cur, static_cast<size_t>(P.splits) * P.I * sizeof(int32_t));
+  P.off_G = carve(cur, static_cast<size_t>(P.I) * P.ng * sizeof(double));
+  P.off_rows = carve(cur, static_cast<size_t>(P.I) * sizeof(int32_t));
   const size_t nn = static_cast<size_t>(P.n) * P.n * sizeof(double);
   P.off_N = carve(cur, nn);
   P.off_Nsym = carve(cur, nn);
@@ -182,7 +184,8 @@ void enqueue(const Plan& P, const rsm_input& in, const rsm_output& out, void* ws
     mark(out, RSM_STEP_GRAM, 1, s);
     // a4 + a5: minor vectors, N accumulation
     mark(out, RSM_STEP_MINOR, 0, s);
-    launch_minor(P, part, prow, cols, N, info, out, s);
+    launch_minor(P, part, prow, cols, at<double>(ws, P.off_G), at<int32_t>(ws, P.off_rows), N,
+                 info, out, s);
     mark(out, RSM_STEP_MINOR, 1, s);
   }
   if (acc_only) return;

@@ -58,7 +58,8 @@ struct Plan {
   int64_t npad = 0;      // 64 x (nb rounded up to a power of two): size of L^{-1}
   size_t part_elem = 4;  // bytes of one partial-Gram element
   // workspace offsets (bytes from the workspace base); ~0 = unused
-  size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0;
+  size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
+         off_rows = 0;
   size_t off_N = 0, off_Nsym = 0, off_L = 0, off_M = 0, off_T = 0, off_Dinv = 0, off_X = 0,
          off_Z = 0, off_NX = 0;
   size_t off_scal = 0;
@@ -81,7 +82,8 @@ void launch_gram(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
                  const uint64_t* wbits, const int32_t* cols, void* part, int32_t* prow,
                  hipStream_t s);
 void launch_minor(const Plan& P, const void* part, const int32_t* prow, const int32_t* cols,
-                  double* N, rsm_info* info, const rsm_output& out, hipStream_t s);
+                  double* G, int32_t* rows, double* N, rsm_info* info, const rsm_output& out,
+                  hipStream_t s);
 void launch_solve_v(const Plan& P, const double* N, double* Nsym, double* Lf, double* Mi,
                     double* T, double* Dinv, double* X, double* Z, double* NX, DevScalars* scal,
                     double* V, rsm_info* info, hipStream_t s);

@@ -227,3 +227,21 @@ def test_trial_begin_shifts_the_stream():
     a.info(), b.info()
     assert np.array_equal(a.taps["cols"].cpu().numpy()[40:], b.taps["cols"].cpu().numpy())
     assert np.array_equal(a.taps["rows"].cpu().numpy()[40:], b.taps["rows"].cpu().numpy())
+
+
+def test_large_l_fp32_parity():
+    """r = 12, l = 13 (the LDS Jacobi path and 256-thread Gram tiles), FP32 data and Gram."""
+    p = synth.paper_synthetic(8000, 150, 12, 0.95, 1e-3, 12, factor_dtype=np.float32,
+                              y_dtype=np.float32, num_submatrices=700, l=13, gram="f32")
+    res, info = _run(p, "f32", taps=True)
+    ora = rsm.rsm(p.Y, p.W, p.r, p.num_submatrices, seed=p.seed_rsm, l=p.l)
+    theta, rms = _compare_full(p, res, info, ora, u=2.0**-24)
+    print(f"large l fp32: theta={theta:.3e} rms={rms:.3e}")
+
+
+def test_small_l_fp64_tiled():
+    """r = 1, l = 2: the smallest template instances."""
+    p = synth.paper_synthetic(700, 40, 1, 0.8, 1e-2, 13, num_submatrices=300, l=2)
+    res, info = _run(p, "f64", taps=True)
+    ora = rsm.rsm(p.Y, p.W, p.r, p.num_submatrices, seed=p.seed_rsm, l=p.l)
+    _compare_full(p, res, info, ora, u=2.0**-53)
