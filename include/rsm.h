@@ -52,7 +52,7 @@ extern "C" {
 /* Size limits of this build. */
 #define RSM_MAX_R 16          /* rank r */
 #define RSM_MAX_L 17          /* columns per sub-matrix l (r < l <= RSM_MAX_L) */
-#define RSM_MAX_N 4096        /* columns of Y */
+#define RSM_MAX_N 2048        /* columns of Y */
 
 /* Return values.  Negative: error, nothing (or, for RSM_E_DEVICE, not everything) was
  * enqueued.  Warnings are never returned; they are bits of rsm_info.warn. */

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "librsm.so")
 ABI_VERSION = 1
 MAX_R = 16
 MAX_L = 17
-MAX_N = 4096
+MAX_N = 2048
 
 OK = 0
 E_ARG = -1

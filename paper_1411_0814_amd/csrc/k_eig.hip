@@ -8,17 +8,23 @@
 //   2. mu = 1e-8 lam_max, so cond(N + mu I) <= 1e8 and cond(L) <= 1e4: the factor and its
 //      explicit inverse stay accurate to ~1e-12 relative, while one step of inverse
 //      iteration still shrinks the unwanted components by (lambda_r + mu) /
-//      (lambda_{b+1} + mu).  Blocked right-looking Cholesky N + mu I = L L^T in 64 x 64
-//      tiles; each diagonal tile's inverse is formed with its factor, so the panel solve
-//      is a product.
+//      (lambda_{b+1} + mu).  Blocked Cholesky N + mu I = L L^T in 64 x 64 tiles, one launch
+//      per tile step: each workgroup of the step solves the two panel tiles it needs with
+//      the inverse of the diagonal tile, updates its trailing tile, and the workgroup that
+//      owns the next diagonal tile factors it at once (look-ahead).  Factoring a diagonal
+//      tile also forms its inverse, which becomes the diagonal tile of M = L^{-1}.
 //   3. M = L^{-1} by recursive doubling over the tile structure:
 //      [A 0; C B]^{-1} = [A^{-1} 0; -B^{-1} C A^{-1}  B^{-1}], log2(tiles) levels of
 //      products (the matrix is padded to a power-of-two number of tiles with identity).
+//      M^T is stored as well, so that both products of an iteration read rows.
 //   4. b = r + 4 vectors: X <- orth(M^T M X), a fixed number of steps, with classical
 //      Gram-Schmidt applied twice (rows held in registers of one workgroup).
 //   5. Rayleigh-Ritz: H = X^T N X, H = Q Theta Q^T by parallel-ordering Jacobi,
 //      V-hat = X Q[:, :r]; lambda_1..lambda_{r+1} = Theta; residual
 //      max_k ||N v_k - theta_k v_k|| / lam_max.
+// Every kernel takes an array of problem descriptors (problem = blockIdx.y), so a batch of
+// problems of different sizes runs in the same launches; workgroups past a problem's own
+// work return at once.
 #include <cmath>
 
 #include "device_util.hpp"
@@ -28,601 +34,840 @@ namespace rsm {
 
 namespace {
 
-constexpr int NB = kCholNB;
+constexpr int NB = kCholNB;     // 64
+constexpr int kLd = NB + 4;     // LDS row stride of product operands (16-byte aligned rows)
+constexpr int kTr = NB + 1;     // LDS row stride of transposition buffers (odd: no conflicts)
+constexpr int kRows = 16;       // output rows per workgroup of the thin products
 constexpr double kShiftRel = 1e-8;
+constexpr int kDescPerLaunch = 16;
 
-__device__ __forceinline__ void atomic_max_pos_f64(double* addr, double v) {
-  // non-negative doubles order like their bit patterns
-  atomicMax(reinterpret_cast<unsigned long long*>(addr),
-            static_cast<unsigned long long>(__double_as_longlong(v)));
+typedef RSM_GLOBAL double* gdouble;
+typedef RSM_GLOBAL const double* gcdouble;
+
+// Generic-pointer view of a global address, for the atomics.
+template <typename T>
+__device__ __forceinline__ T* generic(RSM_GLOBAL T* p) {
+  return (T*)p;
 }
 
-__device__ __forceinline__ double shift_of(const DevScalars* scal) {
-  const double lam = scal->lam_max;
-  // N == 0 (no accepted trial): factor I instead; V-hat is then an arbitrary basis
-  return lam > 0.0 ? kShiftRel * lam : 1.0;
+// Global load / store at a 32-bit element offset from a uniform base: the compiler can then
+// use the scalar-base + 32-bit vector-offset addressing form (every matrix here has fewer
+// than 2^28 elements).
+__device__ __forceinline__ double gld(gcdouble base, uint32_t idx) {
+  return *reinterpret_cast<gcdouble>(reinterpret_cast<RSM_GLOBAL const char*>(base) + (idx << 3));
+}
+__device__ __forceinline__ void gst(gdouble base, uint32_t idx, double v) {
+  *reinterpret_cast<gdouble>(reinterpret_cast<RSM_GLOBAL char*>(base) + (idx << 3)) = v;
 }
 
-// ------------------------------------------------------------------ 1. preparation
-
-// Nsym (full), Lf = lower(N) (the shift is added when a diagonal tile is factored),
-// uncovered columns.
-__global__ void k_eig_prep(const double* __restrict__ N, int64_t n, double* __restrict__ Ns,
-                           double* __restrict__ Lf, double* __restrict__ rowsum, rsm_info* info) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx < n) rowsum[idx] = 0.0;
-  if (idx >= n * n) return;
-  const int64_t j = idx / n, i = idx - j * n;
-  const double v = (i >= j) ? N[i + j * n] : N[j + i * n];
-  Ns[idx] = v;
-  Lf[idx] = (i >= j) ? v : 0.0;
-  if (i == j && v == 0.0) atomicAdd(&info->uncovered, 1);
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(u), l);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(u >> 32), l);
+  return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
 }
 
-// Row sums of |N| over a column chunk (rows in 64-row blocks, columns split in chunks):
+// Orders the LDS accesses of one wavefront around this point (a wavefront's LDS operations
+// complete in issue order, so no wait is needed, only no compiler reordering).
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Sum over the wavefront of NV values per lane with about NV exchanges instead of 6 NV: each
+// halving step sends one half of the values to the partner lane and keeps the other half.
+// Afterwards v[0] of lane l is the full sum of value idx(l); lanes whose low 6 - log2(NV)
+// bits are zero hold distinct indices.
+template <int NV, int OFF>
+__device__ __forceinline__ void sum_many(double* v, int lane, int& idx) {
+  if constexpr (NV > 1) {
+    constexpr int H = NV / 2;
+    const bool up = (lane & OFF) != 0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const double send = up ? v[j] : v[j + H];
+      const double keep = up ? v[j + H] : v[j];
+      v[j] = keep + __shfl_xor(send, OFF, 64);
+    }
+    idx += up ? H : 0;
+    sum_many<H, OFF / 2>(v, lane, idx);
+  } else {
+#pragma unroll
+    for (int off = OFF; off > 0; off >>= 1) v[0] += __shfl_xor(v[0], off, 64);
+  }
+}
+
+template <int K>
+constexpr int pow2_at_least() {
+  int p = 1;
+  while (p < K) p *= 2;
+  return p;
+}
+
+// ------------------------------------------------------------------ 64 x 64 tiles
+
+// Coordinates of element u (0..15) of thread threadIdx.x when 256 threads stage a 64 x 64
+// tile.  TR: lanes run down a column (64 rows) and the tile lands transposed in LDS
+// (S[c][a]); otherwise 16-lane groups run down a column (S[a][c]).  Both read whole
+// 128-byte lines.
+template <bool TR>
+__device__ __forceinline__ void tile_coord(int u, int& a, int& c) {
+  const int t = threadIdx.x;
+  if (TR) {
+    a = t & 63;
+    c = (t >> 6) + 4 * u;
+  } else {
+    a = (t & 15) + 16 * (u & 3);
+    c = ((t >> 4) & 15) + 16 * (u >> 2);
+  }
+}
+
+// Loads the tile src[a + c * ld], rows a < rv and columns c < cv (zero elsewhere); all 16
+// loads are issued before any is used.
+template <bool TR>
+__device__ __forceinline__ void tile_load(double (&v)[16], gcdouble __restrict__ src, int64_t ld,
+                                          int rv, int cv) {
+  const uint32_t ld32 = static_cast<uint32_t>(ld);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    int a, c;
+    tile_coord<TR>(u, a, c);
+    const bool ok = a < rv && c < cv;
+    const double x = gld(src, static_cast<uint32_t>(ok ? a : 0) + static_cast<uint32_t>(ok ? c : 0) * ld32);
+    v[u] = ok ? x : 0.0;
+  }
+}
+
+template <bool TR>
+__device__ __forceinline__ void tile_store(double (*S)[kLd], const double (&v)[16]) {
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    int a, c;
+    tile_coord<TR>(u, a, c);
+    if (TR)
+      S[c][a] = v[u];
+    else
+      S[a][c] = v[u];
+  }
+}
+
+// acc[u][v] += sum_p X[p][4 ty + u] Y[p][4 tx + v]  (tx = t % 16, ty = t / 16): the 64 x 64
+// product X^T Y of two LDS tiles, 4 x 4 outputs per thread.
+__device__ __forceinline__ void mm64(double (&acc)[4][4], const double (*X)[kLd],
+                                     const double (*Y)[kLd]) {
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll 4
+  for (int p = 0; p < NB; ++p) {
+    const double2 x01 = *reinterpret_cast<const double2*>(&X[p][4 * ty]);
+    const double2 x23 = *reinterpret_cast<const double2*>(&X[p][4 * ty + 2]);
+    const double2 y01 = *reinterpret_cast<const double2*>(&Y[p][4 * tx]);
+    const double2 y23 = *reinterpret_cast<const double2*>(&Y[p][4 * tx + 2]);
+    const double xa[4] = {x01.x, x01.y, x23.x, x23.y};
+    const double ya[4] = {y01.x, y01.y, y23.x, y23.y};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(xa[u], ya[v], acc[u][v]);
+  }
+}
+
+// Writes the thread's 4 x 4 outputs as the transposed operand layout S[col][row].
+__device__ __forceinline__ void acc_store_tr(double (*S)[kLd], const double (&acc)[4][4]) {
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[4 * tx + v][4 * ty + u] = acc[u][v];
+}
+
+// ------------------------------------------------------------------ diagonal tile
+
+// The 64 x 64 diagonal tile is factored and inverted by the 256 threads of a workgroup in
+// 16 x 16 blocks: right-looking block Cholesky (the 16 x 16 diagonal blocks by one
+// wavefront, the panel and trailing update by all threads), then L^{-1} block row by block
+// row: X_ii = L_ii^{-1}, X_ik = -X_ii sum_{p=k}^{i-1} L_ip X_pk.
+constexpr int kFB = 16;        // block of the in-tile factorisation
+constexpr int kFBs = kFB + 1;  // its LDS row stride
+constexpr int kNFB = NB / kFB;
+
+struct FactorWork {
+  double Lt[kFB][kFB];            // column p of the current diagonal block's factor at Lt[p][.]
+  double invd[kFB];               // 1 / l_jj of the current block
+  double D[kNFB][kFB][kFBs];      // inverses of the diagonal blocks' factors
+  double S[kNFB - 1][kFB][kFBs];  // partial sums of the inverse
+};
+
+// Step J of the left-looking (Crout) factorisation of a 16 x 16 block by one wavefront, lane
+// = row i (< 16):  l_iJ = (a_iJ - sum_{p<J} l_ip l_Jp) / l_JJ,  l_JJ = sqrt(a_JJ - sum_{p<J}
+// l_Jp^2).  a[] holds the lane's row (finished entries l_ip for p < J); row J of L is read
+// from LDS as a broadcast; the pivot comes from lane J by readlane.  The recursion keeps
+// every register index static.
+template <int J>
+__device__ __forceinline__ void crout_steps(double (&a)[kFB], FactorWork& W, int lane, double mu,
+                                            int& npiv) {
+  if constexpr (J < kFB) {
+    double s2[2] = {a[J], 0.0};
+#pragma unroll
+    for (int p = 0; p < J; ++p) s2[p & 1] -= a[p] * W.Lt[p][J];
+    const double sum = s2[0] + s2[1];
+    double d = readlane_f64(sum, J);
+    if (!(d > 0.0) || !isfinite(d)) {  // uniform: every lane holds the same d
+      d = mu;
+      ++npiv;
+    }
+    const double inv = 1.0 / sqrt(d);
+    a[J] = lane < J ? 0.0 : (lane == J ? d * inv : sum * inv);
+    if (lane < kFB) W.Lt[J][lane] = a[J];
+    if (lane == 0) W.invd[J] = inv;
+    wave_lds_fence();
+    crout_steps<J + 1>(a, W, lane, mu, npiv);
+  }
+}
+
+// Wavefront 0: factor diagonal block KB of As and store the inverse of its factor in W.D[KB]
+// (lane = column c: x_i = (delta_ic - sum_{p<i} l_ip x_p) / l_ii).
+template <int KB>
+__device__ __forceinline__ void fb_diag(double (*As)[kTr], FactorWork& W, double mu, int& npiv) {
+  constexpr int k0 = KB * kFB;
+  const int lane = threadIdx.x;
+  const int row = lane < kFB ? lane : 0;
+  double a[kFB];
+#pragma unroll
+  for (int c = 0; c < kFB; ++c) a[c] = c <= row ? As[k0 + row][k0 + c] : 0.0;
+  crout_steps<0>(a, W, lane, mu, npiv);
+  double x[kFB];
+#pragma unroll
+  for (int i = 0; i < kFB; ++i) {
+    double s2[2] = {i == lane ? 1.0 : 0.0, 0.0};
+#pragma unroll
+    for (int p = 0; p < i; ++p) s2[p & 1] -= W.Lt[p][i] * x[p];
+    x[i] = (s2[0] + s2[1]) * W.invd[i];
+  }
+  if (lane < kFB)
+#pragma unroll
+    for (int i = 0; i < kFB; ++i) W.D[KB][i][lane] = x[i];
+}
+
+// All threads: panel L_rk = A_rk D_k^T for the rows below block KB, then the trailing update
+// A_rc -= L_rk L_ck^T (lower part).  Thread (tr, tc) = (t / 16, t % 16) owns rows tr + 16u
+// and columns tc + 16v of the trailing part.
+template <int KB>
+__device__ __forceinline__ void fb_panel_update(double (*As)[kTr], FactorWork& W) {
+  constexpr int k0 = KB * kFB;
+  constexpr int B = (NB - k0 - kFB) / kFB;
+  if constexpr (B > 0) {
+    const int t = threadIdx.x, tc = t & 15, tr = t >> 4;
+    constexpr int r0 = k0 + kFB;
+    double l[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      double s = 0.0;
+#pragma unroll
+      for (int p = 0; p < kFB; ++p) s = fma(As[r0 + tr + 16 * u][k0 + p], W.D[KB][tc][p], s);
+      l[u] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < B; ++u) As[r0 + tr + 16 * u][k0 + tc] = l[u];
+    __syncthreads();
+    double acc[B][B];
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+      for (int v = 0; v < B; ++v) acc[u][v] = 0.0;
+#pragma unroll
+    for (int p = 0; p < kFB; ++p) {
+      double lr[B], lc[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        lr[u] = As[r0 + tr + 16 * u][k0 + p];
+        lc[u] = As[r0 + tc + 16 * u][k0 + p];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+#pragma unroll
+        for (int v = 0; v < B; ++v) acc[u][v] = fma(lr[u], lc[v], acc[u][v]);
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+      for (int v = 0; v < B; ++v)
+        if (tc + 16 * v <= tr + 16 * u) As[r0 + tr + 16 * u][r0 + tc + 16 * v] -= acc[u][v];
+    __syncthreads();
+  }
+}
+
+// X_Ik for k < I (block row I of L^{-1}), all threads; Xs already holds block rows < I.
+template <int I>
+__device__ __forceinline__ void fb_inverse_row(double (*As)[kTr], double (*Xs)[kTr],
+                                               FactorWork& W) {
+  const int t = threadIdx.x, tc = t & 15, tr = t >> 4;
+#pragma unroll
+  for (int k = 0; k < I; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = kFB * k; q < kFB * I; ++q) s = fma(As[kFB * I + tr][q], Xs[q][kFB * k + tc], s);
+    W.S[k][tr][tc] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < I; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kFB; ++q) s = fma(W.D[I][tr][q], W.S[k][q][tc], s);
+    Xs[kFB * I + tr][kFB * k + tc] = -s;
+  }
+  __syncthreads();
+}
+
+// 256 threads: factor the tile As (64 x kTr in LDS: N + mu I in the lower triangle, identity
+// rows and columns past the matrix) and write its inverse factor X = L^{-1} as tile (t0, t0)
+// of M and X^T as tile (t0, t0) of Mt (column-major, leading dimension ld).  Xs: 64 x kTr of
+// LDS.  Returns the clamped pivots (meaningful in thread 0).
+__device__ __forceinline__ int factor_tile(double (*As)[kTr], double (*Xs)[kTr], FactorWork& W,
+                                           double mu, gdouble __restrict__ M,
+                                           gdouble __restrict__ Mt, int ld, int t0) {
+  int npiv = 0;
+  const int t = threadIdx.x;
+#define RSM_FB_STEP(KB)                                  \
+  if (t < 64) fb_diag<KB>(As, W, mu, npiv);              \
+  __syncthreads();                                       \
+  fb_panel_update<KB>(As, W);
+  RSM_FB_STEP(0)
+  RSM_FB_STEP(1)
+  RSM_FB_STEP(2)
+  RSM_FB_STEP(3)
+#undef RSM_FB_STEP
+  // X: diagonal blocks D, zero above; block rows below the first follow
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int a = t & 63, c = (t >> 6) + 4 * u;
+    const int ba = a / kFB, bc = c / kFB;
+    Xs[a][c] = ba == bc ? W.D[ba][a % kFB][c % kFB] : 0.0;
+  }
+  __syncthreads();
+  fb_inverse_row<1>(As, Xs, W);
+  fb_inverse_row<2>(As, Xs, W);
+  fb_inverse_row<3>(As, Xs, W);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int a = t & 63, c = (t >> 6) + 4 * u;
+    M[(t0 + a) + (t0 + c) * ld] = Xs[a][c];
+    Mt[(t0 + a) + (t0 + c) * ld] = Xs[c][a];
+  }
+  return npiv;
+}
+
+// ------------------------------------------------------------------ descriptors, prep
+
+struct EigProbPack {
+  EigProb p[kDescPerLaunch];
+  int count;
+};
+
+__global__ void k_put_desc(EigProbPack pack, EigProb* dst) {
+  if (static_cast<int>(threadIdx.x) < pack.count) dst[threadIdx.x] = pack.p[threadIdx.x];
+}
+
+// Nsym (full), Lf = lower(N) (the shift is added when a diagonal tile is factored), uncovered
+// columns, the padding of M and Mt (identity), zeroed row sums and small arrays.
+__global__ __launch_bounds__(256) void k_eig_prep(const EigProb* __restrict__ probs) {
+  const EigProb& P = probs[blockIdx.y];
+  const int64_t n = P.n, npad = P.npad;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx < kSmallDoubles) P.small[idx] = 0.0;
+  if (idx >= npad * npad) return;
+  const int64_t c = idx / npad, rr = idx - c * npad;
+  if (rr < n && c < n) {
+    if (c == 0) P.Z[rr] = 0.0;
+    const double v = (rr >= c) ? P.N[rr + c * n] : P.N[c + rr * n];
+    P.Nsym[rr + c * n] = v;
+    P.Lf[rr + c * n] = (rr >= c) ? v : 0.0;
+    if (rr == c && v == 0.0) atomicAdd(generic(&P.info->uncovered), 1);
+  }
+  const int64_t nbn = static_cast<int64_t>(P.nb) * NB;
+  if (rr >= nbn || c >= nbn) {
+    const double v = (rr == c) ? 1.0 : 0.0;
+    P.M[idx] = v;
+    P.Mt[idx] = v;
+  }
+}
+
+// Row sums of |N| over a column chunk (rows in 64-row blocks, columns split in 16 chunks):
 // rowsum_i += sum_{j in chunk} |N_ij|.  max_i rowsum_i >= lambda_max(N) (Gershgorin).
-__global__ __launch_bounds__(256) void k_rowsum(const double* __restrict__ Ns, int64_t n,
-                                                int64_t cols_per_chunk,
-                                                double* __restrict__ rowsum) {
+__global__ __launch_bounds__(256) void k_rowsum(const EigProb* __restrict__ probs) {
   __shared__ double red[4][64];
+  const EigProb& P = probs[blockIdx.z];
+  const int64_t n = P.n;
+  if (static_cast<int64_t>(blockIdx.x) * 64 >= n) return;
+  const int64_t chunk = ceil_div(n, 16);
   const int rr = threadIdx.x % 64, g = threadIdx.x / 64;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + rr;
-  const int64_t j0 = static_cast<int64_t>(blockIdx.y) * cols_per_chunk;
-  const int64_t j1 = (j0 + cols_per_chunk < n) ? (j0 + cols_per_chunk) : n;
+  const int64_t j0 = static_cast<int64_t>(blockIdx.y) * chunk;
+  const int64_t j1 = (j0 + chunk < n) ? (j0 + chunk) : n;
+  const int64_t ic = i < n ? i : n - 1;
   double s = 0.0;
-  if (i < n)
-    for (int64_t j = j0 + g; j < j1; j += 4) s += fabs(Ns[i + j * n]);
+  for (int64_t jb = j0 + g; jb < j1; jb += 32) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t j = jb + 4 * u;
+      const double x = P.Nsym[ic + (j < j1 ? j : j0) * n];
+      v[u] = j < j1 ? fabs(x) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
   red[g][rr] = s;
   __syncthreads();
-  if (g == 0 && i < n) atomic_add_f64(&rowsum[i], red[0][rr] + red[1][rr] + red[2][rr] + red[3][rr]);
+  if (g == 0 && i < n) atomic_add_f64(generic(&P.Z[i]), red[0][rr] + red[1][rr] + red[2][rr] + red[3][rr]);
 }
 
 // ------------------------------------------------------------------ 2. Cholesky
 
-// Factor tile (k, k) of N + mu I and invert the factor, by one wavefront: lane i holds
-// row i of the tile in registers (static indices after full unrolling).  Step j of the
-// factorisation broadcasts column j through LDS; step j of the inverse (L X = I, rows of
-// X finished in order) broadcasts row j of X.  Writes L_kk into Lf and Dinv_kk = L_kk^{-1}.
-// A ragged last tile is completed with the identity.
-// Step J of the left-looking (Crout) factorisation, lane = row: column J of L is
-//   l_iJ = (a_iJ - sum_{p<J} l_ip l_Jp) / l_JJ,   l_JJ = sqrt(a_JJ - sum_{p<J} l_Jp^2),
-// with row J of L read from LDS (broadcast) and the lane's own finished entries l[0..J)
-// in registers.  The pivot lane stores 1 / l_JJ (from rsqrt) for the other lanes and for
-// the inverse.  Four partial sums shorten the dependent chain.  The template recursion
-// keeps every index static.
-template <int J>
-__device__ __forceinline__ void crout_steps(double (&l)[NB], const double (*As)[NB + 1],
-                                            double (*Ls)[NB + 1], double* invd, int lane,
-                                            double mu, int& npiv) {
-  if constexpr (J < NB) {
-    double s4[4] = {As[lane][J], 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int p0 = 0; p0 < J; p0 += 8) {
-#pragma unroll
-      for (int p = p0; p < p0 + 8 && p < J; ++p) s4[p & 3] -= l[p] * Ls[J][p];
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    double sum = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-    if (lane == J) {
-      if (!(sum > 0.0) || !isfinite(sum)) {
-        sum = mu;
-        ++npiv;
-      }
-      const double inv = rsqrt(sum);
-      l[J] = sum * inv;
-      Ls[J][J] = l[J];
-      invd[J] = inv;
-    }
-    __syncthreads();
-    if (lane > J) {
-      l[J] = sum * invd[J];
-      Ls[lane][J] = l[J];
-    }
-    __syncthreads();
-    crout_steps<J + 1>(l, As, Ls, invd, lane, mu, npiv);
-  }
-}
-
-// Step J of X = L^{-1} (lane = row of X): row J of X is final; rows below subtract it.
-template <int J>
-__device__ __forceinline__ void trinv_steps(double (&x)[NB], double* bc, double (*Ls)[NB + 1],
-                                            const double* invd, int lane) {
-  if constexpr (J < NB) {
-    if (lane == J) {
-      const double inv = invd[J];
-#pragma unroll
-      for (int c = 0; c <= J; ++c) {
-        x[c] *= inv;
-        bc[c] = x[c];
-      }
-    }
-    __syncthreads();
-    if (lane > J) {
-      const double lij = Ls[lane][J];
-#pragma unroll
-      for (int c0 = 0; c0 <= J; c0 += 8) {
-#pragma unroll
-        for (int c = c0; c < c0 + 8 && c <= J; ++c) x[c] -= lij * bc[c];
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-    __syncthreads();
-    trinv_steps<J + 1>(x, bc, Ls, invd, lane);
-  }
-}
-
-__global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ Lf, int64_t n, int k,
-                                                  double* __restrict__ Dinv,
-                                                  const double* __restrict__ rowsum,
-                                                  DevScalars* scal, rsm_info* info) {
-  __shared__ double bc[NB];
-  __shared__ double invd[NB];
-  __shared__ double As[NB][NB + 1];
-  __shared__ double Ls[NB][NB + 1];
-  __shared__ double lam;
-  const int lane = threadIdx.x;
-  const int64_t k0 = static_cast<int64_t>(k) * NB;
-  const int kb = static_cast<int>((n - k0) < NB ? (n - k0) : NB);
-  if (k == 0) {  // Gershgorin bound from the row sums, once
-    double v = 0.0;
-    for (int64_t i = lane; i < n; i += NB) v = fmax(v, rowsum[i]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    if (lane == 0) {
-      scal->lam_max = v;
-      lam = v;
-    }
-  } else if (lane == 0) {
-    lam = scal->lam_max;
-  }
-  __syncthreads();
-  const double mu = lam > 0.0 ? kShiftRel * lam : 1.0;
-  if (k == 0 && lane == 0) {
-    scal->mu = mu;
-    info->mu = mu;
-  }
-  // stage the tile (coalesced: lane = row), shift on the diagonal, identity past n
-  for (int c = 0; c < NB; ++c) {
-    double v;
-    if (lane < kb && c < kb)
-      v = (c <= lane) ? Lf[(k0 + lane) + (k0 + c) * n] + (c == lane ? mu : 0.0) : 0.0;
-    else
-      v = (lane == c) ? 1.0 : 0.0;
-    As[lane][c] = v;
-    Ls[lane][c] = 0.0;
-  }
-  __syncthreads();
-  int npiv = 0;
-  {
-    double l[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) l[c] = 0.0;
-    crout_steps<0>(l, As, Ls, invd, lane, mu, npiv);
-  }
-  for (int c = 0; c < NB; ++c)  // L back to memory (lower part)
-    if (lane < kb && c < kb && c <= lane) Lf[(k0 + lane) + (k0 + c) * n] = Ls[lane][c];
-  {
-    double x[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) x[c] = (c == lane) ? 1.0 : 0.0;
-    trinv_steps<0>(x, bc, Ls, invd, lane);
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NB; ++c) Ls[lane][c] = (c <= lane) ? x[c] : 0.0;
-  }
-  __syncthreads();
-  double* out = Dinv + static_cast<int64_t>(k) * NB * NB;
-  for (int c = 0; c < NB; ++c) out[lane + c * NB] = Ls[lane][c];
-  if (npiv) atomicAdd(&scal->pivots, npiv);
-}
-
-// Panel: tile (k+1+bid, k) becomes L_ik = A_ik L_kk^{-T} = A_ik Dinv_kk^T.
-__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Lf, int64_t n, int k,
-                                                    const double* __restrict__ Dinv) {
-  __shared__ double Xs[NB][NB + 1];
-  __shared__ double Ds[NB][NB + 1];
-  const int tid = threadIdx.x;
-  const int64_t k0 = static_cast<int64_t>(k) * NB;
-  const int kb = static_cast<int>((n - k0) < NB ? (n - k0) : NB);
-  const int64_t i0 = k0 + static_cast<int64_t>(blockIdx.x + 1) * NB;
-  const int ib = static_cast<int>((n - i0) < NB ? (n - i0) : NB);
-  const double* dk = Dinv + static_cast<int64_t>(k) * NB * NB;
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int ii = e % NB, jj = e / NB;
-    Xs[ii][jj] = (ii < ib && jj < kb) ? Lf[(i0 + ii) + (k0 + jj) * n] : 0.0;
-    Ds[ii][jj] = dk[e];
-  }
-  __syncthreads();
-  const int tx = tid % 16, ty = tid / 16;
-  double acc[4][4] = {};
-  for (int p = 0; p < NB; ++p) {
-    double a[4], d[4];
+// Gershgorin bound, shift, and the factor + inverse of diagonal tile 0.
+__global__ __launch_bounds__(256) void k_chol_first(const EigProb* __restrict__ probs) {
+  __shared__ double As[NB][kTr];
+  __shared__ double Xs[NB][kTr];
+  __shared__ FactorWork W;
+  __shared__ double red[4];
+  const EigProb& P = probs[blockIdx.y];
+  const int t = threadIdx.x, lane = t & 63;
+  const int n = static_cast<int>(P.n);
+  double v = 0.0;
+  for (int i0 = 0; i0 < n; i0 += 4 * 256) {
+    double x[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      a[u] = Xs[ty * 4 + u][p];
-      d[u] = Ds[tx * 4 + u][p];  // (Dinv^T)[p][c] = Dinv[c][p]
+      const int i = i0 + u * 256 + t;
+      x[u] = P.Z[i < n ? i : 0];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * d[v];
+      if (i0 + u * 256 + t < n) v = fmax(v, x[u]);
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if (lane == 0) red[t >> 6] = v;
+  __syncthreads();
+  v = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  // N == 0 (no accepted trial): factor I instead; V-hat is then an arbitrary basis
+  const double mu = v > 0.0 ? kShiftRel * v : 1.0;
+  if (t == 0) {
+    P.scal->lam_max = v;
+    P.scal->mu = mu;
+    P.info->mu = mu;
+  }
+  const int kb = n < NB ? n : NB;
+  gcdouble Lf = P.Lf;
+  double x[16];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int rr = ty * 4 + u, cc = tx * 4 + v;
-      if (rr < ib && cc < kb) Lf[(i0 + rr) + (k0 + cc) * n] = acc[u][v];
-    }
+  for (int u = 0; u < 16; ++u) {
+    const int a = t & 63, c = (t >> 6) + 4 * u;
+    const bool ok = a < kb && c < kb;
+    x[u] = Lf[(ok ? a : 0) + (ok ? c : 0) * n];
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int a = t & 63, c = (t >> 6) + 4 * u;
+    As[a][c] = (a < kb && c < kb) ? (c < a ? x[u] : (c == a ? x[u] + mu : 0.0))
+                                  : (a == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int npiv = factor_tile(As, Xs, W, mu, P.M, P.Mt, static_cast<int>(P.npad), 0);
+  if (npiv && t == 0) atomicAdd(generic(&P.scal->pivots), npiv);
 }
 
-// Trailing update after panel k: tile (i, j), k < j <= i:  A_ij -= L_ik L_jk^T.
-__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ Lf, int64_t n, int k,
-                                                     int nb) {
-  __shared__ double Li[NB][NB + 1];
-  __shared__ double Lj[NB][NB + 1];
-  int b = blockIdx.x;
-  int ti = k + 1, tj = k + 1;
-  for (int i = k + 1; i < nb; ++i) {
-    const int cnt = i - k;
-    if (b < cnt) {
-      ti = i;
-      tj = k + 1 + b;
-      break;
-    }
-    b -= cnt;
-  }
+// Tile step k (k = 0 .. nb - 2).  Workgroup (i, j), k < j <= i < nb, of the trailing lower
+// triangle:
+//   L_ik = A_ik D_k^T, L_jk = A_jk D_k^T  (D_k = L_kk^{-1}, the diagonal tile k of M),
+//   A_ij -= L_ik L_jk^T.
+// The workgroup with j = k + 1 stores L_ik as tile (i, k) of M (the block C of the
+// recursion); the one with i = j = k + 1 then factors the updated tile (look-ahead).
+__global__ __launch_bounds__(256) void k_chol_step(const EigProb* __restrict__ probs, int k) {
+  __shared__ __align__(16) double S0[NB][kLd];
+  __shared__ __align__(16) double S1[NB][kLd];
+  __shared__ __align__(16) double S2[NB][kLd];
+  const EigProb& P = probs[blockIdx.y];
+  const int rem = P.nb - k - 1;
+  const int bid = static_cast<int>(blockIdx.x);
+  if (rem <= 0 || bid >= rem * (rem + 1) / 2) return;
+  int row = static_cast<int>((sqrtf(8.0f * static_cast<float>(bid) + 1.0f) - 1.0f) * 0.5f);
+  while (row * (row + 1) / 2 > bid) --row;
+  while ((row + 1) * (row + 2) / 2 <= bid) ++row;
+  const int col = bid - row * (row + 1) / 2;
+  const int ti = k + 1 + row, tj = k + 1 + col;
+  const bool diag = ti == tj;
+  const int64_t n = P.n, ld = P.npad;
   const int64_t k0 = static_cast<int64_t>(k) * NB;
   const int64_t i0 = static_cast<int64_t>(ti) * NB, j0 = static_cast<int64_t>(tj) * NB;
   const int ib = static_cast<int>((n - i0) < NB ? (n - i0) : NB);
   const int jb = static_cast<int>((n - j0) < NB ? (n - j0) : NB);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int rr = e % NB, pp = e / NB;
-    Li[rr][pp] = (rr < ib) ? Lf[(i0 + rr) + (k0 + pp) * n] : 0.0;
-    Lj[rr][pp] = (rr < jb) ? Lf[(j0 + rr) + (k0 + pp) * n] : 0.0;
-  }
-  __syncthreads();
-  const int tx = tid % 16, ty = tid / 16;
-  double acc[4][4] = {};
-  for (int p = 0; p < NB; ++p) {
-    double a[4], bb[4];
+  gdouble __restrict__ Lf = P.Lf;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+
+  double vi[16], vj[16], vd[16];
+  tile_load<true>(vi, Lf + i0 + k0 * n, n, ib, NB);
+  if (!diag) tile_load<true>(vj, Lf + j0 + k0 * n, n, jb, NB);
+  tile_load<true>(vd, P.M + k0 + k0 * ld, ld, NB, NB);
+  double cur[4][4];  // A_ij in the output layout
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = Li[ty * 4 + u][p];
-      bb[u] = Lj[tx * 4 + u][p];
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rr = 4 * ty + u, cc = 4 * tx + v;
+      const bool ok = rr < ib && cc < jb;
+      const double x = Lf[(i0 + (ok ? rr : 0)) + (j0 + (ok ? cc : 0)) * n];
+      cur[u][v] = ok ? x : 0.0;
     }
+  tile_store<true>(S0, vi);  // S0[p][row] = A_ik[row][p]
+  if (!diag) tile_store<true>(S2, vj);
+  tile_store<true>(S1, vd);  // S1[p][col] = D_k[col][p]
+  __syncthreads();
+  double li[4][4] = {}, lj[4][4] = {};
+  mm64(li, S0, S1);
+  if (!diag) mm64(lj, S2, S1);
+  __syncthreads();
+  acc_store_tr(S0, li);  // S0[p][row] = L_ik[row][p]
+  if (!diag) acc_store_tr(S2, lj);
+  if (tj == k + 1) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bb[v];
+      for (int v = 0; v < 4; ++v) P.M[(i0 + 4 * ty + u) + (k0 + 4 * tx + v) * ld] = li[u][v];
   }
+  __syncthreads();
+  double upd[4][4] = {};
+  mm64(upd, S0, diag ? S0 : S2);
+  if (bid != 0) {  // not the next diagonal tile: write the updated tile back
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = 4 * ty + u, cc = 4 * tx + v;
+        if (rr < ib && cc < jb && (!diag || cc <= rr))
+          Lf[(i0 + rr) + (j0 + cc) * n] = cur[u][v] - upd[u][v];
+      }
+    return;
+  }
+  // tile (k + 1, k + 1): factor it now
+  __syncthreads();
+  auto As = reinterpret_cast<double (*)[kTr]>(&S1[0][0]);
+  auto Xs = reinterpret_cast<double (*)[kTr]>(&S0[0][0]);
+  FactorWork& W = *reinterpret_cast<FactorWork*>(&S2[0][0]);
+  const double mu = P.scal->mu;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int rr = ty * 4 + u, cc = tx * 4 + v;
-      if (rr < ib && cc < jb && (ti != tj || cc <= rr)) Lf[(i0 + rr) + (j0 + cc) * n] -= acc[u][v];
+      const int rr = 4 * ty + u, cc = 4 * tx + v;
+      As[rr][cc] = (rr < ib && cc < ib) ? cur[u][v] - upd[u][v] + (rr == cc ? mu : 0.0)
+                                        : (rr == cc ? 1.0 : 0.0);
     }
-  }
+  __syncthreads();
+  const int npiv = factor_tile(As, Xs, W, mu, P.M, P.Mt, static_cast<int>(ld), static_cast<int>(i0));
+  if (npiv && threadIdx.x == 0) atomicAdd(generic(&P.scal->pivots), npiv);
 }
 
 // ------------------------------------------------------------------ 3. M = L^{-1}
 
-// M (npad x npad, ld npad): diagonal tiles = Dinv (identity past the last tile), and the
-// strictly lower tiles of L copied in (zero past n) as the blocks C of the recursion.
-__global__ void k_inv_init(const double* __restrict__ Lf, const double* __restrict__ Dinv,
-                           int64_t n, int nb, int64_t npad, double* __restrict__ M) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= npad * npad) return;
-  const int64_t c = idx / npad, rr = idx - c * npad;
-  const int64_t ti = rr / NB, tj = c / NB;
-  double v = 0.0;
-  if (ti == tj) {
-    if (ti < nb)
-      v = Dinv[ti * NB * NB + (rr - ti * NB) + (c - tj * NB) * NB];
-    else
-      v = (rr == c) ? 1.0 : 0.0;
-  } else if (ti > tj && rr < n && c < n) {
-    v = Lf[rr + c * n];
-  }
-  M[idx] = v;
+// Pair (block1, block2) of a level with inverted diagonal blocks of size bs; output tile
+// (ti, tj) of the bs x bs block below the diagonal.
+struct InvTile {
+  int64_t pair, ti, tj, tpb, r1, r2;
+};
+
+__device__ __forceinline__ bool inv_tile(const EigProb& P, int64_t bs, InvTile& t) {
+  if (bs >= P.npad) return false;
+  t.tpb = bs / NB;
+  const int64_t tiles = (P.npad / (2 * bs)) * t.tpb * t.tpb;
+  if (static_cast<int64_t>(blockIdx.x) >= tiles) return false;
+  t.pair = blockIdx.x / (t.tpb * t.tpb);
+  const int64_t rem = blockIdx.x - t.pair * t.tpb * t.tpb;
+  t.ti = rem / t.tpb;
+  t.tj = rem % t.tpb;
+  t.r1 = t.pair * 2 * bs;
+  t.r2 = t.r1 + bs;
+  return true;
 }
 
-// Level with inverted diagonal blocks of size bs: for every pair of consecutive blocks,
-// T = C A^{-1} where C = M[block2, block1] (still the L entries) and A^{-1} = M[block1,
-// block1] (lower triangular).  One 64 x 64 output tile per workgroup.
-__global__ __launch_bounds__(256) void k_inv_stage1(const double* __restrict__ M, int64_t npad,
-                                                    int64_t bs, double* __restrict__ T) {
-  __shared__ double As[NB][NB + 1];
-  __shared__ double Bs[NB][NB + 1];
-  const int64_t tpb = bs / NB;                       // tiles per block side
-  const int64_t pair = blockIdx.x / (tpb * tpb);
-  const int64_t rem = blockIdx.x - pair * tpb * tpb;
-  const int64_t ti = rem / tpb, tj = rem % tpb;      // output tile inside the pair
-  const int64_t r1 = pair * 2 * bs;                  // block 1 origin
-  const int64_t r2 = r1 + bs;                        // block 2 origin
-  const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
+// T = C A^{-1}: C = M[block2, block1] (still the L tiles), A^{-1} = M[block1, block1] (lower
+// triangular), T[ti, tj] = sum_{q >= tj} C[ti, q] A^{-1}[q, tj].  T is column-major with
+// leading dimension npad / 2.
+__global__ __launch_bounds__(256) void k_inv_stage1(const EigProb* __restrict__ probs, int64_t bs) {
+  __shared__ __align__(16) double S0[NB][kLd];
+  __shared__ __align__(16) double S1[NB][kLd];
+  const EigProb& P = probs[blockIdx.y];
+  InvTile t;
+  if (!inv_tile(P, bs, t)) return;
+  const int64_t npad = P.npad;
+  gcdouble __restrict__ M = P.M;
   double acc[4][4] = {};
-  // T[ti, tj] = sum_q C[ti, q] Ainv[q, tj], q >= tj (Ainv lower)
-  for (int64_t q = tj; q < tpb; ++q) {
-    for (int e = tid; e < NB * NB; e += blockDim.x) {
-      const int a = e % NB, c = e / NB;
-      As[a][c] = M[(r2 + ti * NB + a) + (r1 + q * NB + c) * npad];  // C tile
-      Bs[a][c] = M[(r1 + q * NB + a) + (r1 + tj * NB + c) * npad];  // Ainv tile
-    }
+  double vc[16], va[16];
+  tile_load<true>(vc, M + (t.r2 + t.ti * NB) + (t.r1 + t.tj * NB) * npad, npad, NB, NB);
+  tile_load<false>(va, M + (t.r1 + t.tj * NB) + (t.r1 + t.tj * NB) * npad, npad, NB, NB);
+  for (int64_t q = t.tj; q < t.tpb; ++q) {
     __syncthreads();
-    for (int p = 0; p < NB; ++p) {
-      double x[4], y[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        x[u] = As[ty * 4 + u][p];
-        y[u] = Bs[p][tx * 4 + u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += x[u] * y[v];
-    }
+    tile_store<true>(S0, vc);   // S0[p][row] = C[row][p]
+    tile_store<false>(S1, va);  // S1[p][col] = Ainv[p][col]
     __syncthreads();
+    if (q + 1 < t.tpb) {
+      tile_load<true>(vc, M + (t.r2 + t.ti * NB) + (t.r1 + (q + 1) * NB) * npad, npad, NB, NB);
+      tile_load<false>(va, M + (t.r1 + (q + 1) * NB) + (t.r1 + t.tj * NB) * npad, npad, NB, NB);
+    }
+    mm64(acc, S0, S1);
   }
   const int64_t ldt = npad / 2;
-  const int64_t base = (pair * bs + ti * NB) + (tj * NB) * ldt;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t base = (t.pair * bs + t.ti * NB) + (t.tj * NB) * ldt;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      T[base + (ty * 4 + u) + static_cast<int64_t>(tx * 4 + v) * ldt] = acc[u][v];
+      P.T[base + (4 * ty + u) + static_cast<int64_t>(4 * tx + v) * ldt] = acc[u][v];
 }
 
-// M[block2, block1] = -B^{-1} T with B^{-1} = M[block2, block2] (lower triangular).
-__global__ __launch_bounds__(256) void k_inv_stage2(double* __restrict__ M, int64_t npad,
-                                                    int64_t bs, const double* __restrict__ T) {
-  __shared__ double As[NB][NB + 1];
-  __shared__ double Bs[NB][NB + 1];
-  const int64_t tpb = bs / NB;
-  const int64_t pair = blockIdx.x / (tpb * tpb);
-  const int64_t rem = blockIdx.x - pair * tpb * tpb;
-  const int64_t ti = rem / tpb, tj = rem % tpb;
-  const int64_t r1 = pair * 2 * bs;
-  const int64_t r2 = r1 + bs;
-  const int64_t ldt = npad / 2;
-  const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
+// M[block2, block1] = -B^{-1} T, B^{-1} = M[block2, block2] (lower triangular); the same
+// tile goes transposed into Mt.
+__global__ __launch_bounds__(256) void k_inv_stage2(const EigProb* __restrict__ probs, int64_t bs) {
+  __shared__ __align__(16) double S0[NB][kLd];
+  __shared__ __align__(16) double S1[NB][kLd];
+  const EigProb& P = probs[blockIdx.y];
+  InvTile t;
+  if (!inv_tile(P, bs, t)) return;
+  const int64_t npad = P.npad, ldt = npad / 2;
+  gdouble __restrict__ M = P.M;
+  gcdouble __restrict__ T = P.T;
   double acc[4][4] = {};
-  for (int64_t q = 0; q <= ti; ++q) {
-    for (int e = tid; e < NB * NB; e += blockDim.x) {
-      const int a = e % NB, c = e / NB;
-      As[a][c] = M[(r2 + ti * NB + a) + (r2 + q * NB + c) * npad];      // Binv tile
-      Bs[a][c] = T[(pair * bs + q * NB + a) + (tj * NB + c) * ldt];     // T tile
-    }
+  double vb[16], vt[16];
+  tile_load<true>(vb, M + (t.r2 + t.ti * NB) + (t.r2) * npad, npad, NB, NB);
+  tile_load<false>(vt, T + (t.pair * bs) + (t.tj * NB) * ldt, ldt, NB, NB);
+  for (int64_t q = 0; q <= t.ti; ++q) {
     __syncthreads();
-    for (int p = 0; p < NB; ++p) {
-      double x[4], y[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        x[u] = As[ty * 4 + u][p];
-        y[u] = Bs[p][tx * 4 + u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += x[u] * y[v];
-    }
+    tile_store<true>(S0, vb);   // S0[p][row] = Binv[row][p]
+    tile_store<false>(S1, vt);  // S1[p][col] = T[p][col]
     __syncthreads();
+    if (q + 1 <= t.ti) {
+      tile_load<true>(vb, M + (t.r2 + t.ti * NB) + (t.r2 + (q + 1) * NB) * npad, npad, NB, NB);
+      tile_load<false>(vt, T + (t.pair * bs + (q + 1) * NB) + (t.tj * NB) * ldt, ldt, NB, NB);
+    }
+    mm64(acc, S0, S1);
   }
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t rb = t.r2 + t.ti * NB, cb = t.r1 + t.tj * NB;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      M[(r2 + ti * NB + ty * 4 + u) + (r1 + tj * NB + tx * 4 + v) * npad] = -acc[u][v];
+    for (int v = 0; v < 4; ++v) {
+      const int64_t rr = rb + 4 * ty + u, cc = cb + 4 * tx + v;
+      M[rr + cc * npad] = -acc[u][v];
+      P.Mt[cc + rr * npad] = -acc[u][v];
+    }
 }
 
 // ------------------------------------------------------------------ 4. subspace iteration
 
 // Deterministic start block: entries uniform in [-1, 1) from Philox (key = seed, 1).
-__global__ void k_start_vectors(double* __restrict__ X, int64_t n, int b, uint64_t seed) {
+__global__ void k_start_vectors(const EigProb* __restrict__ probs) {
+  const EigProb& P = probs[blockIdx.y];
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= n * b) return;
+  if (idx >= P.n * P.b) return;
   uint64_t c[4] = {static_cast<uint64_t>(idx), 0x5eedull, 0ull, 0ull};
-  Philox4x64::block(c, seed, 1ull);
-  X[idx] = static_cast<double>(static_cast<int64_t>(c[0]) >> 11) * (1.0 / 4503599627370496.0);
+  Philox4x64::block(c, P.seed, 1ull);
+  P.X[idx] = static_cast<double>(static_cast<int64_t>(c[0]) >> 11) * (1.0 / 4503599627370496.0);
 }
 
-__global__ void k_zero(double* __restrict__ x, int64_t count) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < count) x[i] = 0.0;
-}
-
-// Z += op(M)[row tile, col tile] X[col tile]  (one tile pair per workgroup; FP64 atomics).
-// trans = 0: Z = M X with M lower;  trans = 1: Z = M^T X.
-__global__ __launch_bounds__(256) void k_trmm(const double* __restrict__ M, int64_t npad,
-                                              int64_t n, int b, const double* __restrict__ X,
-                                              double* __restrict__ Z, int trans) {
-  __shared__ double Ms[NB][NB + 1];
-  __shared__ double Xs[NB][kEigMaxB + 1];
-  const int nt = static_cast<int>(ceil_div(n, NB));
-  // enumerate the tiles (i, k), k <= i, of the lower triangle of M
-  int bidx = blockIdx.x;
-  int ti = 0, tk = 0;
-  for (int i = 0; i < nt; ++i) {
-    if (bidx <= i) {
-      ti = i;
-      tk = bidx;
-      break;
-    }
-    bidx -= i + 1;
-  }
-  if (trans) {  // M tile (ti, tk) feeds output rows tk of M^T X
-    const int t = ti;
-    ti = tk;
-    tk = t;
-  }
+// Out[j, c] = sum_i A[j, i] In[i, c] for 16 rows j per workgroup, all c < b.  MODE 0: A = M
+// (lower: i < j0 + 16), In = X, Out = Z.  MODE 1: A = Mt (upper: i >= j0), In = Z, Out = NX.
+// MODE 2: A = Nsym (all i), In = X, Out = NX, and H += X[rows]^T NX[rows] (Rayleigh-Ritz).
+// Thread (jr, kp) = (t % 16, t / 16) sums over i = kp mod 16; In is staged through LDS in
+// chunks of 256 rows, the next chunk's loads in flight while the current one is summed; the
+// 16 partial sums are added through LDS.  No atomics on Out.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_apply(const EigProb* __restrict__ probs) {
+  __shared__ double Xs[256][kEigMaxB + 1];
+  __shared__ double Ys[kRows][kEigMaxB + 1];
+  const EigProb& P = probs[blockIdx.y];
+  const int n = static_cast<int>(P.n);
+  const int b = P.b;
+  const int j0 = static_cast<int>(blockIdx.x) * kRows;
+  if (j0 >= n) return;
+  gcdouble __restrict__ A = MODE == 0 ? P.M : (MODE == 1 ? P.Mt : P.Nsym);
+  const uint32_t lda = static_cast<uint32_t>(MODE == 2 ? P.n : P.npad);
+  gcdouble __restrict__ In = MODE == 1 ? P.Z : P.X;
+  gdouble __restrict__ Out = MODE == 0 ? P.Z : P.NX;
   const int tid = threadIdx.x;
-  const int64_t r0 = static_cast<int64_t>(ti) * NB, k0 = static_cast<int64_t>(tk) * NB;
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int a = e % NB, c = e / NB;
-    // element (r0 + a, k0 + c) of op(M); loads run along the first index of M
-    double v;
-    if (!trans) {
-      v = (r0 + a < n && k0 + c < n) ? M[(r0 + a) + (k0 + c) * npad] : 0.0;
-      Ms[a][c] = v;
-    } else {
-      v = (k0 + a < n && r0 + c < n) ? M[(k0 + a) + (r0 + c) * npad] : 0.0;
-      Ms[c][a] = v;
+  const int jr = tid & (kRows - 1), kp = tid / kRows;
+  const uint32_t jrow = static_cast<uint32_t>((j0 + jr < n) ? (j0 + jr) : (n - 1));
+  const int i_lo = MODE == 1 ? j0 : 0;
+  const int i_hi = MODE == 0 ? ((j0 + kRows < n) ? (j0 + kRows) : n) : n;
+  double acc[kEigMaxB];
+#pragma unroll
+  for (int c = 0; c < kEigMaxB; ++c) acc[c] = 0.0;
+  double mv[16], xv[kEigMaxB];
+  auto load_chunk = [&](int c0, double (&m)[16], double (&x)[kEigMaxB]) {
+    const int cnt = (i_hi - c0) < 256 ? (i_hi - c0) : 256;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int il = kp + 16 * s;
+      m[s] = gld(A, jrow + static_cast<uint32_t>(c0 + (il < cnt ? il : 0)) * lda);
+      if (il >= cnt) m[s] = 0.0;
     }
-  }
-  for (int e = tid; e < NB * b; e += blockDim.x) {
-    const int a = e % NB, c = e / NB;
-    Xs[a][c] = (k0 + a < n) ? X[(k0 + a) + static_cast<int64_t>(c) * n] : 0.0;
+#pragma unroll
+    for (int c = 0; c < kEigMaxB; ++c) {
+      const bool ok = tid < cnt && c < b;
+      x[c] = gld(In, static_cast<uint32_t>(c0 + (ok ? tid : 0)) +
+                         static_cast<uint32_t>(ok ? c : 0) * static_cast<uint32_t>(n));
+      if (!ok) x[c] = 0.0;
+    }
+  };
+  int c0 = i_lo;
+  load_chunk(c0, mv, xv);
+  for (;;) {
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kEigMaxB; ++c) Xs[tid][c] = xv[c];
+    __syncthreads();
+    const int c1 = c0 + 256;
+    const bool more = c1 < i_hi;
+    double mn[16], xn[kEigMaxB];
+    if (more) load_chunk(c1, mn, xn);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int il = kp + 16 * s;
+#pragma unroll
+      for (int c = 0; c < kEigMaxB; ++c)
+        if (c < b) acc[c] = fma(mv[s], Xs[il][c], acc[c]);
+    }
+    if (!more) break;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) mv[s] = mn[s];
+#pragma unroll
+    for (int c = 0; c < kEigMaxB; ++c) xv[c] = xn[c];
+    c0 = c1;
   }
   __syncthreads();
-  const int rr = tid % NB;
-  const int cg = tid / NB;  // 4 column groups
-  if (r0 + rr < n) {
-    for (int c = cg; c < b; c += 4) {
+  auto red = reinterpret_cast<double (*)[kRows][kEigMaxB + 1]>(&Xs[0][0]);  // [kp][jr][c]
+#pragma unroll
+  for (int c = 0; c < kEigMaxB; ++c) red[kp][jr][c] = acc[c];
+  __syncthreads();
+  for (int e = tid; e < kRows * b; e += 256) {
+    const int r2 = e % kRows, c = e / kRows;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += red[q][r2][c];
+    if (j0 + r2 < n) gst(Out, static_cast<uint32_t>(j0 + r2 + c * n), s);
+    if (MODE == 2) Ys[r2][c] = (j0 + r2 < n) ? s : 0.0;
+  }
+  if (MODE == 2) {
+    // H += X[j0 .. j0 + 16)^T NX[j0 .. j0 + 16)
+    __syncthreads();
+    auto xr = reinterpret_cast<double (*)[kEigMaxB + 1]>(&Xs[0][0]);
+    for (int e = tid; e < kRows * b; e += 256) {
+      const int r2 = e % kRows, c = e / kRows;
+      xr[r2][c] = (j0 + r2 < n) ? gld(P.X, static_cast<uint32_t>(j0 + r2 + c * n)) : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < b * b; e += 256) {
+      const int i = e / b, j = e % b;
       double s = 0.0;
-#pragma unroll 8
-      for (int p = 0; p < NB; ++p) s += Ms[rr][p] * Xs[p][c];
-      atomic_add_f64(&Z[(r0 + rr) + static_cast<int64_t>(c) * n], s);
+#pragma unroll
+      for (int q = 0; q < kRows; ++q) s += xr[q][i] * Ys[q][j];
+      atomic_add_f64(generic(&P.small[kSmallH + e]), s);
     }
   }
 }
 
-// X = orth(Z): classical Gram-Schmidt applied twice per column, one workgroup of 1024
-// threads, thread t owning rows t, t + 1024, ... (RPT rows) in registers.
-template <int RPT>
-__global__ __launch_bounds__(1024) void k_orth(const double* __restrict__ Z, int64_t n, int b,
-                                               double* __restrict__ X) {
-  __shared__ double red[16][kEigMaxB];
-  __shared__ double h[kEigMaxB];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wid = tid >> 6;
-  double x[RPT][kEigMaxB];
+// One orthonormalisation column K: X[:, K] -= X[:, :K] h twice (classical Gram-Schmidt
+// applied twice), then normalised.  x[s][c] holds rows tid + s NT.
+template <int NT, int RPT, int K>
+__device__ __forceinline__ void orth_cols(double (&x)[RPT][kEigMaxB], int b, double (*red)[32],
+                                          double* h) {
+  if constexpr (K < kEigMaxB) {
+    if (K < b) {
+      constexpr int NW = NT / 64;
+      const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+      if constexpr (K > 0) {
+        constexpr int NV = pow2_at_least<K>();
 #pragma unroll
-  for (int s = 0; s < RPT; ++s) {
-    const int64_t i = tid + static_cast<int64_t>(s) * 1024;
+        for (int pass = 0; pass < 2; ++pass) {
+          double d[NV];
 #pragma unroll
-    for (int c = 0; c < kEigMaxB; ++c) x[s][c] = (i < n && c < b) ? Z[i + c * n] : 0.0;
-  }
+          for (int j = 0; j < NV; ++j) {
+            double p = 0.0;
+            if (j < K)
 #pragma unroll
-  for (int k = 0; k < kEigMaxB; ++k) {
-    if (k < b) {
-      for (int pass = 0; pass < 2; ++pass) {
+              for (int s = 0; s < RPT; ++s) p = fma(x[s][j], x[s][K], p);
+            d[j] = p;
+          }
+          int idx = 0;
+          sum_many<NV, 32>(d, lane, idx);
+          if ((lane & (64 / NV - 1)) == 0) red[wid][idx] = d[0];
+          __syncthreads();
+          if (tid < K) {
+            double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < k; ++j) {
-          double p = 0.0;
+            for (int w = 0; w < NW; ++w) s += red[w][tid];
+            h[tid] = s;
+          }
+          __syncthreads();
 #pragma unroll
-          for (int s = 0; s < RPT; ++s) p += x[s][j] * x[s][k];
-          p = wave_sum(p);
-          if (lane == 0) red[wid][j] = p;
+          for (int j = 0; j < K; ++j) {
+            const double hj = h[j];
+#pragma unroll
+            for (int s = 0; s < RPT; ++s) x[s][K] = fma(-hj, x[s][j], x[s][K]);
+          }
         }
-        __syncthreads();
-        if (tid < k) {
-          double s = 0.0;
-          for (int w = 0; w < 16; ++w) s += red[w][tid];
-          h[tid] = s;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < k; ++j) {
-          const double hj = h[j];
-#pragma unroll
-          for (int s = 0; s < RPT; ++s) x[s][k] -= hj * x[s][j];
-        }
-        __syncthreads();
       }
       double p = 0.0;
 #pragma unroll
-      for (int s = 0; s < RPT; ++s) p += x[s][k] * x[s][k];
+      for (int s = 0; s < RPT; ++s) p = fma(x[s][K], x[s][K], p);
       p = wave_sum(p);
+      __syncthreads();  // h of the last pass has been read
       if (lane == 0) red[wid][0] = p;
       __syncthreads();
-      if (tid == 0) {
-        double s = 0.0;
-        for (int w = 0; w < 16; ++w) s += red[w][0];
-        h[0] = s;
-      }
-      __syncthreads();
-      const double nrm = sqrt(h[0]);
-      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      double nrm2 = 0.0;
 #pragma unroll
-      for (int s = 0; s < RPT; ++s) x[s][k] *= inv;
-      __syncthreads();
+      for (int w = 0; w < NW; ++w) nrm2 += red[w][0];
+      const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) x[s][K] *= inv;
+      __syncthreads();  // red is reused by the next column
+      orth_cols<NT, RPT, K + 1>(x, b, red, h);
     }
   }
+}
+
+// X = orth(NX), one workgroup per problem, NT threads x 4 rows in registers (n <= 4 NT).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_orth(const EigProb* __restrict__ probs) {
+  constexpr int RPT = 4;
+  __shared__ double red[NT / 64][32];
+  __shared__ double h[32];
+  const EigProb& P = probs[blockIdx.y];
+  const int64_t n = P.n;
+  const int b = P.b;
+  if (n > static_cast<int64_t>(NT) * RPT) return;  // the launcher picks NT from n
+  const int tid = threadIdx.x;
+  double x[RPT][kEigMaxB];
 #pragma unroll
   for (int s = 0; s < RPT; ++s) {
-    const int64_t i = tid + static_cast<int64_t>(s) * 1024;
+    const int64_t i = tid + static_cast<int64_t>(s) * NT;
+#pragma unroll
+    for (int c = 0; c < kEigMaxB; ++c) {
+      const bool ok = i < n && c < b;
+      const double v = P.NX[(ok ? i : 0) + static_cast<int64_t>(ok ? c : 0) * n];
+      x[s][c] = ok ? v : 0.0;
+    }
+  }
+  orth_cols<NT, RPT, 0>(x, b, red, h);
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int64_t i = tid + static_cast<int64_t>(s) * NT;
     if (i < n)
 #pragma unroll
       for (int c = 0; c < kEigMaxB; ++c)
-        if (c < b) X[i + c * n] = x[s][c];
-  }
-}
-
-// NX += Nsym[row block, column chunk] X[column chunk] (NX zeroed beforehand; FP64
-// atomics).  Thread per row, X staged through LDS.
-__global__ __launch_bounds__(256) void k_symm_mult(const double* __restrict__ Ns, int64_t n,
-                                                   int b, const double* __restrict__ X,
-                                                   int64_t cols_per_chunk,
-                                                   double* __restrict__ NX) {
-  __shared__ double Xs[NB][kEigMaxB + 1];
-  const int tid = threadIdx.x;
-  const int rr = tid % 64, cg = tid / 64;  // 4 column groups
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + rr;
-  const int64_t j0 = static_cast<int64_t>(blockIdx.y) * cols_per_chunk;
-  const int64_t j1 = (j0 + cols_per_chunk < n) ? (j0 + cols_per_chunk) : n;
-  double acc[6] = {};
-  for (int64_t p0 = j0; p0 < j1; p0 += NB) {
-    __syncthreads();
-    for (int e = tid; e < NB * b; e += blockDim.x) {
-      const int a = e % NB, c = e / NB;
-      Xs[a][c] = (p0 + a < j1) ? X[(p0 + a) + static_cast<int64_t>(c) * n] : 0.0;
-    }
-    __syncthreads();
-    if (i < n) {
-      const int pe = static_cast<int>((j1 - p0) < NB ? (j1 - p0) : NB);
-      for (int p = 0; p < pe; ++p) {
-        const double a = Ns[i + (p0 + p) * n];
-#pragma unroll
-        for (int u = 0; u < 6; ++u) {
-          const int c = cg + 4 * u;
-          if (c < b) acc[u] += a * Xs[p][c];
-        }
-      }
-    }
-  }
-  if (i < n) {
-#pragma unroll
-    for (int u = 0; u < 6; ++u) {
-      const int c = cg + 4 * u;
-      if (c < b) atomic_add_f64(&NX[i + c * n], acc[u]);
-    }
-  }
-}
-
-// H += X[rows]^T NX[rows] over one 64-row block (H zeroed beforehand).
-__global__ __launch_bounds__(256) void k_xtnx(const double* __restrict__ X,
-                                              const double* __restrict__ NX, int64_t n, int b,
-                                              double* __restrict__ H) {
-  __shared__ double xs[NB][kEigMaxB + 1];
-  __shared__ double ys[NB][kEigMaxB + 1];
-  const int tid = threadIdx.x;
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * NB;
-  for (int e = tid; e < NB * b; e += blockDim.x) {
-    const int a = e % NB, c = e / NB;
-    const bool in = r0 + a < n;
-    xs[a][c] = in ? X[(r0 + a) + static_cast<int64_t>(c) * n] : 0.0;
-    ys[a][c] = in ? NX[(r0 + a) + static_cast<int64_t>(c) * n] : 0.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < b * b; e += blockDim.x) {
-    const int i = e / b, j = e % b;
-    double s = 0.0;
-    for (int a = 0; a < NB; ++a) s += xs[a][i] * ys[a][j];
-    atomic_add_f64(&H[e], s);
+        if (c < b) P.X[i + c * n] = x[s][c];
   }
 }
 
@@ -630,46 +875,52 @@ __global__ __launch_bounds__(256) void k_xtnx(const double* __restrict__ X,
 
 typedef double SmallMat[kEigMaxB + 1];
 
-// Parallel-ordering (round-robin) Jacobi on the symmetric b x b matrix H (LDS), one
-// workgroup.  Each round rotates floor(b/2) disjoint index pairs: the rotations are
-// computed in parallel, then applied as H <- J^T H J and Q <- Q J.  For a pair (p, q),
-// p < q, with c, s from the usual tau formula, column p becomes c col_p - s col_q and
-// column q becomes s col_p + c col_q (rows likewise); storing sn[q] = -s makes both
-// "cs[j] col_j - sn[j] col_partner".
-__device__ void jacobi_rounds(SmallMat* H, SmallMat* Q, int b, SmallMat* tmp, int* perm,
-                              double* cs, double* sn, int* partner, int* flag) {
-  const int tid = threadIdx.x;
+// Parallel-ordering (round-robin) Jacobi on the symmetric b x b matrix H (LDS) by one
+// workgroup of 256 threads, thread t owning elements t and t + 256 of the row-major b x b
+// array.  Each round rotates floor(b/2) disjoint index pairs: the rotations are computed in
+// parallel, then applied as H <- J^T H J and Q <- Q J.  For a pair (p, q), p < q, with c, s
+// from the usual tau formula, column p becomes c col_p - s col_q and column q becomes
+// s col_p + c col_q (rows likewise); storing sn[q] = -s makes both "cs[j] col_j - sn[j]
+// col_partner".  An element is rotated away only while it is above both eps sqrt(|a_pp
+// a_qq|) and 4 eps ||H||_F (rounding keeps off-diagonal entries near eps ||H||).
+__device__ void jacobi_block(SmallMat* H, SmallMat* Q, int b, int* perm, double* cs, double* sn,
+                             int* partner, int* flag, double floor_abs) {
+  const int t = threadIdx.x;
   const int bb = b + (b & 1);  // even number of players (one idle slot if b is odd)
-  for (int e = tid; e < b * b; e += blockDim.x) Q[e / b][e % b] = ((e / b) == (e % b)) ? 1.0 : 0.0;
-  if (tid < bb) perm[tid] = tid;
+  const int nel = b * b;
+  const bool own0 = t < nel, own1 = t + 256 < nel;
+  const int i0 = t / b, j0 = t % b, i1 = (t + 256) / b, j1 = (t + 256) % b;
+  if (own0) Q[i0][j0] = i0 == j0 ? 1.0 : 0.0;
+  if (own1) Q[i1][j1] = i1 == j1 ? 1.0 : 0.0;
+  if (t < bb) perm[t] = t;
   __syncthreads();
   for (int sweep = 0; sweep < 30; ++sweep) {
-    if (tid == 0) *flag = 0;
+    if (t == 0) *flag = 0;
     __syncthreads();
     for (int round = 0; round < bb - 1; ++round) {
-      if (tid < bb) partner[tid] = -1;
+      if (t < bb) partner[t] = -1;
       __syncthreads();
-      if (tid < bb / 2) {
-        int p = perm[tid], q = perm[bb - 1 - tid];
+      if (t < bb / 2) {
+        int p = perm[t], q = perm[bb - 1 - t];
         if (p > q) {
-          const int t = p;
+          const int tmp = p;
           p = q;
-          q = t;
+          q = tmp;
         }
         if (q < b) {
           double c = 1.0, s = 0.0;
           const double apq = H[p][q], app = H[p][p], aqq = H[q][q];
-          if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq))) {
+          if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
             const double tau = (aqq - app) / (2.0 * apq);
-            double t;
+            double tt;
             if (fabs(tau) > 1e150) {
-              t = 0.5 / tau;
+              tt = 0.5 / tau;
             } else {
-              t = 1.0 / (fabs(tau) + sqrt(1.0 + tau * tau));
-              if (tau < 0.0) t = -t;
+              tt = 1.0 / (fabs(tau) + sqrt(1.0 + tau * tau));
+              if (tau < 0.0) tt = -tt;
             }
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
             *flag = 1;
           }
           partner[p] = q;
@@ -681,38 +932,46 @@ __device__ void jacobi_rounds(SmallMat* H, SmallMat* Q, int b, SmallMat* tmp, in
         }
       }
       __syncthreads();
-      for (int e = tid; e < b * b; e += blockDim.x) {  // tmp = H J
-        const int i = e / b, j = e % b;
-        const int pj = partner[j];
-        tmp[i][j] = (pj >= 0) ? cs[j] * H[i][j] - sn[j] * H[i][pj] : H[i][j];
+      // H <- J^T H J and Q <- Q J for the owned elements (reads first, then writes)
+      double h0 = 0.0, h1 = 0.0, q0 = 0.0, q1 = 0.0;
+      if (own0) {
+        const int pi = partner[i0], pj = partner[j0];
+        const double ci = pi >= 0 ? cs[i0] : 1.0, si = pi >= 0 ? sn[i0] : 0.0;
+        const double cj = pj >= 0 ? cs[j0] : 1.0, sj = pj >= 0 ? sn[j0] : 0.0;
+        const int ii = pi >= 0 ? pi : i0, jj = pj >= 0 ? pj : j0;
+        const double hij = H[i0][j0], hip = H[i0][jj], hpj = H[ii][j0], hpp = H[ii][jj];
+        h0 = ci * (cj * hij - sj * hip) - si * (cj * hpj - sj * hpp);
+        q0 = cj * Q[i0][j0] - sj * Q[i0][jj];
+      }
+      if (own1) {
+        const int pi = partner[i1], pj = partner[j1];
+        const double ci = pi >= 0 ? cs[i1] : 1.0, si = pi >= 0 ? sn[i1] : 0.0;
+        const double cj = pj >= 0 ? cs[j1] : 1.0, sj = pj >= 0 ? sn[j1] : 0.0;
+        const int ii = pi >= 0 ? pi : i1, jj = pj >= 0 ? pj : j1;
+        const double hij = H[i1][j1], hip = H[i1][jj], hpj = H[ii][j1], hpp = H[ii][jj];
+        h1 = ci * (cj * hij - sj * hip) - si * (cj * hpj - sj * hpp);
+        q1 = cj * Q[i1][j1] - sj * Q[i1][jj];
       }
       __syncthreads();
-      for (int e = tid; e < b * b; e += blockDim.x) {  // H = J^T tmp
-        const int i = e / b, j = e % b;
-        const int pi = partner[i];
-        H[i][j] = (pi >= 0) ? cs[i] * tmp[i][j] - sn[i] * tmp[pi][j] : tmp[i][j];
+      if (own0) {
+        H[i0][j0] = h0;
+        Q[i0][j0] = q0;
+      }
+      if (own1) {
+        H[i1][j1] = h1;
+        Q[i1][j1] = q1;
       }
       __syncthreads();
-      for (int e = tid; e < b * b; e += blockDim.x) {  // tmp = Q J
-        const int i = e / b, j = e % b;
-        const int pj = partner[j];
-        tmp[i][j] = (pj >= 0) ? cs[j] * Q[i][j] - sn[j] * Q[i][pj] : Q[i][j];
-      }
+      // keep H exactly symmetric; circle method for the next round (player 0 fixed)
+      double a0 = 0.0, a1 = 0.0;
+      if (own0) a0 = 0.5 * (H[i0][j0] + H[j0][i0]);
+      if (own1) a1 = 0.5 * (H[i1][j1] + H[j1][i1]);
+      int nxt = 0;
+      if (t < bb) nxt = t == 0 ? perm[0] : (t == 1 ? perm[bb - 1] : perm[t - 1]);
       __syncthreads();
-      for (int e = tid; e < b * b; e += blockDim.x) {
-        const int i = e / b, j = e % b;
-        Q[i][j] = tmp[i][j];
-        if (i < j) {  // keep H exactly symmetric
-          const double avg = 0.5 * (H[i][j] + H[j][i]);
-          H[i][j] = avg;
-          H[j][i] = avg;
-        }
-      }
-      if (tid == 0) {  // circle method: player 0 fixed, the others rotate
-        const int last = perm[bb - 1];
-        for (int k = bb - 1; k > 1; --k) perm[k] = perm[k - 1];
-        perm[1] = last;
-      }
+      if (own0) H[i0][j0] = a0;
+      if (own1) H[i1][j1] = a1;
+      if (t < bb) perm[t] = nxt;
       __syncthreads();
     }
     if (*flag == 0) break;
@@ -720,159 +979,168 @@ __device__ void jacobi_rounds(SmallMat* H, SmallMat* Q, int b, SmallMat* tmp, in
   }
 }
 
-// Small part of Rayleigh-Ritz (one workgroup): Jacobi of H, eigenvalues sorted ascending;
-// writes Qs = Q with its columns in that order and theta.
-__global__ __launch_bounds__(256) void k_rr_small(const double* __restrict__ Hg, int b,
-                                                  double* __restrict__ Qs,
-                                                  double* __restrict__ theta_out) {
+// Small part of Rayleigh-Ritz (one workgroup per problem): Jacobi of H, eigenvalues sorted
+// ascending; writes Qs = Q with its columns in that order and theta; clears res2.
+__global__ __launch_bounds__(256) void k_rr_small(const EigProb* __restrict__ probs) {
   __shared__ SmallMat H[kEigMaxB];
   __shared__ SmallMat Q[kEigMaxB];
-  __shared__ SmallMat tmp[kEigMaxB];
   __shared__ int perm[kEigMaxB + 1];
   __shared__ double cs[kEigMaxB + 1];
   __shared__ double sn[kEigMaxB + 1];
   __shared__ int partner[kEigMaxB + 1];
   __shared__ int flag;
   __shared__ int order[kEigMaxB];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < b * b; e += blockDim.x) {
+  __shared__ double red[4];
+  const EigProb& P = probs[blockIdx.y];
+  const int b = P.b;
+  const int t = threadIdx.x;
+  gcdouble Hg = P.small + kSmallH;
+  double f2 = 0.0;
+  for (int e = t; e < b * b; e += 256) {
     const int i = e / b, j = e % b;
-    H[i][j] = 0.5 * (Hg[i * b + j] + Hg[j * b + i]);
+    const double v = 0.5 * (Hg[i * b + j] + Hg[j * b + i]);
+    H[i][j] = v;
+    f2 += v * v;
   }
+  f2 = wave_sum(f2);
+  if ((t & 63) == 0) red[t >> 6] = f2;
+  if (t < kEigMaxB) P.small[kSmallRes2 + t] = 0.0;
   __syncthreads();
-  jacobi_rounds(H, Q, b, tmp, perm, cs, sn, partner, &flag);
+  f2 = red[0] + red[1] + red[2] + red[3];
+  jacobi_block(H, Q, b, perm, cs, sn, partner, &flag, 4.0 * 2.220446049250313e-16 * sqrt(f2));
   __syncthreads();
-  if (tid < b) {
-    const double dk = H[tid][tid];
+  if (t < b) {
+    const double dk = H[t][t];
     int rk = 0;
     for (int j = 0; j < b; ++j) {
       const double dj = H[j][j];
-      rk += (dj < dk) || (dj == dk && j < tid);
+      rk += (dj < dk) || (dj == dk && j < t);
     }
-    order[rk] = tid;
-    theta_out[rk] = dk;
+    order[rk] = t;
+    P.small[kSmallTheta + rk] = dk;
   }
   __syncthreads();
-  for (int e = tid; e < b * b; e += blockDim.x) {
+  for (int e = t; e < b * b; e += 256) {
     const int j = e / b, k = e % b;  // Qs[j][k] = Q[j][order[k]]
-    Qs[e] = Q[j][order[k]];
+    P.small[kSmallQs + e] = Q[j][order[k]];
   }
 }
 
-// V-hat = X Qs[:, :r] and the squared residual norms ||NX q_k - theta_k X q_k||^2 (per
-// 64-row block, accumulated into res2[k]).
-__global__ __launch_bounds__(256) void k_rr_apply(const double* __restrict__ X,
-                                                  const double* __restrict__ NX, int64_t n,
-                                                  int b, int r, const double* __restrict__ Qs,
-                                                  const double* __restrict__ theta,
-                                                  double* __restrict__ V,
-                                                  double* __restrict__ res2) {
+// V-hat = X Qs[:, :r] (thread per row) and the squared residual norms
+// ||NX q_k - theta_k X q_k||^2, accumulated into res2[k].
+__global__ __launch_bounds__(256) void k_rr_apply(const EigProb* __restrict__ probs) {
   __shared__ double q[kEigMaxB * kEigMaxB];
-  __shared__ double red[4][RSM_MAX_R];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < b * b; e += blockDim.x) q[e] = Qs[e];
-  __syncthreads();
-  const int rr = tid % 64, g = tid / 64;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + rr;
-  for (int k = g; k < r; k += 4) {
-    double v = 0.0, res = 0.0;
-    if (i < n) {
-      for (int j = 0; j < b; ++j) {
-        const double x = X[i + static_cast<int64_t>(j) * n];
-        const double y = NX[i + static_cast<int64_t>(j) * n];
-        v += x * q[j * b + k];
-        res += (y - theta[k] * x) * q[j * b + k];
-      }
-      V[i + static_cast<int64_t>(k) * n] = v;
-    }
-    const double s2 = wave_sum(res * res);
-    if (rr == 0) atomic_add_f64(&res2[k], s2);
+  __shared__ double th[kEigMaxB];
+  const EigProb& P = probs[blockIdx.y];
+  const int64_t n = P.n;
+  const int b = P.b, r = P.r;
+  if (static_cast<int64_t>(blockIdx.x) * 256 >= n) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int e = tid; e < b * b; e += 256) q[e] = P.small[kSmallQs + e];
+  if (tid < b) th[tid] = P.small[kSmallTheta + tid];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + tid;
+  const bool act = i < n;
+  double x[kEigMaxB], y[kEigMaxB];
+#pragma unroll
+  for (int j = 0; j < kEigMaxB; ++j) {
+    const bool ok = act && j < b;
+    const int64_t at = (ok ? i : 0) + static_cast<int64_t>(ok ? j : 0) * n;
+    const double xv = P.X[at], yv = P.NX[at];
+    x[j] = ok ? xv : 0.0;
+    y[j] = ok ? yv : 0.0;
   }
+  __syncthreads();
+  double res[RSM_MAX_R];
+#pragma unroll
+  for (int k = 0; k < RSM_MAX_R; ++k) {
+    double v = 0.0, rs = 0.0;
+    if (k < r) {
+#pragma unroll
+      for (int j = 0; j < kEigMaxB; ++j) {
+        if (j < b) {
+          const double qj = q[j * b + k];
+          v = fma(x[j], qj, v);
+          rs = fma(y[j] - th[k] * x[j], qj, rs);
+        }
+      }
+      if (act) P.V[i + k * n] = v;
+    }
+    res[k] = rs * rs;
+  }
+  int idx = 0;
+  sum_many<RSM_MAX_R, 32>(res, lane, idx);
+  if ((lane & 3) == 0 && idx < r) atomic_add_f64(generic(&P.small[kSmallRes2 + idx]), res[0]);
 }
 
-__global__ void k_rr_finish(int b, int r, const double* __restrict__ theta,
-                            const double* __restrict__ res2, DevScalars* scal, rsm_info* info,
-                            int check_accepted) {
+__global__ void k_rr_finish(const EigProb* __restrict__ probs) {
+  const EigProb& P = probs[blockIdx.y];
   if (threadIdx.x != 0) return;
-  const double lam_max = scal->lam_max;
+  const int b = P.b, r = P.r;
+  gcdouble theta = P.small + kSmallTheta;
+  gcdouble res2 = P.small + kSmallRes2;
+  const double lam_max = P.scal->lam_max;
   double rmax = 0.0;
   for (int k = 0; k < r; ++k) rmax = fmax(rmax, sqrt(res2[k]));
   const double rel = lam_max > 0.0 ? rmax / lam_max : rmax;
+  RSM_GLOBAL rsm_info* info = P.info;
   info->residual = rel;
   for (int k = 0; k <= r && k < b; ++k) info->lambda[k] = theta[k];
   uint32_t warn = 0;
   if (info->uncovered > 0) warn |= RSM_W_RANK_DEFICIENT;
   if (b > r && !(theta[r] > 1e-12 * lam_max)) warn |= RSM_W_RANK_DEFICIENT;
   if (rel > 1e-6) warn |= RSM_W_NOT_CONVERGED;
-  if (scal->pivots > 0) warn |= RSM_W_PIVOT;
-  if (check_accepted && info->accepted == 0) warn |= RSM_W_NO_CONSTRAINTS;
-  atomicOr(&info->warn, warn);
+  if (P.scal->pivots > 0) warn |= RSM_W_PIVOT;
+  if (P.check_accepted && info->accepted == 0) warn |= RSM_W_NO_CONSTRAINTS;
+  atomicOr(generic(&info->warn), warn);
   info->eig_iterations = kEigIters;
 }
 
 }  // namespace
 
-void launch_solve_v(const Plan& P, const double* N, double* Nsym, double* Lf, double* Mi,
-                    double* T, double* Dinv, double* X, double* Z, double* NX, DevScalars* scal,
-                    double* V, rsm_info* info, hipStream_t s) {
-  const int64_t n = P.n;
-  const int b = P.eig_b;
-  const int nb = P.nb;
-  const int64_t npad = P.npad;
-  const unsigned g_nn = static_cast<unsigned>(ceil_div(n * n, 256));
-  const unsigned g_rows = static_cast<unsigned>(ceil_div(n, 64));
-  const int64_t chunk_cols = ceil_div(n, 16);
-  // small scratch carved from T (its first use, by the inverse, is over by then)
-  double* rowsum = Z;              // n values, before the iteration uses Z
-  double* Hb = T;                  // b x b
-  double* Qs = T + kEigMaxB * kEigMaxB;
-  double* theta = Qs + kEigMaxB * kEigMaxB;
-  double* res2 = theta + kEigMaxB;
-  k_eig_prep<<<g_nn, 256, 0, s>>>(N, n, Nsym, Lf, rowsum, info);
-  k_rowsum<<<dim3(g_rows, 16), 256, 0, s>>>(Nsym, n, chunk_cols, rowsum);
-  for (int k = 0; k < nb; ++k) {
-    k_chol_diag<<<1, NB, 0, s>>>(Lf, n, k, Dinv, rowsum, scal, info);
-    if (nb - k - 1 > 0) {
-      k_chol_panel<<<static_cast<unsigned>(nb - k - 1), 256, 0, s>>>(Lf, n, k, Dinv);
-      const int tiles = (nb - k - 1) * (nb - k) / 2;
-      k_chol_update<<<static_cast<unsigned>(tiles), 256, 0, s>>>(Lf, n, k, nb);
-    }
+void launch_solve_v(const EigProb* host, int nprob, EigProb* dev, hipStream_t s) {
+  if (nprob < 1) return;
+  int64_t n_max = 0, npad_max = 0;
+  int nb_max = 0;
+  for (int k = 0; k < nprob; ++k) {
+    n_max = host[k].n > n_max ? host[k].n : n_max;
+    npad_max = host[k].npad > npad_max ? host[k].npad : npad_max;
+    nb_max = host[k].nb > nb_max ? host[k].nb : nb_max;
   }
-  k_inv_init<<<static_cast<unsigned>(ceil_div(npad * npad, 256)), 256, 0, s>>>(Lf, Dinv, n, nb,
-                                                                                npad, Mi);
-  for (int64_t bs = NB; bs < npad; bs *= 2) {
+  for (int k0 = 0; k0 < nprob; k0 += kDescPerLaunch) {
+    EigProbPack pack;
+    pack.count = (nprob - k0) < kDescPerLaunch ? (nprob - k0) : kDescPerLaunch;
+    for (int k = 0; k < pack.count; ++k) pack.p[k] = host[k0 + k];
+    k_put_desc<<<1, kDescPerLaunch, 0, s>>>(pack, dev + k0);
+  }
+  const unsigned np = static_cast<unsigned>(nprob);
+  const unsigned g_rows64 = static_cast<unsigned>(ceil_div(n_max, 64));
+  k_eig_prep<<<dim3(static_cast<unsigned>(ceil_div(npad_max * npad_max, 256)), np), 256, 0, s>>>(dev);
+  k_rowsum<<<dim3(g_rows64, 16, np), 256, 0, s>>>(dev);
+  k_chol_first<<<dim3(1, np), 256, 0, s>>>(dev);
+  for (int k = 0; k + 1 < nb_max; ++k) {
+    const int rem = nb_max - k - 1;
+    k_chol_step<<<dim3(static_cast<unsigned>(rem * (rem + 1) / 2), np), 256, 0, s>>>(dev, k);
+  }
+  for (int64_t bs = NB; bs < npad_max; bs *= 2) {
     const int64_t tpb = bs / NB;
-    const unsigned grid = static_cast<unsigned>((npad / (2 * bs)) * tpb * tpb);
-    k_inv_stage1<<<grid, 256, 0, s>>>(Mi, npad, bs, T);
-    k_inv_stage2<<<grid, 256, 0, s>>>(Mi, npad, bs, T);
+    const unsigned grid = static_cast<unsigned>((npad_max / (2 * bs)) * tpb * tpb);
+    k_inv_stage1<<<dim3(grid, np), 256, 0, s>>>(dev, bs);
+    k_inv_stage2<<<dim3(grid, np), 256, 0, s>>>(dev, bs);
   }
-  k_start_vectors<<<static_cast<unsigned>(ceil_div(n * b, 256)), 256, 0, s>>>(
-      X, n, b, P.seed ^ 0x9E3779B97F4A7C15ull);
-  const int nt = static_cast<int>(ceil_div(n, NB));
-  const unsigned tri = static_cast<unsigned>(nt * (nt + 1) / 2);
-  const unsigned gz = static_cast<unsigned>(ceil_div(n * b, 256));
+  k_start_vectors<<<dim3(static_cast<unsigned>(ceil_div(n_max * kEigMaxB, 256)), np), 256, 0, s>>>(dev);
+  const unsigned g_rows16 = static_cast<unsigned>(ceil_div(n_max, kRows));
   for (int it = 0; it < kEigIters; ++it) {
-    k_zero<<<gz, 256, 0, s>>>(Z, n * b);
-    k_trmm<<<tri, 256, 0, s>>>(Mi, npad, n, b, X, Z, 0);
-    k_zero<<<gz, 256, 0, s>>>(NX, n * b);
-    k_trmm<<<tri, 256, 0, s>>>(Mi, npad, n, b, Z, NX, 1);
-    if (n <= 1024)
-      k_orth<1><<<1, 1024, 0, s>>>(NX, n, b, X);
-    else if (n <= 2048)
-      k_orth<2><<<1, 1024, 0, s>>>(NX, n, b, X);
+    k_apply<0><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
+    k_apply<1><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
+    if (n_max <= 4 * 256)
+      k_orth<256><<<dim3(1, np), 256, 0, s>>>(dev);
     else
-      k_orth<4><<<1, 1024, 0, s>>>(NX, n, b, X);
+      k_orth<512><<<dim3(1, np), 512, 0, s>>>(dev);
   }
-  // Rayleigh-Ritz with the true N
-  k_zero<<<gz, 256, 0, s>>>(NX, n * b);
-  const int64_t small = kEigMaxB * kEigMaxB * 2 + 2 * kEigMaxB;
-  k_zero<<<static_cast<unsigned>(ceil_div(small, 256)), 256, 0, s>>>(Hb, small);
-  k_symm_mult<<<dim3(g_rows, 16), 256, 0, s>>>(Nsym, n, b, X, chunk_cols, NX);
-  k_xtnx<<<g_rows, 256, 0, s>>>(X, NX, n, b, Hb);
-  k_rr_small<<<1, 256, 0, s>>>(Hb, b, Qs, theta);
-  k_rr_apply<<<g_rows, 256, 0, s>>>(X, NX, n, b, P.r, Qs, theta, V, res2);
-  k_rr_finish<<<1, 64, 0, s>>>(b, P.r, theta, res2, scal, info,
-                               (P.flags & RSM_FINALIZE_ONLY) ? 0 : 1);
+  k_apply<2><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
+  k_rr_small<<<dim3(1, np), 256, 0, s>>>(dev);
+  k_rr_apply<<<dim3(static_cast<unsigned>(ceil_div(n_max, 256)), np), 256, 0, s>>>(dev);
+  k_rr_finish<<<dim3(1, np), 64, 0, s>>>(dev);
 }
 
 }  // namespace rsm

@@ -109,12 +109,13 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   P.off_L = carve(cur, nn);
   const size_t pp = static_cast<size_t>(P.npad) * P.npad * sizeof(double);
   P.off_M = carve(cur, pp);
-  P.off_T = carve(cur, pp / 2);
-  P.off_Dinv = carve(cur, static_cast<size_t>(P.nb) * kCholNB * kCholNB * sizeof(double));
+  P.off_Mt = carve(cur, pp);
+  P.off_T = carve(cur, pp / 4);
   const size_t nbv = static_cast<size_t>(P.n) * P.eig_b * sizeof(double);
   P.off_X = carve(cur, nbv);
   P.off_Z = carve(cur, nbv);
   P.off_NX = carve(cur, nbv);
+  P.off_small = carve(cur, kSmallDoubles * sizeof(double));
   P.total = cur;
   return RSM_OK;
 }
@@ -139,71 +140,101 @@ int32_t check_io(const Plan& P, const rsm_input& in, const rsm_output& out) {
   return RSM_OK;
 }
 
+// Column-major Y as the kernels read it: the caller's array, or its packed copy.
+const void* ycm_of(const Plan& P, const rsm_input& in, void* ws) {
+  return P.y_layout == RSM_ROW_MAJOR ? at<void>(ws, P.off_ypack) : in.Y;
+}
+int64_t ldy_of(const Plan& P, const rsm_input& in) {
+  return P.y_layout == RSM_ROW_MAJOR ? P.m : in.ldy;
+}
+
 void mark(const rsm_output& out, int step, int end, hipStream_t s) {
   if (out.step_events && out.step_events[2 * step + end])
     (void)hipEventRecord(static_cast<hipEvent_t>(out.step_events[2 * step + end]), s);
 }
 
-// Enqueue steps a0..a7 of one problem whose scratch starts at `ws`.
-void enqueue(const Plan& P, const rsm_input& in, const rsm_output& out, void* ws,
-             hipStream_t s) {
+// Steps a0..a5 of one problem whose scratch starts at `ws`.
+void enqueue_front(const Plan& P, const rsm_input& in, const rsm_output& out, void* ws,
+                   hipStream_t s) {
   DevScalars* scal = at<DevScalars>(ws, P.off_scal);
   uint64_t* wbits = at<uint64_t>(ws, P.off_wbits);
   rsm_info* info = out.info;
   double* N = out.N ? out.N : at<double>(ws, P.off_N);
-  const bool finalize = P.flags & RSM_FINALIZE_ONLY;
-  const bool acc_only = P.flags & RSM_ACCUMULATE_ONLY;
 
   launch_init_info(info, scal, s);
 
   // a0: mask bit-planes, column-major Y
   mark(out, RSM_STEP_PACK, 0, s);
   launch_pack_mask(in.W, P.w_layout, in.ldw, P.m, P.n, wbits, P.mw, s);
-  const void* ycm = in.Y;
-  int64_t ldy = in.ldy;
-  if (P.y_layout == RSM_ROW_MAJOR) {
-    void* yp = at<void>(ws, P.off_ypack);
-    launch_pack_y(in.Y, P.y_dtype, in.ldy, P.m, P.n, yp, P.m, s);
-    ycm = yp;
-    ldy = P.m;
-  }
+  if (P.y_layout == RSM_ROW_MAJOR)
+    launch_pack_y(in.Y, P.y_dtype, in.ldy, P.m, P.n, at<void>(ws, P.off_ypack), P.m, s);
   mark(out, RSM_STEP_PACK, 1, s);
 
-  if (!finalize) {
-    // a1: subsets
-    mark(out, RSM_STEP_SUBSETS, 0, s);
-    int32_t* cols = out.trial_cols ? out.trial_cols : at<int32_t>(ws, P.off_cols);
-    launch_subsets(P, in.subsets, cols, info, s);
-    if (!(P.flags & RSM_N_ACCUMULATE)) launch_fill_zero(N, P.n * P.n, s);
-    mark(out, RSM_STEP_SUBSETS, 1, s);
-    // a2 + a3: row qualification and Gram partials
-    void* part = at<void>(ws, P.off_part);
-    int32_t* prow = at<int32_t>(ws, P.off_prow);
-    mark(out, RSM_STEP_GRAM, 0, s);
-    launch_gram(P, ycm, ldy, P.y_dtype, wbits, cols, part, prow, s);
-    mark(out, RSM_STEP_GRAM, 1, s);
-    // a4 + a5: minor vectors, N accumulation
-    mark(out, RSM_STEP_MINOR, 0, s);
-    launch_minor(P, part, prow, cols, at<double>(ws, P.off_G), at<int32_t>(ws, P.off_rows), N,
-                 info, out, s);
-    mark(out, RSM_STEP_MINOR, 1, s);
-  }
-  if (acc_only) return;
+  if (P.flags & RSM_FINALIZE_ONLY) return;
+  // a1: subsets
+  mark(out, RSM_STEP_SUBSETS, 0, s);
+  int32_t* cols = out.trial_cols ? out.trial_cols : at<int32_t>(ws, P.off_cols);
+  launch_subsets(P, in.subsets, cols, info, s);
+  if (!(P.flags & RSM_N_ACCUMULATE)) launch_fill_zero(N, P.n * P.n, s);
+  mark(out, RSM_STEP_SUBSETS, 1, s);
+  // a2 + a3: row qualification and Gram partials
+  void* part = at<void>(ws, P.off_part);
+  int32_t* prow = at<int32_t>(ws, P.off_prow);
+  mark(out, RSM_STEP_GRAM, 0, s);
+  launch_gram(P, ycm_of(P, in, ws), ldy_of(P, in), P.y_dtype, wbits, cols, part, prow, s);
+  mark(out, RSM_STEP_GRAM, 1, s);
+  // a4 + a5: minor vectors, N accumulation
+  mark(out, RSM_STEP_MINOR, 0, s);
+  launch_minor(P, part, prow, cols, at<double>(ws, P.off_G), at<int32_t>(ws, P.off_rows), N,
+               info, out, s);
+  mark(out, RSM_STEP_MINOR, 1, s);
+}
 
-  // a6: V-hat
-  mark(out, RSM_STEP_EIG, 0, s);
-  launch_solve_v(P, N, at<double>(ws, P.off_Nsym), at<double>(ws, P.off_L),
-                 at<double>(ws, P.off_M), at<double>(ws, P.off_T), at<double>(ws, P.off_Dinv),
-                 at<double>(ws, P.off_X), at<double>(ws, P.off_Z), at<double>(ws, P.off_NX), scal,
-                 out.V, info, s);
-  mark(out, RSM_STEP_EIG, 1, s);
-  // a7: U-hat
+// Device pointer as the descriptor types it (global memory in the device pass).
+template <typename T>
+RSM_GLOBAL T* gptr(T* p) {
+  return (RSM_GLOBAL T*)p;
+}
+
+// Descriptor of the a6 solve of one problem.
+EigProb eig_desc(const Plan& P, const rsm_output& out, void* ws) {
+  EigProb e{};
+  e.n = P.n;
+  e.npad = P.npad;
+  e.nb = P.nb;
+  e.b = P.eig_b;
+  e.r = P.r;
+  e.check_accepted = (P.flags & RSM_FINALIZE_ONLY) ? 0 : 1;
+  e.seed = P.seed ^ 0x9E3779B97F4A7C15ull;
+  e.N = gptr(out.N ? out.N : at<double>(ws, P.off_N));
+  e.Nsym = gptr(at<double>(ws, P.off_Nsym));
+  e.Lf = gptr(at<double>(ws, P.off_L));
+  e.M = gptr(at<double>(ws, P.off_M));
+  e.Mt = gptr(at<double>(ws, P.off_Mt));
+  e.T = gptr(at<double>(ws, P.off_T));
+  e.X = gptr(at<double>(ws, P.off_X));
+  e.Z = gptr(at<double>(ws, P.off_Z));
+  e.NX = gptr(at<double>(ws, P.off_NX));
+  e.small = gptr(at<double>(ws, P.off_small));
+  e.scal = gptr(at<DevScalars>(ws, P.off_scal));
+  e.V = gptr(out.V);
+  e.info = gptr(out.info);
+  return e;
+}
+
+// Step a7 (and the optional error) of one problem.
+void enqueue_back(const Plan& P, const rsm_input& in, const rsm_output& out, void* ws,
+                  hipStream_t s) {
+  const uint64_t* wbits = at<uint64_t>(ws, P.off_wbits);
+  const void* ycm = ycm_of(P, in, ws);
+  const int64_t ldy = ldy_of(P, in);
   mark(out, RSM_STEP_USOLVE, 0, s);
-  launch_solve_u(P, ycm, ldy, P.y_dtype, wbits, out.V, out.U, info, s);
+  launch_solve_u(P, ycm, ldy, P.y_dtype, wbits, out.V, out.U, out.info, s);
   mark(out, RSM_STEP_USOLVE, 1, s);
   if (P.flags & RSM_COMPUTE_ERROR) {
     mark(out, RSM_STEP_ERROR, 0, s);
-    launch_error(P, ycm, ldy, P.y_dtype, wbits, out.U, out.V, scal, info, s);
+    launch_error(P, ycm, ldy, P.y_dtype, wbits, out.U, out.V, at<DevScalars>(ws, P.off_scal),
+                 out.info, s);
     mark(out, RSM_STEP_ERROR, 1, s);
   }
 }
@@ -233,6 +264,12 @@ const char* rsm_status_string(int32_t status) {
   }
 }
 
+// The workspace of a call: each problem's scratch (256-byte aligned, in order), then the
+// device copies of the a6 descriptors of all problems.
+static size_t desc_bytes(int32_t nprob) {
+  return rsm::align_up(static_cast<size_t>(nprob) * sizeof(rsm::EigProb), 256);
+}
+
 int32_t rsm_workspace_bytes(const rsm_problem* problems, int32_t nprob, size_t* bytes) {
   if (!problems || !bytes || nprob < 1) return RSM_E_ARG;
   size_t total = 0;
@@ -242,7 +279,7 @@ int32_t rsm_workspace_bytes(const rsm_problem* problems, int32_t nprob, size_t* 
     if (st != RSM_OK) return st;
     total += rsm::align_up(P.total, 256);
   }
-  *bytes = total;
+  *bytes = total + desc_bytes(nprob);
   return RSM_OK;
 }
 
@@ -257,20 +294,37 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   if (nprob < 1 || !problems || !inputs || !outputs) return RSM_E_ARG;
   size_t need = 0;
   std::vector<rsm::Plan> plans(static_cast<size_t>(nprob));
+  std::vector<size_t> base(static_cast<size_t>(nprob));
   for (int32_t k = 0; k < nprob; ++k) {
     int32_t st = rsm::make_plan(problems[k], plans[k]);
     if (st == RSM_OK) st = rsm::check_io(plans[k], inputs[k], outputs[k]);
     if (st != RSM_OK) return st;
+    base[k] = need;
     need += rsm::align_up(plans[k].total, 256);
   }
+  const size_t desc_off = need;
+  need += desc_bytes(nprob);
   if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u))
     return RSM_E_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   (void)hipGetLastError();  // clear a stale error from unrelated earlier work
-  size_t off = 0;
+  char* ws = static_cast<char*>(workspace);
+  for (int32_t k = 0; k < nprob; ++k)
+    rsm::enqueue_front(plans[k], inputs[k], outputs[k], ws + base[k], s);
+  // a6 for every problem that finalises, in shared launches
+  std::vector<rsm::EigProb> eig;
+  std::vector<int32_t> who;
   for (int32_t k = 0; k < nprob; ++k) {
-    rsm::enqueue(plans[k], inputs[k], outputs[k], static_cast<char*>(workspace) + off, s);
-    off += rsm::align_up(plans[k].total, 256);
+    if (plans[k].flags & RSM_ACCUMULATE_ONLY) continue;
+    eig.push_back(rsm::eig_desc(plans[k], outputs[k], ws + base[k]));
+    who.push_back(k);
+  }
+  if (!eig.empty()) {
+    for (int32_t k : who) rsm::mark(outputs[k], RSM_STEP_EIG, 0, s);
+    rsm::launch_solve_v(eig.data(), static_cast<int>(eig.size()),
+                        reinterpret_cast<rsm::EigProb*>(ws + desc_off), s);
+    for (int32_t k : who) rsm::mark(outputs[k], RSM_STEP_EIG, 1, s);
+    for (int32_t k : who) rsm::enqueue_back(plans[k], inputs[k], outputs[k], ws + base[k], s);
   }
   return hipGetLastError() == hipSuccess ? RSM_OK : RSM_E_DEVICE;
 }

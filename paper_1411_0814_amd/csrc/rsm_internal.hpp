@@ -60,10 +60,53 @@ struct Plan {
   // workspace offsets (bytes from the workspace base); ~0 = unused
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
          off_rows = 0;
-  size_t off_N = 0, off_Nsym = 0, off_L = 0, off_M = 0, off_T = 0, off_Dinv = 0, off_X = 0,
-         off_Z = 0, off_NX = 0;
+  size_t off_N = 0, off_Nsym = 0, off_L = 0, off_M = 0, off_Mt = 0, off_T = 0, off_X = 0,
+         off_Z = 0, off_NX = 0, off_small = 0;
   size_t off_scal = 0;
   size_t total = 0;
+};
+
+// Small per-problem arrays of the V-hat solver (doubles, in this order): the b x b
+// Rayleigh-Ritz matrix H, its sorted eigenvectors Qs, the Ritz values theta and the squared
+// residual norms res2.
+constexpr int kSmallH = 0;
+constexpr int kSmallQs = kEigMaxB * kEigMaxB;
+constexpr int kSmallTheta = 2 * kEigMaxB * kEigMaxB;
+constexpr int kSmallRes2 = 2 * kEigMaxB * kEigMaxB + kEigMaxB;
+constexpr int kSmallDoubles = 2 * kEigMaxB * kEigMaxB + 2 * kEigMaxB;
+
+// Device-side description of one V-hat solve (step a6).  The solver's kernels take an array
+// of these and run every problem of a batch in the same launch (problem = blockIdx.y); each
+// workgroup reads its problem's sizes and buffers from here.
+// In the device pass the descriptor's pointers are typed as global memory, so accesses
+// through them compile to global (not flat) instructions; the layout is the same.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define RSM_GLOBAL __attribute__((address_space(1)))
+#else
+#define RSM_GLOBAL
+#endif
+
+struct EigProb {
+  int64_t n;             // order of N
+  int64_t npad;          // order of M = L^{-1}: 64 x (tiles rounded up to a power of two)
+  int32_t nb;            // 64 x 64 tiles per dimension of N
+  int32_t b;             // subspace width
+  int32_t r;             // target rank
+  int32_t check_accepted;  // flag "no accepted trial" (off when only finalising a given N)
+  uint64_t seed;         // start-vector stream
+  RSM_GLOBAL const double* N;  // accumulated N (lower triangle, column-major n x n)
+  RSM_GLOBAL double* Nsym;     // N with both triangles
+  RSM_GLOBAL double* Lf;       // trailing matrix of the factorisation (lower)
+  RSM_GLOBAL double* M;        // L^{-1}, npad x npad, lower tiles
+  RSM_GLOBAL double* Mt;       // (L^{-1})^T, npad x npad, upper tiles
+  RSM_GLOBAL double* T;        // recursion temporary (npad/2 x npad/2)
+  RSM_GLOBAL double* X;        // n x b iterate
+  RSM_GLOBAL double* Z;        // n x b; its first n entries hold the row sums at the start
+  RSM_GLOBAL double* NX;       // n x b
+  RSM_GLOBAL double* small;    // kSmallDoubles
+  RSM_GLOBAL DevScalars* scal;
+  RSM_GLOBAL double* V;        // output n x r
+  RSM_GLOBAL rsm_info* info;
 };
 
 // Fills `plan` from `p` (defaults resolved, sizes checked).  Returns RSM_OK or an error.
@@ -84,9 +127,9 @@ void launch_gram(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
 void launch_minor(const Plan& P, const void* part, const int32_t* prow, const int32_t* cols,
                   double* G, int32_t* rows, double* N, rsm_info* info, const rsm_output& out,
                   hipStream_t s);
-void launch_solve_v(const Plan& P, const double* N, double* Nsym, double* Lf, double* Mi,
-                    double* T, double* Dinv, double* X, double* Z, double* NX, DevScalars* scal,
-                    double* V, rsm_info* info, hipStream_t s);
+// V-hat of `nprob` problems in the same launches.  `host` holds their descriptors on the
+// host; `dev` is device memory for nprob descriptors (filled here, on the stream).
+void launch_solve_v(const EigProb* host, int nprob, EigProb* dev, hipStream_t s);
 void launch_solve_u(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
                     const uint64_t* wbits, const double* V, double* U, rsm_info* info,
                     hipStream_t s);
