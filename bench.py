@@ -43,9 +43,49 @@ def parse():
                     help="per-trial column-streaming Gram kernel instead of the tiled one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--cpu-sample-trials", type=int, default=256)
-    ap.add_argument("--cpu-sample-rows", type=int, default=2048)
+    ap.add_argument("--cpu-sample-trials", type=int, default=4096)
+    ap.add_argument("--cpu-sample-rows", type=int, default=2048,
+                    help="rows of U in the parity check")
+    ap.add_argument("--cpu-sample-u-rows", type=int, default=49152)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (calibrates the "
+                         "byte counters of rocprofv3 --pmc) and exit")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    """A plain copy kernel of known size: the byte counters' calibration."""
+    import torch
+    n = mib * (1 << 20)
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n, "launches": 3}), flush=True)
+
+
+def traffic_from_profile(kernel_src):
+    """HBM bytes per launch of the Gram kernel from the committed rocprofv3 counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_gram_tile_paper_scale_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    with open(kernel_src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if vals.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return int(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def make_workload(name):
@@ -119,6 +159,9 @@ def cpu_baseline(p, n_trials, n_rows):
 
 def main():
     args = parse()
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -202,7 +245,9 @@ def main():
         "step_ms": {k: round(float(np.mean(v)), 4) for k, v in per_step.items() if v},
         "roofline": {"bound": "hbm", "kernel": "gram (row qualification + Gram)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile(
+                         os.path.join(ROOT, "paper_1411_0814_amd", "csrc", "k_gram.hip")),
                      "bytes_alg_per_launch": int(b_alg), "launch_ms": round(gram_ms, 4)},
         "info": {"accepted": info["accepted"], "mean_rows": info["rows_total"] / max(1, p.num_submatrices),
                  "warnings": info["warnings"], "residual": info["residual"],
@@ -218,7 +263,7 @@ def main():
                          "oracle_s": round(t_or, 1), "oracle_workers": workers,
                          "pass": bool(theta <= 1e-4 and rms <= 1e-5)}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample_trials, args.cpu_sample_rows)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample_trials, args.cpu_sample_u_rows)
     print(json.dumps(out), flush=True)
 
 
