@@ -38,7 +38,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper_scale",
-                    choices=["paper_scale", "plain_fp64", "precision"])
+                    choices=["paper_scale", "plain_fp64", "precision", "batched", "served"])
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--served-seconds", type=float, default=5.0)
+    ap.add_argument("--served-budget-gib", type=float, default=16.0)
+    ap.add_argument("--parity-problems", type=int, default=4,
+                    help="problems of the batch checked against the oracle")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="omit the batched / served summaries from the default line")
     ap.add_argument("--plain-gram", action="store_true",
                     help="per-trial column-streaming Gram kernel instead of the tiled one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -157,6 +165,133 @@ def cpu_baseline(p, n_trials, n_rows):
     }
 
 
+def _batch_setup(args, torch):
+    """The mixed batch: 256 problems of uneven sizes drawn on the device, and requests."""
+    import synth
+    from paper_1411_0814_amd import Request
+    specs = synth.batched_sizes(args.batch_count)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    inputs = [synth.batched_device(sp, dev) for sp in specs]
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    reqs = [Request(Y=Y, W=W, r=sp["r"], num_submatrices=sp["num_submatrices"],
+                    seed=sp["seed_rsm"], l=sp["l"], gram="f32")
+            for sp, (Y, W) in zip(specs, inputs)]
+    return specs, inputs, reqs, t_gen
+
+
+def run_batched(args, torch):
+    """Batched RSM (one fused call for the whole batch) vs plain RSM (the same problems one
+    at a time through rsm_decompose on one stream), with oracle parity on a sample."""
+    from paper_1411_0814_amd import decompose, decompose_batched, workspace_bytes
+    specs, inputs, reqs, t_gen = _batch_setup(args, torch)
+    stream = torch.cuda.current_stream()
+    ws_need = workspace_bytes(reqs)
+    ws = torch.empty(ws_need + 256, dtype=torch.uint8, device="cuda")
+    ws = ws[(-ws.data_ptr()) % 256:][:ws_need]
+    res = decompose_batched(reqs, stream=stream, workspace=ws)   # warm-up
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.batch_reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        res = decompose_batched(reqs, stream=stream, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    t_batch = float(np.median(times))
+    # plain: one at a time on one stream, one workspace sized for the largest problem
+    ws1_need = max(workspace_bytes([q]) for q in reqs)
+    ws1 = torch.empty(ws1_need + 256, dtype=torch.uint8, device="cuda")
+    ws1 = ws1[(-ws1.data_ptr()) % 256:][:ws1_need]
+    for q in reqs[:8]:
+        decompose(q.Y, q.W, q.r, q.num_submatrices, q.seed, l=q.l, gram=q.gram,
+                  stream=stream, workspace=ws1)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in reqs]
+    t0 = time.perf_counter()
+    for q, (a, b) in zip(reqs, evs):
+        a.record(stream)
+        decompose(q.Y, q.W, q.r, q.num_submatrices, q.seed, l=q.l, gram=q.gram,
+                  stream=stream, workspace=ws1)
+        b.record(stream)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    lat_plain = [a.elapsed_time(b) for a, b in evs]
+    out = {
+        "problems": len(reqs),
+        "batched": {"decompositions_per_s": round(len(reqs) / t_batch, 1),
+                    "ms_per_batch": round(t_batch * 1e3, 3), "reps": args.batch_reps},
+        "plain": {"decompositions_per_s": round(len(reqs) / t_plain, 1),
+                  "ms_total": round(t_plain * 1e3, 3),
+                  "latency_ms": {"p50": round(float(np.percentile(lat_plain, 50)), 4),
+                                 "p99": round(float(np.percentile(lat_plain, 99)), 4)}},
+        "speedup": round(t_plain / t_batch, 2),
+        "gen_s": round(t_gen, 2),
+    }
+    if not args.no_parity and args.parity_problems > 0:
+        from oracle import metrics, rsm
+        pick = np.random.default_rng(7).choice(len(reqs), args.parity_problems, replace=False)
+        worst_t, worst_r, t_or = 0.0, 0.0, time.perf_counter()
+        for k in sorted(int(x) for x in pick):
+            Y = reqs[k].Y.cpu().numpy()
+            W = reqs[k].W.cpu().numpy()
+            ora = rsm.rsm(Y, W, reqs[k].r, reqs[k].num_submatrices, seed=reqs[k].seed,
+                          l=reqs[k].l, with_e=False)
+            V, U = res[k].V.cpu().numpy(), res[k].U.cpu().numpy()
+            worst_t = max(worst_t, metrics.principal_angle_max(V, ora.V))
+            worst_r = max(worst_r, metrics.rel_rms_known(W, U, V, ora.U, ora.V))
+        out["parity"] = {"problems_checked": [int(x) for x in sorted(pick)],
+                         "theta_max_rad": worst_t, "rel_rms_known": worst_r,
+                         "oracle_s": round(time.perf_counter() - t_or, 1),
+                         "pass": bool(worst_t <= 1e-4 and worst_r <= 1e-5)}
+    return out, (specs, inputs, reqs)
+
+
+def run_served(args, torch, batch, saturation):
+    """Poisson traces at 0.5x and 0.9x the batched saturation rate, served with continuous
+    batching and, on the same trace, first-in first-out one at a time (plain)."""
+    from paper_1411_0814_amd import serve
+    specs, inputs, reqs = batch
+    pool = [serve.PoolItem(Y=q.Y, W=q.W, r=q.r, num_submatrices=q.num_submatrices, l=q.l,
+                           gram=q.gram) for q in reqs]
+    budget = int(args.served_budget_gib * (1 << 30))
+    levels = []
+    for frac in (0.5, 0.9):
+        qps = frac * saturation
+        trace = serve.poisson_trace(len(pool), qps, args.served_seconds, seed=11)
+        srv = serve.Server(pool, budget_bytes=budget, batching=True, max_inflight=3)
+        st_b = srv.run(trace)
+        trace_p = serve.poisson_trace(len(pool), qps, args.served_seconds, seed=11)
+        st_p = serve.Server(pool, budget_bytes=budget, batching=False, max_inflight=1).run(
+            trace_p, time_limit=4 * args.served_seconds)
+        torch.cuda.synchronize()
+        levels.append({"qps": round(qps, 1), "fraction_of_saturation": frac,
+                       "continuous_batching": st_b, "plain_fifo": st_p})
+    return {"seconds_per_level": args.served_seconds, "budget_gib": args.served_budget_gib,
+            "levels": levels}
+
+
+def main_batched(args):
+    import torch
+    out, batch = run_batched(args, torch)
+    line = {
+        "metric": METRIC, "value": out["batched"]["decompositions_per_s"],
+        "unit": "decompositions/s", "n_gpus": 1, "steps": args.batch_reps, "warmup": 1,
+        "ms_per_step": out["batched"]["ms_per_batch"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched {out['problems']} problems: m U[4096,65536], "
+                               "n U[128,1024], r U{2..16}, rho U[0.6,0.9], l=r+1, I=4n",
+                   "gram": "f32", "eig_solves": "f64"},
+        "batched": out,
+    }
+    if args.workload == "served":
+        line["served"] = run_served(args, torch, batch, out["batched"]["decompositions_per_s"])
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe_mib:
@@ -166,6 +301,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload in ("batched", "served"):
+        main_batched(args)
+        return
     import torch
 
     from paper_1411_0814_amd import _lib, decompose, workspace_bytes, Request
@@ -264,6 +402,12 @@ def main():
                          "pass": bool(theta <= 1e-4 and rms <= 1e-5)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample_trials, args.cpu_sample_u_rows)
+    if not args.no_batched and args.workload == "paper_scale":
+        del Y, W, ws, results, res, last
+        torch.cuda.empty_cache()
+        bout, batch = run_batched(args, torch)
+        out["batched"] = bout
+        out["served"] = run_served(args, torch, batch, bout["batched"]["decompositions_per_s"])
     print(json.dumps(out), flush=True)
 
 

@@ -194,8 +194,10 @@ int32_t rsm_abi_version(void);
 const char* rsm_status_string(int32_t status);
 
 /* Bytes of workspace rsm_decompose (nprob == 1) or rsm_decompose_batched needs for these
- * problems.  Host only: no device call.  Returns RSM_E_ARG / RSM_E_UNSUPPORTED for a
- * problem the decomposition would reject. */
+ * problems: each problem's scratch (256-byte aligned) plus one small area per call for the
+ * device-side problem descriptors, so a batch needs slightly less than the sum of its
+ * problems' single sizes.  Host only: no device call.  Returns RSM_E_ARG /
+ * RSM_E_UNSUPPORTED for a problem the decomposition would reject. */
 int32_t rsm_workspace_bytes(const rsm_problem* problems, int32_t nprob, size_t* bytes);
 
 /* One decomposition (steps a1..a7, Section IV-A).  `workspace` is device memory of at
@@ -204,7 +206,10 @@ int32_t rsm_workspace_bytes(const rsm_problem* problems, int32_t nprob, size_t* 
 int32_t rsm_decompose(const rsm_problem* p, const rsm_input* in, const rsm_output* out,
                       void* workspace, size_t ws_bytes, void* hip_stream);
 
-/* Several independent decompositions (uneven sizes allowed) fused into shared launches.
+/* Several independent decompositions (uneven sizes allowed) fused into shared launches:
+ * every step runs once for all problems that share its kernel instance (the Gram and
+ * minor-vector steps per l, the U-hat step per r and element type of Y, the V-hat steps
+ * for all problems together), each launch's extent set by its largest problem.
  * problems/inputs/outputs are host arrays of nprob entries; each problem's results equal
  * those of rsm_decompose on it alone, up to the order of floating-point accumulation
  * into N.  workspace: rsm_workspace_bytes(problems, nprob) bytes. */

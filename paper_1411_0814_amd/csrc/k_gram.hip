@@ -19,6 +19,8 @@
 //  * k_gram_tile   — the LDS-reuse kernel: a workgroup stages a 32-row x n-column tile of Y
 //    (and the tile's mask words) in LDS once and every thread — one trial each — gathers
 //    its qualifying rows from LDS.  HBM/L2 traffic drops to (trial groups) x |Y|.
+#include <algorithm>
+
 #include "device_util.hpp"
 #include "rsm_internal.hpp"
 
@@ -26,35 +28,31 @@ namespace rsm {
 
 namespace {
 
-template <typename TY, typename TA>
-__device__ __forceinline__ TA load_as(const TY* p) {
-  return static_cast<TA>(*p);
-}
-
 // ------------------------------------------------------------------ per-trial streamer
 
 template <int L, typename TY, typename TA>
-__global__ __launch_bounds__(256) void k_gram_plain(
-    const TY* __restrict__ Y, int64_t ldy, const uint64_t* __restrict__ wbits, int64_t mw,
-    const int32_t* __restrict__ cols, int64_t I, int64_t words_per_split,
-    TA* __restrict__ part, int32_t* __restrict__ prow) {
+__global__ __launch_bounds__(256) void k_gram_plain(const ProbDesc* __restrict__ probs,
+                                                    IdxList list) {
   constexpr int NG = L * (L + 1) / 2;
+  const ProbDesc& P = probs[list.idx[blockIdx.z]];
+  const int64_t I = P.I, mw = P.mw, ldy = P.ldy;
   const int lane = threadIdx.x & 63;
   const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (t >= I) return;  // wave-uniform
   const int split = blockIdx.y;
-  const int64_t w0 = static_cast<int64_t>(split) * words_per_split;
-  const int64_t w1 = (w0 + words_per_split < mw) ? (w0 + words_per_split) : mw;
+  if (t >= I || split >= P.splits) return;  // wave-uniform
+  const int64_t w0 = static_cast<int64_t>(split) * P.words_per_split;
+  const int64_t w1 = (w0 + P.words_per_split < mw) ? (w0 + P.words_per_split) : mw;
+  auto Y = static_cast<RSM_GLOBAL const TY*>(P.ycm);
 
-  const uint64_t* wcol[L];
-  const TY* ycol[L];
+  RSM_GLOBAL const uint64_t* wcol[L];
+  RSM_GLOBAL const TY* ycol[L];
   bool valid = true;
 #pragma unroll
   for (int a = 0; a < L; ++a) {
-    const int c = static_cast<int>(uniform_u32(static_cast<uint32_t>(cols[t * L + a])));
+    const int c = static_cast<int>(uniform_u32(static_cast<uint32_t>(P.cols[t * L + a])));
     valid &= (c >= 0);
     const int cc = c < 0 ? 0 : c;
-    wcol[a] = wbits + static_cast<int64_t>(cc) * mw;
+    wcol[a] = P.wbits + static_cast<int64_t>(cc) * mw;
     ycol[a] = Y + static_cast<int64_t>(cc) * ldy;
   }
 
@@ -73,7 +71,7 @@ __global__ __launch_bounds__(256) void k_gram_plain(
         const int64_t i = w * 64 + lane;
         TA y[L];
 #pragma unroll
-        for (int a = 0; a < L; ++a) y[a] = load_as<TY, TA>(ycol[a] + i);
+        for (int a = 0; a < L; ++a) y[a] = static_cast<TA>(ycol[a][i]);
         int g = 0;
 #pragma unroll
         for (int a = 0; a < L; ++a)
@@ -83,22 +81,13 @@ __global__ __launch_bounds__(256) void k_gram_plain(
     }
   }
 
-  TA* dst = part + static_cast<int64_t>(split) * NG * I + t;
+  RSM_GLOBAL TA* dst = static_cast<RSM_GLOBAL TA*>(P.part) + static_cast<int64_t>(split) * NG * I + t;
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     const TA v = wave_sum(acc[g]);
     if (lane == 0) dst[static_cast<int64_t>(g) * I] = v;
   }
-  if (lane == 0) prow[static_cast<int64_t>(split) * I + t] = count;
-}
-
-template <int L, typename TY, typename TA>
-void run_plain(const Plan& P, const void* ycm, int64_t ldy, const uint64_t* wbits,
-               const int32_t* cols, void* part, int32_t* prow, hipStream_t s) {
-  dim3 grid(static_cast<unsigned>(ceil_div(P.I, 4)), static_cast<unsigned>(P.splits));
-  k_gram_plain<L, TY, TA><<<grid, 256, 0, s>>>(static_cast<const TY*>(ycm), ldy, wbits, P.mw,
-                                               cols, P.I, P.words_per_split,
-                                               static_cast<TA*>(part), prow);
+  if (lane == 0) P.prow[static_cast<int64_t>(split) * I + t] = count;
 }
 
 // ------------------------------------------------------------------ LDS-tiled kernel
@@ -140,12 +129,8 @@ struct Vec16<double> {
 };
 
 template <int L, typename T, int NT>
-__global__ __launch_bounds__(NT) void k_gram_tile(
-    const T* __restrict__ Y, int64_t ldy, const uint32_t* __restrict__ mask32,
-    int64_t mw32, int64_t m, int n, int n_pad, int m_pad, const int32_t* __restrict__ cols,
-    int64_t I,
-    int64_t chunks_per_split, int64_t chunks, int groups, int xcd_map, T* __restrict__ part,
-    int32_t* __restrict__ prow) {
+__global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ probs,
+                                                  IdxList list) {
   constexpr int NG = L * (L + 1) / 2;
   using V = typename Vec16<T>::type;
   constexpr int kVN = Vec16<T>::kN;                 // elements per 16-byte vector
@@ -155,14 +140,25 @@ __global__ __launch_bounds__(NT) void k_gram_tile(
   constexpr int kMaxCols = static_cast<int>(kTileLdsBytes / (kS * sizeof(T)));
   constexpr int kMaxV = (kMaxCols * kVPC + NT - 1) / NT;
   constexpr int kMaxM = (kMaxCols + NT - 1) / NT;
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int groups = P.gram_groups, splits = P.splits;
+  if (static_cast<int>(blockIdx.x) >= groups * splits) return;  // past this problem's work
+  const int64_t m = P.m, I = P.I, ldy = P.ldy, mw32 = 2 * P.mw;
+  const int n = static_cast<int>(P.n);
+  const int n_pad = static_cast<int>(ceil_div(n, NT / kVPC) * (NT / kVPC));
+  const int m_pad = static_cast<int>(ceil_div(n, NT) * NT);
+  const int64_t chunks = ceil_div(m, kChunk), chunks_per_split = 2 * P.words_per_split;
+  const bool xcd_map = splits % 8 == 0;
+  auto Y = static_cast<RSM_GLOBAL const T*>(P.ycm);
+  auto mask32 = reinterpret_cast<RSM_GLOBAL const uint32_t*>(P.wbits);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);                                   // [n_pad][kS]
   uint32_t* msk = reinterpret_cast<uint32_t*>(tile + static_cast<int64_t>(n_pad) * kS);  // [m_pad]
 
   // Workgroup -> (trial group, row split).  Workgroups are dispatched to the 8 XCDs
-  // round-robin by id, so with xcd_map the ids id = 8 k + x of XCD x enumerate all trial
-  // groups of split 8 (k / groups) + x before the next split: the groups reading the same
-  // rows share that XCD's L2.
+  // round-robin by id (the launch's x extent is a multiple of 8), so with xcd_map the ids
+  // id = 8 k + x of XCD x enumerate all trial groups of split 8 (k / groups) + x before the
+  // next split: the groups reading the same rows share that XCD's L2.
   const int id = blockIdx.x;
   int group, split;
   if (xcd_map) {
@@ -184,7 +180,7 @@ __global__ __launch_bounds__(NT) void k_gram_tile(
   bool valid = active;
 #pragma unroll
   for (int a = 0; a < L; ++a) {
-    int c = active ? cols[t * L + a] : 0;
+    int c = active ? P.cols[t * L + a] : 0;
     valid &= (c >= 0);
     mc[a] = c < 0 ? 0 : c;
   }
@@ -212,7 +208,7 @@ __global__ __launch_bounds__(NT) void k_gram_tile(
       for (int k = 0; k < kMaxV; ++k) {
         if (k < kv) {
           const int c = min(c0 + k * (NT / kVPC), n - 1);
-          vreg[k] = *reinterpret_cast<const V*>(Y + static_cast<int64_t>(c) * ldy + r0 + vpart);
+          vreg[k] = *reinterpret_cast<RSM_GLOBAL const V*>(Y + static_cast<int64_t>(c) * ldy + r0 + vpart);
         }
       }
     } else {  // ragged last chunk: rows past m read as zero
@@ -220,7 +216,7 @@ __global__ __launch_bounds__(NT) void k_gram_tile(
       for (int k = 0; k < kMaxV; ++k) {
         if (k < kv) {
           const int c = min(c0 + k * (NT / kVPC), n - 1);
-          const T* src = Y + static_cast<int64_t>(c) * ldy + r0 + vpart;
+          RSM_GLOBAL const T* src = Y + static_cast<int64_t>(c) * ldy + r0 + vpart;
           T tmp[kVN];
 #pragma unroll
           for (int u = 0; u < kVN; ++u) tmp[u] = (r0 + vpart + u < m) ? src[u] : T(0);
@@ -278,23 +274,27 @@ __global__ __launch_bounds__(NT) void k_gram_tile(
     }
   }
   if (active) {
-    T* dst = part + static_cast<int64_t>(split) * NG * I + t;
+    RSM_GLOBAL T* dst = static_cast<RSM_GLOBAL T*>(P.part) + static_cast<int64_t>(split) * NG * I + t;
 #pragma unroll
     for (int g = 0; g < NG; ++g) dst[static_cast<int64_t>(g) * I] = acc[g];
-    prow[static_cast<int64_t>(split) * I + t] = count;
+    P.prow[static_cast<int64_t>(split) * I + t] = count;
   }
 }
 
 template <int L, typename T>
-void run_tile(const Plan& P, const void* ycm, int64_t ldy, const uint64_t* wbits,
-              const int32_t* cols, void* part, int32_t* prow, hipStream_t s) {
+void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
   constexpr int NT = tile_threads(L, sizeof(T));
   constexpr int kVPC = kChunk / Vec16<T>::kN;
-  const int n = static_cast<int>(P.n);
-  const int n_pad = static_cast<int>(ceil_div(n, NT / kVPC) * (NT / kVPC));
-  const int m_pad = static_cast<int>(ceil_div(n, NT) * NT);
-  const size_t lds = static_cast<size_t>(n_pad) * TileStride<T>::kValue * sizeof(T) +
-                     static_cast<size_t>(m_pad) * sizeof(uint32_t);
+  size_t lds = 0;
+  int wgs = 0;
+  for (int k = 0; k < g.count; ++k) {
+    const int n = static_cast<int>(h[k]->n);
+    const int n_pad = static_cast<int>(ceil_div(n, NT / kVPC) * (NT / kVPC));
+    const int m_pad = static_cast<int>(ceil_div(n, NT) * NT);
+    lds = std::max(lds, static_cast<size_t>(n_pad) * TileStride<T>::kValue * sizeof(T) +
+                            static_cast<size_t>(m_pad) * sizeof(uint32_t));
+    wgs = std::max(wgs, h[k]->gram_wgs);
+  }
   static bool attr_set = false;  // dynamic LDS above 64 KiB must be allowed explicitly
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_tile<L, T, NT>),
@@ -302,60 +302,62 @@ void run_tile(const Plan& P, const void* ycm, int64_t ldy, const uint64_t* wbits
                               static_cast<int>(kTileLdsBytes + 8192));
     attr_set = true;
   }
-  const int64_t chunks = ceil_div(P.m, kChunk);
-  const int groups = static_cast<int>(ceil_div(P.I, NT));
-  const int xcd_map = (P.splits % 8 == 0) ? 1 : 0;
-  const unsigned grid = static_cast<unsigned>(groups) * static_cast<unsigned>(P.splits);
-  k_gram_tile<L, T, NT><<<grid, NT, lds, s>>>(
-      static_cast<const T*>(ycm), ldy, reinterpret_cast<const uint32_t*>(wbits), 2 * P.mw, P.m,
-      n, n_pad, m_pad, cols, P.I, 2 * P.words_per_split, chunks, groups, xcd_map,
-      static_cast<T*>(part), prow);
+  const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
+  k_gram_tile<L, T, NT><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
+}
+
+template <int L, typename TY, typename TA>
+void run_plain(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  int64_t I = 0;
+  int splits = 0;
+  for (int k = 0; k < g.count; ++k) {
+    I = std::max(I, h[k]->I);
+    splits = std::max(splits, h[k]->splits);
+  }
+  const dim3 grid(static_cast<unsigned>(ceil_div(I, 4)), static_cast<unsigned>(splits), g.count);
+  k_gram_plain<L, TY, TA><<<grid, 256, 0, s>>>(d, g);
 }
 
 template <int L>
-void dispatch_types(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
-                    const uint64_t* wbits, const int32_t* cols, void* part, int32_t* prow,
-                    hipStream_t s, bool tiled) {
+void dispatch_types(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  const Plan& P = *h[0];  // the group shares l, y_dtype, precision and kernel choice
   if (P.prec == RSM_GRAM_F64) {
-    if (y_dtype == RSM_F64 && tiled)
-      run_tile<L, double>(P, ycm, ldy, wbits, cols, part, prow, s);
-    else if (y_dtype == RSM_F32)
-      run_plain<L, float, double>(P, ycm, ldy, wbits, cols, part, prow, s);
+    if (P.y_dtype == RSM_F64 && P.tiled)
+      run_tile<L, double>(d, g, h, s);
+    else if (P.y_dtype == RSM_F32)
+      run_plain<L, float, double>(d, g, h, s);
     else
-      run_plain<L, double, double>(P, ycm, ldy, wbits, cols, part, prow, s);
+      run_plain<L, double, double>(d, g, h, s);
   } else {
-    if (y_dtype == RSM_F32 && tiled)
-      run_tile<L, float>(P, ycm, ldy, wbits, cols, part, prow, s);
-    else if (y_dtype == RSM_F32)
-      run_plain<L, float, float>(P, ycm, ldy, wbits, cols, part, prow, s);
+    if (P.y_dtype == RSM_F32 && P.tiled)
+      run_tile<L, float>(d, g, h, s);
+    else if (P.y_dtype == RSM_F32)
+      run_plain<L, float, float>(d, g, h, s);
     else
-      run_plain<L, double, float>(P, ycm, ldy, wbits, cols, part, prow, s);
+      run_plain<L, double, float>(d, g, h, s);
   }
 }
 
 }  // namespace
 
-bool gram_tiled_ok(const Plan& P, const void* ycm, int64_t ldy, int y_dtype) {
+bool gram_tiled_ok(const Plan& P, const void* ycm, int64_t ldy) {
   if (!P.tiled) return false;
-  const bool same = (P.prec == RSM_GRAM_F64) == (y_dtype == RSM_F64);
-  const size_t elem = (y_dtype == RSM_F64) ? 8 : 4;
+  const bool same = (P.prec == RSM_GRAM_F64) == (P.y_dtype == RSM_F64);
+  const size_t elem = (P.y_dtype == RSM_F64) ? 8 : 4;
   if (!same) return false;
-  const size_t stride = (y_dtype == RSM_F64) ? TileStride<double>::kValue : TileStride<float>::kValue;
+  const size_t stride = (P.y_dtype == RSM_F64) ? TileStride<double>::kValue : TileStride<float>::kValue;
   if (static_cast<size_t>(ceil_div(P.n, 64) * 64) * stride * elem > kTileLdsBytes) return false;
   if ((reinterpret_cast<uintptr_t>(ycm) % 16) != 0) return false;
   if ((static_cast<size_t>(ldy) * elem) % 16 != 0) return false;
   return true;
 }
 
-void launch_gram(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
-                 const uint64_t* wbits, const int32_t* cols, void* part, int32_t* prow,
-                 hipStream_t s) {
-  if (P.I == 0) return;
-  const bool tiled = gram_tiled_ok(P, ycm, ldy, y_dtype);
-  switch (P.l) {
+void launch_gram(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  if (!g.count) return;
+  switch (h[0]->l) {
 #define RSM_GRAM_CASE(LL) \
   case LL:                \
-    dispatch_types<LL>(P, ycm, ldy, y_dtype, wbits, cols, part, prow, s, tiled); \
+    dispatch_types<LL>(d, g, h, s); \
     break;
     RSM_GRAM_CASE(2) RSM_GRAM_CASE(3) RSM_GRAM_CASE(4) RSM_GRAM_CASE(5) RSM_GRAM_CASE(6)
     RSM_GRAM_CASE(7) RSM_GRAM_CASE(8) RSM_GRAM_CASE(9) RSM_GRAM_CASE(10) RSM_GRAM_CASE(11)

@@ -17,6 +17,7 @@
 //  For l <= 11 the matrix lives in registers (static indices) and the rotations are
 //  accumulated in a per-thread LDS slice laid out [entry][thread]; larger l keep both in
 //  LDS.
+#include <algorithm>
 #include <cmath>
 
 #include "device_util.hpp"
@@ -44,19 +45,21 @@ __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double a
 // ------------------------------------------------------------------ split reduction
 
 template <typename TA>
-__global__ void k_gram_reduce(const TA* __restrict__ part, const int32_t* __restrict__ prow,
-                              int64_t I, int ng, int splits, double* __restrict__ G,
-                              int32_t* __restrict__ rows) {
+__global__ void k_gram_reduce(const ProbDesc* __restrict__ probs, IdxList list) {
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t I = P.I;
+  const int ng = P.l * (P.l + 1) / 2, splits = P.splits;
+  auto part = static_cast<RSM_GLOBAL const TA*>(P.part);
   const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e < static_cast<int64_t>(ng) * I) {
     double sum = 0.0;
     for (int s = 0; s < splits; ++s) sum += static_cast<double>(part[static_cast<int64_t>(s) * ng * I + e]);
-    G[e] = sum;
+    P.G[e] = sum;
   }
   if (e < I) {
     int r = 0;
-    for (int s = 0; s < splits; ++s) r += prow[static_cast<int64_t>(s) * I + e];
-    rows[e] = r;
+    for (int s = 0; s < splits; ++s) r += P.prow[static_cast<int64_t>(s) * I + e];
+    P.rows[e] = r;
   }
 }
 
@@ -64,9 +67,9 @@ __global__ void k_gram_reduce(const TA* __restrict__ part, const int32_t* __rest
 // vv(i, k) entry i of eigenvector k.
 template <int L, typename EV, typename VV>
 __device__ __forceinline__ void finish_trial(int64_t t, int nvec, int64_t n, const int* c,
-                                             EV ev, VV vv, double* __restrict__ N,
-                                             double* __restrict__ tap_vecs,
-                                             double* __restrict__ tap_eigs) {
+                                             EV ev, VV vv, RSM_GLOBAL double* __restrict__ N,
+                                             RSM_GLOBAL double* __restrict__ tap_vecs,
+                                             RSM_GLOBAL double* __restrict__ tap_eigs) {
   int rank[L];
 #pragma unroll
   for (int k = 0; k < L; ++k) {
@@ -97,7 +100,7 @@ __device__ __forceinline__ void finish_trial(int64_t t, int nvec, int64_t n, con
 #pragma unroll
       for (int k = 0; k < L; ++k)
         if (rank[k] < nvec) pij += vv(i, k) * vv(j, k);
-      atomic_add_f64(&N[static_cast<int64_t>(c[i]) + static_cast<int64_t>(c[j]) * n], pij);
+      atomic_add_f64((double*)&N[static_cast<int64_t>(c[i]) + static_cast<int64_t>(c[j]) * n], pij);
     }
   }
 }
@@ -105,12 +108,20 @@ __device__ __forceinline__ void finish_trial(int64_t t, int nvec, int64_t n, con
 // ------------------------------------------------------------------ registers + LDS
 
 template <int L>
-__global__ __launch_bounds__(64) void k_minor_reg(
-    const double* __restrict__ G, const int32_t* __restrict__ rows_in,
-    const int32_t* __restrict__ cols, int64_t I, int nvec, int min_rows, int64_t n,
-    double* __restrict__ N, rsm_info* info, int32_t* __restrict__ tap_rows,
-    double* __restrict__ tap_gram, double* __restrict__ tap_vecs,
-    double* __restrict__ tap_eigs) {
+__global__ __launch_bounds__(64) void k_minor_reg(const ProbDesc* __restrict__ probs,
+                                                  IdxList list) {
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t I = P.I, n = P.n;
+  const int nvec = P.nvec, min_rows = P.min_rows;
+  RSM_GLOBAL const double* __restrict__ G = P.G;
+  RSM_GLOBAL const int32_t* __restrict__ rows_in = P.rows;
+  RSM_GLOBAL const int32_t* __restrict__ cols = P.cols;
+  RSM_GLOBAL double* __restrict__ N = P.N;
+  RSM_GLOBAL rsm_info* info = P.info;
+  RSM_GLOBAL int32_t* __restrict__ tap_rows = P.tap_rows;
+  RSM_GLOBAL double* __restrict__ tap_gram = P.tap_gram;
+  RSM_GLOBAL double* __restrict__ tap_vecs = P.tap_vecs;
+  RSM_GLOBAL double* __restrict__ tap_eigs = P.tap_eigs;
   constexpr int TPB = 64;
   constexpr int NG = L * (L + 1) / 2;
   __shared__ double Vs[L * L * TPB];
@@ -202,8 +213,8 @@ __global__ __launch_bounds__(64) void k_minor_reg(
   if (active) atomicAdd(&s_rows, static_cast<unsigned long long>(rows));
   __syncthreads();
   if (tid == 0) {
-    atomicAdd(reinterpret_cast<unsigned long long*>(&info->accepted), s_acc);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&info->rows_total), s_rows);
+    atomicAdd((unsigned long long*)&info->accepted, s_acc);
+    atomicAdd((unsigned long long*)&info->rows_total, s_rows);
   }
 }
 
@@ -217,11 +228,19 @@ struct MinorCfg {
 
 template <int L>
 __global__ __launch_bounds__(MinorCfg<L>::kThreads) void k_minor_lds(
-    const double* __restrict__ G, const int32_t* __restrict__ rows_in,
-    const int32_t* __restrict__ cols, int64_t I, int nvec, int min_rows, int64_t n,
-    double* __restrict__ N, rsm_info* info, int32_t* __restrict__ tap_rows,
-    double* __restrict__ tap_gram, double* __restrict__ tap_vecs,
-    double* __restrict__ tap_eigs) {
+    const ProbDesc* __restrict__ probs, IdxList list) {
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t I = P.I, n = P.n;
+  const int nvec = P.nvec, min_rows = P.min_rows;
+  RSM_GLOBAL const double* __restrict__ G = P.G;
+  RSM_GLOBAL const int32_t* __restrict__ rows_in = P.rows;
+  RSM_GLOBAL const int32_t* __restrict__ cols = P.cols;
+  RSM_GLOBAL double* __restrict__ N = P.N;
+  RSM_GLOBAL rsm_info* info = P.info;
+  RSM_GLOBAL int32_t* __restrict__ tap_rows = P.tap_rows;
+  RSM_GLOBAL double* __restrict__ tap_gram = P.tap_gram;
+  RSM_GLOBAL double* __restrict__ tap_vecs = P.tap_vecs;
+  RSM_GLOBAL double* __restrict__ tap_eigs = P.tap_eigs;
   constexpr int TPB = MinorCfg<L>::kThreads;
   extern __shared__ double smem[];
   __shared__ unsigned long long s_acc;
@@ -314,22 +333,19 @@ __global__ __launch_bounds__(MinorCfg<L>::kThreads) void k_minor_lds(
   if (active) atomicAdd(&s_rows, static_cast<unsigned long long>(rows));
   __syncthreads();
   if (tid == 0) {
-    atomicAdd(reinterpret_cast<unsigned long long*>(&info->accepted), s_acc);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&info->rows_total), s_rows);
+    atomicAdd((unsigned long long*)&info->accepted, s_acc);
+    atomicAdd((unsigned long long*)&info->rows_total, s_rows);
   }
 }
 
 template <int L>
-void run_minor(const Plan& P, const double* G, const int32_t* rows, const int32_t* cols,
-               double* N, rsm_info* info, const rsm_output& out, hipStream_t s) {
+void run_minor(const ProbDesc* d, const IdxList& g, int64_t I, hipStream_t s) {
   if constexpr (L <= kRegMaxL) {
-    const unsigned blocks = static_cast<unsigned>(ceil_div(P.I, 64));
-    k_minor_reg<L><<<blocks, 64, 0, s>>>(G, rows, cols, P.I, P.nvec, P.min_rows, P.n, N, info,
-                                         out.trial_rows, out.trial_gram, out.trial_vecs,
-                                         out.trial_eigs);
+    const unsigned blocks = static_cast<unsigned>(ceil_div(I, 64));
+    k_minor_reg<L><<<dim3(blocks, g.count), 64, 0, s>>>(d, g);
   } else {
     constexpr int TPB = MinorCfg<L>::kThreads;
-    const unsigned blocks = static_cast<unsigned>(ceil_div(P.I, TPB));
+    const unsigned blocks = static_cast<unsigned>(ceil_div(I, TPB));
     static bool attr_set = false;  // dynamic LDS above 64 KiB must be allowed explicitly
     if (!attr_set) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_minor_lds<L>),
@@ -337,30 +353,35 @@ void run_minor(const Plan& P, const double* G, const int32_t* rows, const int32_
                                 static_cast<int>(MinorCfg<L>::kLds));
       attr_set = true;
     }
-    k_minor_lds<L><<<blocks, TPB, MinorCfg<L>::kLds, s>>>(
-        G, rows, cols, P.I, P.nvec, P.min_rows, P.n, N, info, out.trial_rows, out.trial_gram,
-        out.trial_vecs, out.trial_eigs);
+    k_minor_lds<L><<<dim3(blocks, g.count), TPB, MinorCfg<L>::kLds, s>>>(d, g);
   }
 }
 
 }  // namespace
 
-void launch_minor(const Plan& P, const void* part, const int32_t* prow, const int32_t* cols,
-                  double* G, int32_t* rows, double* N, rsm_info* info, const rsm_output& out,
-                  hipStream_t s) {
-  if (P.I == 0) return;
-  const int64_t total = static_cast<int64_t>(P.ng) * P.I;
-  const unsigned gblocks = static_cast<unsigned>(ceil_div(total, 256));
-  if (P.part_elem == sizeof(double))
-    k_gram_reduce<double><<<gblocks, 256, 0, s>>>(static_cast<const double*>(part), prow, P.I,
-                                                  P.ng, P.splits, G, rows);
-  else
-    k_gram_reduce<float><<<gblocks, 256, 0, s>>>(static_cast<const float*>(part), prow, P.I,
-                                                 P.ng, P.splits, G, rows);
-  switch (P.l) {
+void launch_minor(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  // the group shares l; the partial-Gram element type follows the precision
+  IdxList sub[2];
+  int64_t I = 0, total[2] = {0, 0};
+  for (int k = 0; k < g.count; ++k) {
+    if (h[k]->I == 0) continue;
+    const int f = h[k]->part_elem == sizeof(double) ? 1 : 0;
+    sub[f].idx[sub[f].count++] = g.idx[k];
+    total[f] = std::max<int64_t>(total[f], static_cast<int64_t>(h[k]->ng) * h[k]->I);
+    I = std::max(I, h[k]->I);
+  }
+  if (sub[0].count)
+    k_gram_reduce<float><<<dim3(static_cast<unsigned>(ceil_div(total[0], 256)), sub[0].count), 256, 0, s>>>(d, sub[0]);
+  if (sub[1].count)
+    k_gram_reduce<double><<<dim3(static_cast<unsigned>(ceil_div(total[1], 256)), sub[1].count), 256, 0, s>>>(d, sub[1]);
+  IdxList all;
+  for (int f = 0; f < 2; ++f)
+    for (int k = 0; k < sub[f].count; ++k) all.idx[all.count++] = sub[f].idx[k];
+  if (!all.count) return;
+  switch (h[0]->l) {
 #define RSM_MINOR_CASE(LL) \
   case LL:                 \
-    run_minor<LL>(P, G, rows, cols, N, info, out, s); \
+    run_minor<LL>(d, all, I, s); \
     break;
     RSM_MINOR_CASE(2) RSM_MINOR_CASE(3) RSM_MINOR_CASE(4) RSM_MINOR_CASE(5)
     RSM_MINOR_CASE(6) RSM_MINOR_CASE(7) RSM_MINOR_CASE(8) RSM_MINOR_CASE(9)

@@ -4,6 +4,8 @@
 //    comparisons on W" of the paper's Section IV-A done 64 rows per instruction.
 //  * Y row-major -> column-major copy (Y is read in place when already column-major).
 //  * C_t for every trial: Philox4x64-10 + Floyd (or a caller-supplied list, validated).
+#include <algorithm>
+
 #include "device_util.hpp"
 #include "rsm_internal.hpp"
 
@@ -19,19 +21,20 @@ __device__ __forceinline__ uint32_t nonzero_bytes_to_bits(uint64_t x) {
   return static_cast<uint32_t>((t * 0x0102040810204080ull) >> 56);  // gather to bits 0..7
 }
 
-// Column-major W: one thread per (column, 64-row word).
-__global__ void k_pack_mask_colmajor(const uint8_t* __restrict__ W, int64_t ldw, int64_t m,
-                                     int64_t n, uint64_t* __restrict__ wbits, int64_t mw) {
+// Column-major W: one thread per (column, 64-row word) of problem list.idx[blockIdx.y].
+__global__ void k_pack_mask_colmajor(const ProbDesc* __restrict__ probs, IdxList list) {
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t m = P.m, n = P.n, mw = P.mw;
   const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gid >= n * mw) return;
   const int64_t j = gid / mw;
   const int64_t w = gid - j * mw;
   const int64_t i0 = w * 64;
-  const uint8_t* src = W + j * ldw + i0;
+  RSM_GLOBAL const uint8_t* src = P.W + j * P.ldw + i0;
   uint64_t word = 0;
   const bool full = (i0 + 64 <= m);
   if (full && ((reinterpret_cast<uintptr_t>(src) & 7u) == 0)) {
-    const uint64_t* s8 = reinterpret_cast<const uint64_t*>(src);
+    auto s8 = reinterpret_cast<RSM_GLOBAL const uint64_t*>(src);
 #pragma unroll
     for (int b = 0; b < 8; ++b)
       word |= static_cast<uint64_t>(nonzero_bytes_to_bits(s8[b])) << (8 * b);
@@ -40,21 +43,23 @@ __global__ void k_pack_mask_colmajor(const uint8_t* __restrict__ W, int64_t ldw,
     for (int64_t k = 0; k < cnt; ++k)
       if (src[k]) word |= 1ull << k;
   }
-  wbits[j * mw + w] = word;
+  P.wbits[j * mw + w] = word;
 }
 
 // Row-major W: a 64-row x 64-column byte tile through LDS, one thread per output word.
-__global__ __launch_bounds__(256) void k_pack_mask_rowmajor(const uint8_t* __restrict__ W,
-                                                            int64_t ldw, int64_t m, int64_t n,
-                                                            uint64_t* __restrict__ wbits,
-                                                            int64_t mw) {
+// Grid (row words, column tiles, problems).
+__global__ __launch_bounds__(256) void k_pack_mask_rowmajor(const ProbDesc* __restrict__ probs,
+                                                            IdxList list) {
   __shared__ uint8_t tile[64][65];
-  const int64_t w = blockIdx.x;          // row word
+  const ProbDesc& P = probs[list.idx[blockIdx.z]];
+  const int64_t m = P.m, n = P.n, mw = P.mw;
+  const int64_t w = blockIdx.x;  // row word
   const int64_t j0 = static_cast<int64_t>(blockIdx.y) * 64;
+  if (w >= mw || j0 >= n) return;
   for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
     const int rr = e / 64, cc = e % 64;
     const int64_t i = w * 64 + rr, j = j0 + cc;
-    tile[rr][cc] = (i < m && j < n) ? (W[i * ldw + j] != 0) : 0;
+    tile[rr][cc] = (i < m && j < n) ? (P.W[i * P.ldw + j] != 0) : 0;
   }
   __syncthreads();
   if (threadIdx.x < 64) {
@@ -62,69 +67,78 @@ __global__ __launch_bounds__(256) void k_pack_mask_rowmajor(const uint8_t* __res
     if (j < n) {
       uint64_t word = 0;
       for (int rr = 0; rr < 64; ++rr) word |= static_cast<uint64_t>(tile[rr][threadIdx.x]) << rr;
-      wbits[j * mw + w] = word;
+      P.wbits[j * mw + w] = word;
     }
   }
 }
 
 // Row-major Y -> column-major (same element type), 64 x 64 tiles through LDS.
+// Grid (row tiles, column tiles, problems).
 template <typename T>
-__global__ __launch_bounds__(256) void k_transpose(const T* __restrict__ src, int64_t lds_,
-                                                   int64_t m, int64_t n, T* __restrict__ dst,
-                                                   int64_t ldd) {
+__global__ __launch_bounds__(256) void k_transpose(const ProbDesc* __restrict__ probs,
+                                                   IdxList list) {
   __shared__ T tile[64][65];
+  const ProbDesc& P = probs[list.idx[blockIdx.z]];
+  const int64_t m = P.m, n = P.n;
   const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 64;
   const int64_t j0 = static_cast<int64_t>(blockIdx.y) * 64;
+  if (i0 >= m || j0 >= n) return;
+  auto src = static_cast<RSM_GLOBAL const T*>(P.Yin);
+  auto dst = static_cast<RSM_GLOBAL T*>(P.ycm);
   for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
     const int rr = e / 64, cc = e % 64;
     const int64_t i = i0 + rr, j = j0 + cc;
-    tile[rr][cc] = (i < m && j < n) ? src[i * lds_ + j] : T(0);
+    tile[rr][cc] = (i < m && j < n) ? src[i * P.ldy_in + j] : T(0);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
     const int cc = e / 64, rr = e % 64;
     const int64_t i = i0 + rr, j = j0 + cc;
-    if (i < m && j < n) dst[j * ldd + i] = tile[rr][cc];
+    if (i < m && j < n) dst[j * P.ldy + i] = tile[rr][cc];
   }
 }
 
-// C_t for t = t0 + k, k = 0..I-1: one thread per trial.
-__global__ void k_subsets(uint64_t seed, int64_t t0, int64_t I, int n, int l,
-                          int32_t* __restrict__ cols) {
+// C_t for t = t0 + k, k = 0..I-1: one thread per trial.  Caller-supplied subsets are
+// copied instead; an unsorted or out-of-range one is replaced by the marker -1 in its first
+// slot (the trial is then rejected) and reported.
+__global__ void k_subsets(const ProbDesc* __restrict__ probs, IdxList list) {
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
   const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= I) return;
+  if (k >= P.I) return;
+  const int n = static_cast<int>(P.n), l = P.l;
+  if (P.user_subsets) {
+    bool ok = true;
+    int prev = -1;
+    for (int a = 0; a < l; ++a) {
+      const int c = P.user_subsets[k * l + a];
+      ok &= (c > prev) && (c < n);
+      prev = c;
+    }
+    for (int a = 0; a < l; ++a) P.cols[k * l + a] = ok ? P.user_subsets[k * l + a] : -1;
+    if (!ok) atomicOr((uint32_t*)&P.info->warn, static_cast<uint32_t>(RSM_W_BAD_SUBSET));
+    return;
+  }
   int c[RSM_MAX_L];
-  draw_subset<RSM_MAX_L>(seed, static_cast<uint64_t>(t0 + k), n, l, c);
+  draw_subset<RSM_MAX_L>(P.seed, static_cast<uint64_t>(P.t0 + k), n, l, c);
 #pragma unroll
   for (int a = 0; a < RSM_MAX_L; ++a)
-    if (a < l) cols[k * l + a] = c[a];
+    if (a < l) P.cols[k * l + a] = c[a];
 }
 
-// Caller-supplied subsets: copied; an unsorted or out-of-range row is replaced by the
-// marker -1 in its first slot (the trial is then rejected) and reported.
-__global__ void k_subsets_user(const int32_t* __restrict__ user, int64_t I, int n, int l,
-                               int32_t* __restrict__ cols, rsm_info* info) {
-  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= I) return;
-  bool ok = true;
-  int prev = -1;
-  for (int a = 0; a < l; ++a) {
-    const int c = user[k * l + a];
-    ok &= (c > prev) && (c < n);
-    prev = c;
-  }
-  for (int a = 0; a < l; ++a) cols[k * l + a] = ok ? user[k * l + a] : -1;
-  if (!ok) atomicOr(&info->warn, static_cast<uint32_t>(RSM_W_BAD_SUBSET));
-}
-
-__global__ void k_fill_zero(double* __restrict__ x, int64_t count) {
+// N = 0 (unless the problem accumulates into a given N).  Grid (blocks, problems).
+__global__ void k_zero_N(const ProbDesc* __restrict__ probs, IdxList list) {
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t count = P.n * P.n;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
        i += stride)
-    x[i] = 0.0;
+    P.N[i] = 0.0;
 }
 
-__global__ void k_init_info(rsm_info* info, DevScalars* scal) {
+__global__ void k_init_info(const ProbDesc* __restrict__ probs, IdxList list) {
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  RSM_GLOBAL rsm_info* info = P.info;
+  RSM_GLOBAL DevScalars* scal = P.scal;
   if (threadIdx.x == 0) {
     info->warn = 0;
     info->uncovered = 0;
@@ -146,49 +160,93 @@ __global__ void k_init_info(rsm_info* info, DevScalars* scal) {
   if (threadIdx.x < RSM_MAX_R + 1) info->lambda[threadIdx.x] = 0.0;
 }
 
-}  // namespace
+struct ProbDescPack {
+  ProbDesc p[8];
+  int count;
+};
 
-void launch_init_info(rsm_info* info, DevScalars* scal, hipStream_t s) {
-  k_init_info<<<1, 64, 0, s>>>(info, scal);
+__global__ void k_put_prob_desc(ProbDescPack pack, ProbDesc* dst) {
+  if (static_cast<int>(threadIdx.x) < pack.count) dst[threadIdx.x] = pack.p[threadIdx.x];
 }
 
-void launch_pack_mask(const uint8_t* W, int layout, int64_t ldw, int64_t m, int64_t n,
-                      uint64_t* wbits, int64_t mw, hipStream_t s) {
-  if (layout == RSM_COL_MAJOR) {
-    const int64_t total = n * mw;
-    k_pack_mask_colmajor<<<static_cast<unsigned>(ceil_div(total, 256)), 256, 0, s>>>(
-        W, ldw, m, n, wbits, mw);
-  } else {
-    dim3 grid(static_cast<unsigned>(mw), static_cast<unsigned>(ceil_div(n, 64)));
-    k_pack_mask_rowmajor<<<grid, 256, 0, s>>>(W, ldw, m, n, wbits, mw);
+// Members of g whose plan satisfies `pred`, as a new list (plans in `hs`).
+template <typename F>
+IdxList select(const IdxList& g, const Plan* const* h, F pred, const Plan** hs) {
+  IdxList out;
+  for (int k = 0; k < g.count; ++k)
+    if (pred(*h[k])) {
+      hs[out.count] = h[k];
+      out.idx[out.count++] = g.idx[k];
+    }
+  return out;
+}
+
+}  // namespace
+
+void put_prob_descs(const ProbDesc* host, int count, ProbDesc* dev, hipStream_t s) {
+  for (int k0 = 0; k0 < count; k0 += 8) {
+    ProbDescPack pack;
+    pack.count = (count - k0) < 8 ? (count - k0) : 8;
+    for (int k = 0; k < pack.count; ++k) pack.p[k] = host[k0 + k];
+    k_put_prob_desc<<<1, 64, 0, s>>>(pack, dev + k0);
   }
 }
 
-void launch_pack_y(const void* Y, int dtype, int64_t ldy, int64_t m, int64_t n, void* ycm,
-                   int64_t ldc, hipStream_t s) {
-  dim3 grid(static_cast<unsigned>(ceil_div(m, 64)), static_cast<unsigned>(ceil_div(n, 64)));
-  if (dtype == RSM_F32)
-    k_transpose<float><<<grid, 256, 0, s>>>(static_cast<const float*>(Y), ldy, m, n,
-                                            static_cast<float*>(ycm), ldc);
-  else
-    k_transpose<double><<<grid, 256, 0, s>>>(static_cast<const double*>(Y), ldy, m, n,
-                                             static_cast<double*>(ycm), ldc);
+void launch_init_info(const ProbDesc* d, const IdxList& g, hipStream_t s) {
+  if (g.count) k_init_info<<<dim3(1, g.count), 64, 0, s>>>(d, g);
 }
 
-void launch_subsets(const Plan& P, const int32_t* user, int32_t* cols, rsm_info* info,
-                    hipStream_t s) {
-  if (P.I == 0) return;
-  const unsigned blocks = static_cast<unsigned>(ceil_div(P.I, 128));
-  if (user)
-    k_subsets_user<<<blocks, 128, 0, s>>>(user, P.I, static_cast<int>(P.n), P.l, cols, info);
-  else
-    k_subsets<<<blocks, 128, 0, s>>>(P.seed, P.t0, P.I, static_cast<int>(P.n), P.l, cols);
+void launch_pack(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  const Plan* hs[kLaunchMax];
+  const IdxList wc = select(g, h, [](const Plan& P) { return P.w_layout == RSM_COL_MAJOR; }, hs);
+  if (wc.count) {
+    int64_t words = 0;
+    for (int k = 0; k < wc.count; ++k) words = std::max<int64_t>(words, hs[k]->n * hs[k]->mw);
+    k_pack_mask_colmajor<<<dim3(static_cast<unsigned>(ceil_div(words, 256)), wc.count), 256, 0, s>>>(d, wc);
+  }
+  const IdxList wr = select(g, h, [](const Plan& P) { return P.w_layout == RSM_ROW_MAJOR; }, hs);
+  if (wr.count) {
+    int64_t mw = 0, nt = 0;
+    for (int k = 0; k < wr.count; ++k) {
+      mw = std::max<int64_t>(mw, hs[k]->mw);
+      nt = std::max<int64_t>(nt, ceil_div(hs[k]->n, 64));
+    }
+    k_pack_mask_rowmajor<<<dim3(static_cast<unsigned>(mw), static_cast<unsigned>(nt), wr.count), 256, 0, s>>>(d, wr);
+  }
+  for (int dt = RSM_F32; dt <= RSM_F64; ++dt) {
+    const IdxList yr = select(g, h, [dt](const Plan& P) {
+      return P.y_layout == RSM_ROW_MAJOR && P.y_dtype == dt; }, hs);
+    if (!yr.count) continue;
+    int64_t mt = 0, nt = 0;
+    for (int k = 0; k < yr.count; ++k) {
+      mt = std::max<int64_t>(mt, ceil_div(hs[k]->m, 64));
+      nt = std::max<int64_t>(nt, ceil_div(hs[k]->n, 64));
+    }
+    const dim3 grid(static_cast<unsigned>(mt), static_cast<unsigned>(nt), yr.count);
+    if (dt == RSM_F32)
+      k_transpose<float><<<grid, 256, 0, s>>>(d, yr);
+    else
+      k_transpose<double><<<grid, 256, 0, s>>>(d, yr);
+  }
 }
 
-void launch_fill_zero(double* x, int64_t count, hipStream_t s) {
-  if (count <= 0) return;
-  const int64_t blocks = ceil_div(count, 256);
-  k_fill_zero<<<static_cast<unsigned>(blocks < 4096 ? blocks : 4096), 256, 0, s>>>(x, count);
+void launch_subsets(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  const Plan* hs[kLaunchMax];
+  const IdxList gs = select(g, h, [](const Plan& P) {
+    return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0; }, hs);
+  if (gs.count) {
+    int64_t I = 0;
+    for (int k = 0; k < gs.count; ++k) I = std::max<int64_t>(I, hs[k]->I);
+    k_subsets<<<dim3(static_cast<unsigned>(ceil_div(I, 128)), gs.count), 128, 0, s>>>(d, gs);
+  }
+  const IdxList gz = select(g, h, [](const Plan& P) {
+    return !(P.flags & RSM_FINALIZE_ONLY) && !(P.flags & RSM_N_ACCUMULATE); }, hs);
+  if (gz.count) {
+    int64_t nn = 0;
+    for (int k = 0; k < gz.count; ++k) nn = std::max<int64_t>(nn, hs[k]->n * hs[k]->n);
+    const int64_t blocks = ceil_div(nn, 256);
+    k_zero_N<<<dim3(static_cast<unsigned>(blocks < 1024 ? blocks : 1024), gz.count), 256, 0, s>>>(d, gz);
+  }
 }
 
 }  // namespace rsm

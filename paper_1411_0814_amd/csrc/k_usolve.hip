@@ -8,6 +8,7 @@
 // counted as underdetermined.
 //
 // Also: the optional error of eq.(ep), e = (sum w)^-1/2 ||W o (Y - U V^T)||_F.
+#include <algorithm>
 #include <cmath>
 
 #include "device_util.hpp"
@@ -21,13 +22,17 @@ constexpr int kUChunk = 256;  // columns of V-hat per LDS stage
 constexpr int kUnroll = 4;    // columns whose loads are issued together
 
 template <int R, typename TY>
-__global__ __launch_bounds__(256) void k_usolve(const TY* __restrict__ Y, int64_t ldy,
-                                                const uint64_t* __restrict__ wbits, int64_t mw,
-                                                int64_t m, int64_t n,
-                                                const double* __restrict__ V,
-                                                double* __restrict__ U, rsm_info* info) {
+__global__ __launch_bounds__(256) void k_usolve(const ProbDesc* __restrict__ probs, IdxList list) {
   constexpr int NA = R * (R + 1) / 2;
   __shared__ double Vs[kUChunk * R];
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t m = P.m, n = P.n, mw = P.mw, ldy = P.ldy;
+  if (static_cast<int64_t>(blockIdx.x) * 256 >= m) return;
+  auto Y = static_cast<RSM_GLOBAL const TY*>(P.ycm);
+  RSM_GLOBAL const uint64_t* __restrict__ wbits = P.wbits;
+  RSM_GLOBAL const double* __restrict__ V = P.V;
+  RSM_GLOBAL double* __restrict__ U = P.U;
+  RSM_GLOBAL rsm_info* info = P.info;
   const int tid = threadIdx.x;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + tid;
   const bool active = i < m;
@@ -139,20 +144,23 @@ __global__ __launch_bounds__(256) void k_usolve(const TY* __restrict__ Y, int64_
   const unsigned long long known = wave_sum<unsigned long long>(active ? static_cast<unsigned long long>(cnt) : 0ull);
   if ((tid & 63) == 0) {
     if (under) {
-      atomicAdd(reinterpret_cast<unsigned long long*>(&info->rows_underdetermined), under);
-      atomicOr(&info->warn, static_cast<uint32_t>(RSM_W_ROWS_UNDERDETERMINED));
+      atomicAdd((unsigned long long*)&info->rows_underdetermined, under);
+      atomicOr((uint32_t*)&info->warn, static_cast<uint32_t>(RSM_W_ROWS_UNDERDETERMINED));
     }
-    if (known) atomicAdd(reinterpret_cast<unsigned long long*>(&info->known), known);
+    if (known) atomicAdd((unsigned long long*)&info->known, known);
   }
 }
 
 template <int R, typename TY>
-__global__ __launch_bounds__(256) void k_error(const TY* __restrict__ Y, int64_t ldy,
-                                               const uint64_t* __restrict__ wbits, int64_t mw,
-                                               int64_t m, int64_t n,
-                                               const double* __restrict__ U,
-                                               const double* __restrict__ V, DevScalars* scal) {
+__global__ __launch_bounds__(256) void k_error(const ProbDesc* __restrict__ probs, IdxList list) {
   __shared__ double Vs[kUChunk * R];
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t m = P.m, n = P.n, mw = P.mw, ldy = P.ldy;
+  if (static_cast<int64_t>(blockIdx.x) * 256 >= m) return;
+  auto Y = static_cast<RSM_GLOBAL const TY*>(P.ycm);
+  RSM_GLOBAL const uint64_t* __restrict__ wbits = P.wbits;
+  RSM_GLOBAL const double* __restrict__ V = P.V;
+  RSM_GLOBAL const double* __restrict__ U = P.U;
   const int tid = threadIdx.x;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + tid;
   const bool active = i < m;
@@ -184,41 +192,34 @@ __global__ __launch_bounds__(256) void k_error(const TY* __restrict__ Y, int64_t
     }
   }
   acc = wave_sum(acc);
-  if ((tid & 63) == 0) atomic_add_f64(&scal->err_acc, acc);
+  if ((tid & 63) == 0) atomic_add_f64((double*)&P.scal->err_acc, acc);
 }
 
-__global__ void k_error_finalize(const DevScalars* scal, rsm_info* info) {
+__global__ void k_error_finalize(const ProbDesc* __restrict__ probs, IdxList list) {
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
   if (threadIdx.x == 0) {
-    const double k = static_cast<double>(info->known);
-    info->e = k > 0.0 ? sqrt(scal->err_acc / k) : 0.0;
+    const double k = static_cast<double>(P.info->known);
+    P.info->e = k > 0.0 ? sqrt(P.scal->err_acc / k) : 0.0;
   }
 }
 
 template <int R>
-void run_usolve(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
-                const uint64_t* wbits, const double* V, double* U, rsm_info* info,
-                hipStream_t s) {
-  const unsigned blocks = static_cast<unsigned>(ceil_div(P.m, 256));
+void run_usolve(const ProbDesc* d, const IdxList& g, int64_t m, int y_dtype, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(ceil_div(m, 256)), g.count);
   if (y_dtype == RSM_F32)
-    k_usolve<R, float><<<blocks, 256, 0, s>>>(static_cast<const float*>(ycm), ldy, wbits, P.mw,
-                                              P.m, P.n, V, U, info);
+    k_usolve<R, float><<<grid, 256, 0, s>>>(d, g);
   else
-    k_usolve<R, double><<<blocks, 256, 0, s>>>(static_cast<const double*>(ycm), ldy, wbits,
-                                               P.mw, P.m, P.n, V, U, info);
+    k_usolve<R, double><<<grid, 256, 0, s>>>(d, g);
 }
 
 template <int R>
-void run_error(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
-               const uint64_t* wbits, const double* U, const double* V, DevScalars* scal,
-               rsm_info* info, hipStream_t s) {
-  const unsigned blocks = static_cast<unsigned>(ceil_div(P.m, 256));
+void run_error(const ProbDesc* d, const IdxList& g, int64_t m, int y_dtype, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(ceil_div(m, 256)), g.count);
   if (y_dtype == RSM_F32)
-    k_error<R, float><<<blocks, 256, 0, s>>>(static_cast<const float*>(ycm), ldy, wbits, P.mw,
-                                             P.m, P.n, U, V, scal);
+    k_error<R, float><<<grid, 256, 0, s>>>(d, g);
   else
-    k_error<R, double><<<blocks, 256, 0, s>>>(static_cast<const double*>(ycm), ldy, wbits,
-                                              P.mw, P.m, P.n, U, V, scal);
-  k_error_finalize<<<1, 64, 0, s>>>(scal, info);
+    k_error<R, double><<<grid, 256, 0, s>>>(d, g);
+  k_error_finalize<<<dim3(1, g.count), 64, 0, s>>>(d, g);
 }
 
 }  // namespace
@@ -226,13 +227,15 @@ void run_error(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
 #define RSM_R_CASES(X)                                                                 \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
-void launch_solve_u(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
-                    const uint64_t* wbits, const double* V, double* U, rsm_info* info,
-                    hipStream_t s) {
-  switch (P.r) {
+// The group shares r and the element type of Y.
+void launch_solve_u(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  if (!g.count) return;
+  int64_t m = 0;
+  for (int k = 0; k < g.count; ++k) m = std::max(m, h[k]->m);
+  switch (h[0]->r) {
 #define RSM_U_CASE(RR) \
   case RR:             \
-    run_usolve<RR>(P, ycm, ldy, y_dtype, wbits, V, U, info, s); \
+    run_usolve<RR>(d, g, m, h[0]->y_dtype, s); \
     break;
     RSM_R_CASES(RSM_U_CASE)
 #undef RSM_U_CASE
@@ -241,13 +244,14 @@ void launch_solve_u(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
   }
 }
 
-void launch_error(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
-                  const uint64_t* wbits, const double* U, const double* V, DevScalars* scal,
-                  rsm_info* info, hipStream_t s) {
-  switch (P.r) {
+void launch_error(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  if (!g.count) return;
+  int64_t m = 0;
+  for (int k = 0; k < g.count; ++k) m = std::max(m, h[k]->m);
+  switch (h[0]->r) {
 #define RSM_E_CASE(RR) \
   case RR:             \
-    run_error<RR>(P, ycm, ldy, y_dtype, wbits, U, V, scal, info, s); \
+    run_error<RR>(d, g, m, h[0]->y_dtype, s); \
     break;
     RSM_R_CASES(RSM_E_CASE)
 #undef RSM_E_CASE

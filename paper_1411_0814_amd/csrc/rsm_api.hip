@@ -1,6 +1,7 @@
 // The C ABI of librsm (include/rsm.h): argument validation, the execution plan and
 // workspace layout of each problem, and the launch sequence of steps a0..a7.
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "rsm_internal.hpp"
@@ -76,9 +77,9 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   P.tiled = !(p.flags & RSM_PLAIN_GRAM) &&
             static_cast<size_t>(ceil_div(p.n, 64) * 64) * tile_stride * acc_elem <= kTileLdsBytes;
   int64_t splits = 1;
+  int64_t groups = 1;
   if (P.tiled) {
-    const int64_t groups =
-        ceil_div(P.I > 0 ? P.I : 1, tile_threads(l, static_cast<int>(acc_elem)));
+    groups = ceil_div(P.I > 0 ? P.I : 1, tile_threads(l, static_cast<int>(acc_elem)));
     splits = kTileTargetGroups / groups;
     if (splits < 1) splits = 1;
     if (splits >= 8) splits -= splits % 8;  // whole XCD rounds (see k_gram_tile)
@@ -89,6 +90,8 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   P.words_per_split = ceil_div(P.mw, splits);
   // the splits actually needed to cover mw words (never more than requested)
   P.splits = static_cast<int>(ceil_div(P.mw, P.words_per_split));
+  P.gram_groups = static_cast<int>(groups);
+  P.gram_wgs = P.gram_groups * P.splits;
 
   // workspace layout
   size_t cur = 0;
@@ -153,47 +156,53 @@ void mark(const rsm_output& out, int step, int end, hipStream_t s) {
     (void)hipEventRecord(static_cast<hipEvent_t>(out.step_events[2 * step + end]), s);
 }
 
-// Steps a0..a5 of one problem whose scratch starts at `ws`.
-void enqueue_front(const Plan& P, const rsm_input& in, const rsm_output& out, void* ws,
-                   hipStream_t s) {
-  DevScalars* scal = at<DevScalars>(ws, P.off_scal);
-  uint64_t* wbits = at<uint64_t>(ws, P.off_wbits);
-  rsm_info* info = out.info;
-  double* N = out.N ? out.N : at<double>(ws, P.off_N);
-
-  launch_init_info(info, scal, s);
-
-  // a0: mask bit-planes, column-major Y
-  mark(out, RSM_STEP_PACK, 0, s);
-  launch_pack_mask(in.W, P.w_layout, in.ldw, P.m, P.n, wbits, P.mw, s);
-  if (P.y_layout == RSM_ROW_MAJOR)
-    launch_pack_y(in.Y, P.y_dtype, in.ldy, P.m, P.n, at<void>(ws, P.off_ypack), P.m, s);
-  mark(out, RSM_STEP_PACK, 1, s);
-
-  if (P.flags & RSM_FINALIZE_ONLY) return;
-  // a1: subsets
-  mark(out, RSM_STEP_SUBSETS, 0, s);
-  int32_t* cols = out.trial_cols ? out.trial_cols : at<int32_t>(ws, P.off_cols);
-  launch_subsets(P, in.subsets, cols, info, s);
-  if (!(P.flags & RSM_N_ACCUMULATE)) launch_fill_zero(N, P.n * P.n, s);
-  mark(out, RSM_STEP_SUBSETS, 1, s);
-  // a2 + a3: row qualification and Gram partials
-  void* part = at<void>(ws, P.off_part);
-  int32_t* prow = at<int32_t>(ws, P.off_prow);
-  mark(out, RSM_STEP_GRAM, 0, s);
-  launch_gram(P, ycm_of(P, in, ws), ldy_of(P, in), P.y_dtype, wbits, cols, part, prow, s);
-  mark(out, RSM_STEP_GRAM, 1, s);
-  // a4 + a5: minor vectors, N accumulation
-  mark(out, RSM_STEP_MINOR, 0, s);
-  launch_minor(P, part, prow, cols, at<double>(ws, P.off_G), at<int32_t>(ws, P.off_rows), N,
-               info, out, s);
-  mark(out, RSM_STEP_MINOR, 1, s);
-}
-
-// Device pointer as the descriptor types it (global memory in the device pass).
+// Device pointer as the descriptors type it (global memory in the device pass).
 template <typename T>
 RSM_GLOBAL T* gptr(T* p) {
   return (RSM_GLOBAL T*)p;
+}
+
+// Descriptor of steps a0..a5 and a7 of one problem.
+ProbDesc prob_desc(const Plan& P, const rsm_input& in, const rsm_output& out, void* ws) {
+  ProbDesc d{};
+  d.m = P.m;
+  d.n = P.n;
+  d.mw = P.mw;
+  d.I = P.I;
+  d.t0 = P.t0;
+  d.ldw = in.ldw;
+  d.ldy_in = in.ldy;
+  d.ldy = ldy_of(P, in);
+  d.r = P.r;
+  d.l = P.l;
+  d.nvec = P.nvec;
+  d.min_rows = P.min_rows;
+  d.y_layout = P.y_layout;
+  d.w_layout = P.w_layout;
+  d.splits = P.splits;
+  d.gram_groups = P.gram_groups;
+  d.words_per_split = P.words_per_split;
+  d.seed = P.seed;
+  d.W = gptr(in.W);
+  d.Yin = gptr(in.Y);
+  d.ycm = gptr(const_cast<void*>(ycm_of(P, in, ws)));
+  d.wbits = gptr(at<uint64_t>(ws, P.off_wbits));
+  d.user_subsets = gptr(in.subsets);
+  d.cols = gptr(out.trial_cols ? out.trial_cols : at<int32_t>(ws, P.off_cols));
+  d.part = gptr(at<void>(ws, P.off_part));
+  d.prow = gptr(at<int32_t>(ws, P.off_prow));
+  d.G = gptr(at<double>(ws, P.off_G));
+  d.rows = gptr(at<int32_t>(ws, P.off_rows));
+  d.N = gptr(out.N ? out.N : at<double>(ws, P.off_N));
+  d.V = gptr(out.V);
+  d.U = gptr(out.U);
+  d.info = gptr(out.info);
+  d.scal = gptr(at<DevScalars>(ws, P.off_scal));
+  d.tap_rows = gptr(out.trial_rows);
+  d.tap_gram = gptr(out.trial_gram);
+  d.tap_vecs = gptr(out.trial_vecs);
+  d.tap_eigs = gptr(out.trial_eigs);
+  return d;
 }
 
 // Descriptor of the a6 solve of one problem.
@@ -222,21 +231,29 @@ EigProb eig_desc(const Plan& P, const rsm_output& out, void* ws) {
   return e;
 }
 
-// Step a7 (and the optional error) of one problem.
-void enqueue_back(const Plan& P, const rsm_input& in, const rsm_output& out, void* ws,
-                  hipStream_t s) {
-  const uint64_t* wbits = at<uint64_t>(ws, P.off_wbits);
-  const void* ycm = ycm_of(P, in, ws);
-  const int64_t ldy = ldy_of(P, in);
-  mark(out, RSM_STEP_USOLVE, 0, s);
-  launch_solve_u(P, ycm, ldy, P.y_dtype, wbits, out.V, out.U, out.info, s);
-  mark(out, RSM_STEP_USOLVE, 1, s);
-  if (P.flags & RSM_COMPUTE_ERROR) {
-    mark(out, RSM_STEP_ERROR, 0, s);
-    launch_error(P, ycm, ldy, P.y_dtype, wbits, out.U, out.V, at<DevScalars>(ws, P.off_scal),
-                 out.info, s);
-    mark(out, RSM_STEP_ERROR, 1, s);
+// Calls fn(list, plans) for the problems selected by `take`, grouped by `key` (problems
+// with equal keys share launches), at most kLaunchMax per launch.
+template <typename Take, typename Key, typename Fn>
+void for_groups(const std::vector<Plan>& plans, Take take, Key key, Fn fn) {
+  std::map<int64_t, std::vector<int32_t>> groups;
+  for (int32_t k = 0; k < static_cast<int32_t>(plans.size()); ++k)
+    if (take(plans[k])) groups[key(plans[k])].push_back(k);
+  for (const auto& kv : groups) {
+    const std::vector<int32_t>& members = kv.second;
+    for (size_t b = 0; b < members.size(); b += kLaunchMax) {
+      IdxList g;
+      const Plan* h[kLaunchMax];
+      for (size_t k = b; k < members.size() && k < b + kLaunchMax; ++k) {
+        h[g.count] = &plans[members[k]];
+        g.idx[g.count++] = members[k];
+      }
+      fn(g, h);
+    }
   }
+}
+
+void mark_all(const rsm_output* outs, const IdxList& g, int step, int end, hipStream_t s) {
+  for (int k = 0; k < g.count; ++k) mark(outs[g.idx[k]], step, end, s);
 }
 
 }  // namespace
@@ -267,7 +284,8 @@ const char* rsm_status_string(int32_t status) {
 // The workspace of a call: each problem's scratch (256-byte aligned, in order), then the
 // device copies of the a6 descriptors of all problems.
 static size_t desc_bytes(int32_t nprob) {
-  return rsm::align_up(static_cast<size_t>(nprob) * sizeof(rsm::EigProb), 256);
+  return rsm::align_up(static_cast<size_t>(nprob) * sizeof(rsm::ProbDesc), 256) +
+         rsm::align_up(static_cast<size_t>(nprob) * sizeof(rsm::EigProb), 256);
 }
 
 int32_t rsm_workspace_bytes(const rsm_problem* problems, int32_t nprob, size_t* bytes) {
@@ -291,16 +309,17 @@ int32_t rsm_decompose(const rsm_problem* p, const rsm_input* in, const rsm_outpu
 int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
                               const rsm_input* inputs, const rsm_output* outputs,
                               void* workspace, size_t ws_bytes, void* hip_stream) {
+  using namespace rsm;
   if (nprob < 1 || !problems || !inputs || !outputs) return RSM_E_ARG;
   size_t need = 0;
-  std::vector<rsm::Plan> plans(static_cast<size_t>(nprob));
+  std::vector<Plan> plans(static_cast<size_t>(nprob));
   std::vector<size_t> base(static_cast<size_t>(nprob));
   for (int32_t k = 0; k < nprob; ++k) {
-    int32_t st = rsm::make_plan(problems[k], plans[k]);
-    if (st == RSM_OK) st = rsm::check_io(plans[k], inputs[k], outputs[k]);
+    int32_t st = make_plan(problems[k], plans[k]);
+    if (st == RSM_OK) st = check_io(plans[k], inputs[k], outputs[k]);
     if (st != RSM_OK) return st;
     base[k] = need;
-    need += rsm::align_up(plans[k].total, 256);
+    need += align_up(plans[k].total, 256);
   }
   const size_t desc_off = need;
   need += desc_bytes(nprob);
@@ -309,23 +328,80 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   (void)hipGetLastError();  // clear a stale error from unrelated earlier work
   char* ws = static_cast<char*>(workspace);
-  for (int32_t k = 0; k < nprob; ++k)
-    rsm::enqueue_front(plans[k], inputs[k], outputs[k], ws + base[k], s);
+  auto* dprob = reinterpret_cast<ProbDesc*>(ws + desc_off);
+  auto* deig = reinterpret_cast<EigProb*>(ws + desc_off + align_up(static_cast<size_t>(nprob) * sizeof(ProbDesc), 256));
+
+  std::vector<ProbDesc> hp(static_cast<size_t>(nprob));
+  for (int32_t k = 0; k < nprob; ++k) {
+    Plan& P = plans[k];
+    P.tiled = gram_tiled_ok(P, ycm_of(P, inputs[k], ws + base[k]), ldy_of(P, inputs[k]));
+    hp[k] = prob_desc(P, inputs[k], outputs[k], ws + base[k]);
+  }
+  put_prob_descs(hp.data(), nprob, dprob, s);
+
+  auto all = [](const Plan&) { return true; };
+  auto front = [](const Plan& P) { return !(P.flags & RSM_FINALIZE_ONLY); };
+  auto one_key = [](const Plan&) { return int64_t(0); };
+  // a0: info, mask bit-planes, column-major Y
+  for_groups(plans, all, one_key, [&](const IdxList& g, const Plan* const* h) {
+    launch_init_info(dprob, g, s);
+    mark_all(outputs, g, RSM_STEP_PACK, 0, s);
+    launch_pack(dprob, g, h, s);
+    mark_all(outputs, g, RSM_STEP_PACK, 1, s);
+  });
+  // a1: subsets, N cleared
+  for_groups(plans, front, one_key, [&](const IdxList& g, const Plan* const* h) {
+    mark_all(outputs, g, RSM_STEP_SUBSETS, 0, s);
+    launch_subsets(dprob, g, h, s);
+    mark_all(outputs, g, RSM_STEP_SUBSETS, 1, s);
+  });
+  // a2 + a3: one launch per (l, element type, precision, kernel)
+  for_groups(plans, [](const Plan& P) { return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0; },
+             [](const Plan& P) {
+               return int64_t(P.l) * 64 + P.y_dtype * 16 + P.prec * 2 + (P.tiled ? 1 : 0);
+             },
+             [&](const IdxList& g, const Plan* const* h) {
+               mark_all(outputs, g, RSM_STEP_GRAM, 0, s);
+               launch_gram(dprob, g, h, s);
+               mark_all(outputs, g, RSM_STEP_GRAM, 1, s);
+             });
+  // a4 + a5: one launch per l
+  for_groups(plans, front, [](const Plan& P) { return int64_t(P.l); },
+             [&](const IdxList& g, const Plan* const* h) {
+               mark_all(outputs, g, RSM_STEP_MINOR, 0, s);
+               launch_minor(dprob, g, h, s);
+               mark_all(outputs, g, RSM_STEP_MINOR, 1, s);
+             });
   // a6 for every problem that finalises, in shared launches
-  std::vector<rsm::EigProb> eig;
+  std::vector<EigProb> eig;
+  IdxList fin;
   std::vector<int32_t> who;
   for (int32_t k = 0; k < nprob; ++k) {
     if (plans[k].flags & RSM_ACCUMULATE_ONLY) continue;
-    eig.push_back(rsm::eig_desc(plans[k], outputs[k], ws + base[k]));
+    eig.push_back(eig_desc(plans[k], outputs[k], ws + base[k]));
     who.push_back(k);
   }
   if (!eig.empty()) {
-    for (int32_t k : who) rsm::mark(outputs[k], RSM_STEP_EIG, 0, s);
-    rsm::launch_solve_v(eig.data(), static_cast<int>(eig.size()),
-                        reinterpret_cast<rsm::EigProb*>(ws + desc_off), s);
-    for (int32_t k : who) rsm::mark(outputs[k], RSM_STEP_EIG, 1, s);
-    for (int32_t k : who) rsm::enqueue_back(plans[k], inputs[k], outputs[k], ws + base[k], s);
+    for (int32_t k : who) mark(outputs[k], RSM_STEP_EIG, 0, s);
+    launch_solve_v(eig.data(), static_cast<int>(eig.size()), deig, s);
+    for (int32_t k : who) mark(outputs[k], RSM_STEP_EIG, 1, s);
   }
+  // a7 (and the optional error): one launch per (r, element type)
+  auto back = [](const Plan& P) { return !(P.flags & RSM_ACCUMULATE_ONLY); };
+  auto ukey = [](const Plan& P) { return int64_t(P.r) * 4 + P.y_dtype; };
+  for_groups(plans, back, ukey, [&](const IdxList& g, const Plan* const* h) {
+    mark_all(outputs, g, RSM_STEP_USOLVE, 0, s);
+    launch_solve_u(dprob, g, h, s);
+    mark_all(outputs, g, RSM_STEP_USOLVE, 1, s);
+  });
+  for_groups(plans, [](const Plan& P) {
+               return !(P.flags & RSM_ACCUMULATE_ONLY) && (P.flags & RSM_COMPUTE_ERROR);
+             }, ukey,
+             [&](const IdxList& g, const Plan* const* h) {
+               mark_all(outputs, g, RSM_STEP_ERROR, 0, s);
+               launch_error(dprob, g, h, s);
+               mark_all(outputs, g, RSM_STEP_ERROR, 1, s);
+             });
   return hipGetLastError() == hipSuccess ? RSM_OK : RSM_E_DEVICE;
 }
 

@@ -9,6 +9,14 @@
 
 #include "rsm.h"
 
+// In the device pass the descriptors' pointers are typed as global memory, so accesses
+// through them compile to global (not flat) instructions; the layout is the same.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define RSM_GLOBAL __attribute__((address_space(1)))
+#else
+#define RSM_GLOBAL
+#endif
+
 namespace rsm {
 
 constexpr int kWave = 64;                 // CDNA wavefront width
@@ -57,6 +65,8 @@ struct Plan {
   int nb = 0;            // Cholesky tiles per dimension
   int64_t npad = 0;      // 64 x (nb rounded up to a power of two): size of L^{-1}
   size_t part_elem = 4;  // bytes of one partial-Gram element
+  int gram_groups = 0;   // tiled Gram: trial groups (workgroups per row split)
+  int gram_wgs = 0;      // workgroups of the Gram step of this problem
   // workspace offsets (bytes from the workspace base); ~0 = unused
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
          off_rows = 0;
@@ -78,14 +88,6 @@ constexpr int kSmallDoubles = 2 * kEigMaxB * kEigMaxB + 2 * kEigMaxB;
 // Device-side description of one V-hat solve (step a6).  The solver's kernels take an array
 // of these and run every problem of a batch in the same launch (problem = blockIdx.y); each
 // workgroup reads its problem's sizes and buffers from here.
-// In the device pass the descriptor's pointers are typed as global memory, so accesses
-// through them compile to global (not flat) instructions; the layout is the same.
-#if defined(__HIP_DEVICE_COMPILE__)
-#define RSM_GLOBAL __attribute__((address_space(1)))
-#else
-#define RSM_GLOBAL
-#endif
-
 struct EigProb {
   int64_t n;             // order of N
   int64_t npad;          // order of M = L^{-1}: 64 x (tiles rounded up to a power of two)
@@ -109,32 +111,70 @@ struct EigProb {
   RSM_GLOBAL rsm_info* info;
 };
 
+// Device-side description of one problem for steps a0..a5 and a7 (problem index =
+// blockIdx.y or .z of a launch, through an IdxList).
+struct ProbDesc {
+  int64_t m, n, mw, I, t0;
+  int64_t ldw;           // caller's mask leading dimension
+  int64_t ldy_in;        // caller's Y leading dimension
+  int64_t ldy;           // leading dimension of the column-major Y the kernels read
+  int32_t r, l, nvec, min_rows;
+  int32_t y_layout, w_layout, splits, gram_groups;
+  int64_t words_per_split;
+  uint64_t seed;
+  RSM_GLOBAL const uint8_t* W;
+  RSM_GLOBAL const void* Yin;  // caller's Y
+  RSM_GLOBAL void* ycm;        // column-major Y (the caller's, or the packed copy)
+  RSM_GLOBAL uint64_t* wbits;
+  RSM_GLOBAL const int32_t* user_subsets;
+  RSM_GLOBAL int32_t* cols;
+  RSM_GLOBAL void* part;
+  RSM_GLOBAL int32_t* prow;
+  RSM_GLOBAL double* G;
+  RSM_GLOBAL int32_t* rows;
+  RSM_GLOBAL double* N;
+  RSM_GLOBAL double* V;
+  RSM_GLOBAL double* U;
+  RSM_GLOBAL rsm_info* info;
+  RSM_GLOBAL DevScalars* scal;
+  RSM_GLOBAL int32_t* tap_rows;
+  RSM_GLOBAL double* tap_gram;
+  RSM_GLOBAL double* tap_vecs;
+  RSM_GLOBAL double* tap_eigs;
+};
+
+// The problems of one launch: indices into a device ProbDesc array, passed by value.
+constexpr int kLaunchMax = 256;
+struct IdxList {
+  int32_t count = 0;
+  int32_t idx[kLaunchMax];
+};
+
 // Fills `plan` from `p` (defaults resolved, sizes checked).  Returns RSM_OK or an error.
 int32_t make_plan(const rsm_problem& p, Plan& plan);
 
-// Host launchers (each enqueues on `s`; errors surface through hipGetLastError).
-void launch_init_info(rsm_info* info, DevScalars* scal, hipStream_t s);
-void launch_pack_mask(const uint8_t* W, int layout, int64_t ldw, int64_t m, int64_t n,
-                      uint64_t* wbits, int64_t mw, hipStream_t s);
-void launch_pack_y(const void* Y, int dtype, int64_t ldy, int64_t m, int64_t n, void* ycm,
-                   int64_t ldc, hipStream_t s);
-void launch_subsets(const Plan& P, const int32_t* user, int32_t* cols, rsm_info* info,
-                    hipStream_t s);
-void launch_fill_zero(double* x, int64_t count, hipStream_t s);
-void launch_gram(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
-                 const uint64_t* wbits, const int32_t* cols, void* part, int32_t* prow,
-                 hipStream_t s);
-void launch_minor(const Plan& P, const void* part, const int32_t* prow, const int32_t* cols,
-                  double* G, int32_t* rows, double* N, rsm_info* info, const rsm_output& out,
-                  hipStream_t s);
+// Host launchers.  Each enqueues on `s` one launch (or one per storage layout) for every
+// problem in `g`; `d` is the device descriptor array and `h[k]` the plan of problem
+// g.idx[k].  Launchers that instantiate a kernel per l or r require the group to share it.
+// Errors surface through hipGetLastError.
+void launch_init_info(const ProbDesc* d, const IdxList& g, hipStream_t s);
+void launch_pack(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
+void launch_subsets(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
+void launch_gram(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
+void launch_minor(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
+void launch_solve_u(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
+void launch_error(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
+
+// Whether the LDS-tiled Gram kernel can run this problem with Y at `ycm` (its eligibility,
+// matching element types, 16-byte alignment of Y and of its columns).
+bool gram_tiled_ok(const Plan& P, const void* ycm, int64_t ldy);
+
 // V-hat of `nprob` problems in the same launches.  `host` holds their descriptors on the
 // host; `dev` is device memory for nprob descriptors (filled here, on the stream).
 void launch_solve_v(const EigProb* host, int nprob, EigProb* dev, hipStream_t s);
-void launch_solve_u(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
-                    const uint64_t* wbits, const double* V, double* U, rsm_info* info,
-                    hipStream_t s);
-void launch_error(const Plan& P, const void* ycm, int64_t ldy, int y_dtype,
-                  const uint64_t* wbits, const double* U, const double* V, DevScalars* scal,
-                  rsm_info* info, hipStream_t s);
+
+// Copies `count` descriptors from the host to device memory `dev` on the stream (kernel
+// arguments carry them; no host-to-device copy engine call).
+void put_prob_descs(const ProbDesc* host, int count, ProbDesc* dev, hipStream_t s);
 
 }  // namespace rsm

@@ -1,0 +1,175 @@
+"""Serving RSM decompositions on one GPU with continuous batching.
+
+Requests arrive over time (each names a device-resident input of a pool and carries its
+own RSM seed).  The server admits waiting requests while their HBM footprint (workspace
+with N and the solver's matrices, plus the factors U-hat and V-hat) fits the budget, and
+launches every admitted group as one batched library call on one of several streams.
+Requests that arrive while batches run are admitted as soon as memory and a stream free
+up, so their work overlaps on the device with the batches still running.  Inputs (Y, W)
+stay resident for the whole run; each request's factors stay on the device in its result.
+
+`batching=False, max_inflight=1` serves the same trace first-in first-out one request at
+a time through the single-problem call: the plain baseline.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import Request, _lib, _problem, decompose, decompose_batched
+
+
+@dataclass
+class Job:
+    """One request of a trace."""
+    rid: int
+    arrival: float          # seconds from the start of the trace
+    item: int               # index into the server's input pool
+    seed: int               # this request's RSM seed
+    start: float = math.nan
+    done: float = math.nan
+    result: object = None
+
+
+def poisson_trace(n_items: int, qps: float, seconds: float, seed: int) -> list[Job]:
+    """Arrivals of a Poisson process of rate qps over `seconds`, uniform over the pool, with
+    a per-request seed."""
+    rng = np.random.default_rng(seed)
+    jobs, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / qps)
+        if t >= seconds:
+            break
+        jobs.append(Job(rid=len(jobs), arrival=t, item=int(rng.integers(n_items)),
+                        seed=int(rng.integers(0, 2**62))))
+    return jobs
+
+
+@dataclass
+class PoolItem:
+    """A device-resident input and its decomposition parameters."""
+    Y: object
+    W: object
+    r: int
+    num_submatrices: int
+    l: int = 0
+    gram: str = "f32"
+    footprint: int = field(default=0)   # bytes per request (filled by the server)
+
+
+class Server:
+    def __init__(self, pool: list[PoolItem], *, budget_bytes: int = 16 << 30,
+                 max_batch: int = 256, max_inflight: int = 3, batching: bool = True,
+                 keep_results: bool = False):
+        import torch
+        self.torch = torch
+        self.pool = pool
+        self.budget = int(budget_bytes)
+        self.max_batch = int(max_batch) if batching else 1
+        self.max_inflight = int(max_inflight)
+        self.batching = batching
+        self.keep = keep_results
+        self.device = pool[0].Y.device
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(self.max_inflight)]
+        for it in pool:
+            it.footprint = self._footprint(it)
+            if it.footprint > self.budget:
+                raise ValueError("a pool item does not fit the memory budget alone")
+
+    def _request(self, job: Job) -> Request:
+        it = self.pool[job.item]
+        return Request(Y=it.Y, W=it.W, r=it.r, num_submatrices=it.num_submatrices,
+                       seed=job.seed, l=it.l, gram=it.gram)
+
+    def _footprint(self, it: PoolItem) -> int:
+        req = Request(Y=it.Y, W=it.W, r=it.r, num_submatrices=it.num_submatrices, seed=0,
+                      l=it.l, gram=it.gram)
+        m, n = it.Y.shape
+        return (_lib.workspace_bytes([_problem(req)]) + 8 * it.r * (m + n) + 4096)
+
+    def run(self, jobs: list[Job], time_limit: float | None = None) -> dict:
+        """Serve `jobs` (sorted by arrival) in real time; returns latency / throughput
+        statistics.  Stops admitting new work after time_limit seconds (if given)."""
+        torch = self.torch
+        pending = deque(sorted(jobs, key=lambda j: j.arrival))
+        waiting: deque[Job] = deque()
+        inflight = []            # [event, jobs, bytes, stream index]
+        free_streams = list(range(self.max_inflight))
+        used = 0
+        batches = 0
+        batch_sizes = []
+        peak_used = 0
+        t0 = time.perf_counter()
+        while pending or waiting or inflight:
+            now = time.perf_counter() - t0
+            if time_limit is not None and now > time_limit and not inflight:
+                break
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            progressed = False
+            for entry in list(inflight):
+                ev, group, nbytes, si = entry
+                if ev.query():
+                    t = time.perf_counter() - t0
+                    for j in group:
+                        j.done = t
+                        if not self.keep:
+                            j.result = None
+                    used -= nbytes
+                    free_streams.append(si)
+                    inflight.remove(entry)
+                    progressed = True
+            admit = time_limit is None or now <= time_limit
+            while admit and waiting and free_streams:
+                group, nbytes = [], 0
+                while waiting and len(group) < self.max_batch:
+                    f = self.pool[waiting[0].item].footprint
+                    if used + nbytes + f > self.budget:
+                        break
+                    group.append(waiting.popleft())
+                    nbytes += f
+                if not group:
+                    break
+                si = free_streams.pop()
+                st = self.streams[si]
+                with torch.cuda.stream(st):
+                    reqs = [self._request(j) for j in group]
+                    if self.batching:
+                        results = decompose_batched(reqs, stream=st)
+                    else:
+                        results = [decompose(q.Y, q.W, q.r, q.num_submatrices, q.seed, l=q.l,
+                                             gram=q.gram, stream=st) for q in reqs]
+                    ev = torch.cuda.Event()
+                    ev.record(st)
+                t = time.perf_counter() - t0
+                for j, res in zip(group, results):
+                    j.start = t
+                    j.result = res
+                used += nbytes
+                peak_used = max(peak_used, used)
+                inflight.append([ev, group, nbytes, si])
+                batches += 1
+                batch_sizes.append(len(group))
+                progressed = True
+            if not progressed:
+                # nothing to do until the next arrival or completion
+                time.sleep(20e-6)
+        done = [j for j in jobs if not math.isnan(j.done)]
+        lat = np.array([j.done - j.arrival for j in done]) if done else np.zeros(1)
+        span = (max(j.done for j in done) - min(j.arrival for j in done)) if done else 0.0
+        return {
+            "requests": len(jobs),
+            "completed": len(done),
+            "throughput_per_s": len(done) / span if span > 0 else 0.0,
+            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                           "p99": float(np.percentile(lat, 99) * 1e3),
+                           "mean": float(lat.mean() * 1e3)},
+            "batches": batches,
+            "mean_batch": float(np.mean(batch_sizes)) if batch_sizes else 0.0,
+            "peak_bytes": int(peak_used),
+            "budget_bytes": self.budget,
+        }

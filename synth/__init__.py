@@ -165,6 +165,22 @@ def batched_problem(spec: dict, gram: str = "f32") -> Problem:
                            name=f"batched {spec['m']}x{spec['n']} r{spec['r']}")
 
 
+def batched_device(spec: dict, device="cuda"):
+    """The same recipe drawn on the device (torch's generator seeded with spec["seed"]):
+    U (m x r), V (n x r) iid N(0,1) in FP32, Y = fl32(U V^T) formed in FP64, W iid
+    Bernoulli(rho).  Returns (Y, W) as column-major (m, n) views.  For workloads too large
+    to draw on the host in seconds; the values differ from batched_problem's."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(spec["seed"]))
+    m, n, r, rho = spec["m"], spec["n"], spec["r"], spec["rho"]
+    U = torch.randn(m, r, generator=g, device=device, dtype=torch.float32)
+    V = torch.randn(n, r, generator=g, device=device, dtype=torch.float32)
+    Yt = (V.double() @ U.double().T).float()                 # (n, m): Y column-major
+    Wt = torch.rand(n, m, generator=g, device=device) < rho
+    return Yt.T, Wt.T
+
+
 # The paper's Table I rows: (m, n, rho, sigma); r = 3, l = 4 (Section V-A).
 TABLE1_ROWS = [
     (65536, 1024, 0.2, 0.2), (98304, 1024, 0.2, 0.2), (131072, 1024, 0.2, 0.2),
