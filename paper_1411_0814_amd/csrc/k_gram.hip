@@ -128,7 +128,9 @@ struct Vec16<double> {
   static constexpr int kN = 2;
 };
 
-template <int L, typename T, int NT>
+// VEC: Y and its leading dimension are 16-byte aligned, so a chunk column is moved as
+// 16-byte vectors; otherwise element by element (same layout in LDS).
+template <int L, typename T, int NT, bool VEC>
 __global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ probs,
                                                   IdxList list) {
   constexpr int NG = L * (L + 1) / 2;
@@ -203,12 +205,26 @@ __global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ p
   uint32_t mreg[kMaxM];
   auto load_chunk = [&](int64_t ch) {
     const int64_t r0 = ch * kChunk;
-    if (r0 + kChunk <= m) {
+    if (VEC && r0 + kChunk <= m) {
 #pragma unroll
       for (int k = 0; k < kMaxV; ++k) {
         if (k < kv) {
           const int c = min(c0 + k * (NT / kVPC), n - 1);
           vreg[k] = *reinterpret_cast<RSM_GLOBAL const V*>(Y + static_cast<int64_t>(c) * ldy + r0 + vpart);
+        }
+      }
+    } else if (r0 + kChunk <= m) {  // unaligned columns: element loads, all issued first
+#pragma unroll
+      for (int k = 0; k < kMaxV; ++k) {
+        if (k < kv) {
+          const int c = min(c0 + k * (NT / kVPC), n - 1);
+          RSM_GLOBAL const T* src = Y + static_cast<int64_t>(c) * ldy + r0 + vpart;
+          T tmp[kVN];
+#pragma unroll
+          for (int u = 0; u < kVN; ++u) tmp[u] = src[u];
+          V v;
+          __builtin_memcpy(&v, tmp, sizeof(V));
+          vreg[k] = v;
         }
       }
     } else {  // ragged last chunk: rows past m read as zero
@@ -281,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ p
   }
 }
 
-template <int L, typename T>
+template <int L, typename T, bool VEC>
 void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
   constexpr int NT = tile_threads(L, sizeof(T));
   constexpr int kVPC = kChunk / Vec16<T>::kN;
@@ -297,13 +313,13 @@ void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStre
   }
   static bool attr_set = false;  // dynamic LDS above 64 KiB must be allowed explicitly
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_tile<L, T, NT>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_tile<L, T, NT, VEC>),
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               static_cast<int>(kTileLdsBytes + 8192));
     attr_set = true;
   }
   const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
-  k_gram_tile<L, T, NT><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
+  k_gram_tile<L, T, NT, VEC><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
 }
 
 template <int L, typename TY, typename TA>
@@ -323,14 +339,14 @@ void dispatch_types(const ProbDesc* d, const IdxList& g, const Plan* const* h, h
   const Plan& P = *h[0];  // the group shares l, y_dtype, precision and kernel choice
   if (P.prec == RSM_GRAM_F64) {
     if (P.y_dtype == RSM_F64 && P.tiled)
-      run_tile<L, double>(d, g, h, s);
+      P.gram_vec ? run_tile<L, double, true>(d, g, h, s) : run_tile<L, double, false>(d, g, h, s);
     else if (P.y_dtype == RSM_F32)
       run_plain<L, float, double>(d, g, h, s);
     else
       run_plain<L, double, double>(d, g, h, s);
   } else {
     if (P.y_dtype == RSM_F32 && P.tiled)
-      run_tile<L, float>(d, g, h, s);
+      P.gram_vec ? run_tile<L, float, true>(d, g, h, s) : run_tile<L, float, false>(d, g, h, s);
     else if (P.y_dtype == RSM_F32)
       run_plain<L, float, float>(d, g, h, s);
     else
@@ -340,16 +356,18 @@ void dispatch_types(const ProbDesc* d, const IdxList& g, const Plan* const* h, h
 
 }  // namespace
 
-bool gram_tiled_ok(const Plan& P, const void* ycm, int64_t ldy) {
+bool gram_tiled_ok(const Plan& P) {
   if (!P.tiled) return false;
   const bool same = (P.prec == RSM_GRAM_F64) == (P.y_dtype == RSM_F64);
   const size_t elem = (P.y_dtype == RSM_F64) ? 8 : 4;
   if (!same) return false;
   const size_t stride = (P.y_dtype == RSM_F64) ? TileStride<double>::kValue : TileStride<float>::kValue;
-  if (static_cast<size_t>(ceil_div(P.n, 64) * 64) * stride * elem > kTileLdsBytes) return false;
-  if ((reinterpret_cast<uintptr_t>(ycm) % 16) != 0) return false;
-  if ((static_cast<size_t>(ldy) * elem) % 16 != 0) return false;
-  return true;
+  return static_cast<size_t>(ceil_div(P.n, 64) * 64) * stride * elem <= kTileLdsBytes;
+}
+
+bool gram_vector_loads(const Plan& P, const void* ycm, int64_t ldy) {
+  const size_t elem = (P.y_dtype == RSM_F64) ? 8 : 4;
+  return (reinterpret_cast<uintptr_t>(ycm) % 16) == 0 && (static_cast<size_t>(ldy) * elem) % 16 == 0;
 }
 
 void launch_gram(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {

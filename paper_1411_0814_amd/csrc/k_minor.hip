@@ -15,8 +15,8 @@
 //      contributes only on C_t x C_t.  Lower triangle only (c_a >= c_b), FP64 atomics.
 //
 //  For l <= 11 the matrix lives in registers (static indices) and the rotations are
-//  accumulated in a per-thread LDS slice laid out [entry][thread]; larger l keep both in
-//  LDS.
+//  accumulated in a per-thread LDS slice laid out [entry][thread]; for larger l one
+//  wavefront works on each trial.
 #include <algorithm>
 #include <cmath>
 
@@ -218,123 +218,207 @@ __global__ __launch_bounds__(64) void k_minor_reg(const ProbDesc* __restrict__ p
   }
 }
 
-// ------------------------------------------------------------------ LDS only (large l)
+// ------------------------------------------------------------------ one wavefront per trial
+//
+// For large l (12..17) the l x l matrix and the rotations of one trial are held in LDS by
+// a wavefront, which runs parallel-ordering (round-robin) Jacobi: each round rotates
+// floor(l/2) disjoint pairs at once (rotation angles computed from the same pre-round
+// entries, so the result is the product of commuting plane rotations), elements spread
+// over the 64 lanes.  The acceptance criterion per pair is the one of the per-thread
+// kernel.  Four trials per workgroup.
+
+constexpr int kWaveTrials = 4;
 
 template <int L>
-struct MinorCfg {
-  static constexpr int kThreads = (16 * L * L * 64 <= 150 * 1024) ? 64 : 32;
-  static constexpr size_t kLds = static_cast<size_t>(16) * L * L * kThreads;
-};
-
-template <int L>
-__global__ __launch_bounds__(MinorCfg<L>::kThreads) void k_minor_lds(
-    const ProbDesc* __restrict__ probs, IdxList list) {
+__global__ __launch_bounds__(64 * kWaveTrials) void k_minor_wave(const ProbDesc* __restrict__ probs,
+                                                                 IdxList list) {
+  constexpr int NG = L * L;
+  constexpr int BB = L + (L & 1);  // even number of players (one idle slot if l is odd)
+  constexpr int LS = L + 1;        // LDS row stride
+  __shared__ double As[kWaveTrials][L][LS];
+  __shared__ double Vs[kWaveTrials][L][LS];
+  __shared__ double Cs[kWaveTrials][BB];
+  __shared__ double Sn[kWaveTrials][BB];
+  __shared__ int Pt[kWaveTrials][BB];
+  __shared__ int Pm[kWaveTrials][BB];
+  __shared__ int Fl[kWaveTrials];
+  __shared__ unsigned long long s_acc, s_rows;
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
   const int64_t I = P.I, n = P.n;
   const int nvec = P.nvec, min_rows = P.min_rows;
-  RSM_GLOBAL const double* __restrict__ G = P.G;
-  RSM_GLOBAL const int32_t* __restrict__ rows_in = P.rows;
-  RSM_GLOBAL const int32_t* __restrict__ cols = P.cols;
-  RSM_GLOBAL double* __restrict__ N = P.N;
-  RSM_GLOBAL rsm_info* info = P.info;
-  RSM_GLOBAL int32_t* __restrict__ tap_rows = P.tap_rows;
-  RSM_GLOBAL double* __restrict__ tap_gram = P.tap_gram;
-  RSM_GLOBAL double* __restrict__ tap_vecs = P.tap_vecs;
-  RSM_GLOBAL double* __restrict__ tap_eigs = P.tap_eigs;
-  constexpr int TPB = MinorCfg<L>::kThreads;
-  extern __shared__ double smem[];
-  __shared__ unsigned long long s_acc;
-  __shared__ unsigned long long s_rows;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid == 0) {
     s_acc = 0;
     s_rows = 0;
   }
-  double* Ab = smem + tid;
-  double* Vb = smem + L * L * TPB + tid;
-  auto a = [&](int i, int j) -> double& { return Ab[(i * L + j) * TPB]; };
-  auto v = [&](int i, int j) -> double& { return Vb[(i * L + j) * TPB]; };
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * TPB + tid;
-  const bool active = t < I;
-  int rows = 0;
+  auto A = As[w];
+  auto V = Vs[w];
+  double* cs = Cs[w];
+  double* sn = Sn[w];
+  int* partner = Pt[w];
+  int* perm = Pm[w];
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWaveTrials + w;
+  const bool active = t < I;  // wave-uniform
   int c[L];
   bool valid = active;
-  if (active) {
-    rows = rows_in[t];
-    int g = 0;
-    for (int i = 0; i < L; ++i)
-      for (int j = 0; j <= i; ++j, ++g) {
-        const double val = G[static_cast<int64_t>(g) * I + t];
-        a(i, j) = val;
-        a(j, i) = val;
-      }
-  }
 #pragma unroll
   for (int k = 0; k < L; ++k) {
-    c[k] = active ? cols[t * L + k] : 0;
+    c[k] = active ? P.cols[t * L + k] : 0;
     valid &= c[k] >= 0;
   }
+  const int rows = active ? P.rows[t] : 0;
   const bool accept = valid && rows >= min_rows;
   if (active) {
-    if (tap_rows) tap_rows[t] = rows;
-    if (tap_gram)
-      for (int i = 0; i < L; ++i)
-        for (int j = 0; j < L; ++j) tap_gram[(t * L + i) * L + j] = a(i, j);
+    // packed lower triangle of G_t, entry (i, j), j <= i, at i (i + 1) / 2 + j
+    for (int i = 0; i < L; ++i)
+      for (int j = lane; j <= i; j += 64) {
+        const double v = P.G[static_cast<int64_t>(i * (i + 1) / 2 + j) * I + t];
+        A[i][j] = v;
+        A[j][i] = v;
+      }
+    for (int e = lane; e < NG; e += 64) V[e / L][e % L] = (e / L == e % L) ? 1.0 : 0.0;
+    if (lane < BB) perm[lane] = lane;
+  }
+  __syncthreads();
+  if (active && lane == 0) {
+    if (P.tap_rows) P.tap_rows[t] = rows;
+    if (P.tap_gram)
+      for (int e = 0; e < NG; ++e) P.tap_gram[t * NG + e] = A[e / L][e % L];
   }
   if (accept) {
-    for (int i = 0; i < L; ++i)
-      for (int j = 0; j < L; ++j) v(i, j) = (i == j) ? 1.0 : 0.0;
     for (int sweep = 0; sweep < kJacobiMaxSweeps; ++sweep) {
-      bool rotated = false;
-      for (int p = 0; p < L - 1; ++p) {
-        for (int q = p + 1; q < L; ++q) {
-          const double apq = a(p, q);
-          const double app = a(p, p);
-          const double aqq = a(q, q);
-          if (!(fabs(apq) > kJacobiEps * sqrt(fabs(app * aqq)))) continue;
-          rotated = true;
-          double cr, sr, tr;
-          jacobi_rotation(app, aqq, apq, cr, sr, tr);
-          for (int k = 0; k < L; ++k) {
-            if (k == p || k == q) continue;
-            const double akp = a(k, p);
-            const double akq = a(k, q);
-            const double nkp = cr * akp - sr * akq;
-            const double nkq = sr * akp + cr * akq;
-            a(k, p) = nkp;
-            a(p, k) = nkp;
-            a(k, q) = nkq;
-            a(q, k) = nkq;
+      if (lane == 0) Fl[w] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      for (int round = 0; round < BB - 1; ++round) {
+        if (lane < BB) partner[lane] = -1;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (lane < BB / 2) {
+          int p = perm[lane], q = perm[BB - 1 - lane];
+          if (p > q) {
+            const int tmp = p;
+            p = q;
+            q = tmp;
           }
-          a(p, p) = app - tr * apq;
-          a(q, q) = aqq + tr * apq;
-          a(p, q) = 0.0;
-          a(q, p) = 0.0;
-          for (int k = 0; k < L; ++k) {
-            const double vkp = v(k, p);
-            const double vkq = v(k, q);
-            v(k, p) = cr * vkp - sr * vkq;
-            v(k, q) = sr * vkp + cr * vkq;
+          if (q < L) {
+            const double apq = A[q][p], app = A[p][p], aqq = A[q][q];
+            double cr = 1.0, sr = 0.0;
+            if (fabs(apq) > kJacobiEps * sqrt(fabs(app * aqq))) {
+              double tr;
+              jacobi_rotation(app, aqq, apq, cr, sr, tr);
+              Fl[w] = 1;
+            }
+            partner[p] = q;
+            partner[q] = p;
+            cs[p] = cr;
+            sn[p] = sr;
+            cs[q] = cr;
+            sn[q] = -sr;
           }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        // A <- J^T A J, V <- V J for the elements of this lane (reads, then writes)
+        constexpr int PER = (NG + 63) / 64;
+        double an[PER], vn[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int e = lane + 64 * k;
+          if (e < NG) {
+            const int i = e / L, j = e % L;
+            const int pi = partner[i], pj = partner[j];
+            const double ci = pi >= 0 ? cs[i] : 1.0, si = pi >= 0 ? sn[i] : 0.0;
+            const double cj = pj >= 0 ? cs[j] : 1.0, sj = pj >= 0 ? sn[j] : 0.0;
+            const int ii = pi >= 0 ? pi : i, jj = pj >= 0 ? pj : j;
+            an[k] = ci * (cj * A[i][j] - sj * A[i][jj]) - si * (cj * A[ii][j] - sj * A[ii][jj]);
+            vn[k] = cj * V[i][j] - sj * V[i][jj];
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int e = lane + 64 * k;
+          if (e < NG) {
+            A[e / L][e % L] = an[k];
+            V[e / L][e % L] = vn[k];
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        // exact symmetry; circle method for the next round (player 0 fixed)
+        double sym[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int e = lane + 64 * k;
+          sym[k] = (e < NG) ? 0.5 * (A[e / L][e % L] + A[e % L][e / L]) : 0.0;
+        }
+        int nxt = 0;
+        if (lane < BB) nxt = lane == 0 ? perm[0] : (lane == 1 ? perm[BB - 1] : perm[lane - 1]);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int e = lane + 64 * k;
+          if (e < NG) A[e / L][e % L] = sym[k];
+        }
+        if (lane < BB) perm[lane] = nxt;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
-      if (!rotated) break;
+      if (Fl[w] == 0) break;
     }
-    finish_trial<L>(t, nvec, n, c, [&](int k) { return a(k, k); },
-                    [&](int i, int k) { return v(i, k); }, N, tap_vecs, tap_eigs);
+    // eigenvalue ranks (ascending), taps, N[C_t, C_t] += sum_{rank < nvec} v v^T
+    int rank[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+      const double dk = A[k][k];
+      int rk = 0;
+#pragma unroll
+      for (int j = 0; j < L; ++j) {
+        const double dj = A[j][j];
+        rk += (dj < dk) || (dj == dk && j < k);
+      }
+      rank[k] = rk;
+    }
+    if (P.tap_eigs && lane < L) {
+      int rk = 0;
+      for (int j = 0; j < L; ++j) rk += (A[j][j] < A[lane][lane]) || (A[j][j] == A[lane][lane] && j < lane);
+      P.tap_eigs[t * L + rk] = A[lane][lane];
+    }
+    if (P.tap_vecs)
+      for (int e = lane; e < NG; e += 64) {
+        const int i = e % L, k = e / L;  // entry i of eigenvector (column) k
+        if (rank[0] >= 0) {
+          int rk = 0;
+          for (int j = 0; j < L; ++j) rk += (A[j][j] < A[k][k]) || (A[j][j] == A[k][k] && j < k);
+          if (rk < nvec) P.tap_vecs[(t * nvec + rk) * L + i] = V[i][k];
+        }
+      }
+    for (int e = lane; e < L * (L + 1) / 2; e += 64) {
+      int i = static_cast<int>((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+      while (i * (i + 1) / 2 > e) --i;
+      while ((i + 1) * (i + 2) / 2 <= e) ++i;
+      const int j = e - i * (i + 1) / 2;
+      double pij = 0.0;
+#pragma unroll
+      for (int k = 0; k < L; ++k)
+        if (rank[k] < nvec) pij += V[i][k] * V[j][k];
+      int ci = 0, cj = 0;
+#pragma unroll
+      for (int k = 0; k < L; ++k) {
+        ci = (k == i) ? c[k] : ci;
+        cj = (k == j) ? c[k] : cj;
+      }
+      atomic_add_f64((double*)&P.N[static_cast<int64_t>(ci) + static_cast<int64_t>(cj) * n], pij);
+    }
   } else if (active) {
-    if (tap_eigs)
-      for (int k = 0; k < L; ++k) tap_eigs[t * L + k] = 0.0;
-    if (tap_vecs)
-      for (int k = 0; k < nvec * L; ++k) tap_vecs[t * nvec * L + k] = 0.0;
+    if (P.tap_eigs)
+      for (int k = lane; k < L; k += 64) P.tap_eigs[t * L + k] = 0.0;
+    if (P.tap_vecs)
+      for (int k = lane; k < nvec * L; k += 64) P.tap_vecs[t * nvec * L + k] = 0.0;
   }
   __syncthreads();
-  if (accept) atomicAdd(&s_acc, 1ull);
-  if (active) atomicAdd(&s_rows, static_cast<unsigned long long>(rows));
+  if (lane == 0 && accept) atomicAdd(&s_acc, 1ull);
+  if (lane == 0 && active) atomicAdd(&s_rows, static_cast<unsigned long long>(rows));
   __syncthreads();
   if (tid == 0) {
-    atomicAdd((unsigned long long*)&info->accepted, s_acc);
-    atomicAdd((unsigned long long*)&info->rows_total, s_rows);
+    atomicAdd((unsigned long long*)&P.info->accepted, s_acc);
+    atomicAdd((unsigned long long*)&P.info->rows_total, s_rows);
   }
 }
 
@@ -344,16 +428,8 @@ void run_minor(const ProbDesc* d, const IdxList& g, int64_t I, hipStream_t s) {
     const unsigned blocks = static_cast<unsigned>(ceil_div(I, 64));
     k_minor_reg<L><<<dim3(blocks, g.count), 64, 0, s>>>(d, g);
   } else {
-    constexpr int TPB = MinorCfg<L>::kThreads;
-    const unsigned blocks = static_cast<unsigned>(ceil_div(I, TPB));
-    static bool attr_set = false;  // dynamic LDS above 64 KiB must be allowed explicitly
-    if (!attr_set) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_minor_lds<L>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                static_cast<int>(MinorCfg<L>::kLds));
-      attr_set = true;
-    }
-    k_minor_lds<L><<<dim3(blocks, g.count), TPB, MinorCfg<L>::kLds, s>>>(d, g);
+    const unsigned blocks = static_cast<unsigned>(ceil_div(I, kWaveTrials));
+    k_minor_wave<L><<<dim3(blocks, g.count), 64 * kWaveTrials, 0, s>>>(d, g);
   }
 }
 

@@ -31,17 +31,34 @@ __global__ void k_pack_mask_colmajor(const ProbDesc* __restrict__ probs, IdxList
   const int64_t w = gid - j * mw;
   const int64_t i0 = w * 64;
   RSM_GLOBAL const uint8_t* src = P.W + j * P.ldw + i0;
+  const int sh = static_cast<int>(reinterpret_cast<uintptr_t>(src) & 7u);
   uint64_t word = 0;
   const bool full = (i0 + 64 <= m);
-  if (full && ((reinterpret_cast<uintptr_t>(src) & 7u) == 0)) {
+  if (full && sh == 0) {
     auto s8 = reinterpret_cast<RSM_GLOBAL const uint64_t*>(src);
+    uint64_t x[8];
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
-      word |= static_cast<uint64_t>(nonzero_bytes_to_bits(s8[b])) << (8 * b);
-  } else {
-    const int64_t cnt = full ? 64 : (m - i0);
-    for (int64_t k = 0; k < cnt; ++k)
-      if (src[k]) word |= 1ull << k;
+    for (int b = 0; b < 8; ++b) x[b] = s8[b];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) word |= static_cast<uint64_t>(nonzero_bytes_to_bits(x[b])) << (8 * b);
+  } else if (full && i0 >= 8 && i0 + 72 <= m) {
+    // unaligned column: the 9 aligned words covering [src, src + 64) lie inside this column
+    auto s8 = reinterpret_cast<RSM_GLOBAL const uint64_t*>(src - sh);
+    uint64_t x[9];
+#pragma unroll
+    for (int b = 0; b < 9; ++b) x[b] = s8[b];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t v = (x[b] >> (8 * sh)) | (x[b + 1] << (64 - 8 * sh));
+      word |= static_cast<uint64_t>(nonzero_bytes_to_bits(v)) << (8 * b);
+    }
+  } else {  // first or last word of an unaligned column, or the ragged tail: bytes
+    const int cnt = full ? 64 : static_cast<int>(m - i0);
+    uint8_t x[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) x[k] = src[k < cnt ? k : 0];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) word |= static_cast<uint64_t>(k < cnt && x[k] != 0) << k;
   }
   P.wbits[j * mw + w] = word;
 }

@@ -19,7 +19,13 @@ namespace rsm {
 namespace {
 
 constexpr int kUChunk = 256;  // columns of V-hat per LDS stage
-constexpr int kUnroll = 4;    // columns whose loads are issued together
+
+// Columns whose loads are issued together: fewer for large r, whose r(r+1)/2 accumulators
+// already fill most of the register file.
+template <int R>
+constexpr int u_unroll() {
+  return R <= 8 ? 4 : (R <= 12 ? 2 : 1);
+}
 
 template <int R, typename TY>
 __global__ __launch_bounds__(256) void k_usolve(const ProbDesc* __restrict__ probs, IdxList list) {
@@ -59,6 +65,7 @@ __global__ __launch_bounds__(256) void k_usolve(const ProbDesc* __restrict__ pro
     if (wave_active) {
       // groups of kUnroll columns: all loads of a group first, then the products; the
       // mask bit is a 0/1 weight, so there is no divergent branch
+      constexpr int kUnroll = u_unroll<R>();
       for (int jj = 0; jj < jn; jj += kUnroll) {
         uint64_t word[kUnroll];
         double y[kUnroll];

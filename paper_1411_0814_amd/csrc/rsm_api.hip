@@ -334,7 +334,8 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   std::vector<ProbDesc> hp(static_cast<size_t>(nprob));
   for (int32_t k = 0; k < nprob; ++k) {
     Plan& P = plans[k];
-    P.tiled = gram_tiled_ok(P, ycm_of(P, inputs[k], ws + base[k]), ldy_of(P, inputs[k]));
+    P.tiled = gram_tiled_ok(P);
+    P.gram_vec = gram_vector_loads(P, ycm_of(P, inputs[k], ws + base[k]), ldy_of(P, inputs[k]));
     hp[k] = prob_desc(P, inputs[k], outputs[k], ws + base[k]);
   }
   put_prob_descs(hp.data(), nprob, dprob, s);
@@ -358,7 +359,8 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   // a2 + a3: one launch per (l, element type, precision, kernel)
   for_groups(plans, [](const Plan& P) { return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0; },
              [](const Plan& P) {
-               return int64_t(P.l) * 64 + P.y_dtype * 16 + P.prec * 2 + (P.tiled ? 1 : 0);
+               return int64_t(P.l) * 64 + P.y_dtype * 16 + P.prec * 4 + (P.tiled ? 2 : 0) +
+                      (P.gram_vec ? 1 : 0);
              },
              [&](const IdxList& g, const Plan* const* h) {
                mark_all(outputs, g, RSM_STEP_GRAM, 0, s);

@@ -10,12 +10,13 @@ from tests.gpu_util import to_device
 pytestmark = pytest.mark.gpu
 
 # (m, n, r, rho, dtype, gram, row_major): several groups of the Gram / U-hat launches, two
-# problems sharing every key, a ragged n and a row-major input
+# problems sharing every key, a ragged n, a row-major input, and columns whose byte offsets
+# are not multiples of 16 (m = 3001, 1803)
 SPECS = [
-    (3000, 150, 3, 0.75, np.float32, "f32", False),
+    (3001, 150, 3, 0.75, np.float32, "f32", False),
     (2500, 96, 5, 0.8, np.float64, "f64", False),
     (4000, 200, 2, 0.7, np.float32, "f32", True),
-    (1800, 70, 8, 0.85, np.float32, "f32", False),
+    (1803, 70, 8, 0.85, np.float32, "f32", False),
     (3300, 150, 3, 0.72, np.float32, "f32", False),
     (2200, 130, 12, 0.9, np.float32, "f32", False),
 ]
