@@ -117,7 +117,8 @@ _G = {}
 
 
 def oracle_parity(p, V_gpu, U_gpu, sample_rows, workers):
-    """theta_max of V-hat and rel RMS of U V^T (sampled rows) against the FP64 oracle."""
+    """theta_max of V-hat and rel RMS of U V^T (sampled rows) against the FP64 oracle.
+    V_gpu / U_gpu may be lists (several GPU results of the same problem)."""
     import multiprocessing as mp
 
     from oracle import metrics, rng, rsm
@@ -133,9 +134,13 @@ def oracle_parity(p, V_gpu, U_gpu, sample_rows, workers):
     rows = np.linspace(0, p.m - 1, sample_rows).astype(np.int64)
     U_ora, _ = rsm.solve_U(p.Y, p.W, V_ora, rows=rows)
     t_oracle = time.perf_counter() - t0
-    theta = metrics.principal_angle_max(V_gpu, V_ora)
-    rms = metrics.rel_rms_known(p.W[rows], U_gpu[rows], V_gpu, U_ora[rows], V_ora)
-    return theta, rms, t_oracle
+    single = not isinstance(V_gpu, list)
+    Vs, Us = ([V_gpu], [U_gpu]) if single else (V_gpu, U_gpu)
+    out = [(metrics.principal_angle_max(V, V_ora),
+            metrics.rel_rms_known(p.W[rows], U[rows], V, U_ora[rows], V_ora)) for V, U in zip(Vs, Us)]
+    if single:
+        return out[0][0], out[0][1], t_oracle
+    return out, t_oracle
 
 
 def cpu_baseline(p, n_trials, n_rows):
@@ -292,6 +297,59 @@ def main_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def main_precision(args):
+    """Precision stress: the same problem with the FP32 Gram and with the split-BF16 Gram on
+    MFMA, each timed and compared with one FP64 oracle run."""
+    import torch
+
+    from paper_1411_0814_amd import decompose
+    p = make_workload("precision")
+    dev = torch.device("cuda:0")
+    Y = torch.from_numpy(p.Yt).to(dev).T
+    W = torch.from_numpy(p.Wt.view(bool)).to(dev).T
+    stream = torch.cuda.current_stream(dev)
+    runs = {}
+    for gram in ("f32", "bf16x2"):
+        for _ in range(max(1, args.warmup)):
+            res = decompose(Y, W, p.r, p.num_submatrices, p.seed_rsm, l=p.l, gram=gram)
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(args.steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            res = decompose(Y, W, p.r, p.num_submatrices, p.seed_rsm, l=p.l, gram=gram)
+            b.record(stream)
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        ms = [a.elapsed_time(b) for a, b in evs]
+        runs[gram] = {"decompositions_per_s": round(1e3 / float(np.mean(ms)), 2),
+                      "ms_p50": round(float(np.percentile(ms, 50)), 4),
+                      "ms_p99": round(float(np.percentile(ms, 99)), 4),
+                      "V": res.V.cpu().numpy(), "U": res.U.cpu().numpy(),
+                      "info": res.info()}
+    workers = min(16, os.cpu_count() or 4)
+    pairs, t_or = oracle_parity(p, [runs[g]["V"] for g in runs], [runs[g]["U"] for g in runs],
+                                args.cpu_sample_rows, workers)
+    for (theta, rms), g in zip(pairs, runs):
+        runs[g].update(theta_max_rad=theta, rel_rms_known=rms)
+        lam = runs[g].pop("info")["lambda"]
+        runs[g]["lambda_r"], runs[g]["lambda_r1"] = lam[p.r - 1], lam[p.r]
+        del runs[g]["V"], runs[g]["U"]
+    line = {
+        "metric": METRIC, "value": runs["bf16x2"]["decompositions_per_s"],
+        "unit": "decompositions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": runs["bf16x2"]["ms_p50"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16x2", "data": "synthetic",
+        "config": {"workload": p.name, "m": p.m, "n": p.n, "r": p.r, "l": p.l,
+                   "num_submatrices": p.num_submatrices, "rho": p.rho,
+                   "singular_values": "geometric 1 .. 1e-3", "noise": 1e-5,
+                   "eig_solves": "f64"},
+        "gram_modes": runs,
+        "oracle": {"s": round(t_or, 1), "workers": workers, "rows_sampled_for_rms": args.cpu_sample_rows},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe_mib:
@@ -303,6 +361,9 @@ def main():
         sys.exit(2)
     if args.workload in ("batched", "served"):
         main_batched(args)
+        return
+    if args.workload == "precision":
+        main_precision(args)
         return
     import torch
 

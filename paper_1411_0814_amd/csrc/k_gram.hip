@@ -128,92 +128,44 @@ struct Vec16<double> {
   static constexpr int kN = 2;
 };
 
-// VEC: Y and its leading dimension are 16-byte aligned, so a chunk column is moved as
-// 16-byte vectors; otherwise element by element (same layout in LDS).
-template <int L, typename T, int NT, bool VEC>
-__global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ probs,
-                                                  IdxList list) {
-  constexpr int NG = L * (L + 1) / 2;
+// Stages 32-row chunks of Y (all n columns) and their mask words from global memory into
+// registers and from registers into the LDS tile.  The tile holds n_pad >= n columns
+// (n_pad a multiple of NT / kVPC) and the mask row m_pad >= n words (a multiple of NT), so
+// every thread moves exactly kv vectors and km mask words per chunk: uniform trip counts,
+// loads issued back to back.  Columns past n repeat column n - 1 (valid addresses, never
+// read back).  Vector k of thread tid is column tid / kVPC + k * (NT / kVPC), rows
+// kVN * (tid % kVPC) + [0, kVN).  Elements are loaded one by one (the compiler merges
+// them into 16-byte loads, which gfx950 allows at 4-byte alignment), so columns need not
+// be 16-byte aligned.
+template <typename T, int NT>
+struct ChunkStager {
   using V = typename Vec16<T>::type;
-  constexpr int kVN = Vec16<T>::kN;                 // elements per 16-byte vector
-  constexpr int kVPC = kChunk / kVN;                // vectors per column of a chunk
-  constexpr int kS = TileStride<T>::kValue;           // LDS elements per column
-  constexpr int kVPS = kS / kVN;                      // 16-byte vectors per column stride
-  constexpr int kMaxCols = static_cast<int>(kTileLdsBytes / (kS * sizeof(T)));
-  constexpr int kMaxV = (kMaxCols * kVPC + NT - 1) / NT;
-  constexpr int kMaxM = (kMaxCols + NT - 1) / NT;
-  const ProbDesc& P = probs[list.idx[blockIdx.y]];
-  const int groups = P.gram_groups, splits = P.splits;
-  if (static_cast<int>(blockIdx.x) >= groups * splits) return;  // past this problem's work
-  const int64_t m = P.m, I = P.I, ldy = P.ldy, mw32 = 2 * P.mw;
-  const int n = static_cast<int>(P.n);
-  const int n_pad = static_cast<int>(ceil_div(n, NT / kVPC) * (NT / kVPC));
-  const int m_pad = static_cast<int>(ceil_div(n, NT) * NT);
-  const int64_t chunks = ceil_div(m, kChunk), chunks_per_split = 2 * P.words_per_split;
-  const bool xcd_map = splits % 8 == 0;
-  auto Y = static_cast<RSM_GLOBAL const T*>(P.ycm);
-  auto mask32 = reinterpret_cast<RSM_GLOBAL const uint32_t*>(P.wbits);
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* tile = reinterpret_cast<T*>(smem_raw);                                   // [n_pad][kS]
-  uint32_t* msk = reinterpret_cast<uint32_t*>(tile + static_cast<int64_t>(n_pad) * kS);  // [m_pad]
-
-  // Workgroup -> (trial group, row split).  Workgroups are dispatched to the 8 XCDs
-  // round-robin by id (the launch's x extent is a multiple of 8), so with xcd_map the ids
-  // id = 8 k + x of XCD x enumerate all trial groups of split 8 (k / groups) + x before the
-  // next split: the groups reading the same rows share that XCD's L2.
-  const int id = blockIdx.x;
-  int group, split;
-  if (xcd_map) {
-    const int x = id & 7, k = id >> 3;
-    const int sl = k / groups;
-    group = k - sl * groups;
-    split = sl * 8 + x;
-  } else {
-    group = id % groups;
-    split = id / groups;
-  }
-  const int tid = threadIdx.x;
-  const int64_t t = static_cast<int64_t>(group) * NT + tid;
-  const bool active = t < I;
-  const int64_t ch0 = static_cast<int64_t>(split) * chunks_per_split;
-  const int64_t ch1 = (ch0 + chunks_per_split < chunks) ? (ch0 + chunks_per_split) : chunks;
-
-  int mc[L];  // column index; its tile values start at mc * kChunk
-  bool valid = active;
-#pragma unroll
-  for (int a = 0; a < L; ++a) {
-    int c = active ? P.cols[t * L + a] : 0;
-    valid &= (c >= 0);
-    mc[a] = c < 0 ? 0 : c;
-  }
-  T acc[NG];
-#pragma unroll
-  for (int g = 0; g < NG; ++g) acc[g] = T(0);
-  int count = 0;
-
-  // Chunk staging.  The tile holds n_pad >= n columns (n_pad a multiple of NT / kVPC) and
-  // the mask row m_pad >= n words (a multiple of NT), so every thread moves exactly kv
-  // vectors and km mask words per chunk: uniform trip counts, loads issued back to back.
-  // Columns past n repeat column n - 1 (valid addresses, never read back).  Vector k of
-  // thread tid is column tid / kVPC + k * (NT / kVPC), rows kVN * (tid % kVPC) + [0, kVN).
+  static constexpr int kVN = Vec16<T>::kN;              // elements per 16-byte vector
+  static constexpr int kVPC = kChunk / kVN;             // vectors per column of a chunk
+  static constexpr int kS = TileStride<T>::kValue;      // LDS elements per column
+  static constexpr int kVPS = kS / kVN;                 // 16-byte vectors per column stride
+  static constexpr int kMaxCols = static_cast<int>(kTileLdsBytes / (kS * sizeof(T)));
+  static constexpr int kMaxV = (kMaxCols * kVPC + NT - 1) / NT;
+  static constexpr int kMaxM = (kMaxCols + NT - 1) / NT;
   static_assert(NT % kVPC == 0, "threads must cover whole columns");
-  const int kv = n_pad * kVPC / NT;
-  const int km = m_pad / NT;
-  const int c0 = tid / kVPC;
-  const int vpart = (tid % kVPC) * kVN;
+
+  RSM_GLOBAL const T* Y;
+  RSM_GLOBAL const uint32_t* mask32;
+  int64_t m, ldy, mw32;
+  int n, kv, km, c0, vpart, tid;
   V vreg[kMaxV];
   uint32_t mreg[kMaxM];
-  auto load_chunk = [&](int64_t ch) {
+
+  __device__ __forceinline__ ChunkStager(const ProbDesc& P, int n_pad, int m_pad)
+      : Y(static_cast<RSM_GLOBAL const T*>(P.ycm)),
+        mask32(reinterpret_cast<RSM_GLOBAL const uint32_t*>(P.wbits)),
+        m(P.m), ldy(P.ldy), mw32(2 * P.mw), n(static_cast<int>(P.n)),
+        kv(n_pad * kVPC / NT), km(m_pad / NT), c0(static_cast<int>(threadIdx.x) / kVPC),
+        vpart((static_cast<int>(threadIdx.x) % kVPC) * kVN), tid(threadIdx.x) {}
+
+  __device__ __forceinline__ void load(int64_t ch) {
     const int64_t r0 = ch * kChunk;
-    if (VEC && r0 + kChunk <= m) {
-#pragma unroll
-      for (int k = 0; k < kMaxV; ++k) {
-        if (k < kv) {
-          const int c = min(c0 + k * (NT / kVPC), n - 1);
-          vreg[k] = *reinterpret_cast<RSM_GLOBAL const V*>(Y + static_cast<int64_t>(c) * ldy + r0 + vpart);
-        }
-      }
-    } else if (r0 + kChunk <= m) {  // unaligned columns: element loads, all issued first
+    if (r0 + kChunk <= m) {
 #pragma unroll
       for (int k = 0; k < kMaxV; ++k) {
         if (k < kv) {
@@ -249,8 +201,9 @@ __global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ p
         mreg[k] = mask32[static_cast<int64_t>(c) * mw32 + ch];
       }
     }
-  };
-  auto store_chunk = [&]() {
+  }
+
+  __device__ __forceinline__ void store(T* tile, uint32_t* msk) const {
     V* tv = reinterpret_cast<V*>(tile) + c0 * kVPS + (tid % kVPC);
 #pragma unroll
     for (int k = 0; k < kMaxV; ++k)
@@ -258,14 +211,72 @@ __global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ p
 #pragma unroll
     for (int k = 0; k < kMaxM; ++k)
       if (k < km) msk[tid + k * NT] = mreg[k];
-  };
+  }
+};
 
-  if (ch0 < ch1) load_chunk(ch0);
+// Workgroup -> (trial group, row split) of the tiled kernels.  Workgroups are dispatched to
+// the 8 XCDs round-robin by id (the launch's x extent is a multiple of 8), so when the
+// splits are a multiple of 8 the ids id = 8 k + x of XCD x enumerate all trial groups of
+// split 8 (k / groups) + x before the next split: the groups reading the same rows share
+// that XCD's L2.
+__device__ __forceinline__ void tile_work(int groups, int splits, int& group, int& split) {
+  const int id = blockIdx.x;
+  if (splits % 8 == 0) {
+    const int x = id & 7, k = id >> 3;
+    const int sl = k / groups;
+    group = k - sl * groups;
+    split = sl * 8 + x;
+  } else {
+    group = id % groups;
+    split = id / groups;
+  }
+}
+
+template <int L, typename T, int NT>
+__global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ probs,
+                                                  IdxList list) {
+  constexpr int NG = L * (L + 1) / 2;
+  using S = ChunkStager<T, NT>;
+  constexpr int kS = S::kS;
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int groups = P.gram_groups, splits = P.splits;
+  if (static_cast<int>(blockIdx.x) >= groups * splits) return;  // past this problem's work
+  const int64_t m = P.m, I = P.I;
+  const int n = static_cast<int>(P.n);
+  const int n_pad = static_cast<int>(ceil_div(n, NT / S::kVPC) * (NT / S::kVPC));
+  const int m_pad = static_cast<int>(ceil_div(n, NT) * NT);
+  const int64_t chunks = ceil_div(m, kChunk), chunks_per_split = 2 * P.words_per_split;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);                                   // [n_pad][kS]
+  uint32_t* msk = reinterpret_cast<uint32_t*>(tile + static_cast<int64_t>(n_pad) * kS);  // [m_pad]
+  int group, split;
+  tile_work(groups, splits, group, split);
+  const int tid = threadIdx.x;
+  const int64_t t = static_cast<int64_t>(group) * NT + tid;
+  const bool active = t < I;
+  const int64_t ch0 = static_cast<int64_t>(split) * chunks_per_split;
+  const int64_t ch1 = (ch0 + chunks_per_split < chunks) ? (ch0 + chunks_per_split) : chunks;
+
+  int mc[L];  // column index; its tile values start at mc * kChunk
+  bool valid = active;
+#pragma unroll
+  for (int a = 0; a < L; ++a) {
+    int c = active ? P.cols[t * L + a] : 0;
+    valid &= (c >= 0);
+    mc[a] = c < 0 ? 0 : c;
+  }
+  T acc[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) acc[g] = T(0);
+  int count = 0;
+
+  S stage(P, n_pad, m_pad);
+  if (ch0 < ch1) stage.load(ch0);
   for (int64_t ch = ch0; ch < ch1; ++ch) {
     __syncthreads();
-    store_chunk();
+    stage.store(tile, msk);
     __syncthreads();
-    if (ch + 1 < ch1) load_chunk(ch + 1);
+    if (ch + 1 < ch1) stage.load(ch + 1);
     if (valid) {
       uint32_t q = 0xffffffffu;
 #pragma unroll
@@ -297,29 +308,177 @@ __global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ p
   }
 }
 
-template <int L, typename T, bool VEC>
+// ------------------------------------------------------------------ split-BF16 on MFMA
+//
+// The same staging, but the Gram products run on the matrix cores: each value x of a
+// trial's qualifying rows is split into bf16 hi = rn(x) and lo = rn(x - hi), and
+// G += Z_hi^T Z_hi + Z_hi^T Z_lo + Z_lo^T Z_hi with FP32 accumulation (the lo * lo term,
+// about 2^-18 relative, is dropped).  One v_mfma_f32_16x16x32_bf16 covers one 32-row chunk
+// of one trial (l <= 16 columns padded to 16): lane (i, g) = (lane % 16, lane / 16) holds
+// rows 8 g .. 8 g + 7 of column i, which is both its A (Z^T) and its B (Z) operand; row i
+// of the 16 x 16 result sits in lanes 16 (i / 4) + j, register i % 4.  Rows that do not
+// qualify enter as zeros.  A wavefront owns 16 trials (64 accumulator registers; the
+// staging registers need the rest), so a workgroup of 8 wavefronts covers 128 trials.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBfTrialsPerWave = 16;
+constexpr int kBfThreads = 512;
+
+template <int L>
+__global__ __launch_bounds__(kBfThreads) void k_gram_bf16(const ProbDesc* __restrict__ probs,
+                                                          IdxList list) {
+  static_assert(L <= 16, "one 16 x 16 tile per trial");
+  constexpr int NT = kBfThreads;
+  constexpr int NG = L * (L + 1) / 2;
+  constexpr int TW = kBfTrialsPerWave;
+  using S = ChunkStager<float, NT>;
+  constexpr int kS = S::kS;
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int groups = P.gram_groups, splits = P.splits;
+  if (static_cast<int>(blockIdx.x) >= groups * splits) return;
+  const int64_t m = P.m, I = P.I;
+  const int n = static_cast<int>(P.n);
+  const int n_pad = static_cast<int>(ceil_div(n, NT / S::kVPC) * (NT / S::kVPC));
+  const int m_pad = static_cast<int>(ceil_div(n, NT) * NT);
+  const int64_t chunks = ceil_div(m, kChunk), chunks_per_split = 2 * P.words_per_split;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* tile = reinterpret_cast<float*>(smem_raw);
+  uint32_t* msk = reinterpret_cast<uint32_t*>(tile + static_cast<int64_t>(n_pad) * kS);
+  int* cnt = reinterpret_cast<int*>(msk + m_pad);  // [NT]: qualifying rows per trial
+  int group, split;
+  tile_work(groups, splits, group, split);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ci = lane & 15, kg = lane >> 4;
+  const int64_t tb = static_cast<int64_t>(group) * (NT / 64) * TW + w * TW;  // first trial of this wavefront
+  const int64_t ch0 = static_cast<int64_t>(split) * chunks_per_split;
+  const int64_t ch1 = (ch0 + chunks_per_split < chunks) ? (ch0 + chunks_per_split) : chunks;
+
+  // column of operand row ci for each trial, 16 bits each, two per register: kAbsent when
+  // the trial is absent or invalid (it then contributes nothing), kPad on the padding rows
+  // ci >= l
+  constexpr uint32_t kAbsent = 0xffffu, kPad = 0xfffeu;
+  uint32_t colp[TW / 2];
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt) {
+    const int64_t t = tb + tt;
+    int c = -2;
+    if (ci < L) c = (t < I) ? P.cols[t * L + ci] : -1;
+    int bad = (c == -1) ? 1 : 0;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) bad |= __shfl_xor(bad, off, 16);
+    const uint32_t code = ci >= L ? kPad : (bad ? kAbsent : static_cast<uint32_t>(c));
+    if (tt & 1)
+      colp[tt / 2] |= code << 16;
+    else
+      colp[tt / 2] = code;
+  }
+  f32x4 acc[TW];
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt) acc[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  cnt[tid] = 0;
+
+  S stage(P, n_pad, m_pad);
+  if (ch0 < ch1) stage.load(ch0);
+  for (int64_t ch = ch0; ch < ch1; ++ch) {
+    __syncthreads();
+    stage.store(tile, msk);
+    __syncthreads();
+    if (ch + 1 < ch1) stage.load(ch + 1);
+#pragma unroll
+    for (int tt = 0; tt < TW; ++tt) {
+      const uint32_t code = (colp[tt / 2] >> (16 * (tt & 1))) & 0xffffu;
+      const int c = code < kPad ? static_cast<int>(code) : -1;
+      uint32_t q = c >= 0 ? msk[c] : (code == kPad ? 0xffffffffu : 0u);
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) q &= __shfl_xor(q, off, 16);
+      const uint32_t bits = (q >> (8 * kg)) & 0xffu;
+      const float* src = tile + (c >= 0 ? c : 0) * kS + 8 * kg;
+      const float4 xa = *reinterpret_cast<const float4*>(src);
+      const float4 xb = *reinterpret_cast<const float4*>(src + 4);
+      const float xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+      bf16x8 hi, lo;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float x = (c >= 0 && ((bits >> k) & 1u)) ? xv[k] : 0.0f;
+        const __bf16 h = static_cast<__bf16>(x);
+        hi[k] = h;
+        lo[k] = static_cast<__bf16>(x - static_cast<float>(h));
+      }
+      acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, hi, acc[tt], 0, 0, 0);
+      acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, lo, acc[tt], 0, 0, 0);
+      acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, hi, acc[tt], 0, 0, 0);
+      if (lane == 0) cnt[w * TW + tt] += __popc(q);
+      // at most four trials' operands in flight (the scheduler would otherwise hoist the
+      // loads of all of them and spill)
+      if ((tt & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  __syncthreads();
+  RSM_GLOBAL float* part = static_cast<RSM_GLOBAL float*>(P.part) + static_cast<int64_t>(split) * NG * I;
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt) {
+    const int64_t t = tb + tt;
+    if (t >= I) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * kg + v, j = ci;
+      if (i < L && j <= i) part[static_cast<int64_t>(i * (i + 1) / 2 + j) * I + t] = acc[tt][v];
+    }
+    if (lane == 0) P.prow[static_cast<int64_t>(split) * I + t] = cnt[w * TW + tt];
+  }
+}
+
+template <int L, typename T>
+size_t tile_lds(const Plan& P, int NT, size_t extra_per_thread) {
+  constexpr int kVPC = kChunk / Vec16<T>::kN;
+  const int n = static_cast<int>(P.n);
+  const int n_pad = static_cast<int>(ceil_div(n, NT / kVPC) * (NT / kVPC));
+  const int m_pad = static_cast<int>(ceil_div(n, NT) * NT);
+  return static_cast<size_t>(n_pad) * TileStride<T>::kValue * sizeof(T) +
+         static_cast<size_t>(m_pad) * sizeof(uint32_t) + NT * extra_per_thread;
+}
+
+template <int L, typename T>
 void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
   constexpr int NT = tile_threads(L, sizeof(T));
-  constexpr int kVPC = kChunk / Vec16<T>::kN;
   size_t lds = 0;
   int wgs = 0;
   for (int k = 0; k < g.count; ++k) {
-    const int n = static_cast<int>(h[k]->n);
-    const int n_pad = static_cast<int>(ceil_div(n, NT / kVPC) * (NT / kVPC));
-    const int m_pad = static_cast<int>(ceil_div(n, NT) * NT);
-    lds = std::max(lds, static_cast<size_t>(n_pad) * TileStride<T>::kValue * sizeof(T) +
-                            static_cast<size_t>(m_pad) * sizeof(uint32_t));
+    lds = std::max(lds, tile_lds<L, T>(*h[k], NT, 0));
     wgs = std::max(wgs, h[k]->gram_wgs);
   }
   static bool attr_set = false;  // dynamic LDS above 64 KiB must be allowed explicitly
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_tile<L, T, NT, VEC>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_tile<L, T, NT>),
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               static_cast<int>(kTileLdsBytes + 8192));
     attr_set = true;
   }
   const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
-  k_gram_tile<L, T, NT, VEC><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
+  k_gram_tile<L, T, NT><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
+}
+
+template <int L>
+void run_bf16(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  if constexpr (L <= 16) {
+    size_t lds = 0;
+    int wgs = 0;
+    for (int k = 0; k < g.count; ++k) {
+      lds = std::max(lds, tile_lds<L, float>(*h[k], kBfThreads, sizeof(int)));
+      wgs = std::max(wgs, h[k]->gram_wgs);
+    }
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_bf16<L>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(kTileLdsBytes + 8192));
+      attr_set = true;
+    }
+    const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
+    k_gram_bf16<L><<<dim3(grid, g.count), kBfThreads, lds, s>>>(d, g);
+  }
 }
 
 template <int L, typename TY, typename TA>
@@ -337,16 +496,18 @@ void run_plain(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStr
 template <int L>
 void dispatch_types(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
   const Plan& P = *h[0];  // the group shares l, y_dtype, precision and kernel choice
-  if (P.prec == RSM_GRAM_F64) {
+  if (P.prec == RSM_GRAM_BF16X2) {
+    run_bf16<L>(d, g, h, s);  // make_plan admits it only for FP32 Y, l <= 16, tiled
+  } else if (P.prec == RSM_GRAM_F64) {
     if (P.y_dtype == RSM_F64 && P.tiled)
-      P.gram_vec ? run_tile<L, double, true>(d, g, h, s) : run_tile<L, double, false>(d, g, h, s);
+      run_tile<L, double>(d, g, h, s);
     else if (P.y_dtype == RSM_F32)
       run_plain<L, float, double>(d, g, h, s);
     else
       run_plain<L, double, double>(d, g, h, s);
   } else {
     if (P.y_dtype == RSM_F32 && P.tiled)
-      P.gram_vec ? run_tile<L, float, true>(d, g, h, s) : run_tile<L, float, false>(d, g, h, s);
+      run_tile<L, float>(d, g, h, s);
     else if (P.y_dtype == RSM_F32)
       run_plain<L, float, float>(d, g, h, s);
     else
@@ -358,16 +519,11 @@ void dispatch_types(const ProbDesc* d, const IdxList& g, const Plan* const* h, h
 
 bool gram_tiled_ok(const Plan& P) {
   if (!P.tiled) return false;
-  const bool same = (P.prec == RSM_GRAM_F64) == (P.y_dtype == RSM_F64);
-  const size_t elem = (P.y_dtype == RSM_F64) ? 8 : 4;
-  if (!same) return false;
-  const size_t stride = (P.y_dtype == RSM_F64) ? TileStride<double>::kValue : TileStride<float>::kValue;
+  const bool f64 = P.prec == RSM_GRAM_F64;
+  if (f64 != (P.y_dtype == RSM_F64)) return false;
+  const size_t elem = f64 ? 8 : 4;
+  const size_t stride = f64 ? TileStride<double>::kValue : TileStride<float>::kValue;
   return static_cast<size_t>(ceil_div(P.n, 64) * 64) * stride * elem <= kTileLdsBytes;
-}
-
-bool gram_vector_loads(const Plan& P, const void* ycm, int64_t ldy) {
-  const size_t elem = (P.y_dtype == RSM_F64) ? 8 : 4;
-  return (reinterpret_cast<uintptr_t>(ycm) % 16) == 0 && (static_cast<size_t>(ldy) * elem) % 16 == 0;
 }
 
 void launch_gram(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {

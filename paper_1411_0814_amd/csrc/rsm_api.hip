@@ -44,7 +44,11 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   const int min_rows = p.min_rows ? p.min_rows : p.r;
   if (min_rows < 1) return RSM_E_ARG;
   if (p.r > RSM_MAX_R || l > RSM_MAX_L || p.n > RSM_MAX_N) return RSM_E_UNSUPPORTED;
-  if (p.gram_prec == RSM_GRAM_BF16X2) return RSM_E_UNSUPPORTED;
+  // split-BF16 runs on the tiled MFMA kernel only: FP32 Y, l <= 16, the n-column tile in LDS
+  if (p.gram_prec == RSM_GRAM_BF16X2 &&
+      (p.y_dtype != RSM_F32 || l > 16 || (p.flags & RSM_PLAIN_GRAM) ||
+       static_cast<size_t>(ceil_div(p.n, 64) * 64) * 36 * sizeof(float) > kTileLdsBytes))
+    return RSM_E_UNSUPPORTED;
 
   P.m = p.m;
   P.n = p.n;
@@ -79,7 +83,9 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   int64_t splits = 1;
   int64_t groups = 1;
   if (P.tiled) {
-    groups = ceil_div(P.I > 0 ? P.I : 1, tile_threads(l, static_cast<int>(acc_elem)));
+    // trials per workgroup: one per thread (FP32 / FP64), 16 per wavefront of 8 (split-BF16)
+    const int per_group = (p.gram_prec == RSM_GRAM_BF16X2) ? 128 : tile_threads(l, static_cast<int>(acc_elem));
+    groups = ceil_div(P.I > 0 ? P.I : 1, per_group);
     splits = kTileTargetGroups / groups;
     if (splits < 1) splits = 1;
     if (splits >= 8) splits -= splits % 8;  // whole XCD rounds (see k_gram_tile)
@@ -335,7 +341,6 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   for (int32_t k = 0; k < nprob; ++k) {
     Plan& P = plans[k];
     P.tiled = gram_tiled_ok(P);
-    P.gram_vec = gram_vector_loads(P, ycm_of(P, inputs[k], ws + base[k]), ldy_of(P, inputs[k]));
     hp[k] = prob_desc(P, inputs[k], outputs[k], ws + base[k]);
   }
   put_prob_descs(hp.data(), nprob, dprob, s);
@@ -359,8 +364,7 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   // a2 + a3: one launch per (l, element type, precision, kernel)
   for_groups(plans, [](const Plan& P) { return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0; },
              [](const Plan& P) {
-               return int64_t(P.l) * 64 + P.y_dtype * 16 + P.prec * 4 + (P.tiled ? 2 : 0) +
-                      (P.gram_vec ? 1 : 0);
+               return int64_t(P.l) * 64 + P.y_dtype * 16 + P.prec * 4 + (P.tiled ? 1 : 0);
              },
              [&](const IdxList& g, const Plan* const* h) {
                mark_all(outputs, g, RSM_STEP_GRAM, 0, s);

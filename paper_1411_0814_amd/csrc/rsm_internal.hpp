@@ -67,7 +67,6 @@ struct Plan {
   size_t part_elem = 4;  // bytes of one partial-Gram element
   int gram_groups = 0;   // tiled Gram: trial groups (workgroups per row split)
   int gram_wgs = 0;      // workgroups of the Gram step of this problem
-  bool gram_vec = true;  // tiled Gram may load Y as 16-byte vectors
   // workspace offsets (bytes from the workspace base); ~0 = unused
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
          off_rows = 0;
@@ -167,10 +166,8 @@ void launch_solve_u(const ProbDesc* d, const IdxList& g, const Plan* const* h, h
 void launch_error(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
 
 // Whether the LDS-tiled Gram kernel can run this problem (its eligibility and matching
-// element types), and whether it can move Y at `ycm` as 16-byte vectors (alignment of Y
-// and of its columns).
+// element types).
 bool gram_tiled_ok(const Plan& P);
-bool gram_vector_loads(const Plan& P, const void* ycm, int64_t ldy);
 
 // V-hat of `nprob` problems in the same launches.  `host` holds their descriptors on the
 // host; `dev` is device memory for nprob descriptors (filled here, on the stream).

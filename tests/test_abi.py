@@ -95,6 +95,11 @@ def _ws(p):
     return code, out.value
 
 
+def test_split_bf16_accepted_for_fp32():
+    code, nbytes = _ws(_prob(gram_prec=_lib.GRAM_BF16X2, y_dtype=_lib.F32, r=15, l=16))
+    assert code == _lib.OK and nbytes > 0
+
+
 def test_workspace_bytes_valid_and_monotone():
     code, small = _ws(_prob())
     assert code == _lib.OK and small > 0
@@ -127,6 +132,10 @@ def test_workspace_bytes_valid_and_monotone():
     (dict(r=17, n=300, m=5000), _lib.E_UNSUPPORTED),
     (dict(l=18, r=5), _lib.E_UNSUPPORTED),
     (dict(n=5000, m=6000), _lib.E_UNSUPPORTED),
+    # split-BF16 runs on the tiled MFMA kernel only: FP32 Y, l <= 16, not the plain kernel
+    (dict(gram_prec=_lib.GRAM_BF16X2, y_dtype=_lib.F64), _lib.E_UNSUPPORTED),
+    (dict(gram_prec=_lib.GRAM_BF16X2, y_dtype=_lib.F32, r=16, l=17), _lib.E_UNSUPPORTED),
+    (dict(gram_prec=_lib.GRAM_BF16X2, y_dtype=_lib.F32, flags=_lib.PLAIN_GRAM), _lib.E_UNSUPPORTED),
 ])
 def test_invalid_problems_rejected_on_host(kw, code):
     assert _ws(_prob(**kw))[0] == code
