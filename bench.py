@@ -330,8 +330,16 @@ def main_precision(args):
     workers = min(16, os.cpu_count() or 4)
     pairs, t_or = oracle_parity(p, [runs[g]["V"] for g in runs], [runs[g]["U"] for g in runs],
                                 args.cpu_sample_rows, workers)
+    # the generating V (orthonormal, strongest direction first): how much of it each
+    # precision recovers, per leading k
+    Vbar = np.linalg.qr(p.Vbar)[0]
     for (theta, rms), g in zip(pairs, runs):
         runs[g].update(theta_max_rad=theta, rel_rms_known=rms)
+        Vg = np.linalg.qr(runs[g]["V"])[0]
+        # largest angle between the leading k generating directions and span(V-hat)
+        runs[g]["theta_vs_generating_V_leading_k"] = {
+            str(k): float(np.arcsin(min(1.0, np.linalg.norm(
+                Vbar[:, :k] - Vg @ (Vg.T @ Vbar[:, :k]), 2)))) for k in (4, 6, 7, 8)}
         lam = runs[g].pop("info")["lambda"]
         runs[g]["lambda_r"], runs[g]["lambda_r1"] = lam[p.r - 1], lam[p.r]
         del runs[g]["V"], runs[g]["U"]

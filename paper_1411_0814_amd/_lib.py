@@ -44,6 +44,7 @@ FINALIZE_ONLY = 1 << 1
 N_ACCUMULATE = 1 << 2
 COMPUTE_ERROR = 1 << 3
 PLAIN_GRAM = 1 << 4
+DETERMINISTIC = 1 << 5
 
 STEPS = ["pack", "subsets", "gram", "minor", "eig", "usolve", "error"]
 

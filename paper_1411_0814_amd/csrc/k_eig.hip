@@ -370,7 +370,7 @@ __global__ void k_put_desc(EigProbPack pack, EigProb* dst) {
 }
 
 // Nsym (full), Lf = lower(N) (the shift is added when a diagonal tile is factored), uncovered
-// columns, the padding of M and Mt (identity), zeroed row sums and small arrays.
+// columns, the padding of M and Mt (identity), zeroed small arrays.
 __global__ __launch_bounds__(256) void k_eig_prep(const EigProb* __restrict__ probs) {
   const EigProb& P = probs[blockIdx.y];
   const int64_t n = P.n, npad = P.npad;
@@ -379,7 +379,6 @@ __global__ __launch_bounds__(256) void k_eig_prep(const EigProb* __restrict__ pr
   if (idx >= npad * npad) return;
   const int64_t c = idx / npad, rr = idx - c * npad;
   if (rr < n && c < n) {
-    if (c == 0) P.Z[rr] = 0.0;
     const double v = (rr >= c) ? P.N[rr + c * n] : P.N[c + rr * n];
     P.Nsym[rr + c * n] = v;
     P.Lf[rr + c * n] = (rr >= c) ? v : 0.0;
@@ -394,7 +393,9 @@ __global__ __launch_bounds__(256) void k_eig_prep(const EigProb* __restrict__ pr
 }
 
 // Row sums of |N| over a column chunk (rows in 64-row blocks, columns split in 16 chunks):
-// rowsum_i += sum_{j in chunk} |N_ij|.  max_i rowsum_i >= lambda_max(N) (Gershgorin).
+// T[chunk n + i] = sum_{j in chunk} |N_ij|; max_i sum_chunk T[chunk n + i] >= lambda_max(N)
+// (Gershgorin).  Partial sums are stored, not added atomically, so the bound does not depend
+// on the order in which workgroups finish.
 __global__ __launch_bounds__(256) void k_rowsum(const EigProb* __restrict__ probs) {
   __shared__ double red[4][64];
   const EigProb& P = probs[blockIdx.z];
@@ -420,7 +421,8 @@ __global__ __launch_bounds__(256) void k_rowsum(const EigProb* __restrict__ prob
   }
   red[g][rr] = s;
   __syncthreads();
-  if (g == 0 && i < n) atomic_add_f64(generic(&P.Z[i]), red[0][rr] + red[1][rr] + red[2][rr] + red[3][rr]);
+  if (g == 0 && i < n)
+    P.T[static_cast<int64_t>(blockIdx.y) * n + i] = (red[0][rr] + red[1][rr]) + (red[2][rr] + red[3][rr]);
 }
 
 // ------------------------------------------------------------------ 2. Cholesky
@@ -440,7 +442,11 @@ __global__ __launch_bounds__(256) void k_chol_first(const EigProb* __restrict__ 
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = i0 + u * 256 + t;
-      x[u] = P.Z[i < n ? i : 0];
+      const int ic = i < n ? i : 0;
+      double sum = 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) sum += P.T[static_cast<int64_t>(c) * n + ic];
+      x[u] = sum;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -679,7 +685,8 @@ __global__ void k_start_vectors(const EigProb* __restrict__ probs) {
 
 // Out[j, c] = sum_i A[j, i] In[i, c] for 16 rows j per workgroup, all c < b.  MODE 0: A = M
 // (lower: i < j0 + 16), In = X, Out = Z.  MODE 1: A = Mt (upper: i >= j0), In = Z, Out = NX.
-// MODE 2: A = Nsym (all i), In = X, Out = NX, and H += X[rows]^T NX[rows] (Rayleigh-Ritz).
+// MODE 2: A = Nsym (all i), In = X, Out = NX, and the block's X[rows]^T NX[rows] of the
+// Rayleigh-Ritz matrix (into M, which is free by then).
 // Thread (jr, kp) = (t % 16, t / 16) sums over i = kp mod 16; In is staged through LDS in
 // chunks of 256 rows, the next chunk's loads in flight while the current one is summed; the
 // 16 partial sums are added through LDS.  No atomics on Out.
@@ -768,12 +775,13 @@ __global__ __launch_bounds__(256) void k_apply(const EigProb* __restrict__ probs
       xr[r2][c] = (j0 + r2 < n) ? gld(P.X, static_cast<uint32_t>(j0 + r2 + c * n)) : 0.0;
     }
     __syncthreads();
+    // this block's share of H, summed over the blocks in order by the Jacobi kernel
     for (int e = tid; e < b * b; e += 256) {
       const int i = e / b, j = e % b;
       double s = 0.0;
 #pragma unroll
       for (int q = 0; q < kRows; ++q) s += xr[q][i] * Ys[q][j];
-      atomic_add_f64(generic(&P.small[kSmallH + e]), s);
+      P.M[static_cast<int64_t>(blockIdx.x) * b * b + e] = s;
     }
   }
 }
@@ -994,17 +1002,31 @@ __global__ __launch_bounds__(256) void k_rr_small(const EigProb* __restrict__ pr
   const EigProb& P = probs[blockIdx.y];
   const int b = P.b;
   const int t = threadIdx.x;
-  gcdouble Hg = P.small + kSmallH;
-  double f2 = 0.0;
+  // H = sum of the blocks' shares (in block order), then symmetrised
+  const int nblk = static_cast<int>(ceil_div(P.n, kRows));
   for (int e = t; e < b * b; e += 256) {
-    const int i = e / b, j = e % b;
-    const double v = 0.5 * (Hg[i * b + j] + Hg[j * b + i]);
-    H[i][j] = v;
-    f2 += v * v;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < nblk; k0 += 4) {
+      double x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = P.M[static_cast<int64_t>(k0 + u < nblk ? k0 + u : 0) * b * b + e];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s4[u] += (k0 + u < nblk) ? x[u] : 0.0;
+    }
+    H[e / b][e % b] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   }
+  __syncthreads();
+  double f2 = 0.0;
+  double hs[2] = {0.0, 0.0};
+  for (int e = t, k = 0; e < b * b; e += 256, ++k) {
+    const int i = e / b, j = e % b;
+    hs[k] = 0.5 * (H[i][j] + H[j][i]);
+    f2 += hs[k] * hs[k];
+  }
+  __syncthreads();
+  for (int e = t, k = 0; e < b * b; e += 256, ++k) H[e / b][e % b] = hs[k];
   f2 = wave_sum(f2);
   if ((t & 63) == 0) red[t >> 6] = f2;
-  if (t < kEigMaxB) P.small[kSmallRes2 + t] = 0.0;
   __syncthreads();
   f2 = red[0] + red[1] + red[2] + red[3];
   jacobi_block(H, Q, b, perm, cs, sn, partner, &flag, 4.0 * 2.220446049250313e-16 * sqrt(f2));
@@ -1031,6 +1053,7 @@ __global__ __launch_bounds__(256) void k_rr_small(const EigProb* __restrict__ pr
 __global__ __launch_bounds__(256) void k_rr_apply(const EigProb* __restrict__ probs) {
   __shared__ double q[kEigMaxB * kEigMaxB];
   __shared__ double th[kEigMaxB];
+  __shared__ double red[4][RSM_MAX_R];
   const EigProb& P = probs[blockIdx.y];
   const int64_t n = P.n;
   const int b = P.b, r = P.r;
@@ -1069,7 +1092,12 @@ __global__ __launch_bounds__(256) void k_rr_apply(const EigProb* __restrict__ pr
   }
   int idx = 0;
   sum_many<RSM_MAX_R, 32>(res, lane, idx);
-  if ((lane & 3) == 0 && idx < r) atomic_add_f64(generic(&P.small[kSmallRes2 + idx]), res[0]);
+  if ((lane & 3) == 0) red[tid >> 6][idx] = res[0];
+  __syncthreads();
+  // this block's squared residuals (into T, free by then), summed in block order by k_rr_finish
+  if (tid < r)
+    P.T[static_cast<int64_t>(blockIdx.x) * RSM_MAX_R + tid] =
+        (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 __global__ void k_rr_finish(const EigProb* __restrict__ probs) {
@@ -1077,10 +1105,14 @@ __global__ void k_rr_finish(const EigProb* __restrict__ probs) {
   if (threadIdx.x != 0) return;
   const int b = P.b, r = P.r;
   gcdouble theta = P.small + kSmallTheta;
-  gcdouble res2 = P.small + kSmallRes2;
   const double lam_max = P.scal->lam_max;
+  const int nblk = static_cast<int>(ceil_div(P.n, 256));
   double rmax = 0.0;
-  for (int k = 0; k < r; ++k) rmax = fmax(rmax, sqrt(res2[k]));
+  for (int k = 0; k < r; ++k) {
+    double s = 0.0;
+    for (int blk = 0; blk < nblk; ++blk) s += P.T[static_cast<int64_t>(blk) * RSM_MAX_R + k];
+    rmax = fmax(rmax, sqrt(s));
+  }
   const double rel = lam_max > 0.0 ? rmax / lam_max : rmax;
   RSM_GLOBAL rsm_info* info = P.info;
   info->residual = rel;

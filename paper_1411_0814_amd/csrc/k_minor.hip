@@ -42,6 +42,16 @@ __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double a
   s = t * c;
 }
 
+// N[idx] += v: FP64 atomics, or (deterministic mode) 64-bit integer atomics on the
+// fixed-point image of N, whose sum does not depend on the order of the updates.
+__device__ __forceinline__ void add_to_N(RSM_GLOBAL double* N, int64_t idx, double v, bool fixed) {
+  if (fixed)
+    atomicAdd((unsigned long long*)&N[idx],
+              static_cast<unsigned long long>(llrint(v * kFixedScale)));
+  else
+    atomic_add_f64((double*)&N[idx], v);
+}
+
 // ------------------------------------------------------------------ split reduction
 
 template <typename TA>
@@ -67,7 +77,8 @@ __global__ void k_gram_reduce(const ProbDesc* __restrict__ probs, IdxList list) 
 // vv(i, k) entry i of eigenvector k.
 template <int L, typename EV, typename VV>
 __device__ __forceinline__ void finish_trial(int64_t t, int nvec, int64_t n, const int* c,
-                                             EV ev, VV vv, RSM_GLOBAL double* __restrict__ N,
+                                             EV ev, VV vv, bool fixed,
+                                             RSM_GLOBAL double* __restrict__ N,
                                              RSM_GLOBAL double* __restrict__ tap_vecs,
                                              RSM_GLOBAL double* __restrict__ tap_eigs) {
   int rank[L];
@@ -100,7 +111,7 @@ __device__ __forceinline__ void finish_trial(int64_t t, int nvec, int64_t n, con
 #pragma unroll
       for (int k = 0; k < L; ++k)
         if (rank[k] < nvec) pij += vv(i, k) * vv(j, k);
-      atomic_add_f64((double*)&N[static_cast<int64_t>(c[i]) + static_cast<int64_t>(c[j]) * n], pij);
+      add_to_N(N, static_cast<int64_t>(c[i]) + static_cast<int64_t>(c[j]) * n, pij, fixed);
     }
   }
 }
@@ -201,7 +212,7 @@ __global__ __launch_bounds__(64) void k_minor_reg(const ProbDesc* __restrict__ p
       if (!rotated) break;
     }
     finish_trial<L>(t, nvec, n, c, [&](int k) { return A(k, k); },
-                    [&](int i, int k) { return v(i, k); }, N, tap_vecs, tap_eigs);
+                    [&](int i, int k) { return v(i, k); }, P.fixed_n != 0, N, tap_vecs, tap_eigs);
   } else if (active) {
     if (tap_eigs)
       for (int k = 0; k < L; ++k) tap_eigs[t * L + k] = 0.0;
@@ -404,7 +415,7 @@ __global__ __launch_bounds__(64 * kWaveTrials) void k_minor_wave(const ProbDesc*
         ci = (k == i) ? c[k] : ci;
         cj = (k == j) ? c[k] : cj;
       }
-      atomic_add_f64((double*)&P.N[static_cast<int64_t>(ci) + static_cast<int64_t>(cj) * n], pij);
+      add_to_N(P.N, static_cast<int64_t>(ci) + static_cast<int64_t>(cj) * n, pij, P.fixed_n != 0);
     }
   } else if (active) {
     if (P.tap_eigs)

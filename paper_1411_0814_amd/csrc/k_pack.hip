@@ -152,6 +152,21 @@ __global__ void k_zero_N(const ProbDesc* __restrict__ probs, IdxList list) {
     P.N[i] = 0.0;
 }
 
+// N <-> 64-bit fixed point with 2^-40 resolution, in place.  Grid (blocks, problems).
+__global__ void k_n_fixed(const ProbDesc* __restrict__ probs, IdxList list, int to_fixed) {
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t count = P.n * P.n;
+  auto bits = reinterpret_cast<RSM_GLOBAL long long*>(P.N);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += stride) {
+    if (to_fixed)
+      bits[i] = llrint(P.N[i] * kFixedScale);
+    else
+      P.N[i] = static_cast<double>(bits[i]) * (1.0 / kFixedScale);
+  }
+}
+
 __global__ void k_init_info(const ProbDesc* __restrict__ probs, IdxList list) {
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
   RSM_GLOBAL rsm_info* info = P.info;
@@ -245,6 +260,16 @@ void launch_pack(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipS
     else
       k_transpose<double><<<grid, 256, 0, s>>>(d, yr);
   }
+}
+
+void launch_n_fixed(const ProbDesc* d, const IdxList& g, const Plan* const* h, bool to_fixed,
+                    hipStream_t s) {
+  if (!g.count) return;
+  int64_t nn = 0;
+  for (int k = 0; k < g.count; ++k) nn = std::max<int64_t>(nn, h[k]->n * h[k]->n);
+  const int64_t blocks = ceil_div(nn, 256);
+  k_n_fixed<<<dim3(static_cast<unsigned>(blocks < 1024 ? blocks : 1024), g.count), 256, 0, s>>>(
+      d, g, to_fixed ? 1 : 0);
 }
 
 void launch_subsets(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {

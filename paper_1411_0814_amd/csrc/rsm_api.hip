@@ -11,7 +11,7 @@ namespace rsm {
 namespace {
 
 constexpr uint32_t kKnownFlags = RSM_ACCUMULATE_ONLY | RSM_FINALIZE_ONLY | RSM_N_ACCUMULATE |
-                                 RSM_COMPUTE_ERROR | RSM_PLAIN_GRAM;
+                                 RSM_COMPUTE_ERROR | RSM_PLAIN_GRAM | RSM_DETERMINISTIC;
 constexpr size_t kAlign = 256;
 
 size_t carve(size_t& cursor, size_t bytes) {
@@ -189,6 +189,7 @@ ProbDesc prob_desc(const Plan& P, const rsm_input& in, const rsm_output& out, vo
   d.gram_groups = P.gram_groups;
   d.words_per_split = P.words_per_split;
   d.seed = P.seed;
+  d.fixed_n = (P.flags & RSM_DETERMINISTIC) ? 1 : 0;
   d.W = gptr(in.W);
   d.Yin = gptr(in.Y);
   d.ycm = gptr(const_cast<void*>(ycm_of(P, in, ws)));
@@ -371,13 +372,24 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
                launch_gram(dprob, g, h, s);
                mark_all(outputs, g, RSM_STEP_GRAM, 1, s);
              });
-  // a4 + a5: one launch per l
+  // a4 + a5: one launch per l.  Deterministic problems accumulate N in fixed point: a
+  // given N is converted to the grid first and everything back to FP64 afterwards.
+  auto fixed = [](const Plan& P) {
+    return !(P.flags & RSM_FINALIZE_ONLY) && (P.flags & RSM_DETERMINISTIC);
+  };
+  for_groups(plans, [&](const Plan& P) { return fixed(P) && (P.flags & RSM_N_ACCUMULATE); },
+             one_key, [&](const IdxList& g, const Plan* const* h) {
+               launch_n_fixed(dprob, g, h, true, s);
+             });
   for_groups(plans, front, [](const Plan& P) { return int64_t(P.l); },
              [&](const IdxList& g, const Plan* const* h) {
                mark_all(outputs, g, RSM_STEP_MINOR, 0, s);
                launch_minor(dprob, g, h, s);
                mark_all(outputs, g, RSM_STEP_MINOR, 1, s);
              });
+  for_groups(plans, fixed, one_key, [&](const IdxList& g, const Plan* const* h) {
+    launch_n_fixed(dprob, g, h, false, s);
+  });
   // a6 for every problem that finalises, in shared launches
   std::vector<EigProb> eig;
   IdxList fin;

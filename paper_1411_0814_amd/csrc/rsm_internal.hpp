@@ -76,14 +76,13 @@ struct Plan {
   size_t total = 0;
 };
 
-// Small per-problem arrays of the V-hat solver (doubles, in this order): the b x b
-// Rayleigh-Ritz matrix H, its sorted eigenvectors Qs, the Ritz values theta and the squared
-// residual norms res2.
-constexpr int kSmallH = 0;
-constexpr int kSmallQs = kEigMaxB * kEigMaxB;
-constexpr int kSmallTheta = 2 * kEigMaxB * kEigMaxB;
-constexpr int kSmallRes2 = 2 * kEigMaxB * kEigMaxB + kEigMaxB;
-constexpr int kSmallDoubles = 2 * kEigMaxB * kEigMaxB + 2 * kEigMaxB;
+// Small per-problem arrays of the V-hat solver (doubles, in this order): the sorted
+// eigenvectors Qs of the b x b Rayleigh-Ritz matrix and the Ritz values theta.  (The
+// Rayleigh-Ritz matrix and the residuals are summed from per-workgroup partials kept in the
+// solver's free matrices, in a fixed order, so that the result does not depend on timing.)
+constexpr int kSmallQs = 0;
+constexpr int kSmallTheta = kEigMaxB * kEigMaxB;
+constexpr int kSmallDoubles = kEigMaxB * kEigMaxB + kEigMaxB;
 
 // Device-side description of one V-hat solve (step a6).  The solver's kernels take an array
 // of these and run every problem of a batch in the same launch (problem = blockIdx.y); each
@@ -101,7 +100,7 @@ struct EigProb {
   RSM_GLOBAL double* Lf;       // trailing matrix of the factorisation (lower)
   RSM_GLOBAL double* M;        // L^{-1}, npad x npad, lower tiles
   RSM_GLOBAL double* Mt;       // (L^{-1})^T, npad x npad, upper tiles
-  RSM_GLOBAL double* T;        // recursion temporary (npad/2 x npad/2)
+  RSM_GLOBAL double* T;        // recursion temporary (npad/2 x npad/2); row-sum and residual partials
   RSM_GLOBAL double* X;        // n x b iterate
   RSM_GLOBAL double* Z;        // n x b; its first n entries hold the row sums at the start
   RSM_GLOBAL double* NX;       // n x b
@@ -122,6 +121,8 @@ struct ProbDesc {
   int32_t y_layout, w_layout, splits, gram_groups;
   int64_t words_per_split;
   uint64_t seed;
+  int32_t fixed_n;       // N accumulated as 64-bit fixed point (deterministic mode)
+  int32_t pad_;
   RSM_GLOBAL const uint8_t* W;
   RSM_GLOBAL const void* Yin;  // caller's Y
   RSM_GLOBAL void* ycm;        // column-major Y (the caller's, or the packed copy)
@@ -161,6 +162,11 @@ void launch_init_info(const ProbDesc* d, const IdxList& g, hipStream_t s);
 void launch_pack(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
 void launch_subsets(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
 void launch_gram(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
+// N between FP64 and its 64-bit fixed-point form (to_fixed: before accumulating onto a given
+// N; otherwise back to FP64 after accumulating).
+constexpr double kFixedScale = 1099511627776.0;  // 2^40
+void launch_n_fixed(const ProbDesc* d, const IdxList& g, const Plan* const* h, bool to_fixed,
+                    hipStream_t s);
 void launch_minor(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
 void launch_solve_u(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
 void launch_error(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);

@@ -58,6 +58,7 @@ class PoolItem:
     num_submatrices: int
     l: int = 0
     gram: str = "f32"
+    flags: int = 0                      # library flags, e.g. DETERMINISTIC
     footprint: int = field(default=0)   # bytes per request (filled by the server)
 
 
@@ -83,7 +84,7 @@ class Server:
     def _request(self, job: Job) -> Request:
         it = self.pool[job.item]
         return Request(Y=it.Y, W=it.W, r=it.r, num_submatrices=it.num_submatrices,
-                       seed=job.seed, l=it.l, gram=it.gram)
+                       seed=job.seed, l=it.l, gram=it.gram, flags=it.flags)
 
     def _footprint(self, it: PoolItem) -> int:
         req = Request(Y=it.Y, W=it.W, r=it.r, num_submatrices=it.num_submatrices, seed=0,
@@ -142,7 +143,8 @@ class Server:
                         results = decompose_batched(reqs, stream=st)
                     else:
                         results = [decompose(q.Y, q.W, q.r, q.num_submatrices, q.seed, l=q.l,
-                                             gram=q.gram, stream=st) for q in reqs]
+                                             gram=q.gram, flags=q.flags, stream=st)
+                                   for q in reqs]
                     ev = torch.cuda.Event()
                     ev.record(st)
                 t = time.perf_counter() - t0
