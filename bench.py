@@ -51,6 +51,8 @@ def parse():
                     help="per-trial column-streaming Gram kernel instead of the tiled one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the built-in Gram tile shapes (no autotuning before timing)")
     ap.add_argument("--cpu-sample-trials", type=int, default=4096)
     ap.add_argument("--cpu-sample-rows", type=int, default=2048,
                     help="rows of U in the parity check")
@@ -186,26 +188,41 @@ def _batch_setup(args, torch):
     return specs, inputs, reqs, t_gen
 
 
-def run_batched(args, torch):
-    """Batched RSM (one fused call for the whole batch) vs plain RSM (the same problems one
-    at a time through rsm_decompose on one stream), with oracle parity on a sample."""
-    from paper_1411_0814_amd import decompose, decompose_batched, workspace_bytes
-    specs, inputs, reqs, t_gen = _batch_setup(args, torch)
-    stream = torch.cuda.current_stream()
+def _time_batch(reqs, reps, stream, torch):
+    """Median seconds of one fused call over the batch (after one warm-up call)."""
+    from paper_1411_0814_amd import decompose_batched, workspace_bytes
     ws_need = workspace_bytes(reqs)
     ws = torch.empty(ws_need + 256, dtype=torch.uint8, device="cuda")
     ws = ws[(-ws.data_ptr()) % 256:][:ws_need]
     res = decompose_batched(reqs, stream=stream, workspace=ws)   # warm-up
     torch.cuda.synchronize()
     times = []
-    for _ in range(args.batch_reps):
+    for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         res = decompose_batched(reqs, stream=stream, workspace=ws)
         e1.record(stream)
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1) * 1e-3)
-    t_batch = float(np.median(times))
+    return float(np.median(times)), res
+
+
+def run_batched(args, torch):
+    """Batched RSM (one fused call for the whole batch) vs plain RSM (the same problems one
+    at a time through rsm_decompose on one stream), with oracle parity on a sample.  The
+    batch is timed with the built-in Gram tile shapes, then autotuned and timed again; the
+    plain leg keeps the built-in shapes."""
+    from paper_1411_0814_amd import decompose, tune, workspace_bytes
+    specs, inputs, reqs, t_gen = _batch_setup(args, torch)
+    stream = torch.cuda.current_stream()
+    tune.clear()
+    t_builtin, res = _time_batch(reqs, args.batch_reps, stream, torch)
+    tuned = None
+    if not args.no_tune:
+        tuned = tune.autotune(reqs, reps=2)
+        t_batch, res = _time_batch(reqs, args.batch_reps, stream, torch)
+    else:
+        t_batch = t_builtin
     # plain: one at a time on one stream, one workspace sized for the largest problem
     ws1_need = max(workspace_bytes([q]) for q in reqs)
     ws1 = torch.empty(ws1_need + 256, dtype=torch.uint8, device="cuda")
@@ -235,7 +252,12 @@ def run_batched(args, torch):
                                  "p99": round(float(np.percentile(lat_plain, 99)), 4)}},
         "speedup": round(t_plain / t_batch, 2),
         "gen_s": round(t_gen, 2),
+        "builtin_tiles": {"decompositions_per_s": round(len(reqs) / t_builtin, 1),
+                          "ms_per_batch": round(t_builtin * 1e3, 3)},
     }
+    if tuned is not None:
+        out["autotune"] = {"seconds": tuned["seconds"], "entries": len(tuned["entries"]),
+                           "groups": tuned["groups"]}
     if not args.no_parity and args.parity_problems > 0:
         from oracle import metrics, rsm
         pick = np.random.default_rng(7).choice(len(reqs), args.parity_problems, replace=False)
@@ -388,6 +410,9 @@ def main():
     stream = torch.cuda.current_stream(dev)
     req = Request(Y=Y, W=W, r=p.r, num_submatrices=p.num_submatrices, seed=p.seed_rsm, l=p.l,
                   gram=gram, flags=flags)
+    from paper_1411_0814_amd import tune
+    tune.clear()
+    tuned = None if args.no_tune or args.plain_gram else tune.autotune([req], reps=3)
     ws_need = workspace_bytes([req])
     ws = torch.empty(ws_need + 256, dtype=torch.uint8, device=dev)
     off = (-ws.data_ptr()) % 256
@@ -461,6 +486,8 @@ def main():
                  "lambda_r": info["lambda"][p.r - 1], "lambda_r1": info["lambda"][p.r]},
         "gen_s": round(t_gen, 1),
     }
+    if tuned is not None:
+        out["autotune"] = {"seconds": tuned["seconds"], "groups": tuned["groups"]}
     if not args.no_parity:
         workers = min(16, os.cpu_count() or 4)
         theta, rms, t_or = oracle_parity(p, last.V.cpu().numpy(), last.U.cpu().numpy(),

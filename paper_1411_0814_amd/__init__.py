@@ -282,3 +282,13 @@ def decompose(Y, W, r: int, num_submatrices: int, seed: int, *, l: int = 0, nvec
     res.stream = stream
     res._keep.append(ws_buf)  # keep the scratch alive until the stream is done
     return res
+
+
+def _load_tune_file():
+    import os
+    if os.environ.get("RSM_TUNE_FILE"):
+        from . import tune
+        tune.load_from_env()
+
+
+_load_tune_file()

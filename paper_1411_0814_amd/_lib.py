@@ -89,8 +89,15 @@ class Output(C.Structure):
     ]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [
+        ("l", C.c_int32), ("gram_prec", C.c_int32), ("y_dtype", C.c_int32),
+        ("batched", C.c_int32), ("gram_threads", C.c_int32), ("gram_wgs", C.c_int32),
+    ]
+
+
 EXPORTS = ["rsm_abi_version", "rsm_status_string", "rsm_workspace_bytes", "rsm_decompose",
-           "rsm_decompose_batched"]
+           "rsm_decompose_batched", "rsm_tune_set", "rsm_tune_get", "rsm_tune_threads"]
 
 _LIB = None
 
@@ -107,6 +114,10 @@ def lib() -> C.CDLL:
             raise LibraryMissing(
                 f"{LIB_PATH} not found: build it with `python -m paper_1411_0814_amd.build` "
                 "(or __graft_entry__.build()); there is no CPU fallback")
+        # torch first: the library must bind to the HIP runtime torch already carries
+        # (the streams and buffers it is given are torch's); loaded first, it would pull a
+        # second runtime into the process, where torch's stream handles are not valid
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         L.rsm_abi_version.restype = C.c_int32
         L.rsm_abi_version.argtypes = []
@@ -121,6 +132,13 @@ def lib() -> C.CDLL:
         L.rsm_decompose_batched.argtypes = [C.c_int32, C.POINTER(Problem), C.POINTER(Input),
                                             C.POINTER(Output), C.c_void_p, C.c_size_t,
                                             C.c_void_p]
+        L.rsm_tune_set.restype = C.c_int32
+        L.rsm_tune_set.argtypes = [C.POINTER(TuneEntry), C.c_int32]
+        L.rsm_tune_get.restype = C.c_int32
+        L.rsm_tune_get.argtypes = [C.POINTER(TuneEntry), C.c_int32, C.POINTER(C.c_int32)]
+        L.rsm_tune_threads.restype = C.c_int32
+        L.rsm_tune_threads.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                       C.c_int32, C.POINTER(C.c_int32)]
         if L.rsm_abi_version() != ABI_VERSION:
             raise LibraryMissing("librsm ABI version mismatch; rebuild the library")
         _LIB = L
@@ -147,3 +165,31 @@ def workspace_bytes(problems) -> int:
     out = C.c_size_t(0)
     check(lib().rsm_workspace_bytes(arr, len(problems), C.byref(out)), "rsm_workspace_bytes")
     return int(out.value)
+
+
+TUNE_FIELDS = [f for f, _ in TuneEntry._fields_]
+
+
+def tune_set(entries) -> None:
+    """Replace the library's tile table with `entries` (dicts with TUNE_FIELDS keys)."""
+    arr = (TuneEntry * max(1, len(entries)))()
+    for k, e in enumerate(entries):
+        for f in TUNE_FIELDS:
+            setattr(arr[k], f, int(e[f]))
+    check(lib().rsm_tune_set(arr, len(entries)), "rsm_tune_set")
+
+
+def tune_get() -> list[dict]:
+    count = C.c_int32(0)
+    check(lib().rsm_tune_get(None, 0, C.byref(count)), "rsm_tune_get")
+    arr = (TuneEntry * max(1, count.value))()
+    check(lib().rsm_tune_get(arr, count.value, C.byref(count)), "rsm_tune_get")
+    return [{f: int(getattr(arr[k], f)) for f in TUNE_FIELDS} for k in range(count.value)]
+
+
+def tune_threads(l: int, gram_prec: int, y_dtype: int) -> list[int]:
+    buf = (C.c_int32 * 8)()
+    count = C.c_int32(0)
+    check(lib().rsm_tune_threads(l, gram_prec, y_dtype, buf, 8, C.byref(count)),
+          "rsm_tune_threads")
+    return [int(buf[k]) for k in range(min(count.value, 8))]

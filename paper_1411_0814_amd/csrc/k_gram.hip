@@ -325,6 +325,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBfTrialsPerWave = 16;
 constexpr int kBfThreads = 512;
+static_assert(kBfThreads / 64 * kBfTrialsPerWave == kBfTrialsPerGroup, "BF16 trial groups");
 
 template <int L>
 __global__ __launch_bounds__(kBfThreads) void k_gram_bf16(const ProbDesc* __restrict__ probs,
@@ -440,9 +441,16 @@ size_t tile_lds(const Plan& P, int NT, size_t extra_per_thread) {
          static_cast<size_t>(m_pad) * sizeof(uint32_t) + NT * extra_per_thread;
 }
 
+// Largest trial count per workgroup built for the tiled kernel: 512 threads leave 128
+// registers per thread, enough for the l(l+1)/2 accumulators up to these l; 256 is always
+// built.
 template <int L, typename T>
-void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
-  constexpr int NT = tile_threads(L, sizeof(T));
+constexpr bool tile_has_512() {
+  return sizeof(T) == 4 ? L <= 10 : L <= 6;
+}
+
+template <int L, typename T, int NT>
+void run_tile_nt(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
   size_t lds = 0;
   int wgs = 0;
   for (int k = 0; k < g.count; ++k) {
@@ -458,6 +466,18 @@ void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStre
   }
   const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
   k_gram_tile<L, T, NT><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
+}
+
+// The group shares its trials per workgroup (part of the launch key).
+template <int L, typename T>
+void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  if constexpr (tile_has_512<L, T>()) {
+    if (h[0]->gram_threads == 512) {
+      run_tile_nt<L, T, 512>(d, g, h, s);
+      return;
+    }
+  }
+  run_tile_nt<L, T, 256>(d, g, h, s);
 }
 
 template <int L>
@@ -516,6 +536,22 @@ void dispatch_types(const ProbDesc* d, const IdxList& g, const Plan* const* h, h
 }
 
 }  // namespace
+
+int gram_threads_built(int l, int prec, int y_dtype, int* out) {
+  if (prec == RSM_GRAM_BF16X2) {
+    if (y_dtype != RSM_F32 || l > 16) return 0;
+    out[0] = kBfTrialsPerGroup;
+    return 1;
+  }
+  const bool f64 = prec == RSM_GRAM_F64;
+  if (f64 != (y_dtype == RSM_F64)) return 0;
+  out[0] = 256;
+  if (l <= (f64 ? 6 : 10)) {
+    out[1] = 512;
+    return 2;
+  }
+  return 1;
+}
 
 bool gram_tiled_ok(const Plan& P) {
   if (!P.tiled) return false;

@@ -2,6 +2,7 @@
 // workspace layout of each problem, and the launch sequence of steps a0..a7.
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "rsm_internal.hpp"
@@ -73,24 +74,37 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   while (nbp < P.nb) nbp *= 2;
   P.npad = nbp * kCholNB;
 
-  // Gram step.  Tiled kernel (one trial per thread, a 32-row x n tile of Y in LDS): split
-  // the rows so that (trial groups) x (splits) is about one workgroup per CU.  Per-trial
-  // streamer: enough wavefronts of (trial, split).
-  const size_t acc_elem = (p.gram_prec == RSM_GRAM_F64) ? sizeof(double) : sizeof(float);
-  const size_t tile_stride = (acc_elem == sizeof(double)) ? 34 : 36;  // see k_gram_tile
-  P.tiled = !(p.flags & RSM_PLAIN_GRAM) &&
-            static_cast<size_t>(ceil_div(p.n, 64) * 64) * tile_stride * acc_elem <= kTileLdsBytes;
+  // Gram kernel: LDS-tiled (Y tile shared by a group of trials) when the n-column tile fits
+  // and the accumulation type matches Y's (split-BF16: FP32 Y), else the per-trial streamer
+  P.tiled = !(p.flags & RSM_PLAIN_GRAM);
+  P.tiled = gram_tiled_ok(P);
+  if (P.tiled) set_gram_shape(P, default_gram_threads(P), 0);
+  else set_gram_shape(P, 0, 0);
+  return RSM_OK;
+}
+
+// Trials per workgroup of the tiled kernels when the tile table does not say otherwise.
+int default_gram_threads(const Plan& P) {
+  if (P.prec == RSM_GRAM_BF16X2) return kBfTrialsPerGroup;
+  return tile_threads(P.l, P.prec == RSM_GRAM_F64 ? 8 : 4);
+}
+
+// Row splits of the Gram step.  Tiled: `threads` trials per workgroup and `splits_hint`
+// splits (chosen for a whole launch), or with splits_hint == 0 enough splits for about one
+// workgroup per CU for this problem alone.  Per-trial streamer: enough wavefronts of
+// (trial, split).
+void set_gram_shape(Plan& P, int threads, int64_t splits_hint) {
   int64_t splits = 1;
   int64_t groups = 1;
   if (P.tiled) {
-    // trials per workgroup: one per thread (FP32 / FP64), 16 per wavefront of 8 (split-BF16)
-    const int per_group = (p.gram_prec == RSM_GRAM_BF16X2) ? 128 : tile_threads(l, static_cast<int>(acc_elem));
-    groups = ceil_div(P.I > 0 ? P.I : 1, per_group);
-    splits = kTileTargetGroups / groups;
+    P.gram_threads = threads;
+    groups = ceil_div(P.I > 0 ? P.I : 1, threads);
+    splits = splits_hint > 0 ? splits_hint : kTileTargetGroups / groups;
     if (splits < 1) splits = 1;
     if (splits >= 8) splits -= splits % 8;  // whole XCD rounds (see k_gram_tile)
-  } else if (P.I > 0 && P.I < 8192) {
-    splits = ceil_div(8192, P.I);
+  } else {
+    P.gram_threads = 0;
+    if (P.I > 0 && P.I < 8192) splits = ceil_div(8192, P.I);
   }
   if (splits > P.mw) splits = P.mw;
   P.words_per_split = ceil_div(P.mw, splits);
@@ -98,16 +112,18 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   P.splits = static_cast<int>(ceil_div(P.mw, P.words_per_split));
   P.gram_groups = static_cast<int>(groups);
   P.gram_wgs = P.gram_groups * P.splits;
+}
 
-  // workspace layout
+// Workspace offsets of one problem (after its Gram shape is fixed).
+void set_layout(Plan& P) {
   size_t cur = 0;
   P.off_scal = carve(cur, sizeof(DevScalars));
   P.off_wbits = carve(cur, static_cast<size_t>(P.n) * P.mw * sizeof(uint64_t));
-  const size_t yelem = (p.y_dtype == RSM_F64) ? sizeof(double) : sizeof(float);
-  P.off_ypack = (p.y_layout == RSM_ROW_MAJOR)
+  const size_t yelem = (P.y_dtype == RSM_F64) ? sizeof(double) : sizeof(float);
+  P.off_ypack = (P.y_layout == RSM_ROW_MAJOR)
                     ? carve(cur, static_cast<size_t>(P.n) * P.m * yelem)
                     : ~size_t(0);
-  P.off_cols = carve(cur, static_cast<size_t>(P.I) * l * sizeof(int32_t));
+  P.off_cols = carve(cur, static_cast<size_t>(P.I) * P.l * sizeof(int32_t));
   P.off_part = carve(cur, static_cast<size_t>(P.splits) * P.I * P.ng * P.part_elem);
   P.off_prow = carve(cur, static_cast<size_t>(P.splits) * P.I * sizeof(int32_t));
   P.off_G = carve(cur, static_cast<size_t>(P.I) * P.ng * sizeof(double));
@@ -126,6 +142,66 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   P.off_NX = carve(cur, nbv);
   P.off_small = carve(cur, kSmallDoubles * sizeof(double));
   P.total = cur;
+}
+
+namespace {
+
+std::mutex g_tune_mu;
+std::vector<rsm_tune_entry> g_tune;  // the tile table (later duplicates of a key win)
+
+std::vector<rsm_tune_entry> tune_snapshot() {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  return g_tune;
+}
+
+const rsm_tune_entry* tune_find(const std::vector<rsm_tune_entry>& t, const Plan& P,
+                                bool batched) {
+  const rsm_tune_entry* hit = nullptr;
+  for (const rsm_tune_entry& e : t)
+    if (e.l == P.l && e.gram_prec == P.prec && e.y_dtype == P.y_dtype &&
+        e.batched == (batched ? 1 : 0))
+      hit = &e;
+  return hit;
+}
+
+}  // namespace
+
+// Plans of one call's problems: each problem's own plan; then, for every launch group of
+// the tiled Gram that the tile table covers (problems sharing l, Y's type and the
+// precision, deterministic ones excepted), the table's trials per workgroup and one row
+// split count for the group, sized so that the launch reaches the table's workgroup
+// target; then the workspace layouts.
+int32_t make_plans(const rsm_problem* problems, int32_t nprob, std::vector<Plan>& plans) {
+  plans.assign(static_cast<size_t>(nprob), Plan{});
+  for (int32_t k = 0; k < nprob; ++k) {
+    const int32_t st = make_plan(problems[k], plans[k]);
+    if (st != RSM_OK) return st;
+  }
+  const std::vector<rsm_tune_entry> table = tune_snapshot();
+  if (!table.empty()) {
+    std::map<int64_t, std::vector<int32_t>> groups;
+    for (int32_t k = 0; k < nprob; ++k) {
+      const Plan& P = plans[k];
+      if (!P.tiled || P.I <= 0 || (P.flags & (RSM_FINALIZE_ONLY | RSM_DETERMINISTIC))) continue;
+      groups[(int64_t(P.l) * 4 + P.y_dtype) * 4 + P.prec].push_back(k);
+    }
+    for (const auto& kv : groups) {
+      const std::vector<int32_t>& members = kv.second;
+      const Plan& P0 = plans[members[0]];
+      const rsm_tune_entry* e = tune_find(table, P0, members.size() > 1);
+      if (!e) continue;
+      const int threads = e->gram_threads ? e->gram_threads : default_gram_threads(P0);
+      int64_t splits = 0;
+      if (e->gram_wgs > 0) {
+        int64_t total = 0;
+        for (int32_t k : members) total += ceil_div(plans[k].I, threads);
+        splits = e->gram_wgs / total;
+        if (splits < 1) splits = 1;
+      }
+      for (int32_t k : members) set_gram_shape(plans[k], threads, splits);
+    }
+  }
+  for (Plan& P : plans) set_layout(P);
   return RSM_OK;
 }
 
@@ -297,13 +373,11 @@ static size_t desc_bytes(int32_t nprob) {
 
 int32_t rsm_workspace_bytes(const rsm_problem* problems, int32_t nprob, size_t* bytes) {
   if (!problems || !bytes || nprob < 1) return RSM_E_ARG;
+  std::vector<rsm::Plan> plans;
+  const int32_t st = rsm::make_plans(problems, nprob, plans);
+  if (st != RSM_OK) return st;
   size_t total = 0;
-  for (int32_t k = 0; k < nprob; ++k) {
-    rsm::Plan P;
-    const int32_t st = rsm::make_plan(problems[k], P);
-    if (st != RSM_OK) return st;
-    total += rsm::align_up(P.total, 256);
-  }
+  for (const rsm::Plan& P : plans) total += rsm::align_up(P.total, 256);
   *bytes = total + desc_bytes(nprob);
   return RSM_OK;
 }
@@ -319,11 +393,12 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   using namespace rsm;
   if (nprob < 1 || !problems || !inputs || !outputs) return RSM_E_ARG;
   size_t need = 0;
-  std::vector<Plan> plans(static_cast<size_t>(nprob));
+  std::vector<Plan> plans;
+  int32_t st = make_plans(problems, nprob, plans);
+  if (st != RSM_OK) return st;
   std::vector<size_t> base(static_cast<size_t>(nprob));
   for (int32_t k = 0; k < nprob; ++k) {
-    int32_t st = make_plan(problems[k], plans[k]);
-    if (st == RSM_OK) st = check_io(plans[k], inputs[k], outputs[k]);
+    st = check_io(plans[k], inputs[k], outputs[k]);
     if (st != RSM_OK) return st;
     base[k] = need;
     need += align_up(plans[k].total, 256);
@@ -339,11 +414,7 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   auto* deig = reinterpret_cast<EigProb*>(ws + desc_off + align_up(static_cast<size_t>(nprob) * sizeof(ProbDesc), 256));
 
   std::vector<ProbDesc> hp(static_cast<size_t>(nprob));
-  for (int32_t k = 0; k < nprob; ++k) {
-    Plan& P = plans[k];
-    P.tiled = gram_tiled_ok(P);
-    hp[k] = prob_desc(P, inputs[k], outputs[k], ws + base[k]);
-  }
+  for (int32_t k = 0; k < nprob; ++k) hp[k] = prob_desc(plans[k], inputs[k], outputs[k], ws + base[k]);
   put_prob_descs(hp.data(), nprob, dprob, s);
 
   auto all = [](const Plan&) { return true; };
@@ -362,10 +433,11 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
     launch_subsets(dprob, g, h, s);
     mark_all(outputs, g, RSM_STEP_SUBSETS, 1, s);
   });
-  // a2 + a3: one launch per (l, element type, precision, kernel)
+  // a2 + a3: one launch per (l, element type, precision, kernel, trials per workgroup)
   for_groups(plans, [](const Plan& P) { return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0; },
              [](const Plan& P) {
-               return int64_t(P.l) * 64 + P.y_dtype * 16 + P.prec * 4 + (P.tiled ? 1 : 0);
+               return ((((int64_t(P.l) * 4 + P.y_dtype) * 4 + P.prec) * 2 + (P.tiled ? 1 : 0)) *
+                       1024) + P.gram_threads;
              },
              [&](const IdxList& g, const Plan* const* h) {
                mark_all(outputs, g, RSM_STEP_GRAM, 0, s);
@@ -421,6 +493,50 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
                mark_all(outputs, g, RSM_STEP_ERROR, 1, s);
              });
   return hipGetLastError() == hipSuccess ? RSM_OK : RSM_E_DEVICE;
+}
+
+int32_t rsm_tune_set(const rsm_tune_entry* entries, int32_t count) {
+  using namespace rsm;
+  if (count < 0 || (count > 0 && !entries)) return RSM_E_ARG;
+  for (int32_t k = 0; k < count; ++k) {
+    const rsm_tune_entry& e = entries[k];
+    if (e.l < 2 || e.l > RSM_MAX_L || e.gram_prec < RSM_GRAM_F64 ||
+        e.gram_prec > RSM_GRAM_BF16X2 || (e.y_dtype != RSM_F32 && e.y_dtype != RSM_F64) ||
+        (e.batched != 0 && e.batched != 1) || e.gram_wgs < 0 || e.gram_wgs > (1 << 20) ||
+        e.gram_threads < 0)
+      return RSM_E_ARG;
+    if (e.gram_threads) {
+      int built[8];
+      const int nb = gram_threads_built(e.l, e.gram_prec, e.y_dtype, built);
+      bool ok = false;
+      for (int j = 0; j < nb; ++j) ok = ok || built[j] == e.gram_threads;
+      if (!ok) return RSM_E_ARG;
+    }
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.assign(entries, entries + count);
+  return RSM_OK;
+}
+
+int32_t rsm_tune_get(rsm_tune_entry* entries, int32_t cap, int32_t* count) {
+  using namespace rsm;
+  if (!count || cap < 0 || (cap > 0 && !entries)) return RSM_E_ARG;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const int32_t n = static_cast<int32_t>(g_tune.size());
+  for (int32_t k = 0; k < n && k < cap; ++k) entries[k] = g_tune[k];
+  *count = n;
+  return RSM_OK;
+}
+
+int32_t rsm_tune_threads(int32_t l, int32_t gram_prec, int32_t y_dtype, int32_t* threads,
+                         int32_t cap, int32_t* count) {
+  using namespace rsm;
+  if (!count || cap < 0 || (cap > 0 && !threads) || l < 2 || l > RSM_MAX_L) return RSM_E_ARG;
+  int built[8];
+  const int nb = gram_threads_built(l, gram_prec, y_dtype, built);
+  for (int j = 0; j < nb && j < cap; ++j) threads[j] = built[j];
+  *count = nb;
+  return RSM_OK;
 }
 
 }  // extern "C"

@@ -7,6 +7,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include <vector>
+
 #include "rsm.h"
 
 // In the device pass the descriptors' pointers are typed as global memory, so accesses
@@ -26,6 +28,9 @@ constexpr int kEigMaxB = RSM_MAX_R + kEigPad + 1;
 constexpr int kEigIters = 3;              // inverse-iteration steps
 constexpr size_t kTileLdsBytes = 148 * 1024;  // LDS budget of the Y tile of the tiled Gram
 constexpr int64_t kTileTargetGroups = 256;    // tiled Gram: workgroups to aim for (one per CU)
+
+// Trials per workgroup of the split-BF16 Gram kernel (16 per wavefront, 8 wavefronts).
+constexpr int kBfTrialsPerGroup = 128;
 
 // Threads (= trials) per workgroup of the tiled Gram kernel: as many as the register file
 // allows with l(l+1)/2 accumulators plus the prefetched next tile held per thread.
@@ -66,6 +71,7 @@ struct Plan {
   int64_t npad = 0;      // 64 x (nb rounded up to a power of two): size of L^{-1}
   size_t part_elem = 4;  // bytes of one partial-Gram element
   int gram_groups = 0;   // tiled Gram: trial groups (workgroups per row split)
+  int gram_threads = 0;  // tiled Gram: trials per workgroup (0: per-trial streamer)
   int gram_wgs = 0;      // workgroups of the Gram step of this problem
   // workspace offsets (bytes from the workspace base); ~0 = unused
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
@@ -151,9 +157,6 @@ struct IdxList {
   int32_t idx[kLaunchMax];
 };
 
-// Fills `plan` from `p` (defaults resolved, sizes checked).  Returns RSM_OK or an error.
-int32_t make_plan(const rsm_problem& p, Plan& plan);
-
 // Host launchers.  Each enqueues on `s` one launch (or one per storage layout) for every
 // problem in `g`; `d` is the device descriptor array and `h[k]` the plan of problem
 // g.idx[k].  Launchers that instantiate a kernel per l or r require the group to share it.
@@ -170,6 +173,19 @@ void launch_n_fixed(const ProbDesc* d, const IdxList& g, const Plan* const* h, b
 void launch_minor(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
 void launch_solve_u(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
 void launch_error(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
+
+// Planning (rsm_api.hip): a problem's own plan (validation, sizes, default Gram shape);
+// the Gram row splits for `threads` trials per workgroup (splits_hint 0: this problem
+// alone); the workspace offsets; all plans of a call, with the tile table applied.
+int32_t make_plan(const rsm_problem& p, Plan& P);
+int default_gram_threads(const Plan& P);
+void set_gram_shape(Plan& P, int threads, int64_t splits_hint);
+void set_layout(Plan& P);
+int32_t make_plans(const rsm_problem* problems, int32_t nprob, std::vector<Plan>& plans);
+
+// Trials-per-workgroup values built for the tiled Gram of (l, precision, Y type), ascending,
+// into out[0..7]; returns their number (0: the per-trial streamer runs it).
+int gram_threads_built(int l, int prec, int y_dtype, int* out);
 
 // Whether the LDS-tiled Gram kernel can run this problem (its eligibility and matching
 // element types).

@@ -46,6 +46,9 @@ int main(void) {
   F(rsm_info, lambda) F(rsm_info, residual) F(rsm_info, mu) F(rsm_info, e)
   F(rsm_output, V) F(rsm_output, info) F(rsm_output, trial_cols) F(rsm_output, trial_eigs)
   F(rsm_output, step_events)
+  printf("rsm_tune_entry %zu\n", sizeof(rsm_tune_entry));
+  F(rsm_tune_entry, l) F(rsm_tune_entry, gram_prec) F(rsm_tune_entry, y_dtype)
+  F(rsm_tune_entry, batched) F(rsm_tune_entry, gram_threads) F(rsm_tune_entry, gram_wgs)
   printf("STEPS %d\n", RSM_NUM_STEPS);
   printf("MAX %d %d %d %d\n", RSM_MAX_R, RSM_MAX_L, RSM_MAX_N, RSM_ABI_VERSION);
   return 0;
@@ -69,9 +72,10 @@ def test_struct_layouts_match_header():
     assert int(got["rsm_input"][0]) == C.sizeof(_lib.Input)
     assert int(got["rsm_info"][0]) == C.sizeof(_lib.Info)
     assert int(got["rsm_output"][0]) == C.sizeof(_lib.Output)
+    assert int(got["rsm_tune_entry"][0]) == C.sizeof(_lib.TuneEntry)
     pyname = {"lambda": "lambda_"}
     structs = {"rsm_problem": _lib.Problem, "rsm_input": _lib.Input, "rsm_info": _lib.Info,
-               "rsm_output": _lib.Output}
+               "rsm_output": _lib.Output, "rsm_tune_entry": _lib.TuneEntry}
     for k, v in got.items():
         if "." in k and k != "STEPS":
             s, f = k.split(".")
@@ -182,3 +186,72 @@ def test_status_strings():
         s = _lib.status_string(code)
         assert s and s != "unknown status"
     assert _lib.status_string(12345) == "unknown status"
+
+
+@pytest.fixture
+def empty_tune_table():
+    _lib.tune_set([])
+    yield
+    _lib.tune_set([])
+
+
+def _entry(**kw):
+    e = {"l": 9, "gram_prec": _lib.GRAM_F32, "y_dtype": _lib.F32, "batched": 0,
+         "gram_threads": 512, "gram_wgs": 1024}
+    e.update(kw)
+    return e
+
+
+def test_tune_threads_lists_built_kernels():
+    F32, F64 = _lib.F32, _lib.F64
+    assert _lib.tune_threads(9, _lib.GRAM_F32, F32) == [256, 512]
+    assert _lib.tune_threads(10, _lib.GRAM_F32, F32) == [256, 512]
+    assert _lib.tune_threads(12, _lib.GRAM_F32, F32) == [256]
+    assert _lib.tune_threads(6, _lib.GRAM_F64, F64) == [256, 512]
+    assert _lib.tune_threads(7, _lib.GRAM_F64, F64) == [256]
+    assert _lib.tune_threads(6, _lib.GRAM_F64, F32) == []        # per-trial streamer
+    assert _lib.tune_threads(16, _lib.GRAM_BF16X2, F32) == [128]
+    assert _lib.tune_threads(17, _lib.GRAM_BF16X2, F32) == []
+
+
+def test_tune_table_roundtrip_and_validation(empty_tune_table):
+    good = [_entry(), _entry(l=12, gram_threads=256, batched=1, gram_wgs=0),
+            _entry(l=16, gram_prec=_lib.GRAM_BF16X2, gram_threads=128, gram_wgs=64)]
+    _lib.tune_set(good)
+    assert _lib.tune_get() == good
+    bad = [_entry(l=1), _entry(l=_lib.MAX_L + 1), _entry(gram_threads=384),
+           _entry(l=12, gram_threads=512), _entry(gram_wgs=-1), _entry(gram_wgs=(1 << 20) + 1),
+           _entry(batched=2), _entry(y_dtype=7), _entry(gram_prec=3),
+           _entry(gram_prec=_lib.GRAM_F64, gram_threads=256)]     # F64 Gram of F32 Y: streamer
+    for e in bad:
+        with pytest.raises(_lib.RSMError) as ei:
+            _lib.tune_set(good[:1] + [e])
+        assert ei.value.code == _lib.E_ARG, e
+        assert _lib.tune_get() == good                           # unchanged on error
+    _lib.tune_set([])
+    assert _lib.tune_get() == []
+
+
+def test_tune_table_sets_the_gram_shape(empty_tune_table):
+    """A table entry changes the Gram row splits (part of the workspace) only for the launch
+    kind it names, and never for deterministic problems."""
+    p = _prob(m=131072, n=1024, r=8, l=9, num_submatrices=8192, gram_prec=_lib.GRAM_F32,
+              y_dtype=_lib.F32)
+    code, base = _ws(p)
+    assert code == _lib.OK
+    # built-in: 16 groups of 512 trials x 16 splits; 8192 workgroups -> 512 splits
+    _lib.tune_set([_entry(gram_wgs=8192)])
+    code, more = _ws(p)
+    part_row = 8192 * 45 * 4 + 8192 * 4            # partial Grams + partial row counts
+    assert more - base >= (512 - 16) * part_row - 4096
+    # 256 trials per workgroup and a one-workgroup-per-group target: a single split
+    _lib.tune_set([_entry(gram_threads=256, gram_wgs=1)])
+    code, fewer = _ws(p)
+    assert base - fewer >= 15 * part_row - 4096
+    # entries for batched launches or another l do not apply to this lone problem
+    _lib.tune_set([_entry(batched=1, gram_wgs=8192), _entry(l=10, gram_wgs=8192)])
+    assert _ws(p)[1] == base
+    _lib.tune_set([_entry(gram_wgs=8192)])
+    assert _ws(_prob(m=131072, n=1024, r=8, l=9, num_submatrices=8192,
+                     gram_prec=_lib.GRAM_F32, y_dtype=_lib.F32,
+                     flags=_lib.DETERMINISTIC))[1] == base
