@@ -1,11 +1,16 @@
 // Step a7: U-hat by eq.(solve.barU) with the L2 norm, row by row:
 //   u_i = argmin_u sum_j w_ij (y_ij - u^T v_j)^2  =>  A_i u_i = b_i,
 //   A_i = sum_{j known} v_j v_j^T (r x r),  b_i = sum_{j known} y_ij v_j.
-// One thread per row; a wavefront covers 64 consecutive rows, i.e. one word of each
-// column's mask bit-plane, read once per wavefront.  V-hat is staged through LDS in
-// chunks of columns and read as a broadcast.  A_i is factorised by Cholesky in registers
-// (FP64).  Rows with fewer than r known entries (or a singular A_i) get u_i = 0 and are
-// counted as underdetermined.
+// Two ways to form A_i and b_i (both FP64):
+//  - k_usolve: one thread per row; a wavefront covers 64 consecutive rows, i.e. one word of
+//    each column's mask bit-plane, read once per wavefront.  V-hat is staged through LDS in
+//    chunks of columns and read as a broadcast.  Used for small r.
+//  - k_uform: for all rows at once, [A | b] = W~ [K | V] as one dense product on the FP64
+//    matrix cores, where row j of K holds the products v_ja v_jb (a >= b) of V-hat's row j
+//    and W~ is the 0/1 mask (for the A part) or the mask times Y (for the b part).  The
+//    r(r+1)/2 + r results per row go to the workspace; k_usolve_ab solves them.
+// A_i is factorised by Cholesky in registers, one thread per row.  Rows with fewer than r
+// known entries (or a singular A_i) get u_i = 0 and are counted as underdetermined.
 //
 // Also: the optional error of eq.(ep), e = (sum w)^-1/2 ||W o (Y - U V^T)||_F.
 #include <algorithm>
@@ -27,6 +32,72 @@ constexpr int u_unroll() {
   return R <= 8 ? 4 : (R <= 12 ? 2 : 1);
 }
 
+// Cholesky of A (packed lower triangle, row-major: entry (a, b), b <= a, at a(a+1)/2 + b)
+// in place, then A u = b by two triangular solves; u_i = 0 unless the row has at least r
+// known entries and every pivot is positive.  Writes U's row, and adds the wavefront's
+// underdetermined rows and known entries to the problem's info.
+template <int R>
+__device__ __forceinline__ void solve_row(const ProbDesc& P, double (&A)[R * (R + 1) / 2],
+                                          const double (&bv)[R], int cnt, bool active,
+                                          int64_t i) {
+  const int64_t m = P.m;
+  bool ok = active && cnt >= R;
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      double d = A[j * (j + 1) / 2 + j];
+#pragma unroll
+      for (int p = 0; p < j; ++p) d -= A[j * (j + 1) / 2 + p] * A[j * (j + 1) / 2 + p];
+      ok &= (d > 0.0);
+      const double ljj = sqrt(d > 0.0 ? d : 1.0);
+      A[j * (j + 1) / 2 + j] = ljj;
+#pragma unroll
+      for (int ii = j + 1; ii < R; ++ii) {
+        double s = A[ii * (ii + 1) / 2 + j];
+#pragma unroll
+        for (int p = 0; p < j; ++p) s -= A[ii * (ii + 1) / 2 + p] * A[j * (j + 1) / 2 + p];
+        A[ii * (ii + 1) / 2 + j] = s / ljj;
+      }
+    }
+  }
+  double u[R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) u[a] = 0.0;
+  if (ok) {
+    // forward: L z = b
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      double s = bv[a];
+#pragma unroll
+      for (int p = 0; p < a; ++p) s -= A[a * (a + 1) / 2 + p] * u[p];
+      u[a] = s / A[a * (a + 1) / 2 + a];
+    }
+    // backward: L^T u = z
+#pragma unroll
+    for (int a = R - 1; a >= 0; --a) {
+      double s = u[a];
+#pragma unroll
+      for (int p = a + 1; p < R; ++p) s -= A[p * (p + 1) / 2 + a] * u[p];
+      u[a] = s / A[a * (a + 1) / 2 + a];
+    }
+  }
+  RSM_GLOBAL double* __restrict__ U = P.U;
+  if (active) {
+#pragma unroll
+    for (int a = 0; a < R; ++a) U[i + static_cast<int64_t>(a) * m] = ok ? u[a] : 0.0;
+  }
+  RSM_GLOBAL rsm_info* info = P.info;
+  const unsigned long long under = wave_sum<unsigned long long>((active && !ok) ? 1ull : 0ull);
+  const unsigned long long known = wave_sum<unsigned long long>(active ? static_cast<unsigned long long>(cnt) : 0ull);
+  if ((threadIdx.x & 63) == 0) {
+    if (under) {
+      atomicAdd((unsigned long long*)&info->rows_underdetermined, under);
+      atomicOr((uint32_t*)&info->warn, static_cast<uint32_t>(RSM_W_ROWS_UNDERDETERMINED));
+    }
+    if (known) atomicAdd((unsigned long long*)&info->known, known);
+  }
+}
+
 template <int R, typename TY>
 __global__ __launch_bounds__(256) void k_usolve(const ProbDesc* __restrict__ probs, IdxList list) {
   constexpr int NA = R * (R + 1) / 2;
@@ -37,8 +108,6 @@ __global__ __launch_bounds__(256) void k_usolve(const ProbDesc* __restrict__ pro
   auto Y = static_cast<RSM_GLOBAL const TY*>(P.ycm);
   RSM_GLOBAL const uint64_t* __restrict__ wbits = P.wbits;
   RSM_GLOBAL const double* __restrict__ V = P.V;
-  RSM_GLOBAL double* __restrict__ U = P.U;
-  RSM_GLOBAL rsm_info* info = P.info;
   const int tid = threadIdx.x;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + tid;
   const bool active = i < m;
@@ -102,59 +171,169 @@ __global__ __launch_bounds__(256) void k_usolve(const ProbDesc* __restrict__ pro
       }
     }
   }
-  // Cholesky A = L L^T in place (lower, packed row-major), then L L^T u = b
-  bool ok = active && cnt >= R;
-  if (ok) {
+  solve_row<R>(P, A, bv, cnt, active, i);
+}
+
+// Solve of the normal equations that k_uform wrote: one thread per row.
+template <int R>
+__global__ __launch_bounds__(256) void k_usolve_ab(const ProbDesc* __restrict__ probs, IdxList list) {
+  constexpr int NA = R * (R + 1) / 2;
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t m = P.m;
+  if (static_cast<int64_t>(blockIdx.x) * 256 >= m) return;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const bool active = i < m;
+  const int64_t ic = active ? i : m - 1;
+  RSM_GLOBAL const double* __restrict__ ab = P.ab;
+  double A[NA];
+  double bv[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      double d = A[j * (j + 1) / 2 + j];
+  for (int g = 0; g < NA; ++g) A[g] = ab[static_cast<int64_t>(g) * m + ic];
 #pragma unroll
-      for (int p = 0; p < j; ++p) d -= A[j * (j + 1) / 2 + p] * A[j * (j + 1) / 2 + p];
-      ok &= (d > 0.0);
-      const double ljj = sqrt(d > 0.0 ? d : 1.0);
-      A[j * (j + 1) / 2 + j] = ljj;
+  for (int a = 0; a < R; ++a) bv[a] = ab[static_cast<int64_t>(NA + a) * m + ic];
+  const int cnt = P.abcnt[ic];
+  solve_row<R>(P, A, bv, cnt, active, i);
+}
+
+// ---------------------------------------------------------------- normal equations on MFMA
+// v_mfma_f64_16x16x4f64: D (16 x 16) += A (16 x 4) B (4 x 16), one double per lane for A
+// and B: A(i, k) in lane i + 16 k, B(k, j) in lane j + 16 k; D(i, j) in lane j + 16 (i % 4),
+// register i / 4.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kUfTiles = 2;                  // 16-row tiles per wavefront
+constexpr int kUfRows = 4 * 16 * kUfTiles;   // rows per workgroup (4 wavefronts)
+constexpr int kUfCols = 32;                  // columns per LDS stage (8 k-steps of 4)
+
+template <int R>
+struct UfShape {
+  static constexpr int kNA = R * (R + 1) / 2;
+  static constexpr int kTA = (kNA + 15) / 16;   // 16-wide output tiles of A entries
+  static constexpr int kT = kTA + 1;            // and one of b (r <= 16)
+  // doubles per staged column: 16 mod 32, so that the 4 k-rows of a B fragment (128 bytes
+  // each) fall on alternate halves of the LDS banks
+  static constexpr int kStride = kT * 16 + ((kT % 2 == 0) ? 16 : 0);
+};
+
+// Row pair (a, b), b <= a, of packed entry e < r(r+1)/2.
+__device__ __forceinline__ void unpack_pair(int e, int& a, int& b) {
+  a = static_cast<int>((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+  while (a * (a + 1) / 2 > e) --a;
+  while ((a + 1) * (a + 2) / 2 <= e) ++a;
+  b = e - a * (a + 1) / 2;
+}
+
+// Workgroup: 128 consecutive rows (4 wavefronts x 2 tiles of 16).  Per stage of 32 columns
+// the workgroup writes K's and V's rows for those columns to LDS ([K | 0 | V | 0] per
+// column, the B operands); each lane loads the mask bit and Y value of its (row, column)
+// position of every k-step (the A operands: the bit as 0/1 for the A part, bit times y for
+// the b part) before the staging, so the loads overlap it.  Rows past m and columns past n
+// have weight 0.
+template <int R, typename TY>
+__global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ probs, IdxList list) {
+  using S = UfShape<R>;
+  constexpr int NA = S::kNA, TA = S::kTA, T = S::kT, LD = S::kStride;
+  __shared__ double Kc[kUfCols * LD];
+  __shared__ double Vc[kUfCols * R];
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t m = P.m, n = P.n, ldy = P.ldy, mw32 = 2 * P.mw;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kUfRows;
+  if (row0 >= m) return;
+  auto Y = static_cast<RSM_GLOBAL const TY*>(P.ycm);
+  auto wbits = reinterpret_cast<RSM_GLOBAL const uint32_t*>(P.wbits);
+  RSM_GLOBAL const double* __restrict__ V = P.V;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  int64_t ic[kUfTiles];
+  bool rok[kUfTiles];
 #pragma unroll
-      for (int ii = j + 1; ii < R; ++ii) {
-        double s = A[ii * (ii + 1) / 2 + j];
+  for (int t = 0; t < kUfTiles; ++t) {
+    const int64_t i = row0 + wv * 16 * kUfTiles + t * 16 + li;
+    rok[t] = i < m;
+    ic[t] = rok[t] ? i : m - 1;
+  }
+  f64x4 acc[kUfTiles][T];
 #pragma unroll
-        for (int p = 0; p < j; ++p) s -= A[ii * (ii + 1) / 2 + p] * A[j * (j + 1) / 2 + p];
-        A[ii * (ii + 1) / 2 + j] = s / ljj;
+  for (int t = 0; t < kUfTiles; ++t)
+#pragma unroll
+    for (int q = 0; q < T; ++q) acc[t][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  int cnt[kUfTiles] = {};
+  for (int64_t c0 = 0; c0 < n; c0 += kUfCols) {
+    // this stage's A operands: mask words and Y values of (row ic[t], column c0 + 4 ks + lk)
+    uint32_t wreg[kUfCols / 4][kUfTiles];
+    TY yreg[kUfCols / 4][kUfTiles];
+#pragma unroll
+    for (int ks = 0; ks < kUfCols / 4; ++ks) {
+      const int64_t j = c0 + 4 * ks + lk;
+      const int64_t jc = j < n ? j : n - 1;
+#pragma unroll
+      for (int t = 0; t < kUfTiles; ++t) {
+        wreg[ks][t] = wbits[jc * mw32 + (ic[t] >> 5)];
+        yreg[ks][t] = Y[jc * ldy + ic[t]];
+      }
+    }
+    __syncthreads();  // the previous stage's B operands are consumed
+    for (int e = tid; e < kUfCols * R; e += 256) {
+      const int c = e / R, a = e - c * R;
+      const int64_t j = c0 + c;
+      Vc[e] = j < n ? V[j + static_cast<int64_t>(a) * n] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < kUfCols * T * 16; e += 256) {
+      const int c = e / (T * 16), q = e - c * (T * 16);
+      double val = 0.0;
+      if (q < NA) {
+        int a, b;
+        unpack_pair(q, a, b);
+        val = Vc[c * R + a] * Vc[c * R + b];
+      } else if (q >= TA * 16 && q - TA * 16 < R) {
+        val = Vc[c * R + (q - TA * 16)];
+      }
+      Kc[c * LD + q] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kUfCols / 4; ++ks) {
+      const bool jok = c0 + 4 * ks + lk < n;
+      double aw[kUfTiles], awy[kUfTiles];
+#pragma unroll
+      for (int t = 0; t < kUfTiles; ++t) {
+        const bool known = jok && rok[t] && ((wreg[ks][t] >> (ic[t] & 31)) & 1u);
+        aw[t] = known ? 1.0 : 0.0;
+        awy[t] = known ? static_cast<double>(yreg[ks][t]) : 0.0;
+        cnt[t] += known ? 1 : 0;
+      }
+      const double* brow = Kc + (4 * ks + lk) * LD + li;
+#pragma unroll
+      for (int q = 0; q < T; ++q) {
+        const double b = brow[q * 16];
+#pragma unroll
+        for (int t = 0; t < kUfTiles; ++t)
+          acc[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(q < TA ? aw[t] : awy[t], b, acc[t][q], 0, 0, 0);
       }
     }
   }
-  double u[R];
+  // D(i, e) of tile (t, q): row i = 4 v + lk of the tile (register v), column e = 16 q + li
+  RSM_GLOBAL double* __restrict__ ab = P.ab;
 #pragma unroll
-  for (int a = 0; a < R; ++a) u[a] = 0.0;
-  if (ok) {
-    // forward: L z = b
+  for (int t = 0; t < kUfTiles; ++t) {
+    const int64_t base = row0 + wv * 16 * kUfTiles + t * 16;
 #pragma unroll
-    for (int a = 0; a < R; ++a) {
-      double s = bv[a];
+    for (int q = 0; q < T; ++q) {
+      const int e = q * 16 + li;
+      const bool eok = q < TA ? (e < NA) : (li < R);
+      const int64_t col = q < TA ? e : NA + li;
 #pragma unroll
-      for (int p = 0; p < a; ++p) s -= A[a * (a + 1) / 2 + p] * u[p];
-      u[a] = s / A[a * (a + 1) / 2 + a];
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = base + 4 * v + lk;
+        if (eok && i < m) ab[col * m + i] = acc[t][q][v];
+      }
     }
-    // backward: L^T u = z
-#pragma unroll
-    for (int a = R - 1; a >= 0; --a) {
-      double s = u[a];
-#pragma unroll
-      for (int p = a + 1; p < R; ++p) s -= A[p * (p + 1) / 2 + a] * u[p];
-      u[a] = s / A[a * (a + 1) / 2 + a];
-    }
-  }
-  if (active) {
-#pragma unroll
-    for (int a = 0; a < R; ++a) U[i + static_cast<int64_t>(a) * m] = ok ? u[a] : 0.0;
-  }
-  const unsigned long long under = wave_sum<unsigned long long>((active && !ok) ? 1ull : 0ull);
-  const unsigned long long known = wave_sum<unsigned long long>(active ? static_cast<unsigned long long>(cnt) : 0ull);
-  if ((tid & 63) == 0) {
-    if (under) {
-      atomicAdd((unsigned long long*)&info->rows_underdetermined, under);
-      atomicOr((uint32_t*)&info->warn, static_cast<uint32_t>(RSM_W_ROWS_UNDERDETERMINED));
-    }
-    if (known) atomicAdd((unsigned long long*)&info->known, known);
+    // known entries of row ic[t]: lanes li, li + 16, li + 32, li + 48 hold its columns
+    int c = cnt[t];
+    c += __shfl_xor(c, 16, 64);
+    c += __shfl_xor(c, 32, 64);
+    if (lk == 0 && rok[t]) P.abcnt[ic[t]] = c;
   }
 }
 
@@ -211,8 +390,20 @@ __global__ void k_error_finalize(const ProbDesc* __restrict__ probs, IdxList lis
 }
 
 template <int R>
-void run_usolve(const ProbDesc* d, const IdxList& g, int64_t m, int y_dtype, hipStream_t s) {
+void run_usolve(const ProbDesc* d, const IdxList& g, int64_t m, int y_dtype, bool mfma,
+                hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(ceil_div(m, 256)), g.count);
+  if constexpr (R >= kUMfmaMinR) {
+    if (mfma) {
+      const dim3 gf(static_cast<unsigned>(ceil_div(m, kUfRows)), g.count);
+      if (y_dtype == RSM_F32)
+        k_uform<R, float><<<gf, 256, 0, s>>>(d, g);
+      else
+        k_uform<R, double><<<gf, 256, 0, s>>>(d, g);
+      k_usolve_ab<R><<<grid, 256, 0, s>>>(d, g);
+      return;
+    }
+  }
   if (y_dtype == RSM_F32)
     k_usolve<R, float><<<grid, 256, 0, s>>>(d, g);
   else
@@ -234,7 +425,7 @@ void run_error(const ProbDesc* d, const IdxList& g, int64_t m, int y_dtype, hipS
 #define RSM_R_CASES(X)                                                                 \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
-// The group shares r and the element type of Y.
+// The group shares r, the element type of Y and the way A_i and b_i are formed.
 void launch_solve_u(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
   if (!g.count) return;
   int64_t m = 0;
@@ -242,7 +433,7 @@ void launch_solve_u(const ProbDesc* d, const IdxList& g, const Plan* const* h, h
   switch (h[0]->r) {
 #define RSM_U_CASE(RR) \
   case RR:             \
-    run_usolve<RR>(d, g, m, h[0]->y_dtype, s); \
+    run_usolve<RR>(d, g, m, h[0]->y_dtype, h[0]->u_mfma, s); \
     break;
     RSM_R_CASES(RSM_U_CASE)
 #undef RSM_U_CASE

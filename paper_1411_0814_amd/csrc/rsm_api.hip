@@ -74,6 +74,8 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   while (nbp < P.nb) nbp *= 2;
   P.npad = nbp * kCholNB;
 
+  P.u_mfma = !(p.flags & RSM_ACCUMULATE_ONLY) && p.r >= kUMfmaMinR;
+
   // Gram kernel: LDS-tiled (Y tile shared by a group of trials) when the n-column tile fits
   // and the accumulation type matches Y's (split-BF16: FP32 Y), else the per-trial streamer
   P.tiled = !(p.flags & RSM_PLAIN_GRAM);
@@ -141,6 +143,10 @@ void set_layout(Plan& P) {
   P.off_Z = carve(cur, nbv);
   P.off_NX = carve(cur, nbv);
   P.off_small = carve(cur, kSmallDoubles * sizeof(double));
+  if (P.u_mfma) {
+    P.off_ab = carve(cur, static_cast<size_t>(P.m) * (P.r * (P.r + 1) / 2 + P.r) * sizeof(double));
+    P.off_abcnt = carve(cur, static_cast<size_t>(P.m) * sizeof(int32_t));
+  }
   P.total = cur;
 }
 
@@ -281,6 +287,8 @@ ProbDesc prob_desc(const Plan& P, const rsm_input& in, const rsm_output& out, vo
   d.U = gptr(out.U);
   d.info = gptr(out.info);
   d.scal = gptr(at<DevScalars>(ws, P.off_scal));
+  d.ab = P.u_mfma ? gptr(at<double>(ws, P.off_ab)) : nullptr;
+  d.abcnt = P.u_mfma ? gptr(at<int32_t>(ws, P.off_abcnt)) : nullptr;
   d.tap_rows = gptr(out.trial_rows);
   d.tap_gram = gptr(out.trial_gram);
   d.tap_vecs = gptr(out.trial_vecs);
@@ -479,7 +487,8 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   // a7 (and the optional error): one launch per (r, element type)
   auto back = [](const Plan& P) { return !(P.flags & RSM_ACCUMULATE_ONLY); };
   auto ukey = [](const Plan& P) { return int64_t(P.r) * 4 + P.y_dtype; };
-  for_groups(plans, back, ukey, [&](const IdxList& g, const Plan* const* h) {
+  auto ukey_v = [](const Plan& P) { return (int64_t(P.r) * 4 + P.y_dtype) * 2 + (P.u_mfma ? 1 : 0); };
+  for_groups(plans, back, ukey_v, [&](const IdxList& g, const Plan* const* h) {
     mark_all(outputs, g, RSM_STEP_USOLVE, 0, s);
     launch_solve_u(dprob, g, h, s);
     mark_all(outputs, g, RSM_STEP_USOLVE, 1, s);

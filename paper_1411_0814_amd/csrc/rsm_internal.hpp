@@ -32,6 +32,10 @@ constexpr int64_t kTileTargetGroups = 256;    // tiled Gram: workgroups to aim f
 // Trials per workgroup of the split-BF16 Gram kernel (16 per wavefront, 8 wavefronts).
 constexpr int kBfTrialsPerGroup = 128;
 
+// U-hat: ranks from which the per-row normal equations are formed on the FP64 matrix cores
+// (one dense product over all columns, 0/1 mask weights) instead of one thread per row.
+constexpr int kUMfmaMinR = 6;
+
 // Threads (= trials) per workgroup of the tiled Gram kernel: as many as the register file
 // allows with l(l+1)/2 accumulators plus the prefetched next tile held per thread.
 __host__ __device__ constexpr int tile_threads(int l, int elem_bytes) {
@@ -72,12 +76,13 @@ struct Plan {
   size_t part_elem = 4;  // bytes of one partial-Gram element
   int gram_groups = 0;   // tiled Gram: trial groups (workgroups per row split)
   int gram_threads = 0;  // tiled Gram: trials per workgroup (0: per-trial streamer)
+  bool u_mfma = false;   // U-hat normal equations formed on the FP64 matrix cores
   int gram_wgs = 0;      // workgroups of the Gram step of this problem
   // workspace offsets (bytes from the workspace base); ~0 = unused
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
          off_rows = 0;
   size_t off_N = 0, off_Nsym = 0, off_L = 0, off_M = 0, off_Mt = 0, off_T = 0, off_X = 0,
-         off_Z = 0, off_NX = 0, off_small = 0;
+         off_Z = 0, off_NX = 0, off_small = 0, off_ab = 0, off_abcnt = 0;
   size_t off_scal = 0;
   size_t total = 0;
 };
@@ -148,6 +153,8 @@ struct ProbDesc {
   RSM_GLOBAL double* tap_gram;
   RSM_GLOBAL double* tap_vecs;
   RSM_GLOBAL double* tap_eigs;
+  RSM_GLOBAL double* ab;       // U-hat normal equations on MFMA: (r(r+1)/2 + r) x m, ld m
+  RSM_GLOBAL int32_t* abcnt;   // known entries per row (m)
 };
 
 // The problems of one launch: indices into a device ProbDesc array, passed by value.
