@@ -16,7 +16,8 @@
 //
 //  For l <= 11 the matrix lives in registers (static indices) and the rotations are
 //  accumulated in a per-thread LDS slice laid out [entry][thread]; for larger l one
-//  wavefront works on each trial.
+//  wavefront works on each trial.  Step 2 is replaced by inverse iteration (k_minor_inv)
+//  when a trial needs only its one minor vector and no eigenvalue taps are requested.
 #include <algorithm>
 #include <cmath>
 
@@ -433,8 +434,158 @@ __global__ __launch_bounds__(64 * kWaveTrials) void k_minor_wave(const ProbDesc*
   }
 }
 
+// ------------------------------------------------------------------ inverse iteration
+//
+// One minor vector per trial (nvec = 1, the default l = r + 1) and no eigen taps: the
+// eigenvector of G_t's smallest eigenvalue by inverse iteration, one thread per trial.
+// G_t = L L^T by Cholesky (FP64, packed in registers).  G_t is positive semidefinite, but
+// its rounding can leave the smallest eigenvalue slightly negative; when a pivot comes out
+// non-positive, G_t + mu I is factorised instead, with mu = 4 u trace(G_t) for the relative
+// accuracy u of the Gram's products and sums (2^-53 FP64, 2^-24 FP32, 2^-16 split-BF16),
+// which exceeds that rounding (the eigenvectors are those of G_t; a pivot still below mu
+// is raised to mu).  Then kInvIters steps of x <- (L L^T)^{-1} x / norm from a fixed
+// irregular start; each shrinks the other eigen-directions by
+// (lambda_1 + mu) / (lambda_k + mu) relative to the minor one, so a trial whose minor
+// eigenvalue is separated converges in a few steps, at O(l^3) instead of a full Jacobi
+// eigen-decomposition.
+constexpr int kInvIters = 8;
+
+// In-place Cholesky of the packed lower triangle a + mu I (entry (i, j), j <= i, at
+// i (i + 1) / 2 + j); pivots below `floor_d` are raised to it.  The diagonal receives the
+// reciprocals 1 / l_jj (the solves multiply by them).  Returns whether every pivot was
+// above the floor.
 template <int L>
-void run_minor(const ProbDesc* d, const IdxList& g, int64_t I, hipStream_t s) {
+__device__ __forceinline__ bool cholesky_packed(double (&a)[L * (L + 1) / 2], double mu,
+                                                double floor_d) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    double d = a[j * (j + 1) / 2 + j] + mu;
+#pragma unroll
+    for (int p = 0; p < j; ++p) d -= a[j * (j + 1) / 2 + p] * a[j * (j + 1) / 2 + p];
+    ok &= d > floor_d;
+    const double ljj = sqrt(d > floor_d ? d : floor_d);
+    const double inv = 1.0 / ljj;
+    a[j * (j + 1) / 2 + j] = inv;
+#pragma unroll
+    for (int i = j + 1; i < L; ++i) {
+      double sum = a[i * (i + 1) / 2 + j];
+#pragma unroll
+      for (int p = 0; p < j; ++p) sum -= a[i * (i + 1) / 2 + p] * a[j * (j + 1) / 2 + p];
+      a[i * (i + 1) / 2 + j] = sum * inv;
+    }
+  }
+  return ok;
+}
+
+template <int L>
+__global__ __launch_bounds__(64) void k_minor_inv(const ProbDesc* __restrict__ probs,
+                                                  IdxList list) {
+  constexpr int NG = L * (L + 1) / 2;
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t I = P.I, n = P.n;
+  __shared__ unsigned long long s_acc, s_rows;
+  __shared__ double xs[L][64];
+  __shared__ int cs[L][64];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_acc = 0;
+    s_rows = 0;
+  }
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * 64 + tid;
+  const bool active = t < I;
+  double a[NG];  // packed lower triangle, entry (i, j), j <= i, at i (i + 1) / 2 + j
+  int c[L];
+  int rows = 0;
+  bool valid = active;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) a[g] = active ? P.G[static_cast<int64_t>(g) * I + t] : 0.0;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    c[k] = active ? P.cols[t * L + k] : 0;
+    valid &= c[k] >= 0;
+  }
+  if (active) rows = P.rows[t];
+  const bool accept = valid && rows >= P.min_rows;
+  if (active) {
+    if (P.tap_rows) P.tap_rows[t] = rows;
+    if (P.tap_gram)
+#pragma unroll
+      for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int j = 0; j < L; ++j)
+          P.tap_gram[(t * L + i) * L + j] = a[i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i];
+  }
+  if (accept) {
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) tr += a[i * (i + 1) / 2 + i];
+    if (!cholesky_packed<L>(a, 0.0, fmax(0x1p-52 * tr, 1e-300))) {
+      const double mu = fmax(4.0 * P.gram_unit * tr, 1e-300);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) a[g] = P.G[static_cast<int64_t>(g) * I + t];
+      cholesky_packed<L>(a, mu, mu);
+    }
+    double x[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) x[i] = 1.0 + 0.5 * static_cast<double>((i * 7 + 3) % 11) / 11.0;
+#pragma unroll 1
+    for (int it = 0; it < kInvIters; ++it) {
+      // L z = x, then L^T y = z (both in x)
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        double sum = x[i];
+#pragma unroll
+        for (int p = 0; p < i; ++p) sum -= a[i * (i + 1) / 2 + p] * x[p];
+        x[i] = sum * a[i * (i + 1) / 2 + i];
+      }
+#pragma unroll
+      for (int i = L - 1; i >= 0; --i) {
+        double sum = x[i];
+#pragma unroll
+        for (int p = i + 1; p < L; ++p) sum -= a[p * (p + 1) / 2 + i] * x[p];
+        x[i] = sum * a[i * (i + 1) / 2 + i];
+      }
+      double nrm = 0.0;
+#pragma unroll
+      for (int i = 0; i < L; ++i) nrm += x[i] * x[i];
+      const double s = 1.0 / sqrt(nrm);
+#pragma unroll
+      for (int i = 0; i < L; ++i) x[i] *= s;
+    }
+    // N[C_t, C_t] += x x^T (lower triangle: c is ascending); x and c go through this
+    // thread's LDS slice so that the l(l+1)/2 updates run as a loop
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      xs[i][tid] = x[i];
+      cs[i][tid] = c[i];
+    }
+    const bool fixed = P.fixed_n != 0;
+#pragma unroll 1
+    for (int i = 0; i < L; ++i) {
+      const double xi = xs[i][tid];
+      const int64_t ci = cs[i][tid];
+#pragma unroll 1
+      for (int j = 0; j <= i; ++j)
+        add_to_N(P.N, ci + static_cast<int64_t>(cs[j][tid]) * n, xi * xs[j][tid], fixed);
+    }
+  }
+  __syncthreads();
+  if (accept) atomicAdd(&s_acc, 1ull);
+  if (active) atomicAdd(&s_rows, static_cast<unsigned long long>(rows));
+  __syncthreads();
+  if (tid == 0) {
+    atomicAdd((unsigned long long*)&P.info->accepted, s_acc);
+    atomicAdd((unsigned long long*)&P.info->rows_total, s_rows);
+  }
+}
+
+template <int L>
+void run_minor(const ProbDesc* d, const IdxList& g, int64_t I, bool inv, hipStream_t s) {
+  if (inv) {
+    k_minor_inv<L><<<dim3(static_cast<unsigned>(ceil_div(I, 64)), g.count), 64, 0, s>>>(d, g);
+    return;
+  }
   if constexpr (L <= kRegMaxL) {
     const unsigned blocks = static_cast<unsigned>(ceil_div(I, 64));
     k_minor_reg<L><<<dim3(blocks, g.count), 64, 0, s>>>(d, g);
@@ -446,29 +597,44 @@ void run_minor(const ProbDesc* d, const IdxList& g, int64_t I, hipStream_t s) {
 
 }  // namespace
 
+void launch_minor_kernel(const ProbDesc* d, const IdxList& all, int l, int64_t I, bool inv,
+                         hipStream_t s);
+
 void launch_minor(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
   // the group shares l; the partial-Gram element type follows the precision
   IdxList sub[2];
-  int64_t I = 0, total[2] = {0, 0};
+  int64_t total[2] = {0, 0};
   for (int k = 0; k < g.count; ++k) {
     if (h[k]->I == 0) continue;
     const int f = h[k]->part_elem == sizeof(double) ? 1 : 0;
     sub[f].idx[sub[f].count++] = g.idx[k];
     total[f] = std::max<int64_t>(total[f], static_cast<int64_t>(h[k]->ng) * h[k]->I);
-    I = std::max(I, h[k]->I);
   }
   if (sub[0].count)
     k_gram_reduce<float><<<dim3(static_cast<unsigned>(ceil_div(total[0], 256)), sub[0].count), 256, 0, s>>>(d, sub[0]);
   if (sub[1].count)
     k_gram_reduce<double><<<dim3(static_cast<unsigned>(ceil_div(total[1], 256)), sub[1].count), 256, 0, s>>>(d, sub[1]);
-  IdxList all;
-  for (int f = 0; f < 2; ++f)
-    for (int k = 0; k < sub[f].count; ++k) all.idx[all.count++] = sub[f].idx[k];
-  if (!all.count) return;
-  switch (h[0]->l) {
+  // inverse iteration for the problems that allow it, Jacobi for the rest
+  IdxList part[2];
+  int64_t Ip[2] = {0, 0};
+  for (int k = 0; k < g.count; ++k) {
+    if (h[k]->I == 0) continue;
+    const int v = h[k]->minor_inv ? 1 : 0;
+    part[v].idx[part[v].count++] = g.idx[k];
+    Ip[v] = std::max(Ip[v], h[k]->I);
+  }
+  for (int v = 0; v < 2; ++v) {
+    if (!part[v].count) continue;
+    launch_minor_kernel(d, part[v], h[0]->l, Ip[v], v == 1, s);
+  }
+}
+
+void launch_minor_kernel(const ProbDesc* d, const IdxList& all, int l, int64_t I, bool inv,
+                         hipStream_t s) {
+  switch (l) {
 #define RSM_MINOR_CASE(LL) \
   case LL:                 \
-    run_minor<LL>(d, all, I, s); \
+    run_minor<LL>(d, all, I, inv, s); \
     break;
     RSM_MINOR_CASE(2) RSM_MINOR_CASE(3) RSM_MINOR_CASE(4) RSM_MINOR_CASE(5)
     RSM_MINOR_CASE(6) RSM_MINOR_CASE(7) RSM_MINOR_CASE(8) RSM_MINOR_CASE(9)

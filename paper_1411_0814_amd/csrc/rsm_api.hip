@@ -272,6 +272,7 @@ ProbDesc prob_desc(const Plan& P, const rsm_input& in, const rsm_output& out, vo
   d.words_per_split = P.words_per_split;
   d.seed = P.seed;
   d.fixed_n = (P.flags & RSM_DETERMINISTIC) ? 1 : 0;
+  d.gram_unit = P.prec == RSM_GRAM_F64 ? 0x1p-53 : (P.prec == RSM_GRAM_F32 ? 0x1p-24 : 0x1p-16);
   d.W = gptr(in.W);
   d.Yin = gptr(in.Y);
   d.ycm = gptr(const_cast<void*>(ycm_of(P, in, ws)));
@@ -408,6 +409,8 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   for (int32_t k = 0; k < nprob; ++k) {
     st = check_io(plans[k], inputs[k], outputs[k]);
     if (st != RSM_OK) return st;
+    // the full spectrum is computed (Jacobi) only when asked for or for several vectors
+    plans[k].minor_inv = plans[k].nvec == 1 && !outputs[k].trial_vecs && !outputs[k].trial_eigs;
     base[k] = need;
     need += align_up(plans[k].total, 256);
   }

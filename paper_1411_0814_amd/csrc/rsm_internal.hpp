@@ -77,6 +77,7 @@ struct Plan {
   int gram_groups = 0;   // tiled Gram: trial groups (workgroups per row split)
   int gram_threads = 0;  // tiled Gram: trials per workgroup (0: per-trial streamer)
   bool u_mfma = false;   // U-hat normal equations formed on the FP64 matrix cores
+  bool minor_inv = false;  // minor vector by inverse iteration (nvec 1, no eigen taps)
   int gram_wgs = 0;      // workgroups of the Gram step of this problem
   // workspace offsets (bytes from the workspace base); ~0 = unused
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
@@ -134,6 +135,7 @@ struct ProbDesc {
   uint64_t seed;
   int32_t fixed_n;       // N accumulated as 64-bit fixed point (deterministic mode)
   int32_t pad_;
+  double gram_unit;      // relative accuracy of the Gram's products and sums
   RSM_GLOBAL const uint8_t* W;
   RSM_GLOBAL const void* Yin;  // caller's Y
   RSM_GLOBAL void* ycm;        // column-major Y (the caller's, or the packed copy)
