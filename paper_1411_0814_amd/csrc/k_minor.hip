@@ -16,8 +16,9 @@
 //
 //  For l <= 11 the matrix lives in registers (static indices) and the rotations are
 //  accumulated in a per-thread LDS slice laid out [entry][thread]; for larger l one
-//  wavefront works on each trial.  Step 2 is replaced by inverse iteration (k_minor_inv)
-//  when a trial needs only its one minor vector and no eigenvalue taps are requested.
+//  wavefront works on each trial.  For l > 11, step 2 is replaced by inverse iteration
+//  with Rayleigh-quotient refinement (k_minor_inv) when a trial needs only its one minor
+//  vector and no eigenvalue taps are requested.
 #include <algorithm>
 #include <cmath>
 
@@ -436,19 +437,26 @@ __global__ __launch_bounds__(64 * kWaveTrials) void k_minor_wave(const ProbDesc*
 
 // ------------------------------------------------------------------ inverse iteration
 //
-// One minor vector per trial (nvec = 1, the default l = r + 1) and no eigen taps: the
-// eigenvector of G_t's smallest eigenvalue by inverse iteration, one thread per trial.
-// G_t = L L^T by Cholesky (FP64, packed in registers).  G_t is positive semidefinite, but
-// its rounding can leave the smallest eigenvalue slightly negative; when a pivot comes out
-// non-positive, G_t + mu I is factorised instead, with mu = 4 u trace(G_t) for the relative
-// accuracy u of the Gram's products and sums (2^-53 FP64, 2^-24 FP32, 2^-16 split-BF16),
-// which exceeds that rounding (the eigenvectors are those of G_t; a pivot still below mu
-// is raised to mu).  Then kInvIters steps of x <- (L L^T)^{-1} x / norm from a fixed
-// irregular start; each shrinks the other eigen-directions by
-// (lambda_1 + mu) / (lambda_k + mu) relative to the minor one, so a trial whose minor
-// eigenvalue is separated converges in a few steps, at O(l^3) instead of a full Jacobi
-// eigen-decomposition.
-constexpr int kInvIters = 8;
+// One minor vector per trial (nvec = 1, the default l = r + 1), no eigen taps, l > 11:
+// the eigenvector of G_t's smallest eigenvalue by inverse iteration refined with Rayleigh
+// quotient shifts, one thread per trial, instead of a full Jacobi eigen-decomposition in
+// a wavefront.
+//  1. G_t = L L^T by Cholesky (FP64, packed in registers).  G_t is positive semidefinite,
+//     but its rounding can leave the smallest eigenvalue slightly negative; when a pivot
+//     comes out non-positive, G_t + mu I is factorised instead, with mu = 4 u trace(G_t)
+//     for the relative accuracy u of the Gram's products and sums (2^-53 FP64, 2^-24 FP32,
+//     2^-16 split-BF16), which exceeds that rounding (a pivot still below mu is raised to
+//     mu).  kInvIters steps x <- (L L^T)^{-1} x / norm from a fixed irregular start shrink
+//     the other eigen-directions by (lambda_1 + mu) / (lambda_k + mu) each.
+//  2. kRqSteps steps with the shift rho = x^T G_t x (the Rayleigh quotient, just above
+//     lambda_1): G_t - rho I = L D L^T without pivoting (a pivot of magnitude below
+//     2^-60 trace(G_t) is set to that magnitude), x <- (L D L^T)^{-1} x / norm.  Near
+//     convergence the factor is nearly singular in the minor direction only, which the
+//     solve amplifies; the convergence is cubic, so trials whose two smallest eigenvalues
+//     are close (noisy data: lambda_1 / lambda_2 up to about 0.6 at the paper-scale
+//     workload) still reach the accuracy of a full eigen-decomposition.
+constexpr int kInvIters = 4;
+constexpr int kRqSteps = 3;
 
 // In-place Cholesky of the packed lower triangle a + mu I (entry (i, j), j <= i, at
 // i (i + 1) / 2 + j); pivots below `floor_d` are raised to it.  The diagonal receives the
@@ -476,6 +484,30 @@ __device__ __forceinline__ bool cholesky_packed(double (&a)[L * (L + 1) / 2], do
     }
   }
   return ok;
+}
+
+// In-place L D L^T of the packed lower triangle a - rho I without pivoting: the diagonal
+// receives d_j, the entries below it L's (unit diagonal implied).  |d_j| below `tiny` is
+// set to `tiny` with its sign.
+template <int L>
+__device__ __forceinline__ void ldlt_packed(double (&a)[L * (L + 1) / 2], double rho,
+                                            double tiny) {
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    double d = a[j * (j + 1) / 2 + j] - rho;
+#pragma unroll
+    for (int p = 0; p < j; ++p) d -= a[j * (j + 1) / 2 + p] * a[j * (j + 1) / 2 + p] * a[p * (p + 1) / 2 + p];
+    if (fabs(d) < tiny) d = d < 0.0 ? -tiny : tiny;
+    a[j * (j + 1) / 2 + j] = d;
+    const double inv = 1.0 / d;
+#pragma unroll
+    for (int i = j + 1; i < L; ++i) {
+      double sum = a[i * (i + 1) / 2 + j];
+#pragma unroll
+      for (int p = 0; p < j; ++p) sum -= a[i * (i + 1) / 2 + p] * a[j * (j + 1) / 2 + p] * a[p * (p + 1) / 2 + p];
+      a[i * (i + 1) / 2 + j] = sum * inv;
+    }
+  }
 }
 
 template <int L>
@@ -553,6 +585,43 @@ __global__ __launch_bounds__(64) void k_minor_inv(const ProbDesc* __restrict__ p
 #pragma unroll
       for (int i = 0; i < L; ++i) x[i] *= s;
     }
+#pragma unroll 1
+    for (int q = 0; q < kRqSteps; ++q) {
+#pragma unroll
+      for (int g = 0; g < NG; ++g) a[g] = P.G[static_cast<int64_t>(g) * I + t];
+      double rho = 0.0;
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        double row = 0.0;
+#pragma unroll
+        for (int j = 0; j < i; ++j) row += a[i * (i + 1) / 2 + j] * x[j];
+        rho += x[i] * (2.0 * row + a[i * (i + 1) / 2 + i] * x[i]);
+      }
+      ldlt_packed<L>(a, rho, fmax(0x1p-60 * tr, 1e-300));
+      // L z = x; z <- z / d; L^T y = z (all in x)
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        double sum = x[i];
+#pragma unroll
+        for (int p = 0; p < i; ++p) sum -= a[i * (i + 1) / 2 + p] * x[p];
+        x[i] = sum;
+      }
+#pragma unroll
+      for (int i = 0; i < L; ++i) x[i] /= a[i * (i + 1) / 2 + i];
+#pragma unroll
+      for (int i = L - 1; i >= 0; --i) {
+        double sum = x[i];
+#pragma unroll
+        for (int p = i + 1; p < L; ++p) sum -= a[p * (p + 1) / 2 + i] * x[p];
+        x[i] = sum;
+      }
+      double nrm = 0.0;
+#pragma unroll
+      for (int i = 0; i < L; ++i) nrm += x[i] * x[i];
+      const double s = 1.0 / sqrt(nrm);
+#pragma unroll
+      for (int i = 0; i < L; ++i) x[i] *= s;
+    }
     // N[C_t, C_t] += x x^T (lower triangle: c is ascending); x and c go through this
     // thread's LDS slice so that the l(l+1)/2 updates run as a loop
 #pragma unroll
@@ -582,14 +651,15 @@ __global__ __launch_bounds__(64) void k_minor_inv(const ProbDesc* __restrict__ p
 
 template <int L>
 void run_minor(const ProbDesc* d, const IdxList& g, int64_t I, bool inv, hipStream_t s) {
-  if (inv) {
-    k_minor_inv<L><<<dim3(static_cast<unsigned>(ceil_div(I, 64)), g.count), 64, 0, s>>>(d, g);
-    return;
-  }
   if constexpr (L <= kRegMaxL) {
+    (void)inv;
     const unsigned blocks = static_cast<unsigned>(ceil_div(I, 64));
     k_minor_reg<L><<<dim3(blocks, g.count), 64, 0, s>>>(d, g);
   } else {
+    if (inv) {
+      k_minor_inv<L><<<dim3(static_cast<unsigned>(ceil_div(I, 64)), g.count), 64, 0, s>>>(d, g);
+      return;
+    }
     const unsigned blocks = static_cast<unsigned>(ceil_div(I, kWaveTrials));
     k_minor_wave<L><<<dim3(blocks, g.count), 64 * kWaveTrials, 0, s>>>(d, g);
   }
@@ -619,7 +689,7 @@ void launch_minor(const ProbDesc* d, const IdxList& g, const Plan* const* h, hip
   int64_t Ip[2] = {0, 0};
   for (int k = 0; k < g.count; ++k) {
     if (h[k]->I == 0) continue;
-    const int v = h[k]->minor_inv ? 1 : 0;
+    const int v = (h[k]->minor_inv && h[0]->l > kRegMaxL) ? 1 : 0;
     part[v].idx[part[v].count++] = g.idx[k];
     Ip[v] = std::max(Ip[v], h[k]->I);
   }
