@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in Gram tile shapes (no autotuning before timing)")
+    ap.add_argument("--tune-file", default=None,
+                    help="install this saved tile table instead of autotuning")
+    ap.add_argument("--save-tune", default=None,
+                    help="write the tile table used for the timed run to this file")
     ap.add_argument("--cpu-sample-trials", type=int, default=4096)
     ap.add_argument("--cpu-sample-rows", type=int, default=2048,
                     help="rows of U in the parity check")
@@ -188,6 +192,20 @@ def _batch_setup(args, torch):
     return specs, inputs, reqs, t_gen
 
 
+def _tune_for(args, reqs):
+    """The tile table for the timed runs: a saved one (--tune-file), else autotuned on
+    these requests; optionally written out (--save-tune)."""
+    from paper_1411_0814_amd import tune
+    if args.tune_file:
+        entries = tune.load(args.tune_file)
+        out = {"seconds": 0.0, "entries": entries, "groups": [], "from_file": args.tune_file}
+    else:
+        out = tune.autotune(reqs, reps=3)
+    if args.save_tune:
+        tune.save(args.save_tune)
+    return out
+
+
 def _time_batch(reqs, reps, stream, torch):
     """Median seconds of one fused call over the batch (after one warm-up call)."""
     from paper_1411_0814_amd import decompose_batched, workspace_bytes
@@ -219,7 +237,7 @@ def run_batched(args, torch):
     t_builtin, res = _time_batch(reqs, args.batch_reps, stream, torch)
     tuned = None
     if not args.no_tune:
-        tuned = tune.autotune(reqs, reps=2)
+        tuned = _tune_for(args, reqs)
         t_batch, res = _time_batch(reqs, args.batch_reps, stream, torch)
     else:
         t_batch = t_builtin
@@ -412,7 +430,7 @@ def main():
                   gram=gram, flags=flags)
     from paper_1411_0814_amd import tune
     tune.clear()
-    tuned = None if args.no_tune or args.plain_gram else tune.autotune([req], reps=3)
+    tuned = None if args.no_tune or args.plain_gram else _tune_for(args, [req])
     ws_need = workspace_bytes([req])
     ws = torch.empty(ws_need + 256, dtype=torch.uint8, device=dev)
     off = (-ws.data_ptr()) % 256
@@ -487,7 +505,8 @@ def main():
         "gen_s": round(t_gen, 1),
     }
     if tuned is not None:
-        out["autotune"] = {"seconds": tuned["seconds"], "groups": tuned["groups"]}
+        out["autotune"] = {"seconds": tuned["seconds"], "entries": tuned["entries"],
+                           "groups": tuned["groups"]}
     if not args.no_parity:
         workers = min(16, os.cpu_count() or 4)
         theta, rms, t_or = oracle_parity(p, last.V.cpu().numpy(), last.U.cpu().numpy(),
