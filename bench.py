@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper_scale",
-                    choices=["paper_scale", "plain_fp64", "precision", "batched", "served"])
+                    choices=["paper_scale", "plain_fp64", "precision", "batched", "served",
+                             "table1"])
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--served-seconds", type=float, default=5.0)
@@ -337,6 +338,66 @@ def main_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def _table1_golden():
+    import csv
+    path = os.path.join(ROOT, "tests", "golden", "table1_rsm.csv")
+    with open(path) as f:
+        return [row for row in csv.DictReader(line for line in f if not line.startswith("#"))]
+
+
+def main_table1(args):
+    """The paper's Table I workloads (r = 3, l = 4, M1, I = 25n, FP64 data): GPU time per
+    decomposition and the error e of eq.(ep) next to the paper's printed e and its
+    one-core Matlab time (context: another machine, another random instance)."""
+    import torch
+
+    import synth
+    from paper_1411_0814_amd import _lib, decompose
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    total_ms = 0.0
+    for k, gold in enumerate(_table1_golden()):
+        p = synth.table1(k)
+        Y = torch.from_numpy(p.Yt).to(dev).T
+        W = torch.from_numpy(p.Wt.view(bool)).to(dev).T
+        for _ in range(max(1, args.warmup)):
+            res = decompose(Y, W, p.r, p.num_submatrices, p.seed_rsm, l=p.l, gram="f64",
+                            flags=_lib.COMPUTE_ERROR)
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(args.steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            res = decompose(Y, W, p.r, p.num_submatrices, p.seed_rsm, l=p.l, gram="f64",
+                            flags=_lib.COMPUTE_ERROR)
+            b.record(stream)
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+        total_ms += ms
+        e = res.info()["e"]
+        e_paper = float(gold["e_rsm"])
+        rows.append({"m": p.m, "n": p.n, "rho": p.rho, "sigma": float(gold["sigma"]),
+                     "I": p.num_submatrices, "gpu_ms": round(ms, 4), "e": round(e, 6),
+                     "e_paper": e_paper, "e_within_1e-3": bool(abs(e - e_paper) <= 1e-3),
+                     "paper_matlab_s": float(gold["t_rsm"])})
+        del Y, W, res
+        torch.cuda.empty_cache()
+    line = {
+        "metric": METRIC, "value": round(len(rows) / (total_ms * 1e-3), 2),
+        "unit": "decompositions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(total_ms / len(rows), 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Table I shapes: r 3, l 4, M1, I 25n, m 65536..131072, "
+                               "n 512..1024, rho 0.2..0.5, sigma 0.1..0.5", "gram": "f64"},
+        "rows": rows,
+        "paper_hardware": "Matlab, FP64, one core of an Intel i5-3470 at 3.2 GHz",
+        "all_e_within_1e-3": all(r["e_within_1e-3"] for r in rows),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main_precision(args):
     """Precision stress: the same problem with the FP32 Gram and with the split-BF16 Gram on
     MFMA, each timed and compared with one FP64 oracle run."""
@@ -412,6 +473,9 @@ def main():
         return
     if args.workload == "precision":
         main_precision(args)
+        return
+    if args.workload == "table1":
+        main_table1(args)
         return
     import torch
 
