@@ -225,11 +225,13 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
                               void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* ---------------------------------------------------------------------------------------
- * Tile table (library-wide, host side).  The fused gather + Gram step (a2 + a3) has two
- * free shape parameters: the trials per workgroup of the tiled kernel (each thread owns
- * one trial's l(l+1)/2 accumulators, so this is also its thread count) and the number of
- * workgroups a launch aims for (rows are split so that trial groups x row splits reaches
- * it; the row splits' partial Grams are summed in split order afterwards).  The best pair
+ * Tile table (library-wide, host side).  The fused gather + Gram step (a2 + a3) has three
+ * free parameters: how the tiled kernel stages Y (1: through registers, 32-row chunks; 2:
+ * straight from global memory into LDS, 16-row chunks, fewer registers per thread), the
+ * trials per workgroup (each thread owns one trial's l(l+1)/2 accumulators, so this is also
+ * its thread count) and the number of workgroups a launch aims for (rows are split so that
+ * trial groups x row splits reaches it; the row splits' partial Grams are summed in split
+ * order afterwards).  The best pair
  * depends on l, precision, Y's element type and on whether the launch serves one problem
  * or a batch, and is found by timing (an autotuner sweeps the candidates on the caller's
  * workload and stores the winners here).  Launches without an entry, and every problem
@@ -246,22 +248,27 @@ typedef struct {
   int32_t batched;       /* 0: the launch holds one problem; 1: several */
   int32_t gram_threads;  /* trials per workgroup, one of rsm_tune_threads(); 0 = built-in */
   int32_t gram_wgs;      /* workgroups the launch aims for, 1..1048576; 0 = built-in */
+  int32_t gram_kernel;   /* RSM_GRAM_KERNEL_*; 0 = built-in */
 } rsm_tune_entry;
 
+#define RSM_GRAM_KERNEL_REGS 1  /* tiled Gram staging Y through registers */
+#define RSM_GRAM_KERNEL_DMA 2   /* tiled Gram loading Y straight into LDS (FP32 Y and Gram) */
+
 /* Replaces the table with `count` entries (0 clears it; later duplicates of a key win).
- * RSM_E_ARG, and the table unchanged, for an entry outside the ranges above or a thread
- * count not built for its (l, precision, type). */
+ * RSM_E_ARG, and the table unchanged, for an entry outside the ranges above, a kernel not
+ * built for its (l, precision, type) or a thread count not built for that kernel. */
 int32_t rsm_tune_set(const rsm_tune_entry* entries, int32_t count);
 
 /* Copies up to `cap` entries of the table into `entries` (may be NULL when cap is 0) and
  * the table's size into *count. */
 int32_t rsm_tune_get(rsm_tune_entry* entries, int32_t cap, int32_t* count);
 
-/* The trials-per-workgroup values built for the tiled Gram of (l, gram_prec, y_dtype),
- * ascending, the built-in one included: up to `cap` into `threads`, their number into
- * *count (0 when that combination runs on the per-trial streaming kernel). */
-int32_t rsm_tune_threads(int32_t l, int32_t gram_prec, int32_t y_dtype, int32_t* threads,
-                         int32_t cap, int32_t* count);
+/* The trials-per-workgroup values built for the tiled Gram of (l, gram_prec, y_dtype) with
+ * staging `gram_kernel` (RSM_GRAM_KERNEL_*), ascending: up to `cap` into `threads`, their
+ * number into *count (0 when that kernel does not run that combination, e.g. the per-trial
+ * streaming kernel's cases). */
+int32_t rsm_tune_threads(int32_t l, int32_t gram_prec, int32_t y_dtype, int32_t gram_kernel,
+                         int32_t* threads, int32_t cap, int32_t* count);
 
 #ifdef __cplusplus
 }

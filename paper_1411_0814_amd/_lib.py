@@ -93,7 +93,11 @@ class TuneEntry(C.Structure):
     _fields_ = [
         ("l", C.c_int32), ("gram_prec", C.c_int32), ("y_dtype", C.c_int32),
         ("batched", C.c_int32), ("gram_threads", C.c_int32), ("gram_wgs", C.c_int32),
+        ("gram_kernel", C.c_int32),
     ]
+
+
+GRAM_KERNEL_REGS, GRAM_KERNEL_DMA = 1, 2
 
 
 EXPORTS = ["rsm_abi_version", "rsm_status_string", "rsm_workspace_bytes", "rsm_decompose",
@@ -137,8 +141,8 @@ def lib() -> C.CDLL:
         L.rsm_tune_get.restype = C.c_int32
         L.rsm_tune_get.argtypes = [C.POINTER(TuneEntry), C.c_int32, C.POINTER(C.c_int32)]
         L.rsm_tune_threads.restype = C.c_int32
-        L.rsm_tune_threads.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
-                                       C.c_int32, C.POINTER(C.c_int32)]
+        L.rsm_tune_threads.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                       C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]
         if L.rsm_abi_version() != ABI_VERSION:
             raise LibraryMissing("librsm ABI version mismatch; rebuild the library")
         _LIB = L
@@ -175,7 +179,7 @@ def tune_set(entries) -> None:
     arr = (TuneEntry * max(1, len(entries)))()
     for k, e in enumerate(entries):
         for f in TUNE_FIELDS:
-            setattr(arr[k], f, int(e[f]))
+            setattr(arr[k], f, int(e.get(f, 0)))
     check(lib().rsm_tune_set(arr, len(entries)), "rsm_tune_set")
 
 
@@ -187,9 +191,9 @@ def tune_get() -> list[dict]:
     return [{f: int(getattr(arr[k], f)) for f in TUNE_FIELDS} for k in range(count.value)]
 
 
-def tune_threads(l: int, gram_prec: int, y_dtype: int) -> list[int]:
+def tune_threads(l: int, gram_prec: int, y_dtype: int, kernel: int = GRAM_KERNEL_REGS) -> list[int]:
     buf = (C.c_int32 * 8)()
     count = C.c_int32(0)
-    check(lib().rsm_tune_threads(l, gram_prec, y_dtype, buf, 8, C.byref(count)),
+    check(lib().rsm_tune_threads(l, gram_prec, y_dtype, kernel, buf, 8, C.byref(count)),
           "rsm_tune_threads")
     return [int(buf[k]) for k in range(min(count.value, 8))]

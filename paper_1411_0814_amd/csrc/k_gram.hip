@@ -19,6 +19,9 @@
 //  * k_gram_tile   — the LDS-reuse kernel: a workgroup stages a 32-row x n-column tile of Y
 //    (and the tile's mask words) in LDS once and every thread — one trial each — gathers
 //    its qualifying rows from LDS.  HBM/L2 traffic drops to (trial groups) x |Y|.
+//  * k_gram_dma    — the same for FP32 with 16-row chunks loaded straight into LDS (no
+//    staging registers: more trials' accumulators fit, two workgroups share a CU).
+//  * k_gram_bf16   — the tile kernel's staging with the products on the matrix cores.
 #include <algorithm>
 
 #include "device_util.hpp"
@@ -308,6 +311,108 @@ __global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ p
   }
 }
 
+// ------------------------------------------------------------------ direct-to-LDS staging
+//
+// FP32 variant of k_gram_tile whose Y tile and mask words travel from global memory
+// straight into LDS (global_load_lds_dword: lane k of a wavefront writes 4 bytes at
+// base + 4 k), so no registers hold staged data and a workgroup's LDS holds one 16-row
+// chunk of all n columns (n x 16 floats, at most 64 KiB): two workgroups share a CU and
+// one's staging overlaps the other's Gram work.  Per chunk a wavefront instruction moves
+// 4 columns x 16 rows of Y (column stride 16 floats) or the 32-bit mask words of 64
+// columns (the word holds two chunks' bits).
+
+constexpr int kDmaRows = 16;
+
+__device__ __forceinline__ void lds_dma4(const void* src, float* dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
+}
+
+template <int L, int NT>
+__global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ probs,
+                                                 IdxList list) {
+  constexpr int NG = L * (L + 1) / 2;
+  constexpr int NW = NT / 64;
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int groups = P.gram_groups, splits = P.splits;
+  if (static_cast<int>(blockIdx.x) >= groups * splits) return;  // past this problem's work
+  const int64_t m = P.m, I = P.I, ldy = P.ldy, mw32 = 2 * P.mw;
+  const int n = static_cast<int>(P.n);
+  const int n4 = (n + 3) & ~3, n64 = (n + 63) & ~63;
+  const int64_t chunks = ceil_div(m, kDmaRows), chunks_per_split = 4 * P.words_per_split;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* tile = reinterpret_cast<float*>(smem_raw);                      // [n4][16]
+  float* mskf = tile + static_cast<int64_t>(n4) * kDmaRows;               // [n64]
+  const uint32_t* msk = reinterpret_cast<const uint32_t*>(mskf);
+  int group, split;
+  tile_work(groups, splits, group, split);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t t = static_cast<int64_t>(group) * NT + tid;
+  const bool active = t < I;
+  const int64_t ch0 = static_cast<int64_t>(split) * chunks_per_split;
+  const int64_t ch1 = (ch0 + chunks_per_split < chunks) ? (ch0 + chunks_per_split) : chunks;
+  auto Y = static_cast<RSM_GLOBAL const float*>(P.ycm);
+  auto wbits32 = reinterpret_cast<RSM_GLOBAL const uint32_t*>(P.wbits);
+
+  int mc[L];
+  bool valid = active;
+#pragma unroll
+  for (int a = 0; a < L; ++a) {
+    int c = active ? P.cols[t * L + a] : 0;
+    valid &= (c >= 0);
+    mc[a] = c < 0 ? 0 : c;
+  }
+  float acc[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) acc[g] = 0.0f;
+  int count = 0;
+  const int rot = (tid * 13) & (kDmaRows - 1);
+  const int colk = lane >> 4, rowk = lane & 15;
+
+  for (int64_t ch = ch0; ch < ch1; ++ch) {
+    __syncthreads();  // the previous chunk's reads are done
+    const int64_t r0 = ch * kDmaRows;
+    const int64_t row = (r0 + rowk < m) ? (r0 + rowk) : (m - 1);  // past m: valid address, bit 0
+    for (int g = wu; g < n4 / 4; g += NW) {
+      const int c = (4 * g + colk < n) ? (4 * g + colk) : (n - 1);
+      lds_dma4((const void*)(Y + static_cast<int64_t>(c) * ldy + row), tile + g * 64);
+    }
+    const int64_t word = ch >> 1;
+    for (int g = wu; g < n64 / 64; g += NW) {
+      const int c = (64 * g + lane < n) ? (64 * g + lane) : (n - 1);
+      lds_dma4((const void*)(wbits32 + static_cast<int64_t>(c) * mw32 + word), mskf + g * 64);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (valid) {
+      uint32_t q = 0xffffffffu;
+#pragma unroll
+      for (int a = 0; a < L; ++a) q &= msk[mc[a]];
+      q = (q >> ((ch & 1) * kDmaRows)) & 0xffffu;
+      count += __popc(q);
+      q = ((q >> rot) | (q << (kDmaRows - rot))) & 0xffffu;
+      while (q) {
+        const int i = (__ffs(q) - 1 + rot) & (kDmaRows - 1);
+        q &= q - 1;
+        float y[L];
+#pragma unroll
+        for (int a = 0; a < L; ++a) y[a] = tile[mc[a] * kDmaRows + i];
+        int g = 0;
+#pragma unroll
+        for (int a = 0; a < L; ++a)
+#pragma unroll
+          for (int b = 0; b <= a; ++b) acc[g++] += y[a] * y[b];
+      }
+    }
+  }
+  if (active) {
+    RSM_GLOBAL float* dst = static_cast<RSM_GLOBAL float*>(P.part) + static_cast<int64_t>(split) * NG * I + t;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) dst[static_cast<int64_t>(g) * I] = acc[g];
+    P.prow[static_cast<int64_t>(split) * I + t] = count;
+  }
+}
+
 // ------------------------------------------------------------------ split-BF16 on MFMA
 //
 // The same staging, but the Gram products run on the matrix cores: each value x of a
@@ -468,9 +573,37 @@ void run_tile_nt(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipS
   k_gram_tile<L, T, NT><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
 }
 
+template <int L, int NT>
+void run_dma(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  size_t lds = 0;
+  int wgs = 0;
+  for (int k = 0; k < g.count; ++k) {
+    const size_t n = static_cast<size_t>(h[k]->n);
+    lds = std::max(lds, ((n + 3) & ~size_t(3)) * kDmaRows * 4 + ((n + 63) & ~size_t(63)) * 4);
+    wgs = std::max(wgs, h[k]->gram_wgs);
+  }
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_dma<L, NT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
+    attr_set = true;
+  }
+  const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
+  k_gram_dma<L, NT><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
+}
+
 // The group shares its trials per workgroup (part of the launch key).
 template <int L, typename T>
 void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (h[0]->gram_kernel == RSM_GRAM_KERNEL_DMA) {
+      if (h[0]->gram_threads == 512)
+        run_dma<L, 512>(d, g, h, s);
+      else
+        run_dma<L, 256>(d, g, h, s);
+      return;
+    }
+  }
   if constexpr (tile_has_512<L, T>()) {
     if (h[0]->gram_threads == 512) {
       run_tile_nt<L, T, 512>(d, g, h, s);
@@ -537,14 +670,20 @@ void dispatch_types(const ProbDesc* d, const IdxList& g, const Plan* const* h, h
 
 }  // namespace
 
-int gram_threads_built(int l, int prec, int y_dtype, int* out) {
+int gram_threads_built(int l, int prec, int y_dtype, int kernel, int* out) {
   if (prec == RSM_GRAM_BF16X2) {
-    if (y_dtype != RSM_F32 || l > 16) return 0;
+    if (kernel != RSM_GRAM_KERNEL_REGS || y_dtype != RSM_F32 || l > 16) return 0;
     out[0] = kBfTrialsPerGroup;
     return 1;
   }
   const bool f64 = prec == RSM_GRAM_F64;
   if (f64 != (y_dtype == RSM_F64)) return 0;
+  if (kernel == RSM_GRAM_KERNEL_DMA) {
+    if (f64) return 0;
+    out[0] = 256;
+    out[1] = 512;
+    return 2;
+  }
   out[0] = 256;
   if (l <= (f64 ? 6 : 10)) {
     out[1] = 512;

@@ -80,14 +80,38 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   // and the accumulation type matches Y's (split-BF16: FP32 Y), else the per-trial streamer
   P.tiled = !(p.flags & RSM_PLAIN_GRAM);
   P.tiled = gram_tiled_ok(P);
-  if (P.tiled) set_gram_shape(P, default_gram_threads(P), 0);
-  else set_gram_shape(P, 0, 0);
+  if (P.tiled) {
+    P.gram_kernel = default_gram_kernel(P);
+    set_gram_shape(P, default_gram_threads(P, P.gram_kernel), 0);
+  } else {
+    P.gram_kernel = 0;
+    set_gram_shape(P, 0, 0);
+  }
   return RSM_OK;
 }
 
+// Staging of the tiled kernels when the tile table does not say otherwise: straight into
+// LDS for FP32 with l >= 15, where the accumulators leave no registers for staging.
+int builtin_gram_kernel(int l, int prec, int y_dtype) {
+  return (prec == RSM_GRAM_F32 && y_dtype == RSM_F32 && l >= 15) ? RSM_GRAM_KERNEL_DMA
+                                                                 : RSM_GRAM_KERNEL_REGS;
+}
+
+int default_gram_kernel(const Plan& P) { return builtin_gram_kernel(P.l, P.prec, P.y_dtype); }
+
+// Whether `threads` trials per workgroup are built for this staging kernel.
+bool threads_built(int l, int prec, int y_dtype, int kernel, int threads) {
+  int built[8];
+  const int nb = gram_threads_built(l, prec, y_dtype, kernel, built);
+  for (int j = 0; j < nb; ++j)
+    if (built[j] == threads) return true;
+  return false;
+}
+
 // Trials per workgroup of the tiled kernels when the tile table does not say otherwise.
-int default_gram_threads(const Plan& P) {
+int default_gram_threads(const Plan& P, int kernel) {
   if (P.prec == RSM_GRAM_BF16X2) return kBfTrialsPerGroup;
+  if (kernel == RSM_GRAM_KERNEL_DMA) return 256;
   return tile_threads(P.l, P.prec == RSM_GRAM_F64 ? 8 : 4);
 }
 
@@ -196,7 +220,10 @@ int32_t make_plans(const rsm_problem* problems, int32_t nprob, std::vector<Plan>
       const Plan& P0 = plans[members[0]];
       const rsm_tune_entry* e = tune_find(table, P0, members.size() > 1);
       if (!e) continue;
-      const int threads = e->gram_threads ? e->gram_threads : default_gram_threads(P0);
+      const int kernel = e->gram_kernel ? e->gram_kernel : default_gram_kernel(P0);
+      int threads = e->gram_threads ? e->gram_threads : default_gram_threads(P0, kernel);
+      if (!threads_built(P0.l, P0.prec, P0.y_dtype, kernel, threads))
+        threads = default_gram_threads(P0, kernel);  // (rsm_tune_set admits built ones only)
       int64_t splits = 0;
       if (e->gram_wgs > 0) {
         int64_t total = 0;
@@ -204,7 +231,10 @@ int32_t make_plans(const rsm_problem* problems, int32_t nprob, std::vector<Plan>
         splits = e->gram_wgs / total;
         if (splits < 1) splits = 1;
       }
-      for (int32_t k : members) set_gram_shape(plans[k], threads, splits);
+      for (int32_t k : members) {
+        plans[k].gram_kernel = kernel;
+        set_gram_shape(plans[k], threads, splits);
+      }
     }
   }
   for (Plan& P : plans) set_layout(P);
@@ -448,7 +478,7 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   for_groups(plans, [](const Plan& P) { return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0; },
              [](const Plan& P) {
                return ((((int64_t(P.l) * 4 + P.y_dtype) * 4 + P.prec) * 2 + (P.tiled ? 1 : 0)) *
-                       1024) + P.gram_threads;
+                       4 + P.gram_kernel) * 1024 + P.gram_threads;
              },
              [&](const IdxList& g, const Plan* const* h) {
                mark_all(outputs, g, RSM_STEP_GRAM, 0, s);
@@ -515,15 +545,15 @@ int32_t rsm_tune_set(const rsm_tune_entry* entries, int32_t count) {
     if (e.l < 2 || e.l > RSM_MAX_L || e.gram_prec < RSM_GRAM_F64 ||
         e.gram_prec > RSM_GRAM_BF16X2 || (e.y_dtype != RSM_F32 && e.y_dtype != RSM_F64) ||
         (e.batched != 0 && e.batched != 1) || e.gram_wgs < 0 || e.gram_wgs > (1 << 20) ||
-        e.gram_threads < 0)
+        e.gram_threads < 0 || e.gram_kernel < 0 || e.gram_kernel > RSM_GRAM_KERNEL_DMA)
       return RSM_E_ARG;
-    if (e.gram_threads) {
-      int built[8];
-      const int nb = gram_threads_built(e.l, e.gram_prec, e.y_dtype, built);
-      bool ok = false;
-      for (int j = 0; j < nb; ++j) ok = ok || built[j] == e.gram_threads;
-      if (!ok) return RSM_E_ARG;
-    }
+    int built[8];
+    if (e.gram_kernel && !gram_threads_built(e.l, e.gram_prec, e.y_dtype, e.gram_kernel, built))
+      return RSM_E_ARG;
+    // thread counts are checked against the entry's kernel, or the built-in one
+    const int kernel = e.gram_kernel ? e.gram_kernel : builtin_gram_kernel(e.l, e.gram_prec, e.y_dtype);
+    if (e.gram_threads && !threads_built(e.l, e.gram_prec, e.y_dtype, kernel, e.gram_threads))
+      return RSM_E_ARG;
   }
   std::lock_guard<std::mutex> lock(g_tune_mu);
   g_tune.assign(entries, entries + count);
@@ -540,12 +570,14 @@ int32_t rsm_tune_get(rsm_tune_entry* entries, int32_t cap, int32_t* count) {
   return RSM_OK;
 }
 
-int32_t rsm_tune_threads(int32_t l, int32_t gram_prec, int32_t y_dtype, int32_t* threads,
-                         int32_t cap, int32_t* count) {
+int32_t rsm_tune_threads(int32_t l, int32_t gram_prec, int32_t y_dtype, int32_t gram_kernel,
+                         int32_t* threads, int32_t cap, int32_t* count) {
   using namespace rsm;
-  if (!count || cap < 0 || (cap > 0 && !threads) || l < 2 || l > RSM_MAX_L) return RSM_E_ARG;
+  if (!count || cap < 0 || (cap > 0 && !threads) || l < 2 || l > RSM_MAX_L ||
+      gram_kernel < RSM_GRAM_KERNEL_REGS || gram_kernel > RSM_GRAM_KERNEL_DMA)
+    return RSM_E_ARG;
   int built[8];
-  const int nb = gram_threads_built(l, gram_prec, y_dtype, built);
+  const int nb = gram_threads_built(l, gram_prec, y_dtype, gram_kernel, built);
   for (int j = 0; j < nb && j < cap; ++j) threads[j] = built[j];
   *count = nb;
   return RSM_OK;

@@ -76,6 +76,7 @@ struct Plan {
   size_t part_elem = 4;  // bytes of one partial-Gram element
   int gram_groups = 0;   // tiled Gram: trial groups (workgroups per row split)
   int gram_threads = 0;  // tiled Gram: trials per workgroup (0: per-trial streamer)
+  int gram_kernel = 0;   // tiled Gram staging: RSM_GRAM_KERNEL_REGS or _DMA (0: streamer)
   bool u_mfma = false;   // U-hat normal equations formed on the FP64 matrix cores
   bool minor_inv = false;  // minor vector by inverse iteration (nvec 1, no eigen taps)
   int gram_wgs = 0;      // workgroups of the Gram step of this problem
@@ -187,14 +188,17 @@ void launch_error(const ProbDesc* d, const IdxList& g, const Plan* const* h, hip
 // the Gram row splits for `threads` trials per workgroup (splits_hint 0: this problem
 // alone); the workspace offsets; all plans of a call, with the tile table applied.
 int32_t make_plan(const rsm_problem& p, Plan& P);
-int default_gram_threads(const Plan& P);
+int builtin_gram_kernel(int l, int prec, int y_dtype);
+int default_gram_kernel(const Plan& P);
+bool threads_built(int l, int prec, int y_dtype, int kernel, int threads);
+int default_gram_threads(const Plan& P, int kernel);
 void set_gram_shape(Plan& P, int threads, int64_t splits_hint);
 void set_layout(Plan& P);
 int32_t make_plans(const rsm_problem* problems, int32_t nprob, std::vector<Plan>& plans);
 
-// Trials-per-workgroup values built for the tiled Gram of (l, precision, Y type), ascending,
-// into out[0..7]; returns their number (0: the per-trial streamer runs it).
-int gram_threads_built(int l, int prec, int y_dtype, int* out);
+// Trials-per-workgroup values built for the tiled Gram of (l, precision, Y type) with the
+// given staging kernel, ascending, into out[0..7]; returns their number (0: not built).
+int gram_threads_built(int l, int prec, int y_dtype, int kernel, int* out);
 
 // Whether the LDS-tiled Gram kernel can run this problem (its eligibility and matching
 // element types).

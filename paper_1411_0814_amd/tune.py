@@ -1,11 +1,13 @@
 """Autotuner of the gather + Gram step's tile shapes.
 
-The tiled Gram kernel (steps a2 + a3) has two free parameters per launch: the trials per
+The tiled Gram kernel (steps a2 + a3) has three free parameters per launch: how Y is
+staged into LDS (through registers in 32-row chunks, or loaded straight into LDS in
+16-row chunks, which leaves more registers for the trials' accumulators), the trials per
 workgroup (one thread per trial, so also the workgroup size) and the number of workgroups
 the launch aims for, which sets how many row splits each trial's Gram is cut into (their
-partial Grams are summed afterwards, in the minor-vector step).  Both trade occupancy
-against re-reads of Y and partial-sum traffic, and the best pair depends on l, Y's element
-type, the Gram precision and on whether the launch serves one problem or a whole batch.
+partial Grams are summed afterwards, in the minor-vector step).  They trade occupancy
+against re-reads of Y and partial-sum traffic, and the best choice depends on l, Y's
+element type, the Gram precision and on whether the launch serves one problem or a batch.
 
 `autotune(requests)` groups the requests the way the library groups its launches, times
 every candidate pair on those very problems (the Gram and minor-vector steps, which hold
@@ -95,8 +97,9 @@ def autotune(requests, *, wgs=WGS_CANDIDATES, reps: int = 3, stream=None,
     base = [e for e in table()] if keep_existing else []
     report = []
     for (l, prec, ydt), members in sorted(groups.items()):
-        threads = _lib.tune_threads(l, prec, ydt)
-        if not threads:
+        shapes = [(kern, nt) for kern in (_lib.GRAM_KERNEL_REGS, _lib.GRAM_KERNEL_DMA)
+                  for nt in _lib.tune_threads(l, prec, ydt, kern)]
+        if not shapes:
             continue                                 # per-trial streamer: nothing to tune
         batched = 1 if len(members) > 1 else 0
         others = [e for e in base if (e["l"], e["gram_prec"], e["y_dtype"], e["batched"])
@@ -108,10 +111,10 @@ def autotune(requests, *, wgs=WGS_CANDIDATES, reps: int = 3, stream=None,
         install(others)
         t_builtin = _time_group(run, stream, reps, torch)
         best, best_t = None, t_builtin
-        for nt in threads:
+        for kern, nt in shapes:
             for w in wgs:
                 cand = {"l": l, "gram_prec": prec, "y_dtype": ydt, "batched": batched,
-                        "gram_threads": nt, "gram_wgs": int(w)}
+                        "gram_threads": nt, "gram_wgs": int(w), "gram_kernel": kern}
                 install(others + [cand])
                 t = _time_group(run, stream, reps, torch)
                 if t < best_t:
@@ -121,7 +124,8 @@ def autotune(requests, *, wgs=WGS_CANDIDATES, reps: int = 3, stream=None,
                        "problems": len(members), "builtin_ms": round(t_builtin, 4),
                        "best_ms": round(best_t, 4),
                        "choice": None if best is None else
-                       {"gram_threads": best["gram_threads"], "gram_wgs": best["gram_wgs"]}})
+                       {"gram_kernel": best["gram_kernel"], "gram_threads": best["gram_threads"],
+                        "gram_wgs": best["gram_wgs"]}})
     install(base)
     return {"entries": base, "groups": report,
             "seconds": round(time.perf_counter() - t_start, 2)}

@@ -49,6 +49,8 @@ int main(void) {
   printf("rsm_tune_entry %zu\n", sizeof(rsm_tune_entry));
   F(rsm_tune_entry, l) F(rsm_tune_entry, gram_prec) F(rsm_tune_entry, y_dtype)
   F(rsm_tune_entry, batched) F(rsm_tune_entry, gram_threads) F(rsm_tune_entry, gram_wgs)
+  F(rsm_tune_entry, gram_kernel)
+  printf("KERNELS %d %d\n", RSM_GRAM_KERNEL_REGS, RSM_GRAM_KERNEL_DMA);
   printf("STEPS %d\n", RSM_NUM_STEPS);
   printf("MAX %d %d %d %d\n", RSM_MAX_R, RSM_MAX_L, RSM_MAX_N, RSM_ABI_VERSION);
   return 0;
@@ -77,11 +79,12 @@ def test_struct_layouts_match_header():
     structs = {"rsm_problem": _lib.Problem, "rsm_input": _lib.Input, "rsm_info": _lib.Info,
                "rsm_output": _lib.Output, "rsm_tune_entry": _lib.TuneEntry}
     for k, v in got.items():
-        if "." in k and k != "STEPS":
+        if "." in k:
             s, f = k.split(".")
             assert getattr(structs[s], pyname.get(f, f)).offset == int(v[0]), k
     assert [int(x) for x in got["MAX"]] == [_lib.MAX_R, _lib.MAX_L, _lib.MAX_N, _lib.ABI_VERSION]
     assert int(got["STEPS"][0]) == len(_lib.STEPS)
+    assert [int(x) for x in got["KERNELS"]] == [_lib.GRAM_KERNEL_REGS, _lib.GRAM_KERNEL_DMA]
 
 
 def _prob(**kw):
@@ -197,13 +200,18 @@ def empty_tune_table():
 
 def _entry(**kw):
     e = {"l": 9, "gram_prec": _lib.GRAM_F32, "y_dtype": _lib.F32, "batched": 0,
-         "gram_threads": 512, "gram_wgs": 1024}
+         "gram_threads": 512, "gram_wgs": 1024, "gram_kernel": 0}
     e.update(kw)
     return e
 
 
 def test_tune_threads_lists_built_kernels():
     F32, F64 = _lib.F32, _lib.F64
+    DMA = _lib.GRAM_KERNEL_DMA
+    assert _lib.tune_threads(17, _lib.GRAM_F32, F32, DMA) == [256, 512]
+    assert _lib.tune_threads(3, _lib.GRAM_F32, F32, DMA) == [256, 512]
+    assert _lib.tune_threads(6, _lib.GRAM_F64, F64, DMA) == []
+    assert _lib.tune_threads(9, _lib.GRAM_BF16X2, F32, DMA) == []
     assert _lib.tune_threads(9, _lib.GRAM_F32, F32) == [256, 512]
     assert _lib.tune_threads(10, _lib.GRAM_F32, F32) == [256, 512]
     assert _lib.tune_threads(12, _lib.GRAM_F32, F32) == [256]
@@ -216,11 +224,18 @@ def test_tune_threads_lists_built_kernels():
 
 def test_tune_table_roundtrip_and_validation(empty_tune_table):
     good = [_entry(), _entry(l=12, gram_threads=256, batched=1, gram_wgs=0),
-            _entry(l=16, gram_prec=_lib.GRAM_BF16X2, gram_threads=128, gram_wgs=64)]
+            _entry(l=16, gram_prec=_lib.GRAM_BF16X2, gram_threads=128, gram_wgs=64),
+            _entry(l=17, gram_threads=512, gram_kernel=_lib.GRAM_KERNEL_DMA),
+            _entry(l=17, gram_threads=512)]          # l = 17 stages straight into LDS by default
     _lib.tune_set(good)
     assert _lib.tune_get() == good
     bad = [_entry(l=1), _entry(l=_lib.MAX_L + 1), _entry(gram_threads=384),
-           _entry(l=12, gram_threads=512), _entry(gram_wgs=-1), _entry(gram_wgs=(1 << 20) + 1),
+           _entry(l=12, gram_threads=512, gram_kernel=_lib.GRAM_KERNEL_REGS),
+           _entry(l=12, gram_threads=512),           # built-in kernel at l = 12: registers
+           _entry(gram_kernel=3), _entry(gram_kernel=-1),
+           _entry(l=6, gram_prec=_lib.GRAM_F64, y_dtype=_lib.F64, gram_threads=0,
+                  gram_kernel=_lib.GRAM_KERNEL_DMA),
+           _entry(gram_wgs=-1), _entry(gram_wgs=(1 << 20) + 1),
            _entry(batched=2), _entry(y_dtype=7), _entry(gram_prec=3),
            _entry(gram_prec=_lib.GRAM_F64, gram_threads=256)]     # F64 Gram of F32 Y: streamer
     for e in bad:

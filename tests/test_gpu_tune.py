@@ -19,14 +19,17 @@ def _empty_table():
     _lib.tune_set([])
 
 
-# (l, Y/Gram type, trials per workgroup, workgroup target): both thread counts, a single
-# row split and many row splits
-CASES = [(3, "f32", 256, 1), (6, "f32", 256, 8192), (9, "f32", 512, 8192), (10, "f32", 256, 64),
-         (12, "f32", 256, 4096), (4, "f64", 256, 2048), (6, "f64", 512, 1)]
+REGS, DMA = 1, 2
+# (l, Y/Gram type, trials per workgroup, workgroup target, staging): both staging kernels,
+# both thread counts, a single row split and many row splits
+CASES = [(3, "f32", 256, 1, REGS), (6, "f32", 256, 8192, REGS), (9, "f32", 512, 8192, REGS),
+         (10, "f32", 256, 64, REGS), (12, "f32", 256, 4096, REGS), (4, "f64", 256, 2048, REGS),
+         (6, "f64", 512, 1, REGS), (3, "f32", 512, 1, DMA), (9, "f32", 256, 8192, DMA),
+         (13, "f32", 512, 64, DMA), (17, "f32", 256, 4096, DMA), (17, "f32", 512, 1, DMA)]
 
 
-@pytest.mark.parametrize("l,prec,threads,wgs", CASES)
-def test_tuned_gram_shapes_exact_rows_and_bounded_gram(l, prec, threads, wgs):
+@pytest.mark.parametrize("l,prec,threads,wgs,kernel", CASES)
+def test_tuned_gram_shapes_exact_rows_and_bounded_gram(l, prec, threads, wgs, kernel):
     from paper_1411_0814_amd import _lib, decompose
     dt = np.float32 if prec == "f32" else np.float64
     r = l - 1
@@ -34,7 +37,7 @@ def test_tuned_gram_shapes_exact_rows_and_bounded_gram(l, prec, threads, wgs):
                               num_submatrices=700, seed_rsm=l, gram=prec)
     _lib.tune_set([{"l": l, "gram_prec": _lib.GRAM_MODES[prec],
                     "y_dtype": _lib.F32 if prec == "f32" else _lib.F64, "batched": 0,
-                    "gram_threads": threads, "gram_wgs": wgs}])
+                    "gram_threads": threads, "gram_wgs": wgs, "gram_kernel": kernel}])
     Y, W = to_device(p)
     res = decompose(Y, W, p.r, p.num_submatrices, p.seed_rsm, l=l, gram=prec, taps=True)
     cols = res.taps["cols"].cpu().numpy()
