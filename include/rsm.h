@@ -227,7 +227,8 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
 /* ---------------------------------------------------------------------------------------
  * Tile table (library-wide, host side).  The fused gather + Gram step (a2 + a3) has three
  * free parameters: how the tiled kernel stages Y (1: through registers, 32-row chunks; 2:
- * straight from global memory into LDS, 16-row chunks, fewer registers per thread), the
+ * straight from global memory into LDS, 16-row chunks, fewer registers per thread; 3: as 2
+ * with two chunk buffers, the next chunk's loads overlapping the sums), the
  * trials per workgroup (each thread owns one trial's l(l+1)/2 accumulators, so this is also
  * its thread count) and the number of workgroups a launch aims for (rows are split so that
  * trial groups x row splits reaches it; the row splits' partial Grams are summed in split
@@ -253,6 +254,7 @@ typedef struct {
 
 #define RSM_GRAM_KERNEL_REGS 1  /* tiled Gram staging Y through registers */
 #define RSM_GRAM_KERNEL_DMA 2   /* tiled Gram loading Y straight into LDS (FP32 Y and Gram) */
+#define RSM_GRAM_KERNEL_DMA2 3  /* the same with two chunk buffers (loads overlap the sums) */
 
 /* Replaces the table with `count` entries (0 clears it; later duplicates of a key win).
  * RSM_E_ARG, and the table unchanged, for an entry outside the ranges above, a kernel not

@@ -97,7 +97,7 @@ class TuneEntry(C.Structure):
     ]
 
 
-GRAM_KERNEL_REGS, GRAM_KERNEL_DMA = 1, 2
+GRAM_KERNEL_REGS, GRAM_KERNEL_DMA, GRAM_KERNEL_DMA2 = 1, 2, 3
 
 
 EXPORTS = ["rsm_abi_version", "rsm_status_string", "rsm_workspace_bytes", "rsm_decompose",

@@ -20,7 +20,8 @@
 //    (and the tile's mask words) in LDS once and every thread — one trial each — gathers
 //    its qualifying rows from LDS.  HBM/L2 traffic drops to (trial groups) x |Y|.
 //  * k_gram_dma    — the same for FP32 with 16-row chunks loaded straight into LDS (no
-//    staging registers: more trials' accumulators fit, two workgroups share a CU).
+//    staging registers: more trials' accumulators fit, two workgroups share a CU), with
+//    one chunk buffer or two (the next chunk's loads in flight during the sums).
 //  * k_gram_bf16   — the tile kernel's staging with the products on the matrix cores.
 #include <algorithm>
 
@@ -327,7 +328,9 @@ __device__ __forceinline__ void lds_dma4(const void* src, float* dst) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
 }
 
-template <int L, int NT>
+// DB: two chunk buffers; the loads of chunk k + 1 are issued right after the barrier that
+// publishes chunk k and land while chunk k is summed (one barrier per chunk).
+template <int L, int NT, bool DB>
 __global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ probs,
                                                  IdxList list) {
   constexpr int NG = L * (L + 1) / 2;
@@ -340,9 +343,9 @@ __global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ pr
   const int n4 = (n + 3) & ~3, n64 = (n + 63) & ~63;
   const int64_t chunks = ceil_div(m, kDmaRows), chunks_per_split = 4 * P.words_per_split;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  float* tile = reinterpret_cast<float*>(smem_raw);                      // [n4][16]
-  float* mskf = tile + static_cast<int64_t>(n4) * kDmaRows;               // [n64]
-  const uint32_t* msk = reinterpret_cast<const uint32_t*>(mskf);
+  // per buffer: the tile [n4][16] floats, then the mask words [n64]
+  const int buf_floats = n4 * kDmaRows + n64;
+  float* const buf0 = reinterpret_cast<float*>(smem_raw);
   int group, split;
   tile_work(groups, splits, group, split);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -369,21 +372,37 @@ __global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ pr
   const int rot = (tid * 13) & (kDmaRows - 1);
   const int colk = lane >> 4, rowk = lane & 15;
 
-  for (int64_t ch = ch0; ch < ch1; ++ch) {
-    __syncthreads();  // the previous chunk's reads are done
+  // loads of chunk ch into the buffer at `dst` (tile, then mask words)
+  auto issue = [&](int64_t ch, float* dst) {
     const int64_t r0 = ch * kDmaRows;
     const int64_t row = (r0 + rowk < m) ? (r0 + rowk) : (m - 1);  // past m: valid address, bit 0
     for (int g = wu; g < n4 / 4; g += NW) {
       const int c = (4 * g + colk < n) ? (4 * g + colk) : (n - 1);
-      lds_dma4((const void*)(Y + static_cast<int64_t>(c) * ldy + row), tile + g * 64);
+      lds_dma4((const void*)(Y + static_cast<int64_t>(c) * ldy + row), dst + g * 64);
     }
     const int64_t word = ch >> 1;
+    float* mdst = dst + n4 * kDmaRows;
     for (int g = wu; g < n64 / 64; g += NW) {
       const int c = (64 * g + lane < n) ? (64 * g + lane) : (n - 1);
-      lds_dma4((const void*)(wbits32 + static_cast<int64_t>(c) * mw32 + word), mskf + g * 64);
+      lds_dma4((const void*)(wbits32 + static_cast<int64_t>(c) * mw32 + word), mdst + g * 64);
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+  };
+  if (DB && ch0 < ch1) issue(ch0, buf0);
+  for (int64_t ch = ch0; ch < ch1; ++ch) {
+    float* cur = buf0;
+    if constexpr (DB) {
+      cur = buf0 + ((ch - ch0) & 1) * buf_floats;
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();  // chunk ch is in `cur`; every wave is done with the other buffer
+      if (ch + 1 < ch1) issue(ch + 1, buf0 + ((ch + 1 - ch0) & 1) * buf_floats);
+    } else {
+      __syncthreads();  // the previous chunk's reads are done
+      issue(ch, cur);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    const float* tile = cur;
+    const uint32_t* msk = reinterpret_cast<const uint32_t*>(cur + n4 * kDmaRows);
     if (valid) {
       uint32_t q = 0xffffffffu;
 #pragma unroll
@@ -573,23 +592,31 @@ void run_tile_nt(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipS
   k_gram_tile<L, T, NT><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
 }
 
-template <int L, int NT>
+template <int L, int NT, bool DB>
 void run_dma(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
   size_t lds = 0;
   int wgs = 0;
   for (int k = 0; k < g.count; ++k) {
     const size_t n = static_cast<size_t>(h[k]->n);
-    lds = std::max(lds, ((n + 3) & ~size_t(3)) * kDmaRows * 4 + ((n + 63) & ~size_t(63)) * 4);
+    const size_t one = ((n + 3) & ~size_t(3)) * kDmaRows * 4 + ((n + 63) & ~size_t(63)) * 4;
+    lds = std::max(lds, DB ? 2 * one : one);
     wgs = std::max(wgs, h[k]->gram_wgs);
   }
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_dma<L, NT>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_dma<L, NT, DB>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 156 * 1024);
     attr_set = true;
   }
   const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
-  k_gram_dma<L, NT><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
+  k_gram_dma<L, NT, DB><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
+}
+
+// Largest trial count per workgroup of the double-buffered kernel: 1024 threads leave 128
+// registers, enough for the accumulators up to l = 12.
+template <int L>
+constexpr bool dma_has_1024() {
+  return L <= 12;
 }
 
 // The group shares its trials per workgroup (part of the launch key).
@@ -598,9 +625,19 @@ void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStre
   if constexpr (sizeof(T) == 4) {
     if (h[0]->gram_kernel == RSM_GRAM_KERNEL_DMA) {
       if (h[0]->gram_threads == 512)
-        run_dma<L, 512>(d, g, h, s);
+        run_dma<L, 512, false>(d, g, h, s);
       else
-        run_dma<L, 256>(d, g, h, s);
+        run_dma<L, 256, false>(d, g, h, s);
+      return;
+    }
+    if (h[0]->gram_kernel == RSM_GRAM_KERNEL_DMA2) {
+      if constexpr (dma_has_1024<L>()) {
+        if (h[0]->gram_threads == 1024) {
+          run_dma<L, 1024, true>(d, g, h, s);
+          return;
+        }
+      }
+      run_dma<L, 512, true>(d, g, h, s);
       return;
     }
   }
@@ -683,6 +720,15 @@ int gram_threads_built(int l, int prec, int y_dtype, int kernel, int* out) {
     out[0] = 256;
     out[1] = 512;
     return 2;
+  }
+  if (kernel == RSM_GRAM_KERNEL_DMA2) {
+    if (f64) return 0;
+    out[0] = 512;
+    if (l <= 12) {
+      out[1] = 1024;
+      return 2;
+    }
+    return 1;
   }
   out[0] = 256;
   if (l <= (f64 ? 6 : 10)) {

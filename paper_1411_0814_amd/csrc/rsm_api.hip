@@ -90,11 +90,13 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   return RSM_OK;
 }
 
-// Staging of the tiled kernels when the tile table does not say otherwise: straight into
-// LDS for FP32 with l >= 15, where the accumulators leave no registers for staging.
+// Staging of the tiled kernels when the tile table does not say otherwise: FP32 loads
+// straight into LDS with two chunk buffers (no staging registers, loads overlapping the
+// sums); FP64 and split-BF16 stage through registers.
 int builtin_gram_kernel(int l, int prec, int y_dtype) {
-  return (prec == RSM_GRAM_F32 && y_dtype == RSM_F32 && l >= 15) ? RSM_GRAM_KERNEL_DMA
-                                                                 : RSM_GRAM_KERNEL_REGS;
+  (void)l;
+  return (prec == RSM_GRAM_F32 && y_dtype == RSM_F32) ? RSM_GRAM_KERNEL_DMA2
+                                                      : RSM_GRAM_KERNEL_REGS;
 }
 
 int default_gram_kernel(const Plan& P) { return builtin_gram_kernel(P.l, P.prec, P.y_dtype); }
@@ -112,6 +114,7 @@ bool threads_built(int l, int prec, int y_dtype, int kernel, int threads) {
 int default_gram_threads(const Plan& P, int kernel) {
   if (P.prec == RSM_GRAM_BF16X2) return kBfTrialsPerGroup;
   if (kernel == RSM_GRAM_KERNEL_DMA) return 256;
+  if (kernel == RSM_GRAM_KERNEL_DMA2) return P.l <= 12 ? 1024 : 512;
   return tile_threads(P.l, P.prec == RSM_GRAM_F64 ? 8 : 4);
 }
 
@@ -545,7 +548,7 @@ int32_t rsm_tune_set(const rsm_tune_entry* entries, int32_t count) {
     if (e.l < 2 || e.l > RSM_MAX_L || e.gram_prec < RSM_GRAM_F64 ||
         e.gram_prec > RSM_GRAM_BF16X2 || (e.y_dtype != RSM_F32 && e.y_dtype != RSM_F64) ||
         (e.batched != 0 && e.batched != 1) || e.gram_wgs < 0 || e.gram_wgs > (1 << 20) ||
-        e.gram_threads < 0 || e.gram_kernel < 0 || e.gram_kernel > RSM_GRAM_KERNEL_DMA)
+        e.gram_threads < 0 || e.gram_kernel < 0 || e.gram_kernel > RSM_GRAM_KERNEL_DMA2)
       return RSM_E_ARG;
     int built[8];
     if (e.gram_kernel && !gram_threads_built(e.l, e.gram_prec, e.y_dtype, e.gram_kernel, built))
@@ -574,7 +577,7 @@ int32_t rsm_tune_threads(int32_t l, int32_t gram_prec, int32_t y_dtype, int32_t 
                          int32_t* threads, int32_t cap, int32_t* count) {
   using namespace rsm;
   if (!count || cap < 0 || (cap > 0 && !threads) || l < 2 || l > RSM_MAX_L ||
-      gram_kernel < RSM_GRAM_KERNEL_REGS || gram_kernel > RSM_GRAM_KERNEL_DMA)
+      gram_kernel < RSM_GRAM_KERNEL_REGS || gram_kernel > RSM_GRAM_KERNEL_DMA2)
     return RSM_E_ARG;
   int built[8];
   const int nb = gram_threads_built(l, gram_prec, y_dtype, gram_kernel, built);

@@ -97,7 +97,8 @@ def autotune(requests, *, wgs=WGS_CANDIDATES, reps: int = 3, stream=None,
     base = [e for e in table()] if keep_existing else []
     report = []
     for (l, prec, ydt), members in sorted(groups.items()):
-        shapes = [(kern, nt) for kern in (_lib.GRAM_KERNEL_REGS, _lib.GRAM_KERNEL_DMA)
+        shapes = [(kern, nt) for kern in (_lib.GRAM_KERNEL_REGS, _lib.GRAM_KERNEL_DMA,
+                                          _lib.GRAM_KERNEL_DMA2)
                   for nt in _lib.tune_threads(l, prec, ydt, kern)]
         if not shapes:
             continue                                 # per-trial streamer: nothing to tune

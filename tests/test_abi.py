@@ -212,6 +212,10 @@ def test_tune_threads_lists_built_kernels():
     assert _lib.tune_threads(3, _lib.GRAM_F32, F32, DMA) == [256, 512]
     assert _lib.tune_threads(6, _lib.GRAM_F64, F64, DMA) == []
     assert _lib.tune_threads(9, _lib.GRAM_BF16X2, F32, DMA) == []
+    DB = _lib.GRAM_KERNEL_DMA2
+    assert _lib.tune_threads(12, _lib.GRAM_F32, F32, DB) == [512, 1024]
+    assert _lib.tune_threads(13, _lib.GRAM_F32, F32, DB) == [512]
+    assert _lib.tune_threads(4, _lib.GRAM_F64, F64, DB) == []
     assert _lib.tune_threads(9, _lib.GRAM_F32, F32) == [256, 512]
     assert _lib.tune_threads(10, _lib.GRAM_F32, F32) == [256, 512]
     assert _lib.tune_threads(12, _lib.GRAM_F32, F32) == [256]
@@ -223,16 +227,19 @@ def test_tune_threads_lists_built_kernels():
 
 
 def test_tune_table_roundtrip_and_validation(empty_tune_table):
-    good = [_entry(), _entry(l=12, gram_threads=256, batched=1, gram_wgs=0),
+    good = [_entry(), _entry(l=12, gram_threads=256, batched=1, gram_wgs=0,
+                             gram_kernel=_lib.GRAM_KERNEL_REGS),
             _entry(l=16, gram_prec=_lib.GRAM_BF16X2, gram_threads=128, gram_wgs=64),
             _entry(l=17, gram_threads=512, gram_kernel=_lib.GRAM_KERNEL_DMA),
-            _entry(l=17, gram_threads=512)]          # l = 17 stages straight into LDS by default
+            _entry(l=17, gram_threads=512),          # FP32 stages straight into LDS by default
+            _entry(l=9, gram_threads=1024)]
     _lib.tune_set(good)
     assert _lib.tune_get() == good
     bad = [_entry(l=1), _entry(l=_lib.MAX_L + 1), _entry(gram_threads=384),
            _entry(l=12, gram_threads=512, gram_kernel=_lib.GRAM_KERNEL_REGS),
-           _entry(l=12, gram_threads=512),           # built-in kernel at l = 12: registers
-           _entry(gram_kernel=3), _entry(gram_kernel=-1),
+           _entry(l=13, gram_threads=1024),          # built-in kernel at l = 13: 512 only
+           _entry(gram_kernel=4), _entry(gram_kernel=-1),
+           _entry(l=13, gram_threads=1024, gram_kernel=_lib.GRAM_KERNEL_DMA2),
            _entry(l=6, gram_prec=_lib.GRAM_F64, y_dtype=_lib.F64, gram_threads=0,
                   gram_kernel=_lib.GRAM_KERNEL_DMA),
            _entry(gram_wgs=-1), _entry(gram_wgs=(1 << 20) + 1),
@@ -254,15 +261,16 @@ def test_tune_table_sets_the_gram_shape(empty_tune_table):
               y_dtype=_lib.F32)
     code, base = _ws(p)
     assert code == _lib.OK
-    # built-in: 16 groups of 512 trials x 16 splits; 8192 workgroups -> 512 splits
+    # built-in: 8 groups of 1024 trials x 32 splits; 512 trials and 8192 workgroups -> 16
+    # groups x 512 splits
     _lib.tune_set([_entry(gram_wgs=8192)])
     code, more = _ws(p)
     part_row = 8192 * 45 * 4 + 8192 * 4            # partial Grams + partial row counts
-    assert more - base >= (512 - 16) * part_row - 4096
-    # 256 trials per workgroup and a one-workgroup-per-group target: a single split
-    _lib.tune_set([_entry(gram_threads=256, gram_wgs=1)])
+    assert more - base >= (512 - 32) * part_row - 4096
+    # a one-workgroup-per-group target: a single split
+    _lib.tune_set([_entry(gram_threads=512, gram_wgs=1)])
     code, fewer = _ws(p)
-    assert base - fewer >= 15 * part_row - 4096
+    assert base - fewer >= 31 * part_row - 4096
     # entries for batched launches or another l do not apply to this lone problem
     _lib.tune_set([_entry(batched=1, gram_wgs=8192), _entry(l=10, gram_wgs=8192)])
     assert _ws(p)[1] == base

@@ -19,13 +19,15 @@ def _empty_table():
     _lib.tune_set([])
 
 
-REGS, DMA = 1, 2
+REGS, DMA, DMA2 = 1, 2, 3
 # (l, Y/Gram type, trials per workgroup, workgroup target, staging): both staging kernels,
 # both thread counts, a single row split and many row splits
 CASES = [(3, "f32", 256, 1, REGS), (6, "f32", 256, 8192, REGS), (9, "f32", 512, 8192, REGS),
          (10, "f32", 256, 64, REGS), (12, "f32", 256, 4096, REGS), (4, "f64", 256, 2048, REGS),
          (6, "f64", 512, 1, REGS), (3, "f32", 512, 1, DMA), (9, "f32", 256, 8192, DMA),
-         (13, "f32", 512, 64, DMA), (17, "f32", 256, 4096, DMA), (17, "f32", 512, 1, DMA)]
+         (13, "f32", 512, 64, DMA), (17, "f32", 256, 4096, DMA), (17, "f32", 512, 1, DMA),
+         (3, "f32", 1024, 1, DMA2), (9, "f32", 1024, 8192, DMA2), (12, "f32", 512, 64, DMA2),
+         (17, "f32", 512, 4096, DMA2)]
 
 
 @pytest.mark.parametrize("l,prec,threads,wgs,kernel", CASES)
