@@ -683,62 +683,55 @@ __global__ void k_start_vectors(const EigProb* __restrict__ probs) {
   P.X[idx] = static_cast<double>(static_cast<int64_t>(c[0]) >> 11) * (1.0 / 4503599627370496.0);
 }
 
-// Out[j, c] = sum_i A[j, i] In[i, c] for 16 rows j per workgroup, all c < b.  MODE 0: A = M
-// (lower: i < j0 + 16), In = X, Out = Z.  MODE 1: A = Mt (upper: i >= j0), In = Z, Out = NX.
-// MODE 2: A = Nsym (all i), In = X, Out = NX, and the block's X[rows]^T NX[rows] of the
-// Rayleigh-Ritz matrix (into M, which is free by then).
-// Thread (jr, kp) = (t % 16, t / 16) sums over i = kp mod 16; In is staged through LDS in
-// chunks of 256 rows, the next chunk's loads in flight while the current one is summed; the
-// 16 partial sums are added through LDS.  No atomics on Out.
+// Out[j, c] = sum_i A[j, i] In[i, c] for all c < b, split over workgroups (j-block of 16
+// rows, i-chunk of 256): each workgroup writes its chunk's share to AP[chunk][c][j] and
+// k_apply_sum adds the shares in chunk order (no atomics: the sum does not depend on
+// timing).  MODE 0: A = M (lower: i < j0 + 16), In = X, Out = Z.  MODE 1: A = Mt (upper:
+// i >= j0), In = Z, Out = NX.  MODE 2: A = Nsym (all i), In = X, Out = NX, and the sum also
+// forms the block's X[rows]^T NX[rows] share of the Rayleigh-Ritz matrix (into M, which is
+// free by then).  Thread (jr, kp) = (t % 16, t / 16) sums over i = kp mod 16; the 16
+// partial sums are added through LDS.  A chunk outside the operator's triangle writes
+// zeros.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_apply(const EigProb* __restrict__ probs) {
+__global__ __launch_bounds__(256) void k_apply(const EigProb* __restrict__ probs, int nks) {
   __shared__ double Xs[256][kEigMaxB + 1];
-  __shared__ double Ys[kRows][kEigMaxB + 1];
   const EigProb& P = probs[blockIdx.y];
   const int n = static_cast<int>(P.n);
   const int b = P.b;
-  const int j0 = static_cast<int>(blockIdx.x) * kRows;
-  if (j0 >= n) return;
+  const int jb = static_cast<int>(blockIdx.x) / nks, ks = static_cast<int>(blockIdx.x) % nks;
+  const int j0 = jb * kRows;
+  if (j0 >= n || ks * 256 >= n) return;
   gcdouble __restrict__ A = MODE == 0 ? P.M : (MODE == 1 ? P.Mt : P.Nsym);
   const uint32_t lda = static_cast<uint32_t>(MODE == 2 ? P.n : P.npad);
   gcdouble __restrict__ In = MODE == 1 ? P.Z : P.X;
-  gdouble __restrict__ Out = MODE == 0 ? P.Z : P.NX;
   const int tid = threadIdx.x;
   const int jr = tid & (kRows - 1), kp = tid / kRows;
   const uint32_t jrow = static_cast<uint32_t>((j0 + jr < n) ? (j0 + jr) : (n - 1));
-  const int i_lo = MODE == 1 ? j0 : 0;
-  const int i_hi = MODE == 0 ? ((j0 + kRows < n) ? (j0 + kRows) : n) : n;
+  int i_lo = MODE == 1 ? j0 : 0;
+  int i_hi = MODE == 0 ? ((j0 + kRows < n) ? (j0 + kRows) : n) : n;
+  i_lo = i_lo > ks * 256 ? i_lo : ks * 256;
+  i_hi = i_hi < ks * 256 + 256 ? i_hi : ks * 256 + 256;
   double acc[kEigMaxB];
 #pragma unroll
   for (int c = 0; c < kEigMaxB; ++c) acc[c] = 0.0;
-  double mv[16], xv[kEigMaxB];
-  auto load_chunk = [&](int c0, double (&m)[16], double (&x)[kEigMaxB]) {
-    const int cnt = (i_hi - c0) < 256 ? (i_hi - c0) : 256;
+  if (i_lo < i_hi) {
+    const int c0 = i_lo;
+    const int cnt = i_hi - c0;
+    double mv[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int il = kp + 16 * s;
-      m[s] = gld(A, jrow + static_cast<uint32_t>(c0 + (il < cnt ? il : 0)) * lda);
-      if (il >= cnt) m[s] = 0.0;
+      mv[s] = gld(A, jrow + static_cast<uint32_t>(c0 + (il < cnt ? il : 0)) * lda);
+      if (il >= cnt) mv[s] = 0.0;
     }
 #pragma unroll
     for (int c = 0; c < kEigMaxB; ++c) {
       const bool ok = tid < cnt && c < b;
-      x[c] = gld(In, static_cast<uint32_t>(c0 + (ok ? tid : 0)) +
-                         static_cast<uint32_t>(ok ? c : 0) * static_cast<uint32_t>(n));
-      if (!ok) x[c] = 0.0;
+      const double x = gld(In, static_cast<uint32_t>(c0 + (ok ? tid : 0)) +
+                                   static_cast<uint32_t>(ok ? c : 0) * static_cast<uint32_t>(n));
+      Xs[tid][c] = ok ? x : 0.0;
     }
-  };
-  int c0 = i_lo;
-  load_chunk(c0, mv, xv);
-  for (;;) {
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < kEigMaxB; ++c) Xs[tid][c] = xv[c];
-    __syncthreads();
-    const int c1 = c0 + 256;
-    const bool more = c1 < i_hi;
-    double mn[16], xn[kEigMaxB];
-    if (more) load_chunk(c1, mn, xn);
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int il = kp + 16 * s;
@@ -746,34 +739,51 @@ __global__ __launch_bounds__(256) void k_apply(const EigProb* __restrict__ probs
       for (int c = 0; c < kEigMaxB; ++c)
         if (c < b) acc[c] = fma(mv[s], Xs[il][c], acc[c]);
     }
-    if (!more) break;
-#pragma unroll
-    for (int s = 0; s < 16; ++s) mv[s] = mn[s];
-#pragma unroll
-    for (int c = 0; c < kEigMaxB; ++c) xv[c] = xn[c];
-    c0 = c1;
   }
   __syncthreads();
   auto red = reinterpret_cast<double (*)[kRows][kEigMaxB + 1]>(&Xs[0][0]);  // [kp][jr][c]
 #pragma unroll
   for (int c = 0; c < kEigMaxB; ++c) red[kp][jr][c] = acc[c];
   __syncthreads();
+  gdouble __restrict__ part = P.AP + static_cast<int64_t>(ks) * b * n;
   for (int e = tid; e < kRows * b; e += 256) {
     const int r2 = e % kRows, c = e / kRows;
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) s += red[q][r2][c];
-    if (j0 + r2 < n) gst(Out, static_cast<uint32_t>(j0 + r2 + c * n), s);
-    if (MODE == 2) Ys[r2][c] = (j0 + r2 < n) ? s : 0.0;
+    if (j0 + r2 < n) gst(part, static_cast<uint32_t>(j0 + r2 + c * n), s);
+  }
+}
+
+// Out = the chunk shares of k_apply summed in chunk order, 16 rows per workgroup; MODE 2
+// also forms the block's share of the Rayleigh-Ritz matrix.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_apply_sum(const EigProb* __restrict__ probs) {
+  __shared__ double Ys[kRows][kEigMaxB + 1];
+  __shared__ double xr[kRows][kEigMaxB + 1];
+  const EigProb& P = probs[blockIdx.y];
+  const int n = static_cast<int>(P.n);
+  const int b = P.b;
+  const int j0 = static_cast<int>(blockIdx.x) * kRows;
+  if (j0 >= n) return;
+  const int nks = static_cast<int>(ceil_div(P.n, 256));
+  gdouble __restrict__ Out = MODE == 0 ? P.Z : P.NX;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kRows * b; e += 256) {
+    const int r2 = e % kRows, c = e / kRows;
+    const int j = j0 + r2;
+    double s = 0.0;
+    if (j < n) {
+      for (int ks = 0; ks < nks; ++ks)
+        s += gld(P.AP, static_cast<uint32_t>(ks * b * n + j + c * n));
+      gst(Out, static_cast<uint32_t>(j + c * n), s);
+    }
+    if (MODE == 2) {
+      Ys[r2][c] = s;
+      xr[r2][c] = (j < n) ? gld(P.X, static_cast<uint32_t>(j + c * n)) : 0.0;
+    }
   }
   if (MODE == 2) {
-    // H += X[j0 .. j0 + 16)^T NX[j0 .. j0 + 16)
-    __syncthreads();
-    auto xr = reinterpret_cast<double (*)[kEigMaxB + 1]>(&Xs[0][0]);
-    for (int e = tid; e < kRows * b; e += 256) {
-      const int r2 = e % kRows, c = e / kRows;
-      xr[r2][c] = (j0 + r2 < n) ? gld(P.X, static_cast<uint32_t>(j0 + r2 + c * n)) : 0.0;
-    }
     __syncthreads();
     // this block's share of H, summed over the blocks in order by the Jacobi kernel
     for (int e = tid; e < b * b; e += 256) {
@@ -1161,15 +1171,20 @@ void launch_solve_v(const EigProb* host, int nprob, EigProb* dev, hipStream_t s)
   }
   k_start_vectors<<<dim3(static_cast<unsigned>(ceil_div(n_max * kEigMaxB, 256)), np), 256, 0, s>>>(dev);
   const unsigned g_rows16 = static_cast<unsigned>(ceil_div(n_max, kRows));
+  const int nks = static_cast<int>(ceil_div(n_max, 256));
+  const unsigned g_apply = g_rows16 * static_cast<unsigned>(nks);
   for (int it = 0; it < kEigIters; ++it) {
-    k_apply<0><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
-    k_apply<1><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
+    k_apply<0><<<dim3(g_apply, np), 256, 0, s>>>(dev, nks);
+    k_apply_sum<0><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
+    k_apply<1><<<dim3(g_apply, np), 256, 0, s>>>(dev, nks);
+    k_apply_sum<1><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
     if (n_max <= 4 * 256)
       k_orth<256><<<dim3(1, np), 256, 0, s>>>(dev);
     else
       k_orth<512><<<dim3(1, np), 512, 0, s>>>(dev);
   }
-  k_apply<2><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
+  k_apply<2><<<dim3(g_apply, np), 256, 0, s>>>(dev, nks);
+  k_apply_sum<2><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
   k_rr_small<<<dim3(1, np), 256, 0, s>>>(dev);
   k_rr_apply<<<dim3(static_cast<unsigned>(ceil_div(n_max, 256)), np), 256, 0, s>>>(dev);
   k_rr_finish<<<dim3(1, np), 64, 0, s>>>(dev);

@@ -18,7 +18,8 @@
 //  accumulated in a per-thread LDS slice laid out [entry][thread]; for larger l one
 //  wavefront works on each trial.  For l > 11, step 2 is replaced by inverse iteration
 //  with Rayleigh-quotient refinement (k_minor_inv) when a trial needs only its one minor
-//  vector and no eigenvalue taps are requested.
+//  vector and no eigenvalue taps are requested (the default); trials where that cannot be
+//  shown to have found the smallest eigenvalue go through the wavefront Jacobi after it.
 #include <algorithm>
 #include <cmath>
 
@@ -242,7 +243,9 @@ __global__ __launch_bounds__(64) void k_minor_reg(const ProbDesc* __restrict__ p
 
 constexpr int kWaveTrials = 4;
 
-template <int L>
+// REDO: only the trials the inverse-iteration kernel left over (flag set), which it has
+// already counted; their minor vectors go into N, nothing else is written.
+template <int L, bool REDO>
 __global__ __launch_bounds__(64 * kWaveTrials) void k_minor_wave(const ProbDesc* __restrict__ probs,
                                                                  IdxList list) {
   constexpr int NG = L * L;
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(64 * kWaveTrials) void k_minor_wave(const ProbDesc*
     valid &= c[k] >= 0;
   }
   const int rows = active ? P.rows[t] : 0;
-  const bool accept = valid && rows >= min_rows;
+  const bool accept = valid && rows >= min_rows && (!REDO || P.mflag[t] != 0);
   if (active) {
     // packed lower triangle of G_t, entry (i, j), j <= i, at i (i + 1) / 2 + j
     for (int i = 0; i < L; ++i)
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(64 * kWaveTrials) void k_minor_wave(const ProbDesc*
     if (lane < BB) perm[lane] = lane;
   }
   __syncthreads();
-  if (active && lane == 0) {
+  if (!REDO && active && lane == 0) {
     if (P.tap_rows) P.tap_rows[t] = rows;
     if (P.tap_gram)
       for (int e = 0; e < NG; ++e) P.tap_gram[t * NG + e] = A[e / L][e % L];
@@ -419,28 +422,30 @@ __global__ __launch_bounds__(64 * kWaveTrials) void k_minor_wave(const ProbDesc*
       }
       add_to_N(P.N, static_cast<int64_t>(ci) + static_cast<int64_t>(cj) * n, pij, P.fixed_n != 0);
     }
-  } else if (active) {
+  } else if (!REDO && active) {
     if (P.tap_eigs)
       for (int k = lane; k < L; k += 64) P.tap_eigs[t * L + k] = 0.0;
     if (P.tap_vecs)
       for (int k = lane; k < nvec * L; k += 64) P.tap_vecs[t * nvec * L + k] = 0.0;
   }
-  __syncthreads();
-  if (lane == 0 && accept) atomicAdd(&s_acc, 1ull);
-  if (lane == 0 && active) atomicAdd(&s_rows, static_cast<unsigned long long>(rows));
-  __syncthreads();
-  if (tid == 0) {
-    atomicAdd((unsigned long long*)&P.info->accepted, s_acc);
-    atomicAdd((unsigned long long*)&P.info->rows_total, s_rows);
+  if constexpr (!REDO) {
+    __syncthreads();
+    if (lane == 0 && accept) atomicAdd(&s_acc, 1ull);
+    if (lane == 0 && active) atomicAdd(&s_rows, static_cast<unsigned long long>(rows));
+    __syncthreads();
+    if (tid == 0) {
+      atomicAdd((unsigned long long*)&P.info->accepted, s_acc);
+      atomicAdd((unsigned long long*)&P.info->rows_total, s_rows);
+    }
   }
 }
 
 // ------------------------------------------------------------------ inverse iteration
 //
-// One minor vector per trial (nvec = 1, the default l = r + 1), no eigen taps, l > 11:
-// the eigenvector of G_t's smallest eigenvalue by inverse iteration refined with Rayleigh
-// quotient shifts, one thread per trial, instead of a full Jacobi eigen-decomposition in
-// a wavefront.
+// One minor vector per trial (nvec = 1, the default l = r + 1), no eigen taps, l > 11: the
+// eigenvector of G_t's smallest eigenvalue by inverse iteration refined with Rayleigh
+// quotient shifts, one thread per trial, instead of a full Jacobi eigen-decomposition in a
+// wavefront (for l <= 11 the register-resident Jacobi is cheaper still).
 //  1. G_t = L L^T by Cholesky (FP64, packed in registers).  G_t is positive semidefinite,
 //     but its rounding can leave the smallest eigenvalue slightly negative; when a pivot
 //     comes out non-positive, G_t + mu I is factorised instead, with mu = 4 u trace(G_t)
@@ -448,7 +453,8 @@ __global__ __launch_bounds__(64 * kWaveTrials) void k_minor_wave(const ProbDesc*
 //     2^-16 split-BF16), which exceeds that rounding (a pivot still below mu is raised to
 //     mu).  kInvIters steps x <- (L L^T)^{-1} x / norm from a fixed irregular start shrink
 //     the other eigen-directions by (lambda_1 + mu) / (lambda_k + mu) each.
-//  2. kRqSteps steps with the shift rho = x^T G_t x (the Rayleigh quotient, just above
+//  2. up to kRqSteps steps, until the residual ||G_t x - rho x|| is below 32 2^-53 trace(G_t),
+//     with the shift rho = x^T G_t x (the Rayleigh quotient, just above
 //     lambda_1): G_t - rho I = L D L^T without pivoting (a pivot of magnitude below
 //     2^-60 trace(G_t) is set to that magnitude), x <- (L D L^T)^{-1} x / norm.  Near
 //     convergence the factor is nearly singular in the minor direction only, which the
@@ -456,7 +462,7 @@ __global__ __launch_bounds__(64 * kWaveTrials) void k_minor_wave(const ProbDesc*
 //     are close (noisy data: lambda_1 / lambda_2 up to about 0.6 at the paper-scale
 //     workload) still reach the accuracy of a full eigen-decomposition.
 constexpr int kInvIters = 4;
-constexpr int kRqSteps = 3;
+constexpr int kRqSteps = 8;   // at most; the steps stop once the residual is at rounding level
 
 // In-place Cholesky of the packed lower triangle a + mu I (entry (i, j), j <= i, at
 // i (i + 1) / 2 + j); pivots below `floor_d` are raised to it.  The diagonal receives the
@@ -548,7 +554,9 @@ __global__ __launch_bounds__(64) void k_minor_inv(const ProbDesc* __restrict__ p
         for (int j = 0; j < L; ++j)
           P.tap_gram[(t * L + i) * L + j] = a[i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i];
   }
+  if (active && !accept) P.mflag[t] = 0;
   if (accept) {
+    bool redo = false;
     double tr = 0.0;
 #pragma unroll
     for (int i = 0; i < L; ++i) tr += a[i * (i + 1) / 2 + i];
@@ -585,18 +593,30 @@ __global__ __launch_bounds__(64) void k_minor_inv(const ProbDesc* __restrict__ p
 #pragma unroll
       for (int i = 0; i < L; ++i) x[i] *= s;
     }
+    // the solve itself runs in FP64: its residual floor is a few units of 2^-53 trace(G_t),
+    // whatever the precision the Gram was accumulated in
+    const double res_tol = 32.0 * 0x1p-53 * tr;
 #pragma unroll 1
     for (int q = 0; q < kRqSteps; ++q) {
 #pragma unroll
       for (int g = 0; g < NG; ++g) a[g] = P.G[static_cast<int64_t>(g) * I + t];
-      double rho = 0.0;
+      // y = G x, rho = x^T y, and stop once the residual G x - rho x is at the Gram's
+      // rounding level
+      double y[L];
 #pragma unroll
       for (int i = 0; i < L; ++i) {
-        double row = 0.0;
+        double sum = 0.0;
 #pragma unroll
-        for (int j = 0; j < i; ++j) row += a[i * (i + 1) / 2 + j] * x[j];
-        rho += x[i] * (2.0 * row + a[i * (i + 1) / 2 + i] * x[i]);
+        for (int j = 0; j < L; ++j) sum += a[i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i] * x[j];
+        y[i] = sum;
       }
+      double rho = 0.0;
+#pragma unroll
+      for (int i = 0; i < L; ++i) rho += x[i] * y[i];
+      double res2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < L; ++i) res2 += (y[i] - rho * x[i]) * (y[i] - rho * x[i]);
+      if (res2 <= res_tol * res_tol) break;
       ldlt_packed<L>(a, rho, fmax(0x1p-60 * tr, 1e-300));
       // L z = x; z <- z / d; L^T y = z (all in x)
 #pragma unroll
@@ -622,6 +642,28 @@ __global__ __launch_bounds__(64) void k_minor_inv(const ProbDesc* __restrict__ p
 #pragma unroll
       for (int i = 0; i < L; ++i) x[i] *= s;
     }
+    // the vector must belong to the smallest eigenvalue: then G - (rho - delta) I, delta =
+    // 4 u trace(G) (below that, eigenvalues are not told apart by the Gram), has no
+    // negative pivot (Sylvester's law of inertia).  Otherwise the trial goes to the Jacobi
+    // pass.
+    {
+#pragma unroll
+      for (int g = 0; g < NG; ++g) a[g] = P.G[static_cast<int64_t>(g) * I + t];
+      double rho = 0.0;
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        double row = 0.0;
+#pragma unroll
+        for (int j = 0; j < i; ++j) row += a[i * (i + 1) / 2 + j] * x[j];
+        rho += x[i] * (2.0 * row + a[i * (i + 1) / 2 + i] * x[i]);
+      }
+      ldlt_packed<L>(a, rho - 4.0 * P.gram_unit * tr, fmax(0x1p-60 * tr, 1e-300));
+      bool neg = false;
+#pragma unroll
+      for (int j = 0; j < L; ++j) neg |= a[j * (j + 1) / 2 + j] < 0.0;
+      P.mflag[t] = neg ? 1 : 0;
+      redo = neg;
+    }
     // N[C_t, C_t] += x x^T (lower triangle: c is ascending); x and c go through this
     // thread's LDS slice so that the l(l+1)/2 updates run as a loop
 #pragma unroll
@@ -631,7 +673,7 @@ __global__ __launch_bounds__(64) void k_minor_inv(const ProbDesc* __restrict__ p
     }
     const bool fixed = P.fixed_n != 0;
 #pragma unroll 1
-    for (int i = 0; i < L; ++i) {
+    for (int i = 0; i < (redo ? 0 : L); ++i) {
       const double xi = xs[i][tid];
       const int64_t ci = cs[i][tid];
 #pragma unroll 1
@@ -652,16 +694,19 @@ __global__ __launch_bounds__(64) void k_minor_inv(const ProbDesc* __restrict__ p
 template <int L>
 void run_minor(const ProbDesc* d, const IdxList& g, int64_t I, bool inv, hipStream_t s) {
   if constexpr (L <= kRegMaxL) {
+    // the register Jacobi is cheap and exact here
     (void)inv;
     const unsigned blocks = static_cast<unsigned>(ceil_div(I, 64));
     k_minor_reg<L><<<dim3(blocks, g.count), 64, 0, s>>>(d, g);
   } else {
+    const unsigned blocks = static_cast<unsigned>(ceil_div(I, kWaveTrials));
     if (inv) {
+      // inverse iteration for every trial, then Jacobi for the few it leaves over
       k_minor_inv<L><<<dim3(static_cast<unsigned>(ceil_div(I, 64)), g.count), 64, 0, s>>>(d, g);
+      k_minor_wave<L, true><<<dim3(blocks, g.count), 64 * kWaveTrials, 0, s>>>(d, g);
       return;
     }
-    const unsigned blocks = static_cast<unsigned>(ceil_div(I, kWaveTrials));
-    k_minor_wave<L><<<dim3(blocks, g.count), 64 * kWaveTrials, 0, s>>>(d, g);
+    k_minor_wave<L, false><<<dim3(blocks, g.count), 64 * kWaveTrials, 0, s>>>(d, g);
   }
 }
 

@@ -157,6 +157,7 @@ void set_layout(Plan& P) {
   P.off_prow = carve(cur, static_cast<size_t>(P.splits) * P.I * sizeof(int32_t));
   P.off_G = carve(cur, static_cast<size_t>(P.I) * P.ng * sizeof(double));
   P.off_rows = carve(cur, static_cast<size_t>(P.I) * sizeof(int32_t));
+  P.off_mflag = carve(cur, static_cast<size_t>(P.I) * sizeof(int32_t));
   const size_t nn = static_cast<size_t>(P.n) * P.n * sizeof(double);
   P.off_N = carve(cur, nn);
   P.off_Nsym = carve(cur, nn);
@@ -169,6 +170,7 @@ void set_layout(Plan& P) {
   P.off_X = carve(cur, nbv);
   P.off_Z = carve(cur, nbv);
   P.off_NX = carve(cur, nbv);
+  P.off_AP = carve(cur, static_cast<size_t>(ceil_div(P.n, 256)) * nbv);
   P.off_small = carve(cur, kSmallDoubles * sizeof(double));
   if (P.u_mfma) {
     P.off_ab = carve(cur, static_cast<size_t>(P.m) * (P.r * (P.r + 1) / 2 + P.r) * sizeof(double));
@@ -316,6 +318,7 @@ ProbDesc prob_desc(const Plan& P, const rsm_input& in, const rsm_output& out, vo
   d.prow = gptr(at<int32_t>(ws, P.off_prow));
   d.G = gptr(at<double>(ws, P.off_G));
   d.rows = gptr(at<int32_t>(ws, P.off_rows));
+  d.mflag = gptr(at<int32_t>(ws, P.off_mflag));
   d.N = gptr(out.N ? out.N : at<double>(ws, P.off_N));
   d.V = gptr(out.V);
   d.U = gptr(out.U);
@@ -349,6 +352,7 @@ EigProb eig_desc(const Plan& P, const rsm_output& out, void* ws) {
   e.X = gptr(at<double>(ws, P.off_X));
   e.Z = gptr(at<double>(ws, P.off_Z));
   e.NX = gptr(at<double>(ws, P.off_NX));
+  e.AP = gptr(at<double>(ws, P.off_AP));
   e.small = gptr(at<double>(ws, P.off_small));
   e.scal = gptr(at<DevScalars>(ws, P.off_scal));
   e.V = gptr(out.V);

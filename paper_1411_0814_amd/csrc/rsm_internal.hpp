@@ -84,7 +84,8 @@ struct Plan {
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
          off_rows = 0;
   size_t off_N = 0, off_Nsym = 0, off_L = 0, off_M = 0, off_Mt = 0, off_T = 0, off_X = 0,
-         off_Z = 0, off_NX = 0, off_small = 0, off_ab = 0, off_abcnt = 0;
+         off_Z = 0, off_NX = 0, off_AP = 0, off_small = 0, off_ab = 0, off_abcnt = 0,
+         off_mflag = 0;
   size_t off_scal = 0;
   size_t total = 0;
 };
@@ -117,6 +118,7 @@ struct EigProb {
   RSM_GLOBAL double* X;        // n x b iterate
   RSM_GLOBAL double* Z;        // n x b; its first n entries hold the row sums at the start
   RSM_GLOBAL double* NX;       // n x b
+  RSM_GLOBAL double* AP;       // thin-product partials: [ceil(n / 256)][b][n]
   RSM_GLOBAL double* small;    // kSmallDoubles
   RSM_GLOBAL DevScalars* scal;
   RSM_GLOBAL double* V;        // output n x r
@@ -156,6 +158,7 @@ struct ProbDesc {
   RSM_GLOBAL double* tap_gram;
   RSM_GLOBAL double* tap_vecs;
   RSM_GLOBAL double* tap_eigs;
+  RSM_GLOBAL int32_t* mflag;   // per trial: minor vector left to the Jacobi pass (I)
   RSM_GLOBAL double* ab;       // U-hat normal equations on MFMA: (r(r+1)/2 + r) x m, ld m
   RSM_GLOBAL int32_t* abcnt;   // known entries per row (m)
 };

@@ -11,14 +11,19 @@ from tests.gpu_util import lower_N, to_device
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("l,dt", [(3, np.float64), (6, np.float32), (9, np.float32),
-                                  (12, np.float64), (15, np.float32), (17, np.float32)])
-def test_inverse_iteration_matches_jacobi_and_oracle(l, dt):
+# (l, dtype, noise): heavy noise makes the two smallest Gram eigenvalues of many trials
+# close, where the Rayleigh-quotient steps can settle on the second one and the inertia
+# check must hand the trial to the Jacobi pass
+@pytest.mark.parametrize("l,dt,noise", [(3, np.float64, 1e-3), (6, np.float32, 1e-3),
+                                        (9, np.float32, 1e-3), (12, np.float64, 1e-3),
+                                        (15, np.float32, 1e-3), (17, np.float32, 1e-3),
+                                        (13, np.float64, 0.5), (17, np.float64, 1.0)])
+def test_inverse_iteration_matches_jacobi_and_oracle(l, dt, noise):
     import torch
     from paper_1411_0814_amd import _lib, decompose
     gram = "f32" if dt == np.float32 else "f64"
     r = l - 1
-    p = synth.paper_synthetic(4001, 120, r, 0.93, 1e-3, 300 + l, factor_dtype=dt, y_dtype=dt,
+    p = synth.paper_synthetic(4001, 120, r, 0.93, noise, 300 + l, factor_dtype=dt, y_dtype=dt,
                               num_submatrices=1500, seed_rsm=l, gram=gram)
     Y, W = to_device(p)
     N_inv = torch.zeros(p.n, p.n, dtype=torch.float64, device="cuda")
@@ -35,13 +40,21 @@ def test_inverse_iteration_matches_jacobi_and_oracle(l, dt):
     err_inv = np.max(np.abs(Na - ora.N)) / scale
     err_jac = np.max(np.abs(Nb - ora.N)) / scale
     if dt == np.float64:
-        # FP64 Grams: both eigen-solvers are accurate to rounding
-        assert np.max(np.abs(Na - Nb)) <= 1e-10 * scale
+        # FP64 Grams: both eigen-solvers are accurate to rounding over the eigen-gap; with
+        # heavy noise the gaps of some trials are small (a trial given the wrong eigenvector
+        # would differ by O(1) on its block, about 1/40 of the scale here)
+        assert np.max(np.abs(Na - Nb)) <= (1e-10 if noise < 0.1 else 1e-6) * scale
     else:
         # FP32 Grams: both are limited by the Gram's rounding, to the same degree
         assert err_inv <= 2.0 * err_jac + 1e-9, (err_inv, err_jac)
-    assert err_inv <= (1e-9 if dt == np.float64 else 1e-4), err_inv
+    # against the oracle's SVD: both GPU paths carry the Gram's rounding over the eigen-gap
+    # (Jacobi keeps relative accuracy on the small eigenvalues, the inverse iteration stops
+    # at a residual of the Gram's rounding level, hence the floor; a wrongly chosen
+    # eigenvector would show as about 1e-2)
+    assert err_inv <= 2.0 * err_jac + 1e-8, (err_inv, err_jac)
+    assert err_inv <= ((1e-9 if noise < 0.1 else 1e-7) if dt == np.float64 else 1e-4), err_inv
     Va, Ua = a.V.cpu().numpy(), a.U.cpu().numpy()
     assert metrics.principal_angle_max(Va, b.V.cpu().numpy()) <= 1e-5
-    assert metrics.principal_angle_max(Va, ora.V) <= 1e-4
-    assert metrics.rel_rms_known(p.W, Ua, Va, ora.U, ora.V) <= 1e-5
+    if noise < 0.1:
+        assert metrics.principal_angle_max(Va, ora.V) <= 1e-4
+        assert metrics.rel_rms_known(p.W, Ua, Va, ora.U, ora.V) <= 1e-5
