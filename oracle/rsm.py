@@ -1,4 +1,4 @@
-"""Plain FP64 CPU oracle of the RSM hot path (M1 sampling, L2 norm).
+"""Plain FP64 CPU oracle of the RSM hot path (M1 and M2 sampling, L2 norm).
 
 TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the benchmark's
 CPU-baseline leg may import this module; the product path never does.
@@ -11,6 +11,7 @@ blocks; nothing is blocked, fused or reordered:
   problem  eq.(problem), eq.(def.rho)  min over U,V of ||W o (Y - U V^T)||, rho = sum(w)/(mn)
   step 1   Section IV-A, step 1        l = r + 1 columns per trial, I trials (an input here)
   step 2   Section III, method M1      pick l columns; keep the rows fully known on them
+           Section III, method M2      pick k rows; keep the columns fully known on them
            Section III, text before eq.(get_xi): the l - r right singular vectors of the
            smallest singular values of each sub-matrix (zeta_j)
            eq.(get_xi)                 xi = e(zeta): zeta's entries at the chosen columns of a zero n-vector
@@ -26,7 +27,10 @@ Readings of points the paper leaves open (each is also listed with the design no
   * nvec = l - r minor vectors per accepted trial, each with unit weight in Xi;
   * singular values beyond the number of rows count as zero (full right basis);
   * "||V|| = 1" is read as V^T V = I_r; "min_U" in eq.(solve.barU) as argmin;
-  * a row with fewer than r known entries gets u_i = 0 and is counted as underdetermined.
+  * a row with fewer than r known entries gets u_i = 0 and is counted as underdetermined;
+  * M2 (rows first): a trial is accepted when more than r columns qualify (the text of
+    Section IV-A on M2), and it contributes all |C_t| - r right singular vectors past the r
+    largest (Section III: "use all zeta_j"), null vectors included.
 """
 from __future__ import annotations
 
@@ -61,6 +65,11 @@ def known_ratio(W: np.ndarray) -> float:
 def qualifying_rows(W: np.ndarray, cols: np.ndarray) -> np.ndarray:
     """M1: the rows whose entries at every chosen column are known, ascending."""
     return np.flatnonzero(np.asarray(W[:, cols], dtype=bool).all(axis=1))
+
+
+def qualifying_cols(W: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """M2: the columns whose entries at every chosen row are known, ascending."""
+    return np.flatnonzero(np.asarray(W[rows, :], dtype=bool).all(axis=0))
 
 
 def minor_right_singular_vectors(Z: np.ndarray, nvec: int) -> np.ndarray:
@@ -115,6 +124,37 @@ def accumulate_N(Y, W, subsets, r, nvec, min_rows, N=None):
     return N, rows, accepted
 
 
+def trial_constraints_rows_first(Y, W, rows, r, min_cols):
+    """Step 2 with M2 for one trial: (qualifying columns, zeta of this trial or None).
+
+    Z = Y[rows, C] is k x |C|; its right singular vectors past the r largest singular
+    values (|C| - r of them, the null space of Z included) are the zeta_j."""
+    C = qualifying_cols(W, rows)
+    if C.size < min_cols:
+        return C, None
+    Z = np.asarray(Y[np.ix_(rows, C)], dtype=np.float64)
+    return C, minor_right_singular_vectors(Z, C.size - r)
+
+
+def accumulate_N_rows_first(Y, W, subsets, r, min_cols, N=None):
+    """Step 2 with M2 and step 3's accumulator: N = sum over trials of sum_j xi_j xi_j^T,
+    xi_j = e(zeta_j) placed at the trial's qualifying columns.  Trials in ascending order.
+    Returns (N, |C_t| per trial, accepted count)."""
+    n = W.shape[1]
+    if N is None:
+        N = np.zeros((n, n), dtype=np.float64)
+    sizes = np.zeros(len(subsets), dtype=np.int64)
+    accepted = 0
+    for t, rows in enumerate(subsets):
+        C, zeta = trial_constraints_rows_first(Y, W, rows, r, min_cols)
+        sizes[t] = C.size
+        if zeta is None:
+            continue
+        accepted += 1
+        N[np.ix_(C, C)] += zeta @ zeta.T
+    return N, sizes, accepted
+
+
 def solve_V(N: np.ndarray, r: int):
     """eq.(solve.barV_L2_norm): V-hat = eigenvectors of N for the r smallest eigenvalues.
 
@@ -157,15 +197,30 @@ def error_e(Y, W, U, V) -> float:
 
 
 def rsm(Y, W, r, num_submatrices, seed, l=None, nvec=None, min_rows=None,
-        trial_begin=0, subsets=None, with_U=True, with_e=True) -> OracleResult:
+        trial_begin=0, subsets=None, with_U=True, with_e=True,
+        rows_first=False) -> OracleResult:
     """The whole path: subsets -> N -> V-hat -> U-hat (and e).
 
     Y: m x n (any float dtype; consumed as FP64), W: m x n bool (True = known).
     `subsets` overrides the random column subsets (I x l); otherwise they are drawn
-    from (seed, trial_begin .. trial_begin + num_submatrices - 1)."""
+    from (seed, trial_begin .. trial_begin + num_submatrices - 1).
+
+    rows_first: sampling M2 instead of M1.  Then l is the number k of rows per trial
+    (default r + 1), the subsets are row subsets drawn from [0, m), min_rows is the least
+    number of qualifying columns for a trial to count (default r + 1, at least r + 1),
+    nvec must be left unset, and `rows` of the result holds |C_t| per trial."""
     W = np.asarray(W, dtype=bool)
     m, n = W.shape
     l = r + 1 if not l else int(l)
+    if rows_first:
+        min_cols = r + 1 if not min_rows else int(min_rows)
+        if not (1 <= r < min(m, n)) or not (r < l <= m) or nvec or min_cols <= r:
+            raise ValueError("invalid r / k / min_cols for rows-first sampling")
+        if subsets is None:
+            subsets = draw_subsets(seed, m, l, int(num_submatrices), int(trial_begin))
+        subsets = np.asarray(subsets, dtype=np.int64)
+        N, rows, accepted = accumulate_N_rows_first(Y, W, subsets, r, min_cols)
+        return _finish(Y, W, r, N, subsets, rows, accepted, with_U, with_e)
     nvec = l - r if not nvec else int(nvec)
     min_rows = r if not min_rows else int(min_rows)
     if not (1 <= r < min(m, n)) or not (r < l <= n) or not (1 <= nvec <= l - r):
@@ -174,6 +229,12 @@ def rsm(Y, W, r, num_submatrices, seed, l=None, nvec=None, min_rows=None,
         subsets = draw_subsets(seed, n, l, int(num_submatrices), int(trial_begin))
     subsets = np.asarray(subsets, dtype=np.int64)
     N, rows, accepted = accumulate_N(Y, W, subsets, r, nvec, min_rows)
+    return _finish(Y, W, r, N, subsets, rows, accepted, with_U, with_e)
+
+
+def _finish(Y, W, r, N, subsets, rows, accepted, with_U, with_e) -> OracleResult:
+    """Step 3 from the accumulated N: V-hat, U-hat and e."""
+    m = W.shape[0]
     V, lam = solve_V(N, r)
     if with_U:
         U, under = solve_U(Y, W, V)

@@ -135,6 +135,20 @@ def test_nvec_two_l_plus_two():
     _compare_full(p, res, info, ora, u=2.0**-53)
 
 
+# l > r + 1 with fewer minor vectors than l - r (the choice of ell the paper allows),
+# through both register Jacobi (l <= 11) and the wavefront Jacobi (l >= 12)
+@pytest.mark.parametrize("r,l,nvec,gram", [(3, 6, 1, "f64"), (3, 6, 2, "f64"),
+                                           (2, 7, 3, "f32"), (4, 13, 3, "f64"),
+                                           (5, 14, 1, "f32")])
+def test_l_above_r_plus_one_with_fewer_vectors(r, l, nvec, gram):
+    dt = np.float32 if gram == "f32" else np.float64
+    p = synth.paper_synthetic(2500, 90, r, 0.9, 0.01, 20 + l, factor_dtype=dt, y_dtype=dt,
+                              num_submatrices=900, l=l, gram=gram)
+    res, info = _run(p, gram, taps=True, nvec=nvec)
+    ora = rsm.rsm(p.Y, p.W, p.r, p.num_submatrices, seed=p.seed_rsm, l=l, nvec=nvec)
+    _compare_full(p, res, info, ora, u=2.0**-24 if gram == "f32" else 2.0**-53)
+
+
 def test_user_subsets_brute_force_tiny():
     """n = 7, l = 3: every C(7,3) subset passed in; N equals the oracle's brute force."""
     import torch
