@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper_scale",
                     choices=["paper_scale", "plain_fp64", "precision", "batched", "served",
-                             "table1"])
+                             "table1", "rows_first"])
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--served-seconds", type=float, default=5.0)
@@ -66,6 +66,11 @@ def parse():
                     help="only run a device-to-device copy of this many MiB (calibrates the "
                          "byte counters of rocprofv3 --pmc) and exit")
     return ap.parse_args()
+
+
+def progress(msg):
+    """One line per finished phase on stderr (the JSON result stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def copy_probe(mib):
@@ -109,14 +114,33 @@ def make_workload(name):
         return synth.paper_scale()
     if name == "plain_fp64":
         return synth.plain_fp64()
+    if name == "rows_first":
+        # the paper-scale problem sampled rows first (method M2, k = r + 1 = 9 rows)
+        p = synth.paper_scale()
+        p.name = "paper-scale shape, rows first (M2, k = 9)"
+        p.rows_first = True
+        return p
     return synth.precision_stress()
+
+
+def _rows_first(p):
+    return bool(getattr(p, "rows_first", False))
 
 
 def _oracle_chunk(args):
     """N over a trial range (worker process; inherits the problem through fork)."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import rsm
     lo, hi = args
     p = _G["p"]
+    with threadpool_limits(limits=1):   # one BLAS thread per worker process
+        return _oracle_chunk_body(p, lo, hi, rsm)
+
+
+def _oracle_chunk_body(p, lo, hi, rsm):
+    if _rows_first(p):
+        return rsm.accumulate_N_rows_first(p.Y, p.W, _G["subsets"][lo:hi], p.r, p.r + 1)[0]
     return rsm.accumulate_N(p.Y, p.W, _G["subsets"][lo:hi], p.r, p.l - p.r, p.r)[0]
 
 
@@ -129,7 +153,8 @@ def oracle_parity(p, V_gpu, U_gpu, sample_rows, workers):
     import multiprocessing as mp
 
     from oracle import metrics, rng, rsm
-    subsets = rng.draw_subsets(p.seed_rsm, p.n, p.l, p.num_submatrices)
+    subsets = rng.draw_subsets(p.seed_rsm, p.m if _rows_first(p) else p.n, p.l,
+                               p.num_submatrices)
     _G.update(p=p, subsets=subsets)
     t0 = time.perf_counter()
     chunks = np.array_split(np.arange(p.num_submatrices), workers * 4)
@@ -156,9 +181,13 @@ def cpu_baseline(p, n_trials, n_rows):
 
     from oracle import rng, rsm
     with threadpool_limits(limits=1):
-        subsets = rng.draw_subsets(p.seed_rsm, p.n, p.l, n_trials)
         t0 = time.perf_counter()
-        N, _, _ = rsm.accumulate_N(p.Y, p.W, subsets, p.r, p.l - p.r, p.r)
+        if _rows_first(p):
+            subsets = rng.draw_subsets(p.seed_rsm, p.m, p.l, n_trials)
+            N, _, _ = rsm.accumulate_N_rows_first(p.Y, p.W, subsets, p.r, p.r + 1)
+        else:
+            subsets = rng.draw_subsets(p.seed_rsm, p.n, p.l, n_trials)
+            N, _, _ = rsm.accumulate_N(p.Y, p.W, subsets, p.r, p.l - p.r, p.r)
         t_trials = time.perf_counter() - t0
         t0 = time.perf_counter()
         N = N + np.eye(p.n) * 1e-3
@@ -495,17 +524,21 @@ def main():
     t_gen = time.perf_counter()
     p = make_workload(args.workload)
     t_gen = time.perf_counter() - t_gen
+    progress(f"workload {p.name} generated in {t_gen:.1f} s")
     dev = torch.device("cuda:0")
     Y = torch.from_numpy(p.Yt).to(dev).T
     W = torch.from_numpy(p.Wt.view(bool)).to(dev).T
     gram = p.gram
     flags = _lib.PLAIN_GRAM if args.plain_gram else 0
+    rows_first = _rows_first(p)
+    if rows_first:
+        flags = _lib.ROWS_FIRST
     stream = torch.cuda.current_stream(dev)
     req = Request(Y=Y, W=W, r=p.r, num_submatrices=p.num_submatrices, seed=p.seed_rsm, l=p.l,
                   gram=gram, flags=flags)
     from paper_1411_0814_amd import tune
     tune.clear()
-    tuned = None if args.no_tune or args.plain_gram else _tune_for(args, [req])
+    tuned = None if args.no_tune or args.plain_gram or rows_first else _tune_for(args, [req])
     ws_need = workspace_bytes([req])
     ws = torch.empty(ws_need + 256, dtype=torch.uint8, device=dev)
     off = (-ws.data_ptr()) % 256
@@ -525,12 +558,14 @@ def main():
     for _ in range(args.warmup):
         res = run(new_events())
     torch.cuda.synchronize()
+    progress(f"{args.warmup} warm-up steps done")
     events = [new_events() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = [run(events[k]) for k in range(args.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    progress(f"{args.steps} timed steps: {elapsed / args.steps * 1e3:.3f} ms each")
 
     steps = _lib.STEPS
     per_step = {name: [] for name in steps}
@@ -545,7 +580,16 @@ def main():
     info = last.info()
     gram_ms = float(np.mean(per_step["gram"]))
     elem = 4 if p.Yt.dtype == np.float32 else 8
-    b_alg = p.num_submatrices * p.l * ((p.m + 7) // 8) + info["rows_total"] * p.l * elem
+    if rows_first:
+        # M2: the k row words of the mask and the k x |C_t| qualifying values per trial
+        b_alg = p.num_submatrices * p.l * ((p.n + 7) // 8) + info["rows_total"] * p.l * elem
+        gram_name = "gram (M2: column qualification + k x k Gram)"
+        traffic = None
+    else:
+        b_alg = p.num_submatrices * p.l * ((p.m + 7) // 8) + info["rows_total"] * p.l * elem
+        gram_name = "gram (row qualification + Gram)"
+        traffic = traffic_from_profile(
+            os.path.join(ROOT, "paper_1411_0814_amd", "csrc", "k_gram.hip"))
     achieved = b_alg / (gram_ms * 1e-3) / 1e9
 
     out = {
@@ -563,16 +607,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": p.name, "m": p.m, "n": p.n, "r": p.r, "l": p.l,
                    "num_submatrices": p.num_submatrices, "rho": p.rho, "gram": gram,
+                   "sampling": "rows first (M2)" if rows_first else "columns first (M1)",
                    "gram_kernel": "plain" if args.plain_gram else "tiled",
                    "eig_solves": "f64"},
         "latency_ms": {"p50": round(float(np.percentile(latency, 50)), 4),
                        "p99": round(float(np.percentile(latency, 99)), 4)},
         "step_ms": {k: round(float(np.mean(v)), 4) for k, v in per_step.items() if v},
-        "roofline": {"bound": "hbm", "kernel": "gram (row qualification + Gram)",
+        "roofline": {"bound": "hbm", "kernel": gram_name,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profile(
-                         os.path.join(ROOT, "paper_1411_0814_amd", "csrc", "k_gram.hip")),
+                     "traffic": traffic,
                      "bytes_alg_per_launch": int(b_alg), "launch_ms": round(gram_ms, 4)},
         "info": {"accepted": info["accepted"], "mean_rows": info["rows_total"] / max(1, p.num_submatrices),
                  "warnings": info["warnings"], "residual": info["residual"],
@@ -586,12 +630,14 @@ def main():
         workers = min(16, os.cpu_count() or 4)
         theta, rms, t_or = oracle_parity(p, last.V.cpu().numpy(), last.U.cpu().numpy(),
                                          args.cpu_sample_rows, workers)
+        progress(f"oracle parity: theta {theta:.3e} rms {rms:.3e} ({t_or:.1f} s)")
         out["parity"] = {"theta_max_rad": theta, "rel_rms_known": rms,
                          "rows_sampled_for_rms": args.cpu_sample_rows,
                          "oracle_s": round(t_or, 1), "oracle_workers": workers,
                          "pass": bool(theta <= 1e-4 and rms <= 1e-5)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample_trials, args.cpu_sample_u_rows)
+        progress("cpu baseline done")
     if not args.no_batched and args.workload == "paper_scale":
         del Y, W, ws, results, res, last
         torch.cuda.empty_cache()

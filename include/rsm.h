@@ -19,6 +19,14 @@
  *                                                              [eq.(solve.barV_L2_norm)]
  *   a7  U-hat row by row: u_i = argmin_u sum_j w_ij (y_ij - u^T v_j)^2      [eq.(solve.barU)]
  *
+ * With RSM_ROWS_FIRST the sub-matrices are drawn by the paper's method M2 instead
+ * (Section III): a1 draws k-row subsets S_t of [0, m); a2 keeps the columns C_t whose
+ * entries at S_t are all known; a3 forms the k x k Gram H_t = Z_t Z_t^T of
+ * Z_t = Y[S_t, C_t]; a4 takes H_t's r largest eigenpairs (u_a, s_a^2), whose vectors
+ * q_a = Z_t^T u_a / s_a are Z_t's r leading right singular vectors; a5 adds the projector
+ * on all |C_t| - r remaining right singular vectors (null vectors included),
+ * I - Q_t Q_t^T, into N[C_t, C_t].  Steps a6 and a7 are shared.
+ *
  * Conventions for every entry point:
  *   - Array arguments are DEVICE pointers owned by the caller; the library never allocates
  *     device memory.  Scratch memory is the caller's `workspace` (size from
@@ -101,13 +109,24 @@ enum {
   RSM_COMPUTE_ERROR = 1u << 3,   /* fill rsm_info.e (eq.(ep)) with an extra pass over Y */
   RSM_PLAIN_GRAM = 1u << 4,      /* use the per-trial column-streaming Gram kernel
                                     (the unblocked baseline) instead of the tiled one */
-  RSM_DETERMINISTIC = 1u << 5    /* bitwise-reproducible results, whatever else shares the
+  RSM_DETERMINISTIC = 1u << 5,   /* bitwise-reproducible results, whatever else shares the
                                     launches: N is accumulated in 64-bit fixed point with
                                     2^-40 resolution (integer atomics, order-free) instead
                                     of FP64 atomics.  Needs |N_ij| < 2^23 (at most 2^23
                                     trials per column pair); a caller's N given with
                                     RSM_N_ACCUMULATE is first rounded to that grid.  The
                                     optional error e is not covered. */
+  RSM_ROWS_FIRST = 1u << 6       /* method M2 (Section III, rows first; see the top of
+                                    this file).  Then `l` is the number k of rows per
+                                    sub-matrix (0 => r + 1; r < k <= min(m, RSM_MAX_L),
+                                    m <= 2^31 - 1), `nvec` must be 0 (every trial gives
+                                    |C_t| - r vectors), `min_rows` is the least |C_t| for a
+                                    trial to count (0 => r + 1; must exceed r; the paper
+                                    forms a sub-matrix only with more than r columns,
+                                    Section IV-A), subsets (drawn or given) are row
+                                    indices in [0, m), H_t is formed in FP64 whatever
+                                    gram_prec says (RSM_GRAM_BF16X2 and RSM_PLAIN_GRAM are
+                                    RSM_E_UNSUPPORTED), and trial_vecs must be NULL. */
 };
 
 typedef struct rsm_problem {
@@ -182,7 +201,8 @@ typedef struct rsm_output {
                                 triangle is not touched).  Read when RSM_FINALIZE_ONLY or
                                 RSM_N_ACCUMULATE is set. */
   rsm_info* info;            /* device, required */
-  /* Optional per-trial taps (device, NULL = not written), trial index k = 0..I-1: */
+  /* Optional per-trial taps (device, NULL = not written), trial index k = 0..I-1
+     (with RSM_ROWS_FIRST: S_t, |C_t|, H_t and its eigenvalues; no vectors): */
   int32_t* trial_cols;       /* I x l: C_t */
   int32_t* trial_rows;       /* I: |R_t| */
   double* trial_gram;        /* I x l x l: G_t (as reduced in FP64) */

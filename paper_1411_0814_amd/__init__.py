@@ -193,13 +193,16 @@ def _prepare(req: Request, p: _lib.Problem, device):
         taps["cols"] = torch.empty((I, l), dtype=torch.int32, device=device)
         taps["rows"] = torch.empty((I,), dtype=torch.int32, device=device)
         taps["gram"] = torch.empty((I, l, l), dtype=torch.float64, device=device)
-        taps["vecs"] = torch.empty((I, nvec, l), dtype=torch.float64, device=device)
         taps["eigs"] = torch.empty((I, l), dtype=torch.float64, device=device)
         out.trial_cols = taps["cols"].data_ptr()
         out.trial_rows = taps["rows"].data_ptr()
         out.trial_gram = taps["gram"].data_ptr()
-        out.trial_vecs = taps["vecs"].data_ptr()
         out.trial_eigs = taps["eigs"].data_ptr()
+        # rows first (method M2): the taps hold S_t, |C_t|, H_t and its eigenvalues; the
+        # trial's vectors are not kept
+        if not (p.flags & _lib.ROWS_FIRST):
+            taps["vecs"] = torch.empty((I, nvec, l), dtype=torch.float64, device=device)
+            out.trial_vecs = taps["vecs"].data_ptr()
     keep = []
     if req.events is not None:
         if len(req.events) != 2 * len(_lib.STEPS):

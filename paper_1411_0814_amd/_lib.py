@@ -45,6 +45,7 @@ N_ACCUMULATE = 1 << 2
 COMPUTE_ERROR = 1 << 3
 PLAIN_GRAM = 1 << 4
 DETERMINISTIC = 1 << 5
+ROWS_FIRST = 1 << 6         # method M2: k-row subsets, qualifying columns
 
 STEPS = ["pack", "subsets", "gram", "minor", "eig", "usolve", "error"]
 

@@ -115,14 +115,15 @@ __global__ __launch_bounds__(256) void k_transpose(const ProbDesc* __restrict__ 
   }
 }
 
-// C_t for t = t0 + k, k = 0..I-1: one thread per trial.  Caller-supplied subsets are
-// copied instead; an unsorted or out-of-range one is replaced by the marker -1 in its first
-// slot (the trial is then rejected) and reported.
+// C_t for t = t0 + k, k = 0..I-1: one thread per trial (method M2: the row subsets S_t,
+// drawn the same way from [0, m)).  Caller-supplied subsets are copied instead; an
+// unsorted or out-of-range one is replaced by the marker -1 in its first slot (the trial
+// is then rejected) and reported.
 __global__ void k_subsets(const ProbDesc* __restrict__ probs, IdxList list) {
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
   const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= P.I) return;
-  const int n = static_cast<int>(P.n), l = P.l;
+  const int n = static_cast<int>(P.rows_first ? P.m : P.n), l = P.l;
   if (P.user_subsets) {
     bool ok = true;
     int prev = -1;

@@ -12,7 +12,8 @@ namespace rsm {
 namespace {
 
 constexpr uint32_t kKnownFlags = RSM_ACCUMULATE_ONLY | RSM_FINALIZE_ONLY | RSM_N_ACCUMULATE |
-                                 RSM_COMPUTE_ERROR | RSM_PLAIN_GRAM | RSM_DETERMINISTIC;
+                                 RSM_COMPUTE_ERROR | RSM_PLAIN_GRAM | RSM_DETERMINISTIC |
+                                 RSM_ROWS_FIRST;
 constexpr size_t kAlign = 256;
 
 size_t carve(size_t& cursor, size_t bytes) {
@@ -38,12 +39,24 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
     return RSM_E_ARG;
   const int64_t mn = p.m < p.n ? p.m : p.n;
   if (p.r >= mn) return RSM_E_ARG;
+  const bool rows_first = p.flags & RSM_ROWS_FIRST;
+  // l: columns per sub-matrix (M1) or rows per sub-matrix k (M2, rows first)
   const int l = p.l ? p.l : p.r + 1;
-  if (l <= p.r || l > p.n) return RSM_E_ARG;
-  const int nvec = p.nvec ? p.nvec : l - p.r;
-  if (nvec < 1 || nvec > l - p.r) return RSM_E_ARG;
-  const int min_rows = p.min_rows ? p.min_rows : p.r;
-  if (min_rows < 1) return RSM_E_ARG;
+  if (l <= p.r || l > (rows_first ? p.m : p.n)) return RSM_E_ARG;
+  int nvec = 0, min_rows = 0;
+  if (rows_first) {
+    // every trial gives |C_t| - r vectors; a trial counts with more than r columns
+    if (p.nvec != 0) return RSM_E_ARG;
+    min_rows = p.min_rows ? p.min_rows : p.r + 1;
+    if (min_rows <= p.r) return RSM_E_ARG;
+    if (p.gram_prec == RSM_GRAM_BF16X2 || (p.flags & RSM_PLAIN_GRAM) || p.m > 0x7fffffff)
+      return RSM_E_UNSUPPORTED;
+  } else {
+    nvec = p.nvec ? p.nvec : l - p.r;
+    if (nvec < 1 || nvec > l - p.r) return RSM_E_ARG;
+    min_rows = p.min_rows ? p.min_rows : p.r;
+    if (min_rows < 1) return RSM_E_ARG;
+  }
   if (p.r > RSM_MAX_R || l > RSM_MAX_L || p.n > RSM_MAX_N) return RSM_E_UNSUPPORTED;
   // split-BF16 runs on the tiled MFMA kernel only: FP32 Y, l <= 16, the n-column tile in LDS
   if (p.gram_prec == RSM_GRAM_BF16X2 &&
@@ -66,6 +79,8 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   P.y_layout = p.y_layout;
   P.w_layout = p.w_layout;
   P.mw = ceil_div(p.m, 64);
+  P.rows_first = rows_first;
+  P.nw = ceil_div(p.n, 64);
   P.ng = l * (l + 1) / 2;
   P.part_elem = (p.gram_prec == RSM_GRAM_F64) ? sizeof(double) : sizeof(float);
   P.eig_b = static_cast<int>((p.r + kEigPad) < p.n ? (p.r + kEigPad) : p.n);
@@ -78,9 +93,17 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
 
   // Gram kernel: LDS-tiled (Y tile shared by a group of trials) when the n-column tile fits
   // and the accumulation type matches Y's (split-BF16: FP32 Y), else the per-trial streamer
-  P.tiled = !(p.flags & RSM_PLAIN_GRAM);
-  P.tiled = gram_tiled_ok(P);
-  if (P.tiled) {
+  P.tiled = !(p.flags & RSM_PLAIN_GRAM) && !rows_first;
+  P.tiled = P.tiled && gram_tiled_ok(P);
+  if (rows_first) {
+    // the M1 Gram kernels do not run: one (unused) split
+    P.gram_kernel = 0;
+    P.gram_threads = 0;
+    P.splits = 1;
+    P.words_per_split = P.mw;
+    P.gram_groups = 0;
+    P.gram_wgs = 0;
+  } else if (P.tiled) {
     P.gram_kernel = default_gram_kernel(P);
     set_gram_shape(P, default_gram_threads(P, P.gram_kernel), 0);
   } else {
@@ -176,6 +199,12 @@ void set_layout(Plan& P) {
     P.off_ab = carve(cur, static_cast<size_t>(P.m) * (P.r * (P.r + 1) / 2 + P.r) * sizeof(double));
     P.off_abcnt = carve(cur, static_cast<size_t>(P.m) * sizeof(int32_t));
   }
+  P.off_rbits = P.off_yrow = P.off_B = ~size_t(0);
+  if (P.rows_first) {
+    P.off_rbits = carve(cur, static_cast<size_t>(P.m) * P.nw * sizeof(uint64_t));
+    if (P.y_layout == RSM_COL_MAJOR) P.off_yrow = carve(cur, static_cast<size_t>(P.m) * P.n * yelem);
+    P.off_B = carve(cur, static_cast<size_t>(P.I) * P.l * P.r * sizeof(double));
+  }
   P.total = cur;
 }
 
@@ -262,6 +291,7 @@ int32_t check_io(const Plan& P, const rsm_input& in, const rsm_output& out) {
   // every mode reads Y and W (a2/a3 or a7)
   if (!in.Y || !in.W) return RSM_E_ARG;
   if (P.y_layout == RSM_COL_MAJOR ? in.ldy < P.m : in.ldy < P.n) return RSM_E_ARG;
+  if (P.rows_first && out.trial_vecs) return RSM_E_ARG;
   if (P.w_layout == RSM_COL_MAJOR ? in.ldw < P.m : in.ldw < P.n) return RSM_E_ARG;
   return RSM_OK;
 }
@@ -326,6 +356,15 @@ ProbDesc prob_desc(const Plan& P, const rsm_input& in, const rsm_output& out, vo
   d.scal = gptr(at<DevScalars>(ws, P.off_scal));
   d.ab = P.u_mfma ? gptr(at<double>(ws, P.off_ab)) : nullptr;
   d.abcnt = P.u_mfma ? gptr(at<int32_t>(ws, P.off_abcnt)) : nullptr;
+  d.rows_first = P.rows_first ? 1 : 0;
+  d.nw = static_cast<int32_t>(P.nw);
+  if (P.rows_first) {
+    const bool yrm = P.y_layout == RSM_ROW_MAJOR;
+    d.ldyr = yrm ? in.ldy : P.n;
+    d.rbits = gptr(at<uint64_t>(ws, P.off_rbits));
+    d.yrow = yrm ? gptr(in.Y) : gptr(static_cast<const void*>(at<void>(ws, P.off_yrow)));
+    d.Bm = gptr(at<double>(ws, P.off_B));
+  }
   d.tap_rows = gptr(out.trial_rows);
   d.tap_gram = gptr(out.trial_gram);
   d.tap_vecs = gptr(out.trial_vecs);
@@ -473,6 +512,7 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
     launch_init_info(dprob, g, s);
     mark_all(outputs, g, RSM_STEP_PACK, 0, s);
     launch_pack(dprob, g, h, s);
+    launch_rows_pack(dprob, g, h, s);
     mark_all(outputs, g, RSM_STEP_PACK, 1, s);
   });
   // a1: subsets, N cleared
@@ -482,7 +522,8 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
     mark_all(outputs, g, RSM_STEP_SUBSETS, 1, s);
   });
   // a2 + a3: one launch per (l, element type, precision, kernel, trials per workgroup)
-  for_groups(plans, [](const Plan& P) { return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0; },
+  for_groups(plans, [](const Plan& P) {
+               return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0 && !P.rows_first; },
              [](const Plan& P) {
                return ((((int64_t(P.l) * 4 + P.y_dtype) * 4 + P.prec) * 2 + (P.tiled ? 1 : 0)) *
                        4 + P.gram_kernel) * 1024 + P.gram_threads;
@@ -490,6 +531,14 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
              [&](const IdxList& g, const Plan* const* h) {
                mark_all(outputs, g, RSM_STEP_GRAM, 0, s);
                launch_gram(dprob, g, h, s);
+               mark_all(outputs, g, RSM_STEP_GRAM, 1, s);
+             });
+  // method M2: a2 + a3 for all rows-first problems in shared launches (per element type)
+  for_groups(plans, [](const Plan& P) {
+               return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0 && P.rows_first; },
+             one_key, [&](const IdxList& g, const Plan* const* h) {
+               mark_all(outputs, g, RSM_STEP_GRAM, 0, s);
+               launch_rows_gram(dprob, g, h, s);
                mark_all(outputs, g, RSM_STEP_GRAM, 1, s);
              });
   // a4 + a5: one launch per l.  Deterministic problems accumulate N in fixed point: a
@@ -501,10 +550,18 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
              one_key, [&](const IdxList& g, const Plan* const* h) {
                launch_n_fixed(dprob, g, h, true, s);
              });
-  for_groups(plans, front, [](const Plan& P) { return int64_t(P.l); },
+  for_groups(plans, [&](const Plan& P) { return front(P) && !P.rows_first; },
+             [](const Plan& P) { return int64_t(P.l); },
              [&](const IdxList& g, const Plan* const* h) {
                mark_all(outputs, g, RSM_STEP_MINOR, 0, s);
                launch_minor(dprob, g, h, s);
+               mark_all(outputs, g, RSM_STEP_MINOR, 1, s);
+             });
+  for_groups(plans, [&](const Plan& P) { return front(P) && P.rows_first; },
+             [](const Plan& P) { return int64_t(P.l); },
+             [&](const IdxList& g, const Plan* const* h) {
+               mark_all(outputs, g, RSM_STEP_MINOR, 0, s);
+               launch_rows_minor(dprob, g, h, s);
                mark_all(outputs, g, RSM_STEP_MINOR, 1, s);
              });
   for_groups(plans, fixed, one_key, [&](const IdxList& g, const Plan* const* h) {

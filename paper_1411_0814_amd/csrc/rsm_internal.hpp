@@ -79,13 +79,15 @@ struct Plan {
   int gram_kernel = 0;   // tiled Gram staging: RSM_GRAM_KERNEL_REGS or _DMA (0: streamer)
   bool u_mfma = false;   // U-hat normal equations formed on the FP64 matrix cores
   bool minor_inv = false;  // minor vector by inverse iteration (nvec 1, no eigen taps)
+  bool rows_first = false; // method M2: k-row subsets, qualifying columns (l holds k)
+  int64_t nw = 0;          // 64-column words per row of the row bit-planes (M2)
   int gram_wgs = 0;      // workgroups of the Gram step of this problem
   // workspace offsets (bytes from the workspace base); ~0 = unused
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
          off_rows = 0;
   size_t off_N = 0, off_Nsym = 0, off_L = 0, off_M = 0, off_Mt = 0, off_T = 0, off_X = 0,
          off_Z = 0, off_NX = 0, off_AP = 0, off_small = 0, off_ab = 0, off_abcnt = 0,
-         off_mflag = 0;
+         off_mflag = 0, off_rbits = 0, off_yrow = 0, off_B = 0;
   size_t off_scal = 0;
   size_t total = 0;
 };
@@ -161,6 +163,13 @@ struct ProbDesc {
   RSM_GLOBAL int32_t* mflag;   // per trial: minor vector left to the Jacobi pass (I)
   RSM_GLOBAL double* ab;       // U-hat normal equations on MFMA: (r(r+1)/2 + r) x m, ld m
   RSM_GLOBAL int32_t* abcnt;   // known entries per row (m)
+  // method M2 (rows first)
+  int32_t rows_first;
+  int32_t nw;                  // 64-column words per row of rbits
+  int64_t ldyr;                // leading dimension of the row-major Y in yrow
+  RSM_GLOBAL uint64_t* rbits;  // row bit-planes: word w of row i, bit b = (W[i, 64 w + b] != 0)
+  RSM_GLOBAL const void* yrow; // row-major Y (the caller's, or the packed copy)
+  RSM_GLOBAL double* Bm;       // per trial k x r: u_a / s_a of the r leading pairs of H_t
 };
 
 // The problems of one launch: indices into a device ProbDesc array, passed by value.
@@ -184,6 +193,10 @@ constexpr double kFixedScale = 1099511627776.0;  // 2^40
 void launch_n_fixed(const ProbDesc* d, const IdxList& g, const Plan* const* h, bool to_fixed,
                     hipStream_t s);
 void launch_minor(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
+// Method M2: a0's row bit-planes and row-major Y; a2 + a3 (H_t), a4 + a5 (N update).
+void launch_rows_pack(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
+void launch_rows_gram(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
+void launch_rows_minor(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
 void launch_solve_u(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
 void launch_error(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s);
 

@@ -148,6 +148,40 @@ def test_invalid_problems_rejected_on_host(kw, code):
     assert _ws(_prob(**kw))[0] == code
 
 
+RF = _lib.ROWS_FIRST
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(flags=RF), _lib.OK),
+    (dict(flags=RF, l=9, r=8, n=1024, m=131072), _lib.OK),
+    (dict(flags=RF, nvec=1), _lib.E_ARG),                       # every trial gives |C| - r
+    (dict(flags=RF, min_rows=5), _lib.E_ARG),                   # a trial needs > r columns
+    (dict(flags=RF, l=5), _lib.E_ARG),                          # k <= r
+    (dict(flags=RF, l=2001), _lib.E_ARG),                       # k > m
+    (dict(flags=RF, l=18), _lib.E_UNSUPPORTED),                 # k > RSM_MAX_L
+    (dict(flags=RF, gram_prec=_lib.GRAM_BF16X2, y_dtype=_lib.F32), _lib.E_UNSUPPORTED),
+    (dict(flags=RF | _lib.PLAIN_GRAM), _lib.E_UNSUPPORTED),
+])
+def test_rows_first_validation(kw, code):
+    assert _ws(_prob(**kw))[0] == code
+
+
+def test_rows_first_workspace_holds_row_planes_and_row_major_copy():
+    # the row bit-planes (m x ceil(n/64) words), k x r doubles per trial and one copy of Y:
+    # the row-major copy when Y is column-major, the column-major copy (for U-hat) when Y
+    # is row-major
+    p = _prob()
+    code, rf = _ws(_prob(flags=RF))
+    _, rf_rm = _ws(_prob(flags=RF, y_layout=_lib.ROW_MAJOR))
+    assert code == _lib.OK
+    words = p.m * ((p.n + 63) // 64) * 8
+    ycopy = p.m * p.n * 4                                        # FP32 Y
+    bmat = p.num_submatrices * (p.r + 1) * p.r * 8
+    nn = p.n * p.n * 8
+    assert rf >= words + ycopy + bmat + 3 * nn
+    assert abs(rf - rf_rm) <= 1024
+
+
 def _decompose_raw(p, inp, out, ws_ptr, ws_bytes):
     return _lib.lib().rsm_decompose(C.byref(p), C.byref(inp), C.byref(out), C.c_void_p(ws_ptr),
                                     C.c_size_t(ws_bytes), None)

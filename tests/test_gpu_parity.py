@@ -136,13 +136,17 @@ def test_nvec_two_l_plus_two():
 
 
 # l > r + 1 with fewer minor vectors than l - r (the choice of ell the paper allows),
-# through both register Jacobi (l <= 11) and the wavefront Jacobi (l >= 12)
-@pytest.mark.parametrize("r,l,nvec,gram", [(3, 6, 1, "f64"), (3, 6, 2, "f64"),
-                                           (2, 7, 3, "f32"), (4, 13, 3, "f64"),
-                                           (5, 14, 1, "f32")])
-def test_l_above_r_plus_one_with_fewer_vectors(r, l, nvec, gram):
+# through both register Jacobi (l <= 11) and the wavefront Jacobi (l >= 12).  The ell
+# vectors are picked among l - r noise directions, so the noise must separate their
+# eigenvalues: at l >= 12 and noise 0.01 every trial's gap between the ell-th and the next
+# eigenvalue is below 1e-6 of the largest (the chosen subspace is not defined to the
+# precision compared); at noise 1 the smallest gap is above 5e-5.
+@pytest.mark.parametrize("r,l,nvec,gram,noise", [(3, 6, 1, "f64", 0.01), (3, 6, 2, "f64", 0.01),
+                                                 (2, 7, 3, "f32", 0.01), (4, 13, 3, "f64", 1.0),
+                                                 (5, 14, 1, "f32", 1.0)])
+def test_l_above_r_plus_one_with_fewer_vectors(r, l, nvec, gram, noise):
     dt = np.float32 if gram == "f32" else np.float64
-    p = synth.paper_synthetic(2500, 90, r, 0.9, 0.01, 20 + l, factor_dtype=dt, y_dtype=dt,
+    p = synth.paper_synthetic(2500, 90, r, 0.9, noise, 20 + l, factor_dtype=dt, y_dtype=dt,
                               num_submatrices=900, l=l, gram=gram)
     res, info = _run(p, gram, taps=True, nvec=nvec)
     ora = rsm.rsm(p.Y, p.W, p.r, p.num_submatrices, seed=p.seed_rsm, l=l, nvec=nvec)
