@@ -12,12 +12,22 @@
 //  a4  k_m2_eig: one thread per trial, cyclic Jacobi (FP64) on H_t = U diag(s^2) U^T; the
 //      r largest eigenpairs give B_t = [u_a / s_a] (k x r), so that the leading right
 //      singular vectors of Z_t are Q_t = Z_t^T B_t.
-//  a5  k_m2_update: one workgroup per trial.  N[C_t, C_t] += I - Q_t Q_t^T, lower triangle,
-//      formed in 64 x 64 blocks of C_t positions: the rows of Q_t for a block are computed
-//      into LDS from the k chosen rows of Y, then 256 threads form 4 x 4 entries each and add
-//      them with FP64 atomics (64-bit fixed point in deterministic mode).
+//  a5  N[C_t, C_t] += I - Q_t Q_t^T (lower triangle) in two passes:
+//      k_m2_qform: one wavefront per trial; lane b of word w computes row 64 w + b of Q_t,
+//      q = B_t^T z (z: the column's k chosen entries), into a dense trial x column x r
+//      array (only qualifying columns are written or read).
+//      k_m2_tiles: one workgroup per 64 x 64 block of N (lower blocks) and range of trials.
+//      The block stays in LDS; each wavefront takes one trial at a time (the next trial's
+//      mask words and rows loading meanwhile), finds the trial's columns inside the block's
+//      row and column ranges from two mask words, holds their rows of Q_t in registers (lane
+//      b: columns 64 bi + b and 64 bj + b), forms every pair's -q_i . q_j (+1 on the
+//      diagonal) with one lane per pair and cross-lane reads, and adds it to the block with
+//      LDS atomics.  The
+//      block is then added into N with one global atomic per entry.  Deterministic mode
+//      uses 64-bit fixed point in LDS and in N (integer atomics, order-free).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "device_util.hpp"
 #include "rsm_internal.hpp"
@@ -182,6 +192,8 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_m2_gram(const ProbDesc* __r
   for (int s = 0; s < 3; ++s)
     if (ln + 64 * s < ng) P.G[static_cast<int64_t>(ln + 64 * s) * P.I + t] = acc[s];
   if (ln == 0) P.rows[t] = valid ? cnt : 0;
+  // the mask words of C_t, empty for a rejected trial (the N-update passes skip it)
+  if (ln < nw) P.cmask[t * nw + ln] = (cnt >= P.min_rows) ? myword : 0ull;
 }
 
 // ------------------------------------------------------------------ a4
@@ -316,117 +328,148 @@ __global__ __launch_bounds__(eig_tpb<K>()) void k_m2_eig(const ProbDesc* __restr
 
 // ------------------------------------------------------------------ a5
 
-constexpr int kQs = RSM_MAX_R + 1;  // LDS row stride of a Q panel
-
-// Grid (I, problems); one workgroup of 256 threads per trial.
+// Grid (ceil(I / 4), problems); one wavefront per accepted trial.
 template <typename T>
-__global__ __launch_bounds__(256) void k_m2_update(const ProbDesc* __restrict__ probs,
-                                                   IdxList list) {
-  __shared__ int sS[kMaxK];
-  __shared__ double sB[kMaxK][RSM_MAX_R];
-  __shared__ int sCl[RSM_MAX_N];
-  __shared__ int sOff[kMaxW + 1];
-  __shared__ double zp[kMaxK][64];
-  __shared__ double qA[64][kQs];
-  __shared__ double qB[64][kQs];
+__global__ __launch_bounds__(64 * kGramWaves) void k_m2_qform(const ProbDesc* __restrict__ probs,
+                                                             IdxList list) {
+  __shared__ double sB[kGramWaves][kMaxK * RSM_MAX_R];
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
-  const int64_t t = blockIdx.x;
-  if (t >= P.I) return;
+  const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kGramWaves + wv;
+  if (t >= P.I) return;  // whole wavefront (no workgroup barrier below)
   const int k = P.l, r = P.r, nw = P.nw;
-  const int64_t n = P.n;
-  const int tid = threadIdx.x;
-  const int cnt = P.rows[t];
-  if (P.cols[t * k] < 0 || cnt < P.min_rows) return;  // rejected (uniform per workgroup)
-  const bool fixed = P.fixed_n != 0;
+  if (P.cols[t * k] < 0 || P.rows[t] < P.min_rows) return;  // rejected
   auto y = static_cast<RSM_GLOBAL const T*>(P.yrow);
-  const int64_t ldyr = P.ldyr;
-  if (tid < k) sS[tid] = P.cols[t * k + tid];
-  for (int e = tid; e < k * r; e += 256) sB[e / r][e % r] = P.Bm[t * k * r + e];
-  __syncthreads();
-  // the qualifying-column list C_t (ascending): word offsets by a scan in wavefront 0
-  uint64_t word = 0;
-  if (tid < 64) {
-    if (tid < nw) {
-      word = ~0ull;
-      for (int i = 0; i < k; ++i) word &= P.rbits[static_cast<int64_t>(sS[i]) * nw + tid];
-    }
-    int c = __popcll(word);
-    int incl = c;
+  const int64_t ldyr = P.ldyr, n = P.n;
+  int S[kMaxK];
 #pragma unroll
-    for (int d = 1; d < 64; d *= 2) {
-      const int o = __shfl_up(incl, d);
-      if (tid >= d) incl += o;
-    }
-    if (tid < nw) sOff[tid] = incl - c;
-    if (tid < nw) {
-      int pos = incl - c;
-      uint64_t wbits = word;
-      while (wbits) {
-        const int b = __ffsll(static_cast<long long>(wbits)) - 1;
-        sCl[pos++] = tid * 64 + b;
-        wbits &= wbits - 1;
+  for (int i = 0; i < kMaxK; ++i) S[i] = i < k ? P.cols[t * k + i] : 0;
+  for (int e = ln; e < k * r; e += 64) sB[wv][e] = P.Bm[t * k * r + e];
+  wave_fence();
+  const uint64_t myword = ln < nw ? P.cmask[t * nw + ln] : 0ull;
+  for (int w = 0; w < nw; ++w) {
+    const uint64_t word = __shfl(myword, w);
+    if (!((word >> ln) & 1ull)) continue;
+    const int64_t col = static_cast<int64_t>(w) * 64 + ln;
+    double z[kMaxK];
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i) z[i] = i < k ? ld_y(y, static_cast<int64_t>(S[i]) * ldyr + col) : 0.0;
+    RSM_GLOBAL double* q = P.Qd + (t * n + col) * r;
+#pragma unroll
+    for (int a = 0; a < RSM_MAX_R; ++a) {
+      if (a < r) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < kMaxK; ++i)
+          if (i < k) s = fma(z[i], sB[wv][i * r + a], s);
+        q[a] = s;
       }
     }
   }
+}
+
+constexpr int kTileWaves = 4;
+
+// Grid (lower 64 x 64 blocks of N, trial ranges, problems); R = r.  Each wavefront walks its
+// trials with the next trial's mask words and Q rows loading while the current one is added.
+template <bool FIXED, int R>
+__global__ __launch_bounds__(64 * kTileWaves) void k_m2_tiles(const ProbDesc* __restrict__ probs,
+                                                             IdxList list, int ranges) {
+  using Acc = typename std::conditional<FIXED, unsigned long long, double>::type;
+  __shared__ Acc acc[64][65];
+  __shared__ int li[kTileWaves][64];
+  __shared__ int lj[kTileWaves][64];
+  const ProbDesc& P = probs[list.idx[blockIdx.z]];
+  const int64_t n = P.n, I = P.I;
+  const int nb = static_cast<int>(ceil_div(n, 64));
+  const int blk = blockIdx.x;
+  if (blk >= nb * (nb + 1) / 2) return;  // whole workgroup
+  int bi = 0;
+  while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
+  const int bj = blk - bi * (bi + 1) / 2;
+  const int64_t per = ceil_div(I, ranges);
+  const int64_t t_begin = static_cast<int64_t>(blockIdx.y) * per;
+  const int64_t t_end = t_begin + per < I ? t_begin + per : I;
+  if (t_begin >= t_end) return;  // whole workgroup
+  const int tid = threadIdx.x, wv = tid / 64, ln = tid % 64;
+  for (int e = tid; e < 64 * 65; e += 64 * kTileWaves) (&acc[0][0])[e] = Acc(0);
   __syncthreads();
-  const int np = (cnt + 63) / 64;
-  // rows of Q for the positions [64 panel, 64 panel + 64) of C_t into q
-  auto panel = [&](int pnl, double (*q)[kQs]) {
-    const int base = pnl * 64;
-    const int pc = min(64, cnt - base);
-    for (int e = tid; e < k * 64; e += 256) {
-      const int i = e / 64, p = e % 64;
-      zp[i][p] = p < pc ? ld_y(y, static_cast<int64_t>(sS[i]) * ldyr + sCl[base + p]) : 0.0;
-    }
-    __syncthreads();
-    for (int e = tid; e < 64 * r; e += 256) {
-      const int p = e % 64, a = e / 64;
-      double s = 0.0;
-      for (int i = 0; i < k; ++i) s = fma(zp[i][p], sB[i][a], s);
-      q[p][a] = s;
-    }
-    __syncthreads();
+  const int nw = P.nw;
+  const bool diag = bi == bj;
+  const uint64_t below = (ln == 0) ? 0ull : (~0ull >> (64 - ln));  // bits under this lane
+  RSM_GLOBAL const uint64_t* cm = P.cmask;
+  RSM_GLOBAL const double* Qd = P.Qd;
+  const int64_t rowi = static_cast<int64_t>(bi) * 64 + ln, rowj = static_cast<int64_t>(bj) * 64 + ln;
+  auto words = [&](int64_t t, uint64_t& wi, uint64_t& wj) {
+    wi = t < t_end ? cm[t * nw + bi] : 0ull;
+    wj = t < t_end ? cm[t * nw + bj] : 0ull;
   };
-  const int ty = tid / 16, tx = tid % 16;
-  for (int pa = 0; pa < np; ++pa) {
-    panel(pa, qA);
-    for (int pb = 0; pb <= pa; ++pb) {
-      double (*qb)[kQs] = qA;
-      if (pb != pa) {
-        panel(pb, qB);
-        qb = qB;
-      }
-      double acc[4][4];
+  auto rows_of = [&](int64_t t, uint64_t wi, uint64_t wj, double* qi, double* qj) {
+    const bool hi = (wi >> ln) & 1ull, hj = (wj >> ln) & 1ull;
+    RSM_GLOBAL const double* Qt = Qd + t * n * R;
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+    for (int a = 0; a < R; ++a) {
+      qi[a] = hi ? Qt[rowi * R + a] : 0.0;
+      qj[a] = hj ? Qt[rowj * R + a] : 0.0;
+    }
+  };
+  int64_t t = t_begin + wv;
+  uint64_t wi, wj, wi_n, wj_n;
+  double qi[R], qj[R], qi_n[R], qj_n[R];
+  words(t, wi, wj);
+  rows_of(t, wi, wj, qi, qj);
+  words(t + kTileWaves, wi_n, wj_n);
+  for (; t < t_end; t += kTileWaves) {
+    // next trial's rows and the mask words of the one after it, in flight meanwhile
+    rows_of(t + kTileWaves, wi_n, wj_n, qi_n, qj_n);
+    uint64_t wi_nn, wj_nn;
+    words(t + 2 * kTileWaves, wi_nn, wj_nn);
+    if (wi != 0 && wj != 0) {
+      if ((wi >> ln) & 1ull) li[wv][__popcll(wi & below)] = ln;
+      if ((wj >> ln) & 1ull) lj[wv][__popcll(wj & below)] = ln;
+      wave_fence();
+      const int ni = __popcll(wi), nj = __popcll(wj);
+      const int pairs = ni * nj;
+      for (int base = 0; base < pairs; base += 64) {
+        const int p = base + ln;
+        const int ii = p / nj, jj = p - (p / nj) * nj;
+        const bool valid = p < pairs && !(diag && jj > ii);
+        const int si = p < pairs ? li[wv][ii] : 0;
+        const int sj = p < pairs ? lj[wv][jj] : 0;
+        double dot = 0.0;
 #pragma unroll
-        for (int v2 = 0; v2 < 4; ++v2) acc[u][v2] = 0.0;
-      for (int a = 0; a < r; ++a) {
-        double xa[4], xb[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) xa[u] = qA[ty + 16 * u][a];
-#pragma unroll
-        for (int v2 = 0; v2 < 4; ++v2) xb[v2] = qb[tx + 16 * v2][a];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v2 = 0; v2 < 4; ++v2) acc[u][v2] = fma(xa[u], xb[v2], acc[u][v2]);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int ia = pa * 64 + ty + 16 * u;
-        if (ia >= cnt) continue;
-#pragma unroll
-        for (int v2 = 0; v2 < 4; ++v2) {
-          const int ib = pb * 64 + tx + 16 * v2;
-          if (ib >= cnt || ib > ia) continue;
-          const double val = (ia == ib ? 1.0 : 0.0) - acc[u][v2];
-          add_to_N_m2(P.N, static_cast<int64_t>(sCl[ia]) + static_cast<int64_t>(sCl[ib]) * n,
-                      val, fixed);
+        for (int a = 0; a < R; ++a) dot = fma(__shfl(qi[a], si), __shfl(qj[a], sj), dot);
+        if (valid) {
+          const double v = (diag && si == sj ? 1.0 : 0.0) - dot;
+          if constexpr (FIXED)
+            atomicAdd(&acc[si][sj], static_cast<unsigned long long>(llrint(v * kFixedScale)));
+          else
+            atomicAdd(&acc[si][sj], v);
         }
       }
-      __syncthreads();  // before the next panel overwrites qB / qA
+      wave_fence();  // before the next trial overwrites li / lj
     }
+    wi = wi_n;
+    wj = wj_n;
+    wi_n = wi_nn;
+    wj_n = wj_nn;
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      qi[a] = qi_n[a];
+      qj[a] = qj_n[a];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 64 * kTileWaves) {
+    const int i = e / 64, j = e % 64;
+    const int64_t row = static_cast<int64_t>(bi) * 64 + i, col = static_cast<int64_t>(bj) * 64 + j;
+    if (row >= n || col > row) continue;
+    const Acc v = acc[i][j];
+    if (v == Acc(0)) continue;
+    if constexpr (FIXED)
+      atomicAdd((unsigned long long*)&P.N[row + col * n], v);
+    else
+      atomic_add_f64((double*)&P.N[row + col * n], v);
   }
 }
 
@@ -440,6 +483,19 @@ IdxList pick(const IdxList& g, const Plan* const* h, F pred, const Plan** hs) {
       out.idx[out.count++] = g.idx[k];
     }
   return out;
+}
+
+template <int R>
+void tiles_dispatch(bool fixed, int r, dim3 grid, const ProbDesc* d, const IdxList& g, int ranges,
+                    hipStream_t s) {
+  if (r == R) {
+    if (fixed)
+      k_m2_tiles<true, R><<<grid, 64 * kTileWaves, 0, s>>>(d, g, ranges);
+    else
+      k_m2_tiles<false, R><<<grid, 64 * kTileWaves, 0, s>>>(d, g, ranges);
+    return;
+  }
+  if constexpr (R < RSM_MAX_R) tiles_dispatch<R + 1>(fixed, r, grid, d, g, ranges, s);
 }
 
 template <int K>
@@ -513,13 +569,27 @@ void launch_rows_minor(const ProbDesc* d, const IdxList& g, const Plan* const* h
   for (int dt = RSM_F32; dt <= RSM_F64; ++dt) {
     const IdxList gd = pick(g, h, [dt](const Plan& P) { return P.y_dtype == dt && P.I > 0; }, hs);
     if (!gd.count) continue;
-    int64_t Id = 0;
-    for (int k = 0; k < gd.count; ++k) Id = std::max<int64_t>(Id, hs[k]->I);
-    const dim3 grid(static_cast<unsigned>(Id), gd.count);
+    const dim3 grid(static_cast<unsigned>(ceil_div(I, kGramWaves)), gd.count);
     if (dt == RSM_F32)
-      k_m2_update<float><<<grid, 256, 0, s>>>(d, gd);
+      k_m2_qform<float><<<grid, 64 * kGramWaves, 0, s>>>(d, gd);
     else
-      k_m2_update<double><<<grid, 256, 0, s>>>(d, gd);
+      k_m2_qform<double><<<grid, 64 * kGramWaves, 0, s>>>(d, gd);
+  }
+  // blocks of N x trial ranges: about four workgroups per CU over the launch
+  for (int key = 0; key < 2 * (RSM_MAX_R + 1); ++key) {
+    const int fx = key & 1, rr = key >> 1;
+    const IdxList gf = pick(g, h, [fx, rr](const Plan& P) {
+      return P.I > 0 && P.r == rr && ((P.flags & RSM_DETERMINISTIC) != 0) == (fx == 1); }, hs);
+    if (!gf.count) continue;
+    int64_t blocks = 0;
+    for (int k = 0; k < gf.count; ++k) {
+      const int64_t nb = ceil_div(hs[k]->n, 64);
+      blocks = std::max<int64_t>(blocks, nb * (nb + 1) / 2);
+    }
+    int64_t ranges = 1024 / (blocks * gf.count);
+    ranges = std::max<int64_t>(1, std::min<int64_t>(ranges, ceil_div(I, 64)));
+    const dim3 grid(static_cast<unsigned>(blocks), static_cast<unsigned>(ranges), gf.count);
+    tiles_dispatch<1>(fx == 1, rr, grid, d, gf, static_cast<int>(ranges), s);
   }
 }
 

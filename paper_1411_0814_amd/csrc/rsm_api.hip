@@ -199,11 +199,13 @@ void set_layout(Plan& P) {
     P.off_ab = carve(cur, static_cast<size_t>(P.m) * (P.r * (P.r + 1) / 2 + P.r) * sizeof(double));
     P.off_abcnt = carve(cur, static_cast<size_t>(P.m) * sizeof(int32_t));
   }
-  P.off_rbits = P.off_yrow = P.off_B = ~size_t(0);
+  P.off_rbits = P.off_yrow = P.off_B = P.off_cmask = P.off_Qd = ~size_t(0);
   if (P.rows_first) {
     P.off_rbits = carve(cur, static_cast<size_t>(P.m) * P.nw * sizeof(uint64_t));
     if (P.y_layout == RSM_COL_MAJOR) P.off_yrow = carve(cur, static_cast<size_t>(P.m) * P.n * yelem);
     P.off_B = carve(cur, static_cast<size_t>(P.I) * P.l * P.r * sizeof(double));
+    P.off_cmask = carve(cur, static_cast<size_t>(P.I) * P.nw * sizeof(uint64_t));
+    P.off_Qd = carve(cur, static_cast<size_t>(P.I) * P.n * P.r * sizeof(double));
   }
   P.total = cur;
 }
@@ -364,6 +366,8 @@ ProbDesc prob_desc(const Plan& P, const rsm_input& in, const rsm_output& out, vo
     d.rbits = gptr(at<uint64_t>(ws, P.off_rbits));
     d.yrow = yrm ? gptr(in.Y) : gptr(static_cast<const void*>(at<void>(ws, P.off_yrow)));
     d.Bm = gptr(at<double>(ws, P.off_B));
+    d.cmask = gptr(at<uint64_t>(ws, P.off_cmask));
+    d.Qd = gptr(at<double>(ws, P.off_Qd));
   }
   d.tap_rows = gptr(out.trial_rows);
   d.tap_gram = gptr(out.trial_gram);

@@ -87,7 +87,7 @@ struct Plan {
          off_rows = 0;
   size_t off_N = 0, off_Nsym = 0, off_L = 0, off_M = 0, off_Mt = 0, off_T = 0, off_X = 0,
          off_Z = 0, off_NX = 0, off_AP = 0, off_small = 0, off_ab = 0, off_abcnt = 0,
-         off_mflag = 0, off_rbits = 0, off_yrow = 0, off_B = 0;
+         off_mflag = 0, off_rbits = 0, off_yrow = 0, off_B = 0, off_cmask = 0, off_Qd = 0;
   size_t off_scal = 0;
   size_t total = 0;
 };
@@ -170,6 +170,8 @@ struct ProbDesc {
   RSM_GLOBAL uint64_t* rbits;  // row bit-planes: word w of row i, bit b = (W[i, 64 w + b] != 0)
   RSM_GLOBAL const void* yrow; // row-major Y (the caller's, or the packed copy)
   RSM_GLOBAL double* Bm;       // per trial k x r: u_a / s_a of the r leading pairs of H_t
+  RSM_GLOBAL uint64_t* cmask;  // per trial nw words: the qualifying columns C_t
+  RSM_GLOBAL double* Qd;       // per trial n x r (row j of Q_t at column j; C_t only)
 };
 
 // The problems of one launch: indices into a device ProbDesc array, passed by value.
