@@ -191,7 +191,7 @@ constexpr int kFBs = kFB + 1;  // its LDS row stride
 constexpr int kNFB = NB / kFB;
 
 struct FactorWork {
-  double Lt[kFB][kFB];            // column p of the current diagonal block's factor at Lt[p][.]
+  double Lt[kFB][kFB];            // the current diagonal block's factor: Lt[p][i] = l_ip
   double invd[kFB];               // 1 / l_jj of the current block
   double D[kNFB][kFB][kFBs];      // inverses of the diagonal blocks' factors
   double S[kNFB - 1][kFB][kFBs];  // partial sums of the inverse
@@ -199,42 +199,48 @@ struct FactorWork {
 
 // Step J of the left-looking (Crout) factorisation of a 16 x 16 block by one wavefront, lane
 // = row i (< 16):  l_iJ = (a_iJ - sum_{p<J} l_ip l_Jp) / l_JJ,  l_JJ = sqrt(a_JJ - sum_{p<J}
-// l_Jp^2).  a[] holds the lane's row (finished entries l_ip for p < J); row J of L is read
-// from LDS as a broadcast; the pivot comes from lane J by readlane.  The recursion keeps
-// every register index static.
+// l_Jp^2).  a[] holds the lane's row (finished entries l_ip for p < J); the finished row J
+// of L and the pivot are read from lane J's registers (readlane), so a step has no LDS
+// round trip.  The recursion keeps every register index static.
 template <int J>
-__device__ __forceinline__ void crout_steps(double (&a)[kFB], FactorWork& W, int lane, double mu,
-                                            int& npiv) {
+__device__ __forceinline__ void crout_steps(double (&a)[kFB], double (&invd)[kFB], int lane,
+                                            double mu, int& npiv) {
   if constexpr (J < kFB) {
     double s2[2] = {a[J], 0.0};
 #pragma unroll
-    for (int p = 0; p < J; ++p) s2[p & 1] -= a[p] * W.Lt[p][J];
+    for (int p = 0; p < J; ++p) s2[p & 1] -= a[p] * readlane_f64(a[p], J);
     const double sum = s2[0] + s2[1];
     double d = readlane_f64(sum, J);
     if (!(d > 0.0) || !isfinite(d)) {  // uniform: every lane holds the same d
       d = mu;
       ++npiv;
     }
-    const double inv = 1.0 / sqrt(d);
+    const double inv = rsqrt(d);
     a[J] = lane < J ? 0.0 : (lane == J ? d * inv : sum * inv);
-    if (lane < kFB) W.Lt[J][lane] = a[J];
-    if (lane == 0) W.invd[J] = inv;
-    wave_lds_fence();
-    crout_steps<J + 1>(a, W, lane, mu, npiv);
+    invd[J] = inv;
+    crout_steps<J + 1>(a, invd, lane, mu, npiv);
   }
 }
 
 // Wavefront 0: factor diagonal block KB of As and store the inverse of its factor in W.D[KB]
-// (lane = column c: x_i = (delta_ic - sum_{p<i} l_ip x_p) / l_ii).
+// (the factor goes to LDS once; lane = column c: x_i = (delta_ic - sum_{p<i} l_ip x_p) /
+// l_ii with row i of L read as broadcasts).
 template <int KB>
 __device__ __forceinline__ void fb_diag(double (*As)[kTr], FactorWork& W, double mu, int& npiv) {
   constexpr int k0 = KB * kFB;
   const int lane = threadIdx.x;
   const int row = lane < kFB ? lane : 0;
-  double a[kFB];
+  double a[kFB], invd[kFB];
 #pragma unroll
   for (int c = 0; c < kFB; ++c) a[c] = c <= row ? As[k0 + row][k0 + c] : 0.0;
-  crout_steps<0>(a, W, lane, mu, npiv);
+  crout_steps<0>(a, invd, lane, mu, npiv);
+  if (lane < kFB)
+#pragma unroll
+    for (int p = 0; p < kFB; ++p) W.Lt[p][lane] = a[p];
+  if (lane == 0)
+#pragma unroll
+    for (int p = 0; p < kFB; ++p) W.invd[p] = invd[p];
+  wave_lds_fence();
   double x[kFB];
 #pragma unroll
   for (int i = 0; i < kFB; ++i) {
