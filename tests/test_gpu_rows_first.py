@@ -157,3 +157,28 @@ def test_rows_first_paper_scale_shape():
     rms = metrics.rel_rms_known(p.W[rows], Ug[rows], V, Uo[rows], ora.V)
     assert theta <= 1e-4 and rms <= 1e-5, (theta, rms)
     print(f"rows first paper-scale shape: theta={theta:.3e} rms={rms:.3e}")
+
+
+def test_rows_first_split_run_equals_whole_bitwise():
+    """Trials [0, I/3) then [I/3, I) onto one N (deterministic mode: bitwise), then
+    finalised: the per-GPU share of a sharded run."""
+    import torch
+    from paper_1411_0814_amd import _lib, decompose
+    p = synth.paper_synthetic(2500, 180, 4, 0.85, 0.01, 56, factor_dtype=np.float32,
+                              y_dtype=np.float32, num_submatrices=600, l=5)
+    Y, W = to_device(p)
+    I, cut = p.num_submatrices, p.num_submatrices // 3
+    base = _lib.ROWS_FIRST | _lib.DETERMINISTIC
+    whole = decompose(Y, W, p.r, I, p.seed_rsm, l=p.l, flags=base,
+                      N=torch.zeros((p.n, p.n), dtype=torch.float64, device="cuda"))
+    N = torch.zeros((p.n, p.n), dtype=torch.float64, device="cuda")
+    decompose(Y, W, p.r, cut, p.seed_rsm, l=p.l, N=N, flags=base | _lib.ACCUMULATE_ONLY)
+    decompose(Y, W, p.r, I - cut, p.seed_rsm, l=p.l, N=N, trial_begin=cut,
+              flags=base | _lib.ACCUMULATE_ONLY | _lib.N_ACCUMULATE)
+    fin = decompose(Y, W, p.r, 0, p.seed_rsm, l=p.l, N=N, flags=base | _lib.FINALIZE_ONLY)
+    fin.info()
+    whole.info()
+    torch.cuda.synchronize()
+    assert torch.equal(torch.tril(N.T), torch.tril(whole.N.T))
+    assert torch.equal(fin.V, whole.V)
+    assert torch.equal(fin.U, whole.U)
