@@ -22,9 +22,10 @@
 //      row and column ranges from two mask words, holds their rows of Q_t in registers (lane
 //      b: columns 64 bi + b and 64 bj + b), forms every pair's -q_i . q_j (+1 on the
 //      diagonal) with one lane per pair and cross-lane reads, and adds it to the block with
-//      LDS atomics.  The
-//      block is then added into N with one global atomic per entry.  Deterministic mode
-//      uses 64-bit fixed point in LDS and in N (integer atomics, order-free).
+//      LDS atomics.  The block is then added into N with one global atomic per entry.
+//      Deterministic mode uses 64-bit fixed point in LDS and in N (integer atomics,
+//      order-free).  A trial is skipped by every pass when it has at most r qualifying
+//      columns (its mask words are then stored empty).
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
@@ -37,7 +38,6 @@ namespace rsm {
 namespace {
 
 constexpr int kMaxK = RSM_MAX_L;
-constexpr int kMaxW = RSM_MAX_N / 64;     // 64-column words per row
 constexpr double kJacobiEpsM2 = 2.220446049250313e-16;  // 2^-52
 constexpr int kJacobiSweepsM2 = 40;
 // An eigenvalue s_a^2 of H_t at or below this fraction of the largest is taken as zero
@@ -47,14 +47,6 @@ constexpr double kRankTolM2 = 1e-13;
 __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ void add_to_N_m2(RSM_GLOBAL double* N, int64_t idx, double v, bool fixed) {
-  if (fixed)
-    atomicAdd((unsigned long long*)&N[idx],
-              static_cast<unsigned long long>(llrint(v * kFixedScale)));
-  else
-    atomic_add_f64((double*)&N[idx], v);
 }
 
 template <typename T>
