@@ -151,33 +151,54 @@ __device__ __forceinline__ void tile_store(double (*S)[kLd], const double (&v)[1
   }
 }
 
-// acc[u][v] += sum_p X[p][4 ty + u] Y[p][4 tx + v]  (tx = t % 16, ty = t / 16): the 64 x 64
-// product X^T Y of two LDS tiles, 4 x 4 outputs per thread.
-__device__ __forceinline__ void mm64(double (&acc)[4][4], const double (*X)[kLd],
-                                     const double (*Y)[kLd]) {
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll 4
-  for (int p = 0; p < NB; ++p) {
-    const double2 x01 = *reinterpret_cast<const double2*>(&X[p][4 * ty]);
-    const double2 x23 = *reinterpret_cast<const double2*>(&X[p][4 * ty + 2]);
-    const double2 y01 = *reinterpret_cast<const double2*>(&Y[p][4 * tx]);
-    const double2 y23 = *reinterpret_cast<const double2*>(&Y[p][4 * tx + 2]);
-    const double xa[4] = {x01.x, x01.y, x23.x, x23.y};
-    const double ya[4] = {y01.x, y01.y, y23.x, y23.y};
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(xa[u], ya[v], acc[u][v]);
-  }
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Output coordinates (row, column of the 64 x 64 tile) of accumulator acc[u][v] of this
+// thread in the layout of the FP64 matrix-core product: wavefront w owns the 32 x 32
+// quadrant at (32 (w / 2), 32 (w % 2)), u is its 16 x 16 sub-tile (2 ti + tj) and v the
+// register: row 16 ti + 4 v + lane / 16, column 16 tj + lane % 16.
+__device__ __forceinline__ int acc_row(int u, int v) {
+  return 32 * (static_cast<int>(threadIdx.x) >> 7) + 16 * (u >> 1) + 4 * v +
+         ((static_cast<int>(threadIdx.x) & 63) >> 4);
+}
+__device__ __forceinline__ int acc_col(int u, int v) {
+  (void)v;
+  return 32 * ((static_cast<int>(threadIdx.x) >> 6) & 1) + 16 * (u & 1) +
+         (static_cast<int>(threadIdx.x) & 15);
 }
 
-// Writes the thread's 4 x 4 outputs as the transposed operand layout S[col][row].
-__device__ __forceinline__ void acc_store_tr(double (*S)[kLd], const double (&acc)[4][4]) {
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+// acc[u][v] += sum_p X[p][acc_row(u, v)] Y[p][acc_col(u, v)]: the 64 x 64 product X^T Y of
+// two LDS tiles on the FP64 matrix cores (v_mfma_f64_16x16x4f64: A(i, k) from lane
+// i + 16 k, B(k, j) from lane j + 16 k, D(i, j) in lane j + 16 (i mod 4), register i / 4).
+__device__ __forceinline__ void mm64(double (&acc)[4][4], const double (*X)[kLd],
+                                     const double (*Y)[kLd]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  f64x4 c[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) c[u] = f64x4{acc[u][0], acc[u][1], acc[u][2], acc[u][3]};
+#pragma unroll 4
+  for (int p0 = 0; p0 < NB; p0 += 4) {
+    const double a0 = X[p0 + g][r0 + j], a1 = X[p0 + g][r0 + 16 + j];
+    const double b0 = Y[p0 + g][c0 + j], b1 = Y[p0 + g][c0 + 16 + j];
+    c[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c[0], 0, 0, 0);
+    c[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c[1], 0, 0, 0);
+    c[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c[2], 0, 0, 0);
+    c[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c[3], 0, 0, 0);
+  }
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) S[4 * tx + v][4 * ty + u] = acc[u][v];
+    for (int v = 0; v < 4; ++v) acc[u][v] = c[u][v];
+}
+
+// Writes the thread's outputs as the transposed operand layout S[col][row].
+__device__ __forceinline__ void acc_store_tr(double (*S)[kLd], const double (&acc)[4][4]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[acc_col(u, v)][acc_row(u, v)] = acc[u][v];
 }
 
 // ------------------------------------------------------------------ diagonal tile
@@ -516,7 +537,6 @@ __global__ __launch_bounds__(256) void k_chol_step(const EigProb* __restrict__ p
   const int ib = static_cast<int>((n - i0) < NB ? (n - i0) : NB);
   const int jb = static_cast<int>((n - j0) < NB ? (n - j0) : NB);
   gdouble __restrict__ Lf = P.Lf;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 
   double vi[16], vj[16], vd[16];
   tile_load<true>(vi, Lf + i0 + k0 * n, n, ib, NB);
@@ -527,7 +547,7 @@ __global__ __launch_bounds__(256) void k_chol_step(const EigProb* __restrict__ p
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int rr = 4 * ty + u, cc = 4 * tx + v;
+      const int rr = acc_row(u, v), cc = acc_col(u, v);
       const bool ok = rr < ib && cc < jb;
       const double x = Lf[(i0 + (ok ? rr : 0)) + (j0 + (ok ? cc : 0)) * n];
       cur[u][v] = ok ? x : 0.0;
@@ -546,7 +566,7 @@ __global__ __launch_bounds__(256) void k_chol_step(const EigProb* __restrict__ p
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) P.M[(i0 + 4 * ty + u) + (k0 + 4 * tx + v) * ld] = li[u][v];
+      for (int v = 0; v < 4; ++v) P.M[(i0 + acc_row(u, v)) + (k0 + acc_col(u, v)) * ld] = li[u][v];
   }
   __syncthreads();
   double upd[4][4] = {};
@@ -556,7 +576,7 @@ __global__ __launch_bounds__(256) void k_chol_step(const EigProb* __restrict__ p
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int rr = 4 * ty + u, cc = 4 * tx + v;
+        const int rr = acc_row(u, v), cc = acc_col(u, v);
         if (rr < ib && cc < jb && (!diag || cc <= rr))
           Lf[(i0 + rr) + (j0 + cc) * n] = cur[u][v] - upd[u][v];
       }
@@ -572,7 +592,7 @@ __global__ __launch_bounds__(256) void k_chol_step(const EigProb* __restrict__ p
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int rr = 4 * ty + u, cc = 4 * tx + v;
+      const int rr = acc_row(u, v), cc = acc_col(u, v);
       As[rr][cc] = (rr < ib && cc < ib) ? cur[u][v] - upd[u][v] + (rr == cc ? mu : 0.0)
                                         : (rr == cc ? 1.0 : 0.0);
     }
@@ -630,13 +650,12 @@ __global__ __launch_bounds__(256) void k_inv_stage1(const EigProb* __restrict__ 
     mm64(acc, S0, S1);
   }
   const int64_t ldt = npad / 2;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int64_t base = (t.pair * bs + t.ti * NB) + (t.tj * NB) * ldt;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      P.T[base + (4 * ty + u) + static_cast<int64_t>(4 * tx + v) * ldt] = acc[u][v];
+      P.T[base + acc_row(u, v) + static_cast<int64_t>(acc_col(u, v)) * ldt] = acc[u][v];
 }
 
 // M[block2, block1] = -B^{-1} T, B^{-1} = M[block2, block2] (lower triangular); the same
@@ -665,13 +684,12 @@ __global__ __launch_bounds__(256) void k_inv_stage2(const EigProb* __restrict__ 
     }
     mm64(acc, S0, S1);
   }
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int64_t rb = t.r2 + t.ti * NB, cb = t.r1 + t.tj * NB;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t rr = rb + 4 * ty + u, cc = cb + 4 * tx + v;
+      const int64_t rr = rb + acc_row(u, v), cc = cb + acc_col(u, v);
       M[rr + cc * npad] = -acc[u][v];
       P.Mt[cc + rr * npad] = -acc[u][v];
     }

@@ -24,8 +24,8 @@
 //      diagonal) with one lane per pair and cross-lane reads, and adds it to the block with
 //      LDS atomics.  The block is then added into N with one global atomic per entry.
 //      Deterministic mode uses 64-bit fixed point in LDS and in N (integer atomics,
-//      order-free).  A trial is skipped by every pass when it has at most r qualifying
-//      columns (its mask words are then stored empty).
+//      order-free).  A trial is skipped by every pass when it has fewer than min_rows
+//      qualifying columns (default r + 1; its mask words are then stored empty).
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
