@@ -126,7 +126,10 @@ enum {
                                     Section IV-A), subsets (drawn or given) are row
                                     indices in [0, m), H_t is formed in FP64 whatever
                                     gram_prec says (RSM_GRAM_BF16X2 and RSM_PLAIN_GRAM are
-                                    RSM_E_UNSUPPORTED), and trial_vecs must be NULL. */
+                                    RSM_E_UNSUPPORTED), and trial_vecs must be NULL.
+                                    The workspace then also holds the row bit-planes,
+                                    a row-major copy of a column-major Y, and I x n x r
+                                    doubles for the rows of every trial's Q_t. */
 };
 
 typedef struct rsm_problem {

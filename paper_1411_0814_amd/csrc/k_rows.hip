@@ -9,9 +9,10 @@
 //      is the AND of the k row words; lane b owns column 64 w + b, loads its k entries
 //      (a coalesced read of 64 consecutive entries of each chosen row), and the k x k Gram
 //      H_t = Z_t Z_t^T is summed in FP64 over the words, one entry per lane.
-//  a4  k_m2_eig: one thread per trial, cyclic Jacobi (FP64) on H_t = U diag(s^2) U^T; the
-//      r largest eigenpairs give B_t = [u_a / s_a] (k x r), so that the leading right
-//      singular vectors of Z_t are Q_t = Z_t^T B_t.
+//  a4  k_m2_eig_reg (k <= 11) / k_m2_eig: one thread per trial, cyclic Jacobi (FP64) on
+//      H_t = U diag(s^2) U^T (packed in registers, or in LDS for larger k); the r largest
+//      eigenpairs give B_t = [u_a / s_a] (k x r), so that the leading right singular
+//      vectors of Z_t are Q_t = Z_t^T B_t.
 //  a5  N[C_t, C_t] += I - Q_t Q_t^T (lower triangle) in two passes:
 //      k_m2_qform: one wavefront per trial; lane b of word w computes row 64 w + b of Q_t,
 //      q = B_t^T z (z: the column's k chosen entries), into a dense trial x column x r
@@ -159,26 +160,40 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_m2_gram(const ProbDesc* __r
     eb[s] = e - a * (a + 1) / 2;
   }
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int w = 0; w < nw; ++w) {
-    const uint64_t word = __shfl(myword, w);
-    if (word == 0) continue;
+  // this lane's entries of the k chosen rows at column 64 w + ln (zero if not qualifying);
+  // the next word's are loaded while the current one is summed
+  auto load_z = [&](int w, double* z) {
+    const uint64_t word = w < nw ? __shfl(myword, w) : 0ull;
     const bool mine = (word >> ln) & 1ull;
     const int64_t col = static_cast<int64_t>(w) * 64 + ln;
 #pragma unroll
     for (int i = 0; i < kMaxK; ++i)
-      if (i < k) zs[wv][i][ln] = mine ? ld_y(y, static_cast<int64_t>(S[i]) * ldyr + col) : 0.0;
-    wave_fence();
+      z[i] = (mine && i < k) ? ld_y(y, static_cast<int64_t>(S[i]) * ldyr + col) : 0.0;
+  };
+  double zc[kMaxK], zn[kMaxK];
+  load_z(0, zc);
+  for (int w = 0; w < nw; ++w) {
+    load_z(w + 1, zn);
+    const uint64_t word = __shfl(myword, w);
+    if (word != 0) {
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      if (ln + 64 * s < ng) {
-        const double* za = zs[wv][ea[s]];
-        const double* zb = zs[wv][eb[s]];
-        double part = 0.0;
-        for (int p = 0; p < 64; ++p) part = fma(za[p], zb[p], part);
-        acc[s] += part;
+      for (int i = 0; i < kMaxK; ++i)
+        if (i < k) zs[wv][i][ln] = zc[i];
+      wave_fence();
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        if (ln + 64 * s < ng) {
+          const double* za = zs[wv][ea[s]];
+          const double* zb = zs[wv][eb[s]];
+          double part = 0.0;
+          for (int p = 0; p < 64; ++p) part = fma(za[p], zb[p], part);
+          acc[s] += part;
+        }
       }
+      wave_fence();
     }
-    wave_fence();
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i) zc[i] = zn[i];
   }
 #pragma unroll
   for (int s = 0; s < 3; ++s)
@@ -318,6 +333,129 @@ __global__ __launch_bounds__(eig_tpb<K>()) void k_m2_eig(const ProbDesc* __restr
   }
 }
 
+// The same for k <= 11 with H_t packed in registers (static indices throughout) and the
+// rotations in LDS: 64 trials per workgroup.
+template <int K>
+__global__ __launch_bounds__(64) void k_m2_eig_reg(const ProbDesc* __restrict__ probs,
+                                                   IdxList list) {
+  constexpr int TPB = 64;
+  constexpr int NG = K * (K + 1) / 2;
+  __shared__ double Vs[K * K * TPB];
+  __shared__ unsigned long long s_acc, s_cols;
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_acc = 0;
+    s_cols = 0;
+  }
+  __syncthreads();
+  const int64_t I = P.I;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * TPB + tid;
+  const bool active = t < I;
+  const int r = P.r;
+  double h[NG];
+  auto A = [&](int i, int j) -> double& { return i >= j ? h[i * (i + 1) / 2 + j] : h[j * (j + 1) / 2 + i]; };
+  auto v = [&](int i, int j) -> double& { return Vs[(i * K + j) * TPB + tid]; };
+  int cnt = 0;
+  bool valid = false;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) h[g] = active ? P.G[static_cast<int64_t>(g) * I + t] : 0.0;
+  if (active) {
+    cnt = P.rows[t];
+    valid = P.cols[t * K] >= 0;
+    if (P.tap_rows) P.tap_rows[t] = cnt;
+    if (P.tap_gram)
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = 0; j < K; ++j) P.tap_gram[(t * K + i) * K + j] = A(i, j);
+  }
+  const bool accept = active && valid && cnt >= P.min_rows;
+  if (accept) {
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+      for (int j = 0; j < K; ++j) v(i, j) = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < kJacobiSweepsM2; ++sweep) {
+      bool rotated = false;
+#pragma unroll
+      for (int p = 0; p < K - 1; ++p) {
+#pragma unroll
+        for (int q = p + 1; q < K; ++q) {
+          const double apq = A(q, p);
+          const double app = A(p, p);
+          const double aqq = A(q, q);
+          if (fabs(apq) > kJacobiEpsM2 * sqrt(fabs(app * aqq))) {
+            rotated = true;
+            const double d = aqq - app;
+            const double e2 = 2.0 * apq;
+            const double den = fabs(d) + sqrt(d * d + e2 * e2);
+            const double tr = (d >= 0.0 ? e2 : -e2) / den;
+            const double cr = rsqrt(1.0 + tr * tr);
+            const double sr = tr * cr;
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) {
+              if (kk == p || kk == q) continue;
+              const double akp = A(kk, p);
+              const double akq = A(kk, q);
+              A(kk, p) = cr * akp - sr * akq;
+              A(kk, q) = sr * akp + cr * akq;
+            }
+            A(p, p) = app - tr * apq;
+            A(q, q) = aqq + tr * apq;
+            A(q, p) = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) {
+              const double vkp = v(kk, p);
+              const double vkq = v(kk, q);
+              v(kk, p) = cr * vkp - sr * vkq;
+              v(kk, q) = sr * vkp + cr * vkq;
+            }
+          }
+        }
+      }
+      if (!rotated) break;
+    }
+    int rank[K];
+    double dmax = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      const double dk = A(kk, kk);
+      dmax = fmax(dmax, dk);
+      int rk = 0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const double dj = A(j, j);
+        rk += (dj < dk) || (dj == dk && j < kk);
+      }
+      rank[kk] = rk;
+    }
+    if (P.tap_eigs)
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) P.tap_eigs[t * K + rank[kk]] = A(kk, kk);
+    RSM_GLOBAL double* B = P.Bm + t * K * r;
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      const int a = K - 1 - rank[kk];
+      if (a < r) {
+        const double dk = A(kk, kk);
+        const double inv = (dk > kRankTolM2 * dmax && dk > 0.0) ? rsqrt(dk) : 0.0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) B[i * r + a] = v(i, kk) * inv;
+      }
+    }
+  } else if (active && P.tap_eigs) {
+    for (int kk = 0; kk < K; ++kk) P.tap_eigs[t * K + kk] = 0.0;
+  }
+  if (accept) atomicAdd(&s_acc, 1ull);
+  if (active) atomicAdd(&s_cols, static_cast<unsigned long long>(cnt));
+  __syncthreads();
+  if (tid == 0) {
+    atomicAdd((unsigned long long*)&P.info->accepted, s_acc);
+    atomicAdd((unsigned long long*)&P.info->rows_total, s_cols);
+  }
+}
+
 // ------------------------------------------------------------------ a5
 
 // Grid (ceil(I / 4), problems); one wavefront per accepted trial.
@@ -339,24 +477,36 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_m2_qform(const ProbDesc* __
   for (int e = ln; e < k * r; e += 64) sB[wv][e] = P.Bm[t * k * r + e];
   wave_fence();
   const uint64_t myword = ln < nw ? P.cmask[t * nw + ln] : 0ull;
-  for (int w = 0; w < nw; ++w) {
-    const uint64_t word = __shfl(myword, w);
-    if (!((word >> ln) & 1ull)) continue;
+  // the next word's entries load while the current one's Q rows are formed
+  auto load_z = [&](int w, double* z) {
+    const uint64_t word = w < nw ? __shfl(myword, w) : 0ull;
+    const bool mine = (word >> ln) & 1ull;
     const int64_t col = static_cast<int64_t>(w) * 64 + ln;
-    double z[kMaxK];
 #pragma unroll
-    for (int i = 0; i < kMaxK; ++i) z[i] = i < k ? ld_y(y, static_cast<int64_t>(S[i]) * ldyr + col) : 0.0;
-    RSM_GLOBAL double* q = P.Qd + (t * n + col) * r;
+    for (int i = 0; i < kMaxK; ++i)
+      z[i] = (mine && i < k) ? ld_y(y, static_cast<int64_t>(S[i]) * ldyr + col) : 0.0;
+  };
+  double z[kMaxK], zn[kMaxK];
+  load_z(0, z);
+  for (int w = 0; w < nw; ++w) {
+    load_z(w + 1, zn);
+    const uint64_t word = __shfl(myword, w);
+    const int64_t col = static_cast<int64_t>(w) * 64 + ln;
+    if ((word >> ln) & 1ull) {
+      RSM_GLOBAL double* q = P.Qd + (t * n + col) * r;
 #pragma unroll
-    for (int a = 0; a < RSM_MAX_R; ++a) {
-      if (a < r) {
-        double s = 0.0;
+      for (int a = 0; a < RSM_MAX_R; ++a) {
+        if (a < r) {
+          double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < kMaxK; ++i)
-          if (i < k) s = fma(z[i], sB[wv][i * r + a], s);
-        q[a] = s;
+          for (int i = 0; i < kMaxK; ++i)
+            if (i < k) s = fma(z[i], sB[wv][i * r + a], s);
+          q[a] = s;
+        }
       }
     }
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i) z[i] = zn[i];
   }
 }
 
@@ -492,8 +642,12 @@ void tiles_dispatch(bool fixed, int r, dim3 grid, const ProbDesc* d, const IdxLi
 
 template <int K>
 void run_eig(const ProbDesc* d, const IdxList& g, int64_t I, hipStream_t s) {
-  constexpr int TPB = eig_tpb<K>();
-  k_m2_eig<K><<<dim3(static_cast<unsigned>(ceil_div(I, TPB)), g.count), TPB, 0, s>>>(d, g);
+  if constexpr (K <= 11) {
+    k_m2_eig_reg<K><<<dim3(static_cast<unsigned>(ceil_div(I, 64)), g.count), 64, 0, s>>>(d, g);
+  } else {
+    constexpr int TPB = eig_tpb<K>();
+    k_m2_eig<K><<<dim3(static_cast<unsigned>(ceil_div(I, TPB)), g.count), TPB, 0, s>>>(d, g);
+  }
 }
 
 template <int K>

@@ -79,6 +79,19 @@ def test_rows_first_parity(m, n, r, k, rho, noise, dt, rm, trials):
     print(f"rows first m={m} n={n} r={r} k={k}: theta={theta:.3e} rms={rms:.3e}")
 
 
+def test_rows_first_maximum_sizes():
+    """n = 2048, r = 16, k = 17 rows per trial (the LDS-resident k x k eigen-solve)."""
+    import torch
+    p = synth.paper_synthetic(3000, 2048, 16, 0.8, 0.01, 62, num_submatrices=2000, l=17,
+                              seed_rsm=5)
+    N = torch.zeros((p.n, p.n), dtype=torch.float64, device="cuda")
+    res, info = _run(p, taps=True, N=N)
+    ora = rsm.rsm(p.Y, p.W, p.r, p.num_submatrices, seed=p.seed_rsm, l=17, rows_first=True,
+                  with_e=False)
+    theta, rms = _compare(p, res, info, ora, theta_tol=1e-4, rms_tol=1e-5, n_gram=40)
+    print(f"rows first maximum sizes: theta={theta:.3e} rms={rms:.3e}")
+
+
 def test_rows_first_noise_free_exact_recovery():
     p = synth.paper_synthetic(1500, 120, 4, 0.85, 0.0, 51, num_submatrices=800, l=5)
     res, info = _run(p)
