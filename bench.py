@@ -48,6 +48,8 @@ def parse():
                     help="problems of the batch checked against the oracle")
     ap.add_argument("--no-batched", action="store_true",
                     help="omit the batched / served summaries from the default line")
+    ap.add_argument("--no-rows-first", action="store_true",
+                    help="omit the rows-first (method M2) summary from the default line")
     ap.add_argument("--plain-gram", action="store_true",
                     help="per-trial column-streaming Gram kernel instead of the tiled one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -204,6 +206,36 @@ def cpu_baseline(p, n_trials, n_rows):
                    f"one n x n eigh; scaled to one decomposition ({est:.1f} s estimated)"),
         "measured_s": round(t_trials + t_eig + t_u, 2),
     }
+
+
+def run_rows_first(args, torch, p, Y, W, stream, steps=10, warmup=2):
+    """The same resident problem sampled rows first (method M2, k = l rows per trial):
+    decompositions/s over `steps` back-to-back calls and parity against the oracle."""
+    from paper_1411_0814_amd import _lib, decompose
+    kw = dict(l=p.l, gram=p.gram, flags=_lib.ROWS_FIRST, stream=stream)
+    for _ in range(warmup):
+        res = decompose(Y, W, p.r, p.num_submatrices, p.seed_rsm, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = decompose(Y, W, p.r, p.num_submatrices, p.seed_rsm, **kw)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    info = res.info()
+    out = {"decompositions_per_s": round(steps / elapsed, 3),
+           "ms_per_decomposition": round(elapsed / steps * 1e3, 4),
+           "k_rows_per_trial": p.l, "mean_qualifying_columns": info["rows_total"] / max(1, p.num_submatrices)}
+    if not args.no_parity:
+        p.rows_first = True
+        try:
+            workers = min(16, os.cpu_count() or 4)
+            theta, rms, t_or = oracle_parity(p, res.V.cpu().numpy(), res.U.cpu().numpy(),
+                                             args.cpu_sample_rows, workers)
+        finally:
+            p.rows_first = False
+        out["parity"] = {"theta_max_rad": theta, "rel_rms_known": rms,
+                         "pass": bool(theta <= 1e-4 and rms <= 1e-5)}
+    return out
 
 
 def _batch_setup(args, torch):
@@ -638,6 +670,9 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample_trials, args.cpu_sample_u_rows)
         progress("cpu baseline done")
+    if not args.no_rows_first and args.workload == "paper_scale":
+        out["rows_first"] = run_rows_first(args, torch, p, Y, W, stream)
+        progress("rows-first summary done")
     if not args.no_batched and args.workload == "paper_scale":
         del Y, W, ws, results, res, last
         torch.cuda.empty_cache()
