@@ -258,20 +258,33 @@ __global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ prob
 #pragma unroll
     for (int q = 0; q < T; ++q) acc[t][q] = f64x4{0.0, 0.0, 0.0, 0.0};
   int cnt[kUfTiles] = {};
-  for (int64_t c0 = 0; c0 < n; c0 += kUfCols) {
-    // this stage's A operands: mask words and Y values of (row ic[t], column c0 + 4 ks + lk)
-    uint32_t wreg[kUfCols / 4][kUfTiles];
-    TY yreg[kUfCols / 4][kUfTiles];
+  // (a, b) of the packed A entry in each column slot q of a staged row, once per workgroup
+  __shared__ int8_t pa[T * 16], pb[T * 16];
+  for (int q = tid; q < T * 16; q += 256) {
+    int a = -1, b = -1;
+    if (q < NA) unpack_pair(q, a, b);
+    pa[q] = static_cast<int8_t>(a);
+    pb[q] = static_cast<int8_t>(b);
+  }
+  // A operands of a stage: mask words and Y values of (row ic[t], column c0 + 4 ks + lk);
+  // the next stage's are loaded while the current one runs on the matrix cores
+  uint32_t wreg[kUfCols / 4][kUfTiles], wnext[kUfCols / 4][kUfTiles];
+  TY yreg[kUfCols / 4][kUfTiles], ynext[kUfCols / 4][kUfTiles];
+  auto load_stage = [&](int64_t cs, uint32_t (&wr)[kUfCols / 4][kUfTiles],
+                        TY (&yr)[kUfCols / 4][kUfTiles]) {
 #pragma unroll
     for (int ks = 0; ks < kUfCols / 4; ++ks) {
-      const int64_t j = c0 + 4 * ks + lk;
+      const int64_t j = cs + 4 * ks + lk;
       const int64_t jc = j < n ? j : n - 1;
 #pragma unroll
       for (int t = 0; t < kUfTiles; ++t) {
-        wreg[ks][t] = wbits[jc * mw32 + (ic[t] >> 5)];
-        yreg[ks][t] = Y[jc * ldy + ic[t]];
+        wr[ks][t] = wbits[jc * mw32 + (ic[t] >> 5)];
+        yr[ks][t] = Y[jc * ldy + ic[t]];
       }
     }
+  };
+  load_stage(0, wreg, yreg);
+  for (int64_t c0 = 0; c0 < n; c0 += kUfCols) {
     __syncthreads();  // the previous stage's B operands are consumed
     for (int e = tid; e < kUfCols * R; e += 256) {
       const int c = e / R, a = e - c * R;
@@ -283,15 +296,14 @@ __global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ prob
       const int c = e / (T * 16), q = e - c * (T * 16);
       double val = 0.0;
       if (q < NA) {
-        int a, b;
-        unpack_pair(q, a, b);
-        val = Vc[c * R + a] * Vc[c * R + b];
+        val = Vc[c * R + pa[q]] * Vc[c * R + pb[q]];
       } else if (q >= TA * 16 && q - TA * 16 < R) {
         val = Vc[c * R + (q - TA * 16)];
       }
       Kc[c * LD + q] = val;
     }
     __syncthreads();
+    if (c0 + kUfCols < n) load_stage(c0 + kUfCols, wnext, ynext);
 #pragma unroll
     for (int ks = 0; ks < kUfCols / 4; ++ks) {
       const bool jok = c0 + 4 * ks + lk < n;
@@ -312,6 +324,13 @@ __global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ prob
           acc[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(q < TA ? aw[t] : awy[t], b, acc[t][q], 0, 0, 0);
       }
     }
+#pragma unroll
+    for (int ks = 0; ks < kUfCols / 4; ++ks)
+#pragma unroll
+      for (int t = 0; t < kUfTiles; ++t) {
+        wreg[ks][t] = wnext[ks][t];
+        yreg[ks][t] = ynext[ks][t];
+      }
   }
   // D(i, e) of tile (t, q): row i = 4 v + lk of the tile (register v), column e = 16 q + li
   RSM_GLOBAL double* __restrict__ ab = P.ab;
