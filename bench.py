@@ -137,11 +137,11 @@ def _oracle_chunk(args):
     lo, hi = args
     p = _G["p"]
     with threadpool_limits(limits=1):   # one BLAS thread per worker process
-        return _oracle_chunk_body(p, lo, hi, rsm)
+        return _oracle_chunk_body(p, lo, hi, rsm, _G["rows_first"])
 
 
-def _oracle_chunk_body(p, lo, hi, rsm):
-    if _rows_first(p):
+def _oracle_chunk_body(p, lo, hi, rsm, rows_first):
+    if rows_first:
         return rsm.accumulate_N_rows_first(p.Y, p.W, _G["subsets"][lo:hi], p.r, p.r + 1)[0]
     return rsm.accumulate_N(p.Y, p.W, _G["subsets"][lo:hi], p.r, p.l - p.r, p.r)[0]
 
@@ -149,15 +149,16 @@ def _oracle_chunk_body(p, lo, hi, rsm):
 _G = {}
 
 
-def oracle_parity(p, V_gpu, U_gpu, sample_rows, workers):
+def oracle_parity(p, V_gpu, U_gpu, sample_rows, workers, rows_first=None):
     """theta_max of V-hat and rel RMS of U V^T (sampled rows) against the FP64 oracle.
-    V_gpu / U_gpu may be lists (several GPU results of the same problem)."""
+    V_gpu / U_gpu may be lists (several GPU results of the same problem).  rows_first:
+    sampling M2 (default: the workload's own)."""
     import multiprocessing as mp
 
     from oracle import metrics, rng, rsm
-    subsets = rng.draw_subsets(p.seed_rsm, p.m if _rows_first(p) else p.n, p.l,
-                               p.num_submatrices)
-    _G.update(p=p, subsets=subsets)
+    rows_first = _rows_first(p) if rows_first is None else rows_first
+    subsets = rng.draw_subsets(p.seed_rsm, p.m if rows_first else p.n, p.l, p.num_submatrices)
+    _G.update(p=p, subsets=subsets, rows_first=rows_first)
     t0 = time.perf_counter()
     chunks = np.array_split(np.arange(p.num_submatrices), workers * 4)
     ranges = [(int(c[0]), int(c[-1]) + 1) for c in chunks if len(c)]
@@ -226,13 +227,9 @@ def run_rows_first(args, torch, p, Y, W, stream, steps=10, warmup=2):
            "ms_per_decomposition": round(elapsed / steps * 1e3, 4),
            "k_rows_per_trial": p.l, "mean_qualifying_columns": info["rows_total"] / max(1, p.num_submatrices)}
     if not args.no_parity:
-        p.rows_first = True
-        try:
-            workers = min(16, os.cpu_count() or 4)
-            theta, rms, t_or = oracle_parity(p, res.V.cpu().numpy(), res.U.cpu().numpy(),
-                                             args.cpu_sample_rows, workers)
-        finally:
-            p.rows_first = False
+        workers = min(16, os.cpu_count() or 4)
+        theta, rms, _ = oracle_parity(p, res.V.cpu().numpy(), res.U.cpu().numpy(),
+                                      args.cpu_sample_rows, workers, rows_first=True)
         out["parity"] = {"theta_max_rad": theta, "rel_rms_known": rms,
                          "pass": bool(theta <= 1e-4 and rms <= 1e-5)}
     return out
