@@ -27,6 +27,14 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
   return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
+// 8 bytes -> 8 bits: bit k set iff byte k is nonzero.
+__device__ __forceinline__ uint32_t nonzero_bytes_to_bits(uint64_t x) {
+  const uint64_t lo7 = 0x7F7F7F7F7F7F7F7Full;
+  uint64_t t = ((x & lo7) + lo7) | x;          // high bit of each byte = (byte != 0)
+  t = (t >> 7) & 0x0101010101010101ull;        // one bit per byte, at bit 8k
+  return static_cast<uint32_t>((t * 0x0102040810204080ull) >> 56);  // gather to bits 0..7
+}
+
 // ---------------------------------------------------------------- subset generator
 // Philox4x64 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11): per round the counter
 // words 0 and 2 are multiplied (64 x 64 -> 128 bits) by two fixed odd constants and the

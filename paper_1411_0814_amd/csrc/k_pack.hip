@@ -13,14 +13,6 @@ namespace rsm {
 
 namespace {
 
-// 8 bytes -> 8 bits: bit k set iff byte k is nonzero.
-__device__ __forceinline__ uint32_t nonzero_bytes_to_bits(uint64_t x) {
-  const uint64_t lo7 = 0x7F7F7F7F7F7F7F7Full;
-  uint64_t t = ((x & lo7) + lo7) | x;          // high bit of each byte = (byte != 0)
-  t = (t >> 7) & 0x0101010101010101ull;        // one bit per byte, at bit 8k
-  return static_cast<uint32_t>((t * 0x0102040810204080ull) >> 56);  // gather to bits 0..7
-}
-
 // Column-major W: one thread per (column, 64-row word) of problem list.idx[blockIdx.y].
 __global__ void k_pack_mask_colmajor(const ProbDesc* __restrict__ probs, IdxList list) {
   const ProbDesc& P = probs[list.idx[blockIdx.y]];

@@ -57,36 +57,40 @@ __device__ __forceinline__ double ld_y(RSM_GLOBAL const T* y, int64_t idx) {
 
 // ------------------------------------------------------------------ a0
 
-// Row bit-planes from W in either storage order: a 64 x 64 byte tile through LDS (loads
-// coalesced along the storage order), one thread per output word.
-// Grid (64-row tiles, 64-column words, problems).
+// Row bit-planes from W in either storage order: a 64-row x 256-column byte tile through
+// LDS (loads coalesced along the storage order, 8-byte aligned rows), then each thread packs
+// one 64-column word of one row, 8 bytes at a time.
+// Grid (64-row tiles, 256-column tiles, problems).
+constexpr int kRbCols = 256;
+constexpr int kRbStride = kRbCols + 8;
+
 __global__ __launch_bounds__(256) void k_pack_rowbits(const ProbDesc* __restrict__ probs,
                                                       IdxList list) {
-  __shared__ uint8_t tile[64][65];
+  __shared__ __align__(8) uint8_t tile[64][kRbStride];
   const ProbDesc& P = probs[list.idx[blockIdx.z]];
   const int64_t m = P.m, n = P.n;
   const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 64;
-  const int64_t w = blockIdx.y;
-  const int64_t j0 = w * 64;
+  const int64_t j0 = static_cast<int64_t>(blockIdx.y) * kRbCols;
   if (i0 >= m || j0 >= n) return;
   const bool rowmajor = P.w_layout == RSM_ROW_MAJOR;
-  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+  for (int e = threadIdx.x; e < 64 * kRbCols; e += blockDim.x) {
     // row-major: consecutive threads take consecutive columns; column-major: rows
-    const int rr = rowmajor ? e / 64 : e % 64;
-    const int cc = rowmajor ? e % 64 : e / 64;
+    const int rr = rowmajor ? e / kRbCols : e % 64;
+    const int cc = rowmajor ? e % kRbCols : e / 64;
     const int64_t i = i0 + rr, j = j0 + cc;
     uint8_t v = 0;
-    if (i < m && j < n) v = (rowmajor ? P.W[i * P.ldw + j] : P.W[i + j * P.ldw]) != 0;
+    if (i < m && j < n) v = rowmajor ? P.W[i * P.ldw + j] : P.W[i + j * P.ldw];
     tile[rr][cc] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 64) {
-    const int64_t i = i0 + threadIdx.x;
-    if (i < m) {
-      uint64_t word = 0;
-      for (int cc = 0; cc < 64; ++cc) word |= static_cast<uint64_t>(tile[threadIdx.x][cc]) << cc;
-      P.rbits[i * P.nw + w] = word;
-    }
+  const int rr = threadIdx.x / 4, wd = threadIdx.x % 4;
+  const int64_t i = i0 + rr, w = j0 / 64 + wd;
+  if (i < m && w < P.nw) {
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(&tile[rr][64 * wd]);
+    uint64_t word = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) word |= static_cast<uint64_t>(nonzero_bytes_to_bits(src[b])) << (8 * b);
+    P.rbits[i * P.nw + w] = word;
   }
 }
 
@@ -666,12 +670,12 @@ void launch_rows_pack(const ProbDesc* d, const IdxList& g, const Plan* const* h,
   const Plan* hs[kLaunchMax];
   const IdxList rf = pick(g, h, [](const Plan& P) { return P.rows_first; }, hs);
   if (!rf.count) return;
-  int64_t mt = 0, nwm = 0;
+  int64_t mt = 0, ct = 0;
   for (int k = 0; k < rf.count; ++k) {
     mt = std::max<int64_t>(mt, ceil_div(hs[k]->m, 64));
-    nwm = std::max<int64_t>(nwm, hs[k]->nw);
+    ct = std::max<int64_t>(ct, ceil_div(hs[k]->n, kRbCols));
   }
-  k_pack_rowbits<<<dim3(static_cast<unsigned>(mt), static_cast<unsigned>(nwm), rf.count), 256, 0, s>>>(d, rf);
+  k_pack_rowbits<<<dim3(static_cast<unsigned>(mt), static_cast<unsigned>(ct), rf.count), 256, 0, s>>>(d, rf);
   for (int dt = RSM_F32; dt <= RSM_F64; ++dt) {
     const IdxList yc = pick(g, h, [dt](const Plan& P) {
       return P.rows_first && P.y_layout == RSM_COL_MAJOR && P.y_dtype == dt; }, hs);
