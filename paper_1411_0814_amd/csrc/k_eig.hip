@@ -276,50 +276,50 @@ __device__ __forceinline__ void fb_diag(double (*As)[kTr], FactorWork& W, double
 }
 
 // All threads: panel L_rk = A_rk D_k^T for the rows below block KB, then the trailing update
-// A_rc -= L_rk L_ck^T (lower part).  Thread (tr, tc) = (t / 16, t % 16) owns rows tr + 16u
-// and columns tc + 16v of the trailing part.
+// A_rc -= L_rk L_ck^T (lower part), on the FP64 matrix cores one 16 x 16 output tile per
+// wavefront at a time.  A panel tile is read and written by the wavefront that owns it, so
+// only the trailing update waits for the whole panel.
 template <int KB>
 __device__ __forceinline__ void fb_panel_update(double (*As)[kTr], FactorWork& W) {
   constexpr int k0 = KB * kFB;
   constexpr int B = (NB - k0 - kFB) / kFB;
   if constexpr (B > 0) {
-    const int t = threadIdx.x, tc = t & 15, tr = t >> 4;
     constexpr int r0 = k0 + kFB;
-    double l[B];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    // panel: tile u = rows r0 + 16 u .. of L_rk; A(i, k) = A_rk[16 u + i][4 s + k],
+    // B(k, j) = D_k[j][4 s + k]
+    for (int u = w; u < B; u += 4) {
+      f64x4 c = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int u = 0; u < B; ++u) {
-      double s = 0.0;
-#pragma unroll
-      for (int p = 0; p < kFB; ++p) s = fma(As[r0 + tr + 16 * u][k0 + p], W.D[KB][tc][p], s);
-      l[u] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < B; ++u) As[r0 + tr + 16 * u][k0 + tc] = l[u];
-    __syncthreads();
-    double acc[B][B];
-#pragma unroll
-    for (int u = 0; u < B; ++u)
-#pragma unroll
-      for (int v = 0; v < B; ++v) acc[u][v] = 0.0;
-#pragma unroll
-    for (int p = 0; p < kFB; ++p) {
-      double lr[B], lc[B];
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        lr[u] = As[r0 + tr + 16 * u][k0 + p];
-        lc[u] = As[r0 + tc + 16 * u][k0 + p];
+      for (int s4 = 0; s4 < kFB; s4 += 4) {
+        const double a = As[r0 + 16 * u + li][k0 + s4 + lk];
+        const double bb = W.D[KB][li][s4 + lk];
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, c, 0, 0, 0);
       }
 #pragma unroll
-      for (int u = 0; u < B; ++u)
-#pragma unroll
-        for (int v = 0; v < B; ++v) acc[u][v] = fma(lr[u], lc[v], acc[u][v]);
+      for (int v = 0; v < 4; ++v) As[r0 + 16 * u + 4 * v + lk][k0 + li] = c[v];
     }
+    __syncthreads();
+    // trailing tiles (u, v), v <= u: A(i, k) = L[16 u + i][4 s + k], B(k, j) = L[16 v + j][4 s + k]
+    constexpr int NT = B * (B + 1) / 2;
+    for (int tl = w; tl < NT; tl += 4) {
+      int u = 0;
+      while ((u + 1) * (u + 2) / 2 <= tl) ++u;
+      const int v = tl - u * (u + 1) / 2;
+      f64x4 c = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int u = 0; u < B; ++u)
+      for (int s4 = 0; s4 < kFB; s4 += 4) {
+        const double a = As[r0 + 16 * u + li][k0 + s4 + lk];
+        const double bb = As[r0 + 16 * v + li][k0 + s4 + lk];
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, c, 0, 0, 0);
+      }
 #pragma unroll
-      for (int v = 0; v < B; ++v)
-        if (tc + 16 * v <= tr + 16 * u) As[r0 + tr + 16 * u][r0 + tc + 16 * v] -= acc[u][v];
+      for (int q = 0; q < 4; ++q) {
+        const int i = 4 * q + lk, j = li;
+        if (u != v || j <= i) As[r0 + 16 * u + i][r0 + 16 * v + j] -= c[q];
+      }
+    }
     __syncthreads();
   }
 }
