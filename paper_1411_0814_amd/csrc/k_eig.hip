@@ -12,7 +12,8 @@
 //      per tile step: each workgroup of the step solves the two panel tiles it needs with
 //      the inverse of the diagonal tile, updates its trailing tile, and the workgroup that
 //      owns the next diagonal tile factors it at once (look-ahead).  Factoring a diagonal
-//      tile also forms its inverse, which becomes the diagonal tile of M = L^{-1}.
+//      tile also forms its inverse, which becomes the diagonal tile of M = L^{-1}.  The
+//      64 x 64 tile products run on the FP64 matrix cores.
 //   3. M = L^{-1} by recursive doubling over the tile structure:
 //      [A 0; C B]^{-1} = [A^{-1} 0; -B^{-1} C A^{-1}  B^{-1}], log2(tiles) levels of
 //      products (the matrix is padded to a power-of-two number of tiles with identity).
@@ -205,8 +206,9 @@ __device__ __forceinline__ void acc_store_tr(double (*S)[kLd], const double (&ac
 
 // The 64 x 64 diagonal tile is factored and inverted by the 256 threads of a workgroup in
 // 16 x 16 blocks: right-looking block Cholesky (the 16 x 16 diagonal blocks by one
-// wavefront, the panel and trailing update by all threads), then L^{-1} block row by block
-// row: X_ii = L_ii^{-1}, X_ik = -X_ii sum_{p=k}^{i-1} L_ip X_pk.
+// wavefront in registers, the panel and trailing update by all four wavefronts on the
+// matrix cores), then L^{-1} block row by block row: X_ii = L_ii^{-1},
+// X_ik = -X_ii sum_{p=k}^{i-1} L_ip X_pk.
 constexpr int kFB = 16;        // block of the in-tile factorisation
 constexpr int kFBs = kFB + 1;  // its LDS row stride
 constexpr int kNFB = NB / kFB;
