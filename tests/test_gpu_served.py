@@ -58,3 +58,29 @@ def test_plain_fifo_serves_one_at_a_time():
     assert stats["mean_batch"] == 1.0
     starts = sorted(j.start for j in jobs)
     assert starts == [j.start for j in sorted(jobs, key=lambda j: j.arrival)]
+
+
+def test_served_mix_of_column_and_row_sampling_bitwise_alone():
+    """Rows-first (method M2) and column-first requests served together in deterministic
+    mode: every result is bit for bit the one computed alone."""
+    import torch
+    from paper_1411_0814_amd import _lib, decompose, serve
+    pool = _pool()
+    det = _lib.DETERMINISTIC
+    pool[0].flags = det | _lib.ROWS_FIRST
+    pool[1].flags = det
+    pool[2].flags = det | _lib.ROWS_FIRST
+    pool[3].flags = det
+    jobs = serve.poisson_trace(len(pool), qps=2000.0, seconds=0.02, seed=5)
+    srv = serve.Server(pool, batching=True, max_inflight=2, keep_results=True)
+    stats = srv.run(jobs)
+    torch.cuda.synchronize()
+    assert stats["completed"] == len(jobs) and stats["batches"] < len(jobs)
+    assert {pool[j.item].flags for j in jobs} == {det, det | _lib.ROWS_FIRST}
+    for j in jobs:
+        it = pool[j.item]
+        alone = decompose(it.Y, it.W, it.r, it.num_submatrices, j.seed, l=it.l,
+                          flags=it.flags)
+        torch.cuda.synchronize()
+        assert torch.equal(alone.V, j.result.V)
+        assert torch.equal(alone.U, j.result.U)
