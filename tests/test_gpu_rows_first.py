@@ -195,3 +195,16 @@ def test_rows_first_split_run_equals_whole_bitwise():
     assert torch.equal(torch.tril(N.T), torch.tril(whole.N.T))
     assert torch.equal(fin.V, whole.V)
     assert torch.equal(fin.U, whole.U)
+
+
+def test_rows_first_error_e_matches_oracle():
+    """eq.(ep) on the rows-first result (the optional error pass shared with M1)."""
+    from paper_1411_0814_amd import _lib
+    p = synth.paper_synthetic(2000, 120, 4, 0.85, 0.02, 57, num_submatrices=500, l=5)
+    res, info = _run(p, flags=_lib.COMPUTE_ERROR)
+    ora = rsm.rsm(p.Y, p.W, p.r, p.num_submatrices, seed=p.seed_rsm, l=5, rows_first=True)
+    # the GPU's V-hat differs from the oracle's by ~1e-7 rad here (H_t route, FP64), which
+    # moves e by ~1e-8 relative
+    assert abs(info["e"] - ora.e) <= 1e-6 * ora.e
+    # and close to the noise level of the data
+    assert 0.5 * p.sigma < info["e"] < 2.0 * p.sigma
