@@ -441,13 +441,15 @@ __global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ pr
 // of one trial (l <= 16 columns padded to 16): lane (i, g) = (lane % 16, lane / 16) holds
 // rows 8 g .. 8 g + 7 of column i, which is both its A (Z^T) and its B (Z) operand; row i
 // of the 16 x 16 result sits in lanes 16 (i / 4) + j, register i % 4.  Rows that do not
-// qualify enter as zeros.  A wavefront owns 16 trials (64 accumulator registers; the
-// staging registers need the rest), so a workgroup of 8 wavefronts covers 128 trials.
+// qualify enter as zeros.  A wavefront owns 8 trials (32 accumulator registers), so a
+// workgroup of 8 wavefronts covers 64 trials: with 16 trials the accumulators, the staging
+// registers and the operands exceeded the 256 registers of two wavefronts per SIMD and the
+// loop spilled to scratch.
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBfTrialsPerWave = 16;
+constexpr int kBfTrialsPerWave = 8;
 constexpr int kBfThreads = 512;
 static_assert(kBfThreads / 64 * kBfTrialsPerWave == kBfTrialsPerGroup, "BF16 trial groups");
 

@@ -29,8 +29,8 @@ constexpr int kEigIters = 3;              // inverse-iteration steps
 constexpr size_t kTileLdsBytes = 148 * 1024;  // LDS budget of the Y tile of the tiled Gram
 constexpr int64_t kTileTargetGroups = 256;    // tiled Gram: workgroups to aim for (one per CU)
 
-// Trials per workgroup of the split-BF16 Gram kernel (16 per wavefront, 8 wavefronts).
-constexpr int kBfTrialsPerGroup = 128;
+// Trials per workgroup of the split-BF16 Gram kernel (8 per wavefront, 8 wavefronts).
+constexpr int kBfTrialsPerGroup = 64;
 
 // U-hat: ranks from which the per-row normal equations are formed on the FP64 matrix cores
 // (one dense product over all columns, 0/1 mask weights) instead of one thread per row.

@@ -256,14 +256,14 @@ def test_tune_threads_lists_built_kernels():
     assert _lib.tune_threads(6, _lib.GRAM_F64, F64) == [256, 512]
     assert _lib.tune_threads(7, _lib.GRAM_F64, F64) == [256]
     assert _lib.tune_threads(6, _lib.GRAM_F64, F32) == []        # per-trial streamer
-    assert _lib.tune_threads(16, _lib.GRAM_BF16X2, F32) == [128]
+    assert _lib.tune_threads(16, _lib.GRAM_BF16X2, F32) == [64]
     assert _lib.tune_threads(17, _lib.GRAM_BF16X2, F32) == []
 
 
 def test_tune_table_roundtrip_and_validation(empty_tune_table):
     good = [_entry(), _entry(l=12, gram_threads=256, batched=1, gram_wgs=0,
                              gram_kernel=_lib.GRAM_KERNEL_REGS),
-            _entry(l=16, gram_prec=_lib.GRAM_BF16X2, gram_threads=128, gram_wgs=64),
+            _entry(l=16, gram_prec=_lib.GRAM_BF16X2, gram_threads=64, gram_wgs=64),
             _entry(l=17, gram_threads=512, gram_kernel=_lib.GRAM_KERNEL_DMA),
             _entry(l=17, gram_threads=512),          # FP32 stages straight into LDS by default
             _entry(l=9, gram_threads=1024)]
