@@ -20,11 +20,14 @@ def _run(p, gram):
     return res, res.info()
 
 
-@pytest.mark.parametrize("m,n,r,rho", [(6000, 120, 4, 0.8), (5003, 200, 8, 0.85), (3000, 64, 15, 0.95)])
-def test_split_bf16_parity(m, n, r, rho):
+# (m, n, r, rho, extra trials): 8 n trials fill whole 64-trial workgroups at these n; the
+# extra 37 leave a ragged last group (and the last trial is among the checked Grams)
+@pytest.mark.parametrize("m,n,r,rho,extra", [(6000, 120, 4, 0.8, 0), (5003, 200, 8, 0.85, 0),
+                                             (3000, 64, 15, 0.95, 0), (4001, 150, 6, 0.8, 37)])
+def test_split_bf16_parity(m, n, r, rho, extra):
     p = synth.paper_synthetic(m, n, r, rho, 1e-2, 21 + r, factor_dtype=np.float32,
                               y_dtype=np.float32, relative_sigma=True,
-                              num_submatrices=8 * n, seed_rsm=3 + r)
+                              num_submatrices=8 * n + extra, seed_rsm=3 + r)
     res, info = _run(p, "bf16x2")
     ora = rsm.rsm(p.Y, p.W, p.r, p.num_submatrices, seed=p.seed_rsm, l=p.l, with_e=False)
     cols = res.taps["cols"].cpu().numpy()
