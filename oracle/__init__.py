@@ -17,7 +17,13 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   rsm.solve_V             noise-free exact recovery (Theorem 1 with Psi = 0);
                           rho = 1, l = n gives the truncated SVD (Eckart-Young)
   rsm.solve_U             per-row lstsq; rho = 1 closed form U = Y V
-  rsm.error_e             the paper's printed Table I error at a Table I shape
+  rsm.embed               eq.(get_xi) by hand; a shifted index also breaks the brute-force N
+  rsm.error_e             the paper's printed Table I error at a Table I shape; the
+                          definition eq.(ep) evaluated entry by entry
+  metrics.principal_..    sine and cosine forms agree above 1e-8; a 1e-12 perturbation
+                          is resolved by the sine form only
+  metrics.rel_rms_known   the ratio summed entry by entry over the known entries only
+                          (a dropped mask or the other normaliser fails it)
 """
 from . import metrics, rng, rsm  # noqa: F401
 from .rsm import OracleResult, rsm as run  # noqa: F401

@@ -56,12 +56,6 @@ class OracleResult:
     extra: dict = field(default_factory=dict)
 
 
-def known_ratio(W: np.ndarray) -> float:
-    """rho of eq.(def.rho)."""
-    W = np.asarray(W, dtype=bool)
-    return float(W.sum()) / W.size
-
-
 def qualifying_rows(W: np.ndarray, cols: np.ndarray) -> np.ndarray:
     """M1: the rows whose entries at every chosen column are known, ascending."""
     return np.flatnonzero(np.asarray(W[:, cols], dtype=bool).all(axis=1))
@@ -118,9 +112,11 @@ def accumulate_N(Y, W, subsets, r, nvec, min_rows, N=None):
         if zeta is None:
             continue
         accepted += 1
-        # xi = e(zeta) is zero outside the chosen columns, so xi xi^T only touches the
-        # cols x cols block of N.
-        N[np.ix_(cols, cols)] += zeta @ zeta.T
+        xi = embed(zeta, cols, n)                    # eq.(get_xi): the columns of Xi
+        # eq.(XI): N = Xi Xi^T = sum xi xi^T.  xi xi^T vanishes outside the rows (and
+        # columns) where xi is nonzero, so only that block of N is added to.
+        S = np.flatnonzero(np.any(xi != 0.0, axis=1))
+        N[np.ix_(S, S)] += xi[S] @ xi[S].T
     return N, rows, accepted
 
 
@@ -151,7 +147,9 @@ def accumulate_N_rows_first(Y, W, subsets, r, min_cols, N=None):
         if zeta is None:
             continue
         accepted += 1
-        N[np.ix_(C, C)] += zeta @ zeta.T
+        xi = embed(zeta, C, n)                       # eq.(get_xi) at the trial's columns
+        S = np.flatnonzero(np.any(xi != 0.0, axis=1))
+        N[np.ix_(S, S)] += xi[S] @ xi[S].T           # eq.(XI)
     return N, sizes, accepted
 
 

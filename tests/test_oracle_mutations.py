@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import test_oracle_pins as pins
-from oracle import rsm
+from oracle import metrics, rsm
 
 _orig_qualifying_rows = rsm.qualifying_rows
 _orig_minor = rsm.minor_right_singular_vectors
@@ -60,6 +60,19 @@ def _accumulate_drop_last(Y, W, subsets, r, nvec, min_rows, N=None):
 _orig_accumulate = rsm.accumulate_N
 
 
+def _rel_rms_no_mask(W, U1, V1, U2, V2, block=8192):
+    # mistake: every entry counted, known or not
+    P1, P2 = U1 @ V1.T, U2 @ V2.T
+    return float(np.sqrt(np.sum((P1 - P2) ** 2) / np.sum(P2 ** 2)))
+
+
+def _rel_rms_other_normaliser(W, U1, V1, U2, V2, block=8192):
+    # mistake: normalised by the first product instead of the reference one
+    W = np.asarray(W, dtype=bool)
+    P1, P2 = U1 @ V1.T, U2 @ V2.T
+    return float(np.sqrt(np.sum(np.where(W, P1 - P2, 0.0) ** 2) / np.sum(np.where(W, P1, 0.0) ** 2)))
+
+
 def _fails(fn) -> bool:
     try:
         fn()
@@ -75,6 +88,8 @@ def _fails(fn) -> bool:
      ["test_minor_vector_is_null_on_true_rows_noise_free",
       "test_minor_vector_projector_matches_gram_eigh_noisy", "test_N_brute_force_all_subsets_tiny"]),
     ("embed", _embed_shifted, ["test_embedding"]),
+    # the accumulator builds every xi through embed, so the same slip is caught there too
+    ("embed", _embed_shifted, ["test_N_brute_force_all_subsets_tiny"]),
     ("solve_V", _largest_eigvecs, ["test_full_mask_l_equals_n_is_truncated_svd"]),
     ("solve_U", _solve_U_no_mask, ["test_U_is_masked_least_squares"]),
     ("solve_U", _solve_U_sign, ["test_U_full_mask_closed_form"]),
@@ -86,8 +101,15 @@ def test_planted_mistake_is_caught(monkeypatch, attr, bad, tests):
     assert caught, f"no pin caught the planted mistake in {attr}"
 
 
+@pytest.mark.parametrize("bad", [_rel_rms_no_mask, _rel_rms_other_normaliser])
+def test_planted_mistake_in_the_parity_metric_is_caught(monkeypatch, bad):
+    monkeypatch.setattr(metrics, "rel_rms_known", bad)
+    assert _fails(pins.test_rel_rms_known_brute_force)
+
+
 def test_pins_pass_without_mistakes():
     # the same pins, unpatched, are green (guards against a pin that always fails)
     for name in ["test_qualifying_rows_brute_force", "test_embedding",
+                 "test_rel_rms_known_brute_force", "test_N_invariants_noisy",
                  "test_U_full_mask_closed_form", "test_minor_vector_projector_matches_gram_eigh_noisy"]:
         getattr(pins, name)()

@@ -209,6 +209,38 @@ def test_principal_angle_forms_agree():
     assert 1e-14 < metrics.principal_angle_max(A, B) < 1e-10
 
 
+def test_rel_rms_known_brute_force():
+    # the parity metric written out entry by entry: only the known entries (w_ij = 1, the
+    # W o of eq.(problem)) enter either sum, and the normaliser is the second (reference)
+    # product.  The two products differ in scale, so the other normaliser gives another
+    # number; half the entries are unknown and carry large differences, so dropping the
+    # mask does too.
+    g = np.random.default_rng(18)
+    m, n, r = 23, 11, 3
+    U1, V1 = g.standard_normal((m, r)), g.standard_normal((n, r))
+    U2, V2 = 2.5 * g.standard_normal((m, r)), g.standard_normal((n, r))
+    W = g.random((m, n)) < 0.5
+    num = den = 0.0
+    for i in range(m):
+        for j in range(n):
+            if W[i, j]:
+                a = sum(U1[i, k] * V1[j, k] for k in range(r))
+                b = sum(U2[i, k] * V2[j, k] for k in range(r))
+                num += (a - b) ** 2
+                den += b ** 2
+    expect = (num / den) ** 0.5
+    for block in (5, 8192):  # one row block and several (a ragged last one)
+        assert abs(metrics.rel_rms_known(W, U1, V1, U2, V2, block=block) - expect) <= 1e-13 * expect
+    # no known entry differs: zero, whatever the unknown entries hold
+    U3 = U2.copy()
+    U3[~W.any(axis=1)] += 1.0
+    Wr = np.zeros_like(W)
+    Wr[:, 0] = True
+    V3 = V2.copy()
+    V3[1:] += 7.0
+    assert metrics.rel_rms_known(Wr, U2, V3, U2, V2) == 0.0
+
+
 def test_rel_rms_basis_invariant():
     g = np.random.default_rng(17)
     U = g.standard_normal((40, 3))
