@@ -248,6 +248,34 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
                               void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Step 1 (Section IV-A): how many sub-matrices to draw.  Host only: no device call, no
+ * allocation, thread-safe.  Every function returns RSM_OK or RSM_E_ARG (a NULL output
+ * pointer or an argument outside the stated range; the output is then untouched).
+ *
+ * Lemma 1: C_{n,rho}(k) = (1 - rho)^n at k = 0, 1 - rho^n at k = n, otherwise the standard
+ * normal distribution function at sgn(k/n - rho) sqrt(2 n phi(k/n, rho)), phi the
+ * Kullback-Leibler divergence of Bernoulli(k/n) from Bernoulli(rho).  It brackets the
+ * binomial distribution function: C(k) <= P(X <= k) <= C(k + 1) for X ~ B(n, rho) (the
+ * lemma's sum "up to k" read as inclusive).  Needs n >= 1, 0 <= k <= n, 0 < rho < 1. */
+int32_t rsm_lemma1_c(int64_t n, double rho, int64_t k, double* value);
+
+/* Theorem 3: after at most
+ *     I = m n rho / (k (r + 1) (1 - C_{n, rho^k}(r + 2))) ln(1 / (1 - eps))
+ * trials every known entry of Y has been in some sub-matrix with probability >= eps.
+ * rows_first != 0: the theorem as stated, k = l rows per trial (method M2).
+ * rows_first == 0: method M1 (l columns per trial), the same bound for Y^T (m and n
+ * exchanged).  l = 0 means r + 1.  Needs m, n >= 1, r >= 1, l > r, 0 < rho < 1,
+ * 0 < eps < 1 and r + 2 <= (columns kept per trial's side: n for M2, m for M1).  *bound is
+ * +inf when a trial is unlikely to keep more than r columns (rows for M1). */
+int32_t rsm_trials_bound(int64_t m, int64_t n, double rho, int32_t r, int32_t l, double eps,
+                         int32_t rows_first, double* bound);
+
+/* rsm_trials_bound rounded up to a trial count for num_submatrices; RSM_E_ARG as well when
+ * the bound is infinite or does not fit an int64_t. */
+int32_t rsm_plan_trials(int64_t m, int64_t n, double rho, int32_t r, int32_t l, double eps,
+                        int32_t rows_first, int64_t* trials);
+
+/* ---------------------------------------------------------------------------------------
  * Tile table (library-wide, host side).  The fused gather + Gram step (a2 + a3) has three
  * free parameters: how the tiled kernel stages Y (1: through registers, 32-row chunks; 2:
  * straight from global memory into LDS, 16-row chunks, fewer registers per thread; 3: as 2

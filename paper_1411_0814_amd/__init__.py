@@ -236,10 +236,13 @@ def decompose_batched(requests: Sequence[Request], stream=None, workspace=None) 
     stream = stream or torch.cuda.current_stream(device)
     probs = [_problem(r) for r in requests]
     ws_need = _lib.workspace_bytes(probs)
-    prepared = [_prepare(r, p, device) for r, p in zip(requests, probs)]
-    if workspace is None:
-        ws_buf, ws_ptr = _workspace(ws_need, device)
-    else:
+    # allocated on the stream the kernels run on, so the caching allocator does not hand
+    # these blocks to other streams while the kernels may still use them
+    with torch.cuda.stream(stream):
+        prepared = [_prepare(r, p, device) for r, p in zip(requests, probs)]
+        if workspace is None:
+            ws_buf, ws_ptr = _workspace(ws_need, device)
+    if workspace is not None:
         ws_buf, ws_ptr = workspace, workspace.data_ptr()
         if workspace.numel() * workspace.element_size() < ws_need or ws_ptr % 256:
             raise ValueError("workspace too small or misaligned")
@@ -272,10 +275,12 @@ def decompose(Y, W, r: int, num_submatrices: int, seed: int, *, l: int = 0, nvec
     stream = stream or torch.cuda.current_stream(device)
     p = _problem(req)
     ws_need = _lib.workspace_bytes([p])
-    inp, out, res = _prepare(req, p, device)
-    if workspace is None:
-        ws_buf, ws_ptr = _workspace(ws_need, device)
-    else:
+    # allocated on the launch stream (see decompose_batched)
+    with torch.cuda.stream(stream):
+        inp, out, res = _prepare(req, p, device)
+        if workspace is None:
+            ws_buf, ws_ptr = _workspace(ws_need, device)
+    if workspace is not None:
         ws_buf, ws_ptr = workspace, workspace.data_ptr()
         if workspace.numel() * workspace.element_size() < ws_need or ws_ptr % 256:
             raise ValueError("workspace too small or misaligned")

@@ -102,7 +102,8 @@ GRAM_KERNEL_REGS, GRAM_KERNEL_DMA, GRAM_KERNEL_DMA2 = 1, 2, 3
 
 
 EXPORTS = ["rsm_abi_version", "rsm_status_string", "rsm_workspace_bytes", "rsm_decompose",
-           "rsm_decompose_batched", "rsm_tune_set", "rsm_tune_get", "rsm_tune_threads"]
+           "rsm_decompose_batched", "rsm_tune_set", "rsm_tune_get", "rsm_tune_threads",
+           "rsm_lemma1_c", "rsm_trials_bound", "rsm_plan_trials"]
 
 _LIB = None
 
@@ -144,6 +145,14 @@ def lib() -> C.CDLL:
         L.rsm_tune_threads.restype = C.c_int32
         L.rsm_tune_threads.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                        C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]
+        L.rsm_lemma1_c.restype = C.c_int32
+        L.rsm_lemma1_c.argtypes = [C.c_int64, C.c_double, C.c_int64, C.POINTER(C.c_double)]
+        L.rsm_trials_bound.restype = C.c_int32
+        L.rsm_trials_bound.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_int32, C.c_int32,
+                                       C.c_double, C.c_int32, C.POINTER(C.c_double)]
+        L.rsm_plan_trials.restype = C.c_int32
+        L.rsm_plan_trials.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_int32, C.c_int32,
+                                      C.c_double, C.c_int32, C.POINTER(C.c_int64)]
         if L.rsm_abi_version() != ABI_VERSION:
             raise LibraryMissing("librsm ABI version mismatch; rebuild the library")
         _LIB = L

@@ -62,6 +62,17 @@ class PoolItem:
     footprint: int = field(default=0)   # bytes per request (filled by the server)
 
 
+def footprint(it: PoolItem) -> int:
+    """HBM bytes one request on `it` holds while in flight: the library's workspace for
+    exactly the problem the server will run (its flags included: rows-first sampling
+    carves extra buffers), the factors U-hat (m x r) and V-hat (n x r) in FP64, and the
+    small info record."""
+    req = Request(Y=it.Y, W=it.W, r=it.r, num_submatrices=it.num_submatrices, seed=0,
+                  l=it.l, gram=it.gram, flags=it.flags)
+    m, n = it.Y.shape
+    return _lib.workspace_bytes([_problem(req)]) + 8 * it.r * (m + n) + 4096
+
+
 class Server:
     def __init__(self, pool: list[PoolItem], *, budget_bytes: int = 16 << 30,
                  max_batch: int = 256, max_inflight: int = 3, batching: bool = True,
@@ -87,10 +98,7 @@ class Server:
                        seed=job.seed, l=it.l, gram=it.gram, flags=it.flags)
 
     def _footprint(self, it: PoolItem) -> int:
-        req = Request(Y=it.Y, W=it.W, r=it.r, num_submatrices=it.num_submatrices, seed=0,
-                      l=it.l, gram=it.gram)
-        m, n = it.Y.shape
-        return (_lib.workspace_bytes([_problem(req)]) + 8 * it.r * (m + n) + 4096)
+        return footprint(it)
 
     def run(self, jobs: list[Job], time_limit: float | None = None) -> dict:
         """Serve `jobs` (sorted by arrival) in real time; returns latency / throughput
@@ -160,18 +168,39 @@ class Server:
             if not progressed:
                 # nothing to do until the next arrival or completion
                 time.sleep(20e-6)
-        done = [j for j in jobs if not math.isnan(j.done)]
-        lat = np.array([j.done - j.arrival for j in done]) if done else np.zeros(1)
-        span = (max(j.done for j in done) - min(j.arrival for j in done)) if done else 0.0
-        return {
-            "requests": len(jobs),
-            "completed": len(done),
-            "throughput_per_s": len(done) / span if span > 0 else 0.0,
-            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                           "p99": float(np.percentile(lat, 99) * 1e3),
-                           "mean": float(lat.mean() * 1e3)},
+        t_stop = time.perf_counter() - t0
+        stats = latency_stats(jobs, t_stop)
+        stats.update({
             "batches": batches,
             "mean_batch": float(np.mean(batch_sizes)) if batch_sizes else 0.0,
             "peak_bytes": int(peak_used),
             "budget_bytes": self.budget,
-        }
+        })
+        return stats
+
+
+def latency_stats(jobs: list[Job], t_stop: float) -> dict:
+    """Completion counts, throughput and latency percentiles of a served trace.  Requests
+    never completed (admission stopped at a time limit) have waited at least until the
+    stop, so `latency_all_ms` counts them at t_stop: exact when nothing was left unserved,
+    otherwise lower bounds of the percentiles over every request."""
+    done = [j for j in jobs if not math.isnan(j.done)]
+    lat = np.array([j.done - j.arrival for j in done]) if done else np.zeros(1)
+    span = (max(j.done for j in done) - min(j.arrival for j in done)) if done else 0.0
+    unserved = [j for j in jobs if math.isnan(j.done)]
+    lat_all = np.concatenate([lat if done else np.zeros(0),
+                              np.array([max(0.0, t_stop - j.arrival) for j in unserved])])
+    if lat_all.size == 0:
+        lat_all = np.zeros(1)
+    return {
+        "requests": len(jobs),
+        "completed": len(done),
+        "unserved": len(unserved),
+        "throughput_per_s": len(done) / span if span > 0 else 0.0,
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p99": float(np.percentile(lat, 99) * 1e3),
+                       "mean": float(lat.mean() * 1e3)},
+        "latency_all_ms": {"p50": float(np.percentile(lat_all, 50) * 1e3),
+                           "p99": float(np.percentile(lat_all, 99) * 1e3),
+                           "lower_bound": bool(unserved)},
+    }

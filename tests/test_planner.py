@@ -85,3 +85,26 @@ def test_rejects_bad_arguments():
         planner.trials_bound(100, 50, 0.5, 3, 4, 1.0)
     with pytest.raises(ValueError):
         planner.lemma1_C(10, 0.0, 3)
+
+
+def test_planner_is_the_library_entry_point():
+    # the Python names are thin calls of the C ABI: the same numbers come back from ctypes
+    import ctypes as C
+    from paper_1411_0814_amd import _lib
+    out = C.c_double()
+    assert _lib.lib().rsm_trials_bound(5000, 300, 0.6, 4, 0, 0.9, 0, C.byref(out)) == _lib.OK
+    assert out.value == planner.trials_bound(5000, 300, 0.6, 4, None, 0.9)
+    cnt = C.c_int64()
+    assert _lib.lib().rsm_plan_trials(5000, 300, 0.6, 4, 5, 0.9, 1, C.byref(cnt)) == _lib.OK
+    assert cnt.value == math.ceil(planner.trials_bound_rows_first(5000, 300, 0.6, 4, 5, 0.9))
+    assert planner.plan_trials(5000, 300, 0.6, 4, 5, 0.9, rows_first=True) == cnt.value
+    # NULL output pointers are rejected
+    assert _lib.lib().rsm_lemma1_c(10, 0.5, 3, None) == _lib.E_ARG
+
+
+def test_hopeless_density_has_no_plan():
+    # rho^l so small that no trial keeps more than r rows: the bound is infinite and no
+    # trial count is planned
+    assert planner.trials_bound(100, 50, 0.01, 3, 4, 0.9) == math.inf
+    with pytest.raises(ValueError):
+        planner.plan_trials(100, 50, 0.01, 3, 4, 0.9)
