@@ -69,7 +69,9 @@ enum {
   RSM_E_ARG = -1,          /* a NULL pointer, a size out of range, an inconsistent field */
   RSM_E_WORKSPACE = -2,    /* ws_bytes below rsm_workspace_bytes(), or workspace misaligned */
   RSM_E_DEVICE = -3,       /* a HIP launch or query failed */
-  RSM_E_UNSUPPORTED = -4   /* valid request outside this build's limits (RSM_MAX_*) */
+  RSM_E_UNSUPPORTED = -4,  /* valid request outside this build's limits (RSM_MAX_*) */
+  RSM_E_SCRATCH = -5       /* rsm_decompose_noalloc: the problem's workspace exceeds
+                              RSM_NOALLOC_MAX_BYTES */
 };
 
 /* Bits of rsm_info.warn (per problem, written by the device). */
@@ -235,6 +237,20 @@ int32_t rsm_workspace_bytes(const rsm_problem* problems, int32_t nprob, size_t* 
  * matter and on exit are undefined.  The call returns after enqueueing. */
 int32_t rsm_decompose(const rsm_problem* p, const rsm_input* in, const rsm_output* out,
                       void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): rsm_decompose with its workspace taken
+ * from a scratch array built into the library, RSM_NOALLOC_MAX_BYTES per device, held
+ * until the process ends (its device address is looked up once per device, on the first
+ * call there).  The caller still owns and passes Y, W and the outputs; the call allocates
+ * nothing.  Returns RSM_E_SCRATCH, with nothing enqueued, when rsm_workspace_bytes(p, 1)
+ * exceeds the limit; otherwise as rsm_decompose.  The device is the stream's (the current
+ * device for the NULL stream).  Every call on a device shares that device's array: calls
+ * that may overlap on one device (different streams, or host threads) race and must be
+ * serialised by the caller; calls in order on one stream are safe. */
+#define RSM_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int32_t rsm_decompose_noalloc(const rsm_problem* p, const rsm_input* in, const rsm_output* out,
+                              void* hip_stream);
 
 /* Several independent decompositions (uneven sizes allowed) fused into shared launches:
  * every step runs once for all problems that share its kernel instance (the Gram and

@@ -23,7 +23,7 @@ from typing import Optional, Sequence
 from . import _lib
 from ._lib import RSMError, LibraryMissing  # noqa: F401
 
-__all__ = ["decompose", "decompose_batched", "workspace_bytes", "Request", "Result",
+__all__ = ["decompose", "decompose_noalloc", "decompose_batched", "workspace_bytes", "Request", "Result",
            "RSMError", "LibraryMissing"]
 
 
@@ -289,6 +289,28 @@ def decompose(Y, W, r: int, num_submatrices: int, seed: int, *, l: int = 0, nvec
     _lib.check(code, "rsm_decompose")
     res.stream = stream
     res._keep.append(ws_buf)  # keep the scratch alive until the stream is done
+    return res
+
+
+def decompose_noalloc(Y, W, r: int, num_submatrices: int, seed: int, *, l: int = 0,
+                      nvec: int = 0, min_rows: int = 0, gram: str = "f32", trial_begin: int = 0,
+                      subsets=None, N=None, flags: int = 0, stream=None) -> Result:
+    """As decompose, through rsm_decompose_noalloc: the library takes its workspace from its
+    own per-device scratch array (no workspace tensor).  Outputs are still allocated here."""
+    torch = _torch()
+    L = _lib.lib()
+    req = Request(Y=Y, W=W, r=r, num_submatrices=num_submatrices, seed=seed, l=l, nvec=nvec,
+                  min_rows=min_rows, gram=gram, trial_begin=trial_begin, subsets=subsets, N=N,
+                  flags=flags)
+    device = Y.device
+    stream = stream or torch.cuda.current_stream(device)
+    p = _problem(req)
+    with torch.cuda.stream(stream):
+        inp, out, res = _prepare(req, p, device)
+    code = L.rsm_decompose_noalloc(C.byref(p), C.byref(inp), C.byref(out),
+                                   C.c_void_p(stream.cuda_stream))
+    _lib.check(code, "rsm_decompose_noalloc")
+    res.stream = stream
     return res
 
 

@@ -23,6 +23,8 @@ E_ARG = -1
 E_WORKSPACE = -2
 E_DEVICE = -3
 E_UNSUPPORTED = -4
+E_SCRATCH = -5
+NOALLOC_MAX_BYTES = 64 << 20   # RSM_NOALLOC_MAX_BYTES
 
 W_NO_CONSTRAINTS = 1
 W_RANK_DEFICIENT = 2
@@ -103,7 +105,7 @@ GRAM_KERNEL_REGS, GRAM_KERNEL_DMA, GRAM_KERNEL_DMA2 = 1, 2, 3
 
 EXPORTS = ["rsm_abi_version", "rsm_status_string", "rsm_workspace_bytes", "rsm_decompose",
            "rsm_decompose_batched", "rsm_tune_set", "rsm_tune_get", "rsm_tune_threads",
-           "rsm_lemma1_c", "rsm_trials_bound", "rsm_plan_trials"]
+           "rsm_lemma1_c", "rsm_trials_bound", "rsm_plan_trials", "rsm_decompose_noalloc"]
 
 _LIB = None
 
@@ -134,6 +136,9 @@ def lib() -> C.CDLL:
         L.rsm_decompose.restype = C.c_int32
         L.rsm_decompose.argtypes = [C.POINTER(Problem), C.POINTER(Input), C.POINTER(Output),
                                     C.c_void_p, C.c_size_t, C.c_void_p]
+        L.rsm_decompose_noalloc.restype = C.c_int32
+        L.rsm_decompose_noalloc.argtypes = [C.POINTER(Problem), C.POINTER(Input), C.POINTER(Output),
+                                            C.c_void_p]
         L.rsm_decompose_batched.restype = C.c_int32
         L.rsm_decompose_batched.argtypes = [C.c_int32, C.POINTER(Problem), C.POINTER(Input),
                                             C.POINTER(Output), C.c_void_p, C.c_size_t,

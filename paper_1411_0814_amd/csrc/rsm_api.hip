@@ -432,6 +432,41 @@ void mark_all(const rsm_output* outs, const IdxList& g, int step, int end, hipSt
 
 }  // namespace rsm
 
+// Scratch of rsm_decompose_noalloc: one array per device, in the code object's data,
+// held until the process ends.  In host code `scratch` is only a handle for
+// hipGetSymbolAddress; kernels are given the device address that call returns.
+static __device__ __align__(256) unsigned char scratch[RSM_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev`, looked up once per device with that device
+// current.
+int32_t scratch_address(int dev, void** ptr) {
+  if (dev < 0 || dev >= kMaxDevices) return RSM_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return RSM_E_DEVICE;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return RSM_E_DEVICE;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return RSM_E_DEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return RSM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int32_t rsm_abi_version(void) { return RSM_ABI_VERSION; }
@@ -443,6 +478,7 @@ const char* rsm_status_string(int32_t status) {
     case RSM_E_WORKSPACE: return "workspace too small or misaligned";
     case RSM_E_DEVICE: return "device launch failed";
     case RSM_E_UNSUPPORTED: return "outside the limits of this build";
+    case RSM_E_SCRATCH: return "problem needs more scratch than RSM_NOALLOC_MAX_BYTES";
     case RSM_W_NO_CONSTRAINTS: return "warning: no trial accepted";
     case RSM_W_RANK_DEFICIENT: return "warning: V-hat not unique (uncovered column or no eigen-gap)";
     case RSM_W_ROWS_UNDERDETERMINED: return "warning: rows with fewer than r known entries";
@@ -474,6 +510,28 @@ int32_t rsm_workspace_bytes(const rsm_problem* problems, int32_t nprob, size_t* 
 int32_t rsm_decompose(const rsm_problem* p, const rsm_input* in, const rsm_output* out,
                       void* workspace, size_t ws_bytes, void* hip_stream) {
   return rsm_decompose_batched(1, p, in, out, workspace, ws_bytes, hip_stream);
+}
+
+int32_t rsm_decompose_noalloc(const rsm_problem* p, const rsm_input* in, const rsm_output* out,
+                              void* hip_stream) {
+  if (!p) return RSM_E_ARG;
+  size_t need = 0;
+  const int32_t st = rsm_workspace_bytes(p, 1, &need);
+  if (st != RSM_OK) return st;
+  if (need > RSM_NOALLOC_MAX_BYTES) return RSM_E_SCRATCH;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int dev = -1;
+  if (s) {
+    hipDevice_t d = -1;
+    if (hipStreamGetDevice(s, &d) != hipSuccess) return RSM_E_DEVICE;
+    dev = static_cast<int>(d);
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return RSM_E_DEVICE;
+  }
+  void* ws = nullptr;
+  const int32_t sa = scratch_address(dev, &ws);
+  if (sa != RSM_OK) return sa;
+  return rsm_decompose_batched(1, p, in, out, ws, RSM_NOALLOC_MAX_BYTES, hip_stream);
 }
 
 int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,

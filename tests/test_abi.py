@@ -217,9 +217,26 @@ def test_decompose_validates_before_any_launch():
     assert _lib.lib().rsm_decompose_batched(0, None, None, None, None, 0, None) == _lib.E_ARG
 
 
+def test_noalloc_rejects_on_host_before_any_device_call():
+    # no GPU is needed: a problem whose workspace exceeds the built-in scratch, and a NULL
+    # problem, are rejected before the call looks at the device
+    fake = 1 << 40
+    L = _lib.lib()
+    inp = _lib.Input(Y=fake, ldy=131072, W=fake, ldw=131072, subsets=None)
+    out = _lib.Output(V=fake, U=fake, N=None, info=fake)
+    big = _prob(m=131072, n=1024, r=8, l=9, num_submatrices=8192, y_dtype=_lib.F32,
+                gram_prec=_lib.GRAM_F32)
+    code, need = _ws(big)
+    assert code == _lib.OK and need > _lib.NOALLOC_MAX_BYTES
+    assert L.rsm_decompose_noalloc(C.byref(big), C.byref(inp), C.byref(out), None) == _lib.E_SCRATCH
+    assert L.rsm_decompose_noalloc(None, C.byref(inp), C.byref(out), None) == _lib.E_ARG
+    bad = _prob(r=0)
+    assert L.rsm_decompose_noalloc(C.byref(bad), C.byref(inp), C.byref(out), None) == _lib.E_ARG
+
+
 def test_status_strings():
     for code in [_lib.OK, _lib.E_ARG, _lib.E_WORKSPACE, _lib.E_DEVICE, _lib.E_UNSUPPORTED,
-                 *_lib.WARNINGS]:
+                 _lib.E_SCRATCH, *_lib.WARNINGS]:
         s = _lib.status_string(code)
         assert s and s != "unknown status"
     assert _lib.status_string(12345) == "unknown status"
