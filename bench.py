@@ -479,7 +479,7 @@ def main_precision(args):
     W = torch.from_numpy(p.Wt.view(bool)).to(dev).T
     stream = torch.cuda.current_stream(dev)
     runs = {}
-    for gram in ("f32", "bf16x2"):
+    for gram in ("f64", "f32", "bf16x2"):
         for _ in range(max(1, args.warmup)):
             res = decompose(Y, W, p.r, p.num_submatrices, p.seed_rsm, l=p.l, gram=gram)
         torch.cuda.synchronize()
@@ -510,8 +510,11 @@ def main_precision(args):
         runs[g]["theta_vs_generating_V_leading_k"] = {
             str(k): float(np.arcsin(min(1.0, np.linalg.norm(
                 Vbar[:, :k] - Vg @ (Vg.T @ Vbar[:, :k]), 2)))) for k in (4, 6, 7, 8)}
-        lam = runs[g].pop("info")["lambda"]
+        inf = runs[g].pop("info")
+        lam = inf["lambda"]
         runs[g]["lambda_r"], runs[g]["lambda_r1"] = lam[p.r - 1], lam[p.r]
+        runs[g].update(eig_iterations=inf["eig_iterations"], residual=inf["residual"],
+                       warnings=inf["warnings"])
         del runs[g]["V"], runs[g]["U"]
     line = {
         "metric": METRIC, "value": runs["bf16x2"]["decompositions_per_s"],

@@ -18,11 +18,11 @@
 //      [A 0; C B]^{-1} = [A^{-1} 0; -B^{-1} C A^{-1}  B^{-1}], log2(tiles) levels of
 //      products (the matrix is padded to a power-of-two number of tiles with identity).
 //      M^T is stored as well, so that both products of an iteration read rows.
-//   4. b = r + 4 vectors: X <- orth(M^T M X), a fixed number of steps, with classical
-//      Gram-Schmidt applied twice (rows held in registers of one workgroup).
-//   5. Rayleigh-Ritz: H = X^T N X, H = Q Theta Q^T by parallel-ordering Jacobi,
-//      V-hat = X Q[:, :r]; lambda_1..lambda_{r+1} = Theta; residual
-//      max_k ||N v_k - theta_k v_k|| / lam_max.
+//   4. b = r + 4 vectors: X <- orth(M^T M X) by inverse subspace iteration until the
+//      residual test of the r wanted Ritz pairs passes (one launch, k_subspace);
+//   5. Rayleigh-Ritz at check iterations: H = X^T N X, H = Q Theta Q^T by parallel-ordering
+//      Jacobi, V-hat = X Q[:, :r]; lambda_1..lambda_{r+1} = Theta; residual
+//      max_k ||N v_k - theta_k v_k|| / lam_max, the stopping test.
 // Every kernel takes an array of problem descriptors (problem = blockIdx.y), so a batch of
 // problems of different sizes runs in the same launches; workgroups past a problem's own
 // work return at once.
@@ -38,7 +38,6 @@ namespace {
 constexpr int NB = kCholNB;     // 64
 constexpr int kLd = NB + 4;     // LDS row stride of product operands (16-byte aligned rows)
 constexpr int kTr = NB + 1;     // LDS row stride of transposition buffers (odd: no conflicts)
-constexpr int kRows = 16;       // output rows per workgroup of the thin products
 constexpr double kShiftRel = 1e-8;
 constexpr int kDescPerLaunch = 16;
 
@@ -51,14 +50,11 @@ __device__ __forceinline__ T* generic(RSM_GLOBAL T* p) {
   return (T*)p;
 }
 
-// Global load / store at a 32-bit element offset from a uniform base: the compiler can then
+// Global load at a 32-bit element offset from a uniform base: the compiler can then
 // use the scalar-base + 32-bit vector-offset addressing form (every matrix here has fewer
 // than 2^28 elements).
 __device__ __forceinline__ double gld(gcdouble base, uint32_t idx) {
   return *reinterpret_cast<gcdouble>(reinterpret_cast<RSM_GLOBAL const char*>(base) + (idx << 3));
-}
-__device__ __forceinline__ void gst(gdouble base, uint32_t idx, double v) {
-  *reinterpret_cast<gdouble>(reinterpret_cast<RSM_GLOBAL char*>(base) + (idx << 3)) = v;
 }
 
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -73,36 +69,6 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
-}
-
-// Sum over the wavefront of NV values per lane with about NV exchanges instead of 6 NV: each
-// halving step sends one half of the values to the partner lane and keeps the other half.
-// Afterwards v[0] of lane l is the full sum of value idx(l); lanes whose low 6 - log2(NV)
-// bits are zero hold distinct indices.
-template <int NV, int OFF>
-__device__ __forceinline__ void sum_many(double* v, int lane, int& idx) {
-  if constexpr (NV > 1) {
-    constexpr int H = NV / 2;
-    const bool up = (lane & OFF) != 0;
-#pragma unroll
-    for (int j = 0; j < H; ++j) {
-      const double send = up ? v[j] : v[j + H];
-      const double keep = up ? v[j + H] : v[j];
-      v[j] = keep + __shfl_xor(send, OFF, 64);
-    }
-    idx += up ? H : 0;
-    sum_many<H, OFF / 2>(v, lane, idx);
-  } else {
-#pragma unroll
-    for (int off = OFF; off > 0; off >>= 1) v[0] += __shfl_xor(v[0], off, 64);
-  }
-}
-
-template <int K>
-constexpr int pow2_at_least() {
-  int p = 1;
-  while (p < K) p *= 2;
-  return p;
 }
 
 // ------------------------------------------------------------------ 64 x 64 tiles
@@ -404,7 +370,11 @@ __global__ __launch_bounds__(256) void k_eig_prep(const EigProb* __restrict__ pr
   const EigProb& P = probs[blockIdx.y];
   const int64_t n = P.n, npad = P.npad;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (idx < kSmallDoubles) P.small[idx] = 0.0;
+  if (idx == 0) {
+    P.scal->bar = 0;
+    P.scal->ticket = 0;
+    P.scal->stalled = 0;
+  }
   if (idx >= npad * npad) return;
   const int64_t c = idx / npad, rr = idx - c * npad;
   if (rr < n && c < n) {
@@ -697,7 +667,582 @@ __global__ __launch_bounds__(256) void k_inv_stage2(const EigProb* __restrict__ 
     }
 }
 
-// ------------------------------------------------------------------ 4. subspace iteration
+// ------------------------------------------------------------------ 4-5. subspace iteration
+//
+// Inverse subspace iteration and Rayleigh-Ritz run in one launch (k_subspace).  Each problem
+// is taken by a group of G = ceil(n_max / kSubRows) workgroups; workgroup `rank` owns rows
+// 16 rank .. 16 rank + 15 of the n x b iterate (ranks past the problem's own rows only keep
+// step).  A group's workgroups meet at group barriers: device-scope release fence, an
+// arrival count, device-scope acquire; a wait that exceeds its bound stops the launch and
+// flags RSM_W_NOT_CONVERGED instead of hanging.  Workgroups take their (group, rank) from a
+// ticket counter in the order they start, so a group only waits for workgroups that have
+// started after its own first ones: the groups whose workgroups have all started always
+// finish.  Data another workgroup wrote in this launch is read after a barrier, whose
+// release (writer) and acquire (reader) fences make it visible across the XCDs' caches.
+// One iteration:
+//   Z = M X, Y = M^T Z                       (M = L^{-1}: Y = (N + mu I)^{-1} X)
+//   Y <- Y R^{-1} two or three times, R^T R the Cholesky factorisation of the b x b Gram
+//   Y^T Y, the first with a shift: shifted Cholesky QR, orthonormal to rounding even when Y
+//   is nearly rank deficient (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, SIAM J. Sci.
+//   Comput. 42, 2020);
+// and at check iterations (2, 3, 4, 5, 6, 7, 8, 10, 12, 15, ... : about 25% apart) the
+// Rayleigh-Ritz step: NX = N X, H = X^T N X = Q Theta Q^T (Jacobi), X <- X Q with Theta
+// ascending, and the residuals ||N x_k - theta_k x_k|| of the r wanted pairs.  The
+// iteration stops when max_k residual <= kSubTol lam_max, when the residual, already below
+// kSubFloor lam_max, stops halving between checks (the rounding level of the factor), or
+// after kEigMaxIters steps.  Every partial sum (products, Grams, residuals) is formed per
+// workgroup and summed in rank order, so results do not depend on timing.
+
+constexpr int kSubChunk = 128;                    // values of i staged per chunk
+constexpr int kSubStride = kEigMaxB + 1;          // LDS row stride of b-wide rows
+constexpr int kSubThreads = 256;
+constexpr double kSubTol = 1e-10;                 // converged: residual / lam_max
+constexpr double kSubFloor = 1e-8;                // below this a stalled residual stops
+constexpr long long kSubWaitTicks = 400000000LL;  // bound of one barrier wait (wall clock)
+constexpr int kSubMaxWgs = 512;                   // workgroups of one launch at most
+constexpr int kSubMinB = 2, kSubMaxB = RSM_MAX_R + kEigPad;  // subspace widths built
+constexpr double kEps = 2.220446049250313e-16;
+constexpr double kUnit = 1.1102230246251565e-16;  // unit roundoff of FP64
+
+struct SubShared {
+  double stage[kSubChunk][kSubStride];  // staged rows of the right-hand block
+  double As[kSubChunk][kSubRows + 1];   // staged slab of the operator (transposed)
+  double red[4][kSubRows][kSubStride];  // per-wavefront partial sums
+  double Yr[kSubRows][kSubStride];      // this workgroup's rows of the iterate
+  double NYr[kSubRows][kSubStride];     // its rows of N X
+  double B[kEigMaxB][kSubStride];       // b x b Gram / Rayleigh-Ritz matrix
+  double Q[kEigMaxB][kSubStride];       // rotations of the Jacobi method
+  double cs[kEigMaxB + 1], sn[kEigMaxB + 1], th[kEigMaxB + 1], rdiag[kEigMaxB + 1];
+  int partner[kEigMaxB + 1], order[kEigMaxB];
+  int stop;                             // a barrier wait failed: stop
+  int group, rank;
+};
+
+// Problems of one k_subspace launch (they share the subspace width b).
+struct SubList {
+  int32_t count;
+  int32_t idx[kLaunchMax];
+};
+
+// The group barrier.  `arrivals` counts this workgroup's barriers times G (every workgroup
+// of a group calls it equally often), so the k-th barrier waits for k G arrivals.
+__device__ void group_barrier(RSM_GLOBAL uint32_t* ctr, RSM_GLOBAL uint32_t* stalled,
+                              uint32_t& arrivals, uint32_t G, SubShared& S) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  arrivals += G;
+  if (threadIdx.x == 0 && !S.stop) {
+    uint32_t* c = (uint32_t*)ctr;
+    uint32_t* st = (uint32_t*)stalled;
+    __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = wall_clock64();
+    while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < arrivals) {
+      if (__hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+          wall_clock64() - t0 > kSubWaitTicks) {
+        __hip_atomic_store(st, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        S.stop = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// dst[jr][c] = sum_{lo <= i < hi} A[row_jr + i lda] In[i + c n] for c < B, row_jr = j0 + jr
+// (rows at or past n give zero rows).  Per chunk of kSubChunk values of i, the operator's
+// 16 x kSubChunk slab and the chunk's rows of In are staged in LDS (all loads of a chunk in
+// flight together); thread (jr, kp) = (t % 16, t / 16) sums i = kp mod 16 of the
+// chunk for all B columns, and the 16 partial sums of a row are added by two cross-lane
+// steps and then over the four wavefronts in order.  All threads.
+template <int B>
+__device__ void row_product(gcdouble __restrict__ A, uint32_t lda, gcdouble In, int n, int j0,
+                            int lo, int hi, SubShared& S, double (*dst)[kSubStride]) {
+  constexpr int kIn = (kSubChunk * B + kSubThreads - 1) / kSubThreads;  // In values per thread
+  constexpr int kA = kSubChunk * kSubRows / kSubThreads;                 // operator values
+  const int t = threadIdx.x, jr = t & 15, kp = t >> 4;
+  const uint32_t row = static_cast<uint32_t>(j0 + jr < n ? j0 + jr : n - 1);
+  double acc[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) acc[c] = 0.0;
+  for (int i0 = lo; i0 < hi; i0 += kSubChunk) {
+    const int cnt = (hi - i0) < kSubChunk ? (hi - i0) : kSubChunk;
+    double xv[kIn], av[kA];
+#pragma unroll
+    for (int u = 0; u < kIn; ++u) {
+      const int e = t + u * kSubThreads, il = e % kSubChunk, c = e / kSubChunk;
+      const bool ok = c < B && il < cnt;
+      xv[u] = gld(In, static_cast<uint32_t>(i0 + (ok ? il : 0)) +
+                          static_cast<uint32_t>(ok ? c : 0) * static_cast<uint32_t>(n));
+      if (!ok) xv[u] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kA; ++u) {
+      const int il = kp + 16 * u;
+      av[u] = gld(A, row + static_cast<uint32_t>(i0 + (il < cnt ? il : 0)) * lda);
+      if (il >= cnt) av[u] = 0.0;
+    }
+    __syncthreads();  // the previous chunk has been used
+#pragma unroll
+    for (int u = 0; u < kIn; ++u) {
+      const int e = t + u * kSubThreads, il = e % kSubChunk, c = e / kSubChunk;
+      if (c < B) S.stage[il][c] = xv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kA; ++u) S.As[kp + 16 * u][jr] = av[u];
+    __syncthreads();
+#pragma unroll 2
+    for (int il = kp; il < kSubChunk; il += 16) {
+      const double a = S.As[il][jr];
+#pragma unroll
+      for (int c = 0; c < B; ++c) acc[c] = fma(a, S.stage[il][c], acc[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    acc[c] += __shfl_xor(acc[c], 16, 64);
+    acc[c] += __shfl_xor(acc[c], 32, 64);
+  }
+  if ((t & 63) < 16)
+#pragma unroll
+    for (int c = 0; c < B; ++c) S.red[t >> 6][jr][c] = acc[c];
+  __syncthreads();
+  for (int e = t; e < kSubRows * B; e += kSubThreads) {
+    const int r2 = e % kSubRows, c = e / kSubRows;
+    const double v = (S.red[0][r2][c] + S.red[1][r2][c]) + (S.red[2][r2][c] + S.red[3][r2][c]);
+    dst[r2][c] = j0 + r2 < n ? v : 0.0;
+  }
+  __syncthreads();
+}
+
+// dst[c1 B + c2] = sum_jr X[jr][c1] C[jr][c2]: this workgroup's share of X^T C.
+template <int B>
+__device__ __forceinline__ void put_partial(const double (*X)[kSubStride],
+                                            const double (*C)[kSubStride], gdouble dst) {
+  for (int e = threadIdx.x; e < B * B; e += kSubThreads) {
+    const int c1 = e / B, c2 = e % B;
+    double s = 0.0;
+#pragma unroll
+    for (int jr = 0; jr < kSubRows; ++jr) s = fma(X[jr][c1], C[jr][c2], s);
+    dst[e] = s;
+  }
+}
+
+// dst[e / B][e % B] = sum over the gp ranks of src[rank * stride + e], in rank order (rank k
+// into running sum k mod 4, the four added pairwise at the end; 16 loads in flight).
+template <int B>
+__device__ __forceinline__ void sum_partials(gcdouble src, int64_t stride, int gp,
+                                             double (*dst)[kSubStride]) {
+  for (int e = threadIdx.x; e < B * B; e += kSubThreads) {
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 16 <= gp; k += 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = src[(k + u) * stride + e];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s4[u & 3] += v[u];
+    }
+    for (; k < gp; ++k) s4[k & 3] += src[k * stride + e];
+    dst[e / B][e % B] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+  }
+  __syncthreads();
+}
+
+// Wavefront 0: Bm = L L^T, rows of Bm in registers (lane i holds row i), L written back to
+// the lower triangle of Bm (the upper one is left as it was) and rdiag[k] = 1 / l_kk.  Step k
+// reads the pivot and the finished column k of L from the owning lanes (readlane), so no
+// step waits on LDS.  A pivot that is not positive (a numerically rank-deficient Gram
+// despite the shift) is replaced by the smallest normal number, which keeps the solve
+// finite.
+template <int B>
+__device__ void chol_wave(double (*Bm)[kSubStride], double* rdiag) {
+  const int lane = threadIdx.x;
+  const int i = lane < B ? lane : 0;
+  double a[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) a[j] = Bm[i][j];
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    double d = readlane_f64(a[k], k);
+    if (!(d > 0.0) || !isfinite(d)) d = 2.2250738585072014e-308;
+    const double piv = sqrt(d), inv = 1.0 / piv;
+    if (lane == k) {
+      a[k] = piv;
+      rdiag[k] = inv;
+    }
+    if (lane > k) a[k] *= inv;
+#pragma unroll
+    for (int j = k + 1; j < B; ++j) {
+      const double ljk = readlane_f64(a[k], j);
+      if (lane >= j) a[j] = fma(-a[k], ljk, a[j]);
+    }
+  }
+  if (lane < B)
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+      if (j <= lane) Bm[lane][j] = a[j];
+}
+
+// Rows of the iterate times R^{-1} (R = L^T): x L^T = y by forward substitution, one row per
+// thread in registers.
+template <int B>
+__device__ __forceinline__ void rows_solve(double (*Yr)[kSubStride], const double (*L)[kSubStride],
+                                           const double* rdiag) {
+  const int t = threadIdx.x;
+  if (t < kSubRows) {
+    double x[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) x[c] = Yr[t][c];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      double s = x[c];
+#pragma unroll
+      for (int k = 0; k < c; ++k) s = fma(-x[k], L[c][k], s);
+      x[c] = s * rdiag[c];
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) Yr[t][c] = x[c];
+  }
+  __syncthreads();
+}
+
+// Cyclic Jacobi with parallel (round-robin) ordering of the symmetric B x B matrix H in LDS
+// by wavefront 0: H_in = Q H_out Q^T with H_out diagonal to rounding.  Round k of a sweep
+// pairs the bb = B + (B odd) players by the circle method: pair 0 is (k, bb - 1), pair m > 0 is
+// (k + m, k - m) mod (bb - 1), so index i's partner is (2k - i) mod (bb - 1) (bb - 1 for k;
+// player B, when B is odd, sits the round out).  Lane m finds pair m's rotation: for
+// p < q, with c, s from the usual tau formula, column p becomes c col_p - s col_q and column
+// q becomes s col_p + c col_q (rows likewise); index p stores (c, s) and q (c, -s), making
+// both "cs[j] col_j - sn[j] col_partner(j)".  An element is rotated away only while it is
+// above both eps sqrt(|a_pp a_qq|) and 4 eps ||H||_F.  New entries are formed for the lower
+// triangle and mirrored, so H stays exactly symmetric.
+template <int B>
+__device__ void jacobi_wave(double (*H)[kSubStride], double (*Q)[kSubStride], SubShared& S) {
+  constexpr int bb = B + (B & 1);
+  constexpr int nr = bb - 1;
+  constexpr int nl = B * (B + 1) / 2;
+  constexpr int kH = (nl + 63) / 64, kQ = (B * B + 63) / 64;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < B * B; e += 64) Q[e / B][e % B] = (e / B == e % B) ? 1.0 : 0.0;
+  double f2 = 0.0;
+  for (int e = lane; e < B * B; e += 64) f2 = fma(H[e / B][e % B], H[e / B][e % B], f2);
+  f2 = wave_sum(f2);
+  const double floor_abs = 4.0 * kEps * sqrt(f2);
+  // the lane's lower-triangle elements (i >= j), packed index e = i (i + 1) / 2 + j
+  int li[kH], lj[kH];
+#pragma unroll
+  for (int k = 0; k < kH; ++k) {
+    const int e = lane + 64 * k;
+    int i = static_cast<int>((sqrtf(8.0f * static_cast<float>(e) + 1.0f) - 1.0f) * 0.5f);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    li[k] = i;
+    lj[k] = e - i * (i + 1) / 2;
+  }
+  wave_lds_fence();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    int rotated = 0;
+    for (int k = 0; k < nr; ++k) {
+      double c = 1.0, s = 0.0;
+      if (lane < bb / 2) {
+        int p = lane == 0 ? k : (k + lane) % nr;
+        int q = lane == 0 ? nr : (k - lane + nr) % nr;
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        if (q < B) {
+          const double apq = H[p][q], app = H[p][p], aqq = H[q][q];
+          if (apq * apq > kEps * kEps * fabs(app * aqq) && fabs(apq) > floor_abs) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            double tt;
+            if (fabs(tau) > 1e150) {
+              tt = 0.5 / tau;
+            } else {
+              tt = 1.0 / (fabs(tau) + sqrt(fma(tau, tau, 1.0)));
+              if (tau < 0.0) tt = -tt;
+            }
+            c = 1.0 / sqrt(fma(tt, tt, 1.0));
+            s = tt * c;
+            rotated = 1;
+          }
+        }
+      }
+      // index `lane`'s partner and rotation
+      int part = 0, m = 0;
+      if (lane == nr || lane == k) {
+        part = lane == nr ? k : nr;
+      } else {
+        part = (2 * k - lane + 2 * nr) % nr;
+        const int d = (lane - k + nr) % nr;
+        m = d <= (nr - 1) / 2 ? d : nr - d;
+      }
+      const double cm = __shfl(c, m, 64), sm = __shfl(s, m, 64);
+      if (lane < B) {
+        const bool on = part < B;
+        S.partner[lane] = on ? part : lane;
+        S.cs[lane] = on ? cm : 1.0;
+        S.sn[lane] = on ? (lane < part ? sm : -sm) : 0.0;
+      }
+      wave_lds_fence();
+      double hn[kH], qn[kQ];
+#pragma unroll
+      for (int u = 0; u < kH; ++u) {
+        hn[u] = 0.0;
+        if (lane + 64 * u < nl) {
+          const int i = li[u], j = lj[u];
+          const int ii = S.partner[i], jj = S.partner[j];
+          const double ci = S.cs[i], si = S.sn[i], cj = S.cs[j], sj = S.sn[j];
+          hn[u] = ci * (cj * H[i][j] - sj * H[i][jj]) - si * (cj * H[ii][j] - sj * H[ii][jj]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kQ; ++u) {
+        qn[u] = 0.0;
+        const int e = lane + 64 * u;
+        if (e < B * B) {
+          const int i = e / B, j = e % B;
+          qn[u] = S.cs[j] * Q[i][j] - S.sn[j] * Q[i][S.partner[j]];
+        }
+      }
+      wave_lds_fence();
+#pragma unroll
+      for (int u = 0; u < kH; ++u)
+        if (lane + 64 * u < nl) {
+          H[li[u]][lj[u]] = hn[u];
+          H[lj[u]][li[u]] = hn[u];
+        }
+#pragma unroll
+      for (int u = 0; u < kQ; ++u) {
+        const int e = lane + 64 * u;
+        if (e < B * B) Q[e / B][e % B] = qn[u];
+      }
+      wave_lds_fence();
+    }
+    if (!__any(rotated)) break;
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(kSubThreads) void k_subspace(const EigProb* __restrict__ probs,
+                                                          SubList list, int G, int ngroups) {
+  __shared__ SubShared S;
+  const int t = threadIdx.x;
+  const EigProb& P0 = probs[list.idx[0]];
+  if (t == 0) {
+    const uint32_t tk = atomicAdd(generic(&P0.scal->ticket), 1u);
+    S.group = static_cast<int>(tk / static_cast<uint32_t>(G));
+    S.rank = static_cast<int>(tk % static_cast<uint32_t>(G));
+    S.stop = 0;
+  }
+  __syncthreads();
+  const int group = S.group, rank = S.rank;
+  if (group >= ngroups) return;  // not reached: the grid is G x ngroups
+  RSM_GLOBAL uint32_t* ctr = &probs[list.idx[group]].scal->bar;
+  RSM_GLOBAL uint32_t* stalled = &P0.scal->stalled;
+  uint32_t arrivals = 0;
+  constexpr int64_t mstride = B * B;
+  for (int li = group; li < list.count; li += ngroups) {
+    const EigProb& P = probs[list.idx[li]];
+    const int n = static_cast<int>(P.n), r = P.r;
+    const int gp = static_cast<int>(ceil_div(P.n, kSubRows));
+    const int j0 = rank * kSubRows;
+    const bool act = rank < gp;
+    const uint32_t ld = static_cast<uint32_t>(P.npad);
+    const double lam_max = P.scal->lam_max;
+    gdouble sp_mat = P.SP;                                            // [2][gp][B^2]
+    gdouble sp_res = P.SP + 2 * static_cast<int64_t>(gp) * kEigMaxB * kEigMaxB;  // [gp][R]
+    int it = 0, next_check = 2;
+    double rel = 0.0, prev_rel = 0.0;
+    bool first_check = true;
+    while (!S.stop) {
+      ++it;
+      // Z = M X (rows j0.., i <= j0 + 15), then Y = M^T Z (i >= j0)
+      if (act) {
+        row_product<B>(P.M, ld, P.X, n, j0, 0, (j0 + kSubRows < n ? j0 + kSubRows : n), S, S.Yr);
+        for (int e = t; e < kSubRows * B; e += kSubThreads) {
+          const int r2 = e % kSubRows, c = e / kSubRows;
+          if (j0 + r2 < n) P.Z[(j0 + r2) + static_cast<int64_t>(c) * n] = S.Yr[r2][c];
+        }
+      }
+      group_barrier(ctr, stalled, arrivals, G, S);
+      if (S.stop) break;
+      if (act) row_product<B>(P.Mt, ld, P.Z, n, j0, j0, n, S, S.Yr);
+      // shifted Cholesky QR: a second pass always, a third when the first factor's diagonal
+      // spans more than 1e4 (cond(Y) beyond about 1e4 leaves the second pass's Gram
+      // ill conditioned); every workgroup takes the same decision from the same factor
+      int passes = 3;
+      for (int pass = 0; pass < passes && !S.stop; ++pass) {
+        gdouble buf = sp_mat + (pass & 1) * gp * mstride;
+        if (act) put_partial<B>(S.Yr, S.Yr, buf + rank * mstride);
+        group_barrier(ctr, stalled, arrivals, G, S);
+        if (S.stop) break;
+        sum_partials<B>(buf, mstride, gp, S.B);
+        if (pass == 0 && t == 0) {
+          double tr = 0.0;
+          for (int c = 0; c < B; ++c) tr += S.B[c][c];
+          const double shift = 11.0 * (static_cast<double>(n) * B + B * (B + 1.0)) * kUnit * tr;
+          for (int c = 0; c < B; ++c) S.B[c][c] += shift;
+        }
+        __syncthreads();
+        if (t < 64) chol_wave<B>(S.B, S.rdiag);
+        __syncthreads();
+        if (pass == 0) {
+          double dmin = S.B[0][0], dmax = S.B[0][0];
+          for (int c = 1; c < B; ++c) {
+            dmin = fmin(dmin, S.B[c][c]);
+            dmax = fmax(dmax, S.B[c][c]);
+          }
+          if (dmin >= 1e-4 * dmax) passes = 2;
+        }
+        rows_solve<B>(S.Yr, S.B, S.rdiag);
+      }
+      if (S.stop) break;
+      if (act)
+        for (int e = t; e < kSubRows * B; e += kSubThreads) {
+          const int r2 = e % kSubRows, c = e / kSubRows;
+          if (j0 + r2 < n) P.X[(j0 + r2) + static_cast<int64_t>(c) * n] = S.Yr[r2][c];
+        }
+      const bool check = it >= next_check || it >= kEigMaxIters;
+      group_barrier(ctr, stalled, arrivals, G, S);
+      if (S.stop || !check) continue;
+      // Rayleigh-Ritz: NX = N X, H = X^T N X
+      gdouble hbuf = sp_mat + gp * mstride;  // buffer 1 (last read in pass 1)
+      if (act) {
+        row_product<B>(P.Nsym, static_cast<uint32_t>(n), P.X, n, j0, 0, n, S, S.NYr);
+        put_partial<B>(S.Yr, S.NYr, hbuf + rank * mstride);
+      }
+      group_barrier(ctr, stalled, arrivals, G, S);
+      if (S.stop) break;
+      sum_partials<B>(hbuf, mstride, gp, S.B);
+      double hs[(B * B + kSubThreads - 1) / kSubThreads];
+#pragma unroll
+      for (int k = 0; k < (B * B + kSubThreads - 1) / kSubThreads; ++k) {
+        const int e = t + k * kSubThreads;
+        hs[k] = e < B * B ? 0.5 * (S.B[e / B][e % B] + S.B[e % B][e / B]) : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < (B * B + kSubThreads - 1) / kSubThreads; ++k) {
+        const int e = t + k * kSubThreads;
+        if (e < B * B) S.B[e / B][e % B] = hs[k];
+      }
+      __syncthreads();
+      if (t < 64) jacobi_wave<B>(S.B, S.Q, S);
+      __syncthreads();
+      if (t < B) {
+        const double dk = S.B[t][t];
+        int rk = 0;
+        for (int j = 0; j < B; ++j) {
+          const double dj = S.B[j][j];
+          rk += (dj < dk) || (dj == dk && j < t);
+        }
+        S.order[rk] = t;
+        S.th[rk] = dk;
+      }
+      __syncthreads();
+      // Ritz vectors (ascending) in this workgroup's rows, and the residual terms; thread
+      // (row, k) forms entry k of the row's rotated X and N X
+      for (int e = t; e < kSubRows * B; e += kSubThreads) {
+        const int r2 = e % kSubRows, k = e / kSubRows;
+        const int ok = S.order[k];
+        double xv = 0.0, yv = 0.0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+          xv = fma(S.Yr[r2][c], S.Q[c][ok], xv);
+          yv = fma(S.NYr[r2][c], S.Q[c][ok], yv);
+        }
+        S.red[1][r2][k] = xv;
+        S.red[2][r2][k] = yv;
+        const double rk = yv - S.th[k] * xv;
+        S.red[0][r2][k] = (j0 + r2 < n && k < r) ? rk * rk : 0.0;
+      }
+      __syncthreads();
+      for (int e = t; e < kSubRows * B; e += kSubThreads) {
+        const int r2 = e % kSubRows, k = e / kSubRows;
+        S.Yr[r2][k] = S.red[1][r2][k];
+        S.NYr[r2][k] = S.red[2][r2][k];
+      }
+      __syncthreads();
+      if (act) {
+        if (t < r) {
+          double s = 0.0;
+#pragma unroll
+          for (int jr = 0; jr < kSubRows; ++jr) s += S.red[0][jr][t];
+          sp_res[rank * RSM_MAX_R + t] = s;
+        }
+        for (int e = t; e < kSubRows * B; e += kSubThreads) {
+          const int r2 = e % kSubRows, c = e / kSubRows;
+          if (j0 + r2 < n) P.X[(j0 + r2) + static_cast<int64_t>(c) * n] = S.Yr[r2][c];
+        }
+      }
+      group_barrier(ctr, stalled, arrivals, G, S);
+      if (S.stop) break;
+      if (t < r) {
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < gp; ++q) s4[q & 3] += sp_res[q * RSM_MAX_R + t];
+        S.cs[t] = sqrt((s4[0] + s4[1]) + (s4[2] + s4[3]));
+      }
+      __syncthreads();
+      double rmax = 0.0;
+      for (int k = 0; k < r; ++k) rmax = fmax(rmax, S.cs[k]);
+      rel = lam_max > 0.0 ? rmax / lam_max : rmax;
+      __syncthreads();
+      const bool stalled_near_floor = !first_check && rel <= kSubFloor && rel > 0.5 * prev_rel;
+      if (rel <= kSubTol || stalled_near_floor || it >= kEigMaxIters) break;
+      first_check = false;
+      prev_rel = rel;
+      next_check = it + 1 + it / 4;
+    }
+    // V-hat = the r leading (smallest) Ritz vectors
+    if (act && !S.stop)
+      for (int e = t; e < kSubRows * r; e += kSubThreads) {
+        const int r2 = e % kSubRows, c = e / kSubRows;
+        if (j0 + r2 < n) P.V[(j0 + r2) + static_cast<int64_t>(c) * n] = S.Yr[r2][c];
+      }
+    if (rank == 0 && t == 0) {
+      RSM_GLOBAL rsm_info* info = P.info;
+      uint32_t warn = 0;
+      if (S.stop) {
+        warn |= RSM_W_NOT_CONVERGED;
+        info->residual = __builtin_nan("");
+      } else {
+        info->residual = rel;
+        for (int k = 0; k <= r && k < B; ++k) info->lambda[k] = S.th[k];
+        if (B > r && !(S.th[r] > 1e-12 * lam_max)) warn |= RSM_W_RANK_DEFICIENT;
+        if (rel > 1e-6) warn |= RSM_W_NOT_CONVERGED;
+      }
+      if (info->uncovered > 0) warn |= RSM_W_RANK_DEFICIENT;
+      if (P.scal->pivots > 0) warn |= RSM_W_PIVOT;
+      if (P.check_accepted && info->accepted == 0) warn |= RSM_W_NO_CONSTRAINTS;
+      atomicOr(generic(&info->warn), warn);
+      info->eig_iterations = it;
+    }
+    __syncthreads();
+  }
+}
+
+template <int B>
+void launch_subspace_b(const EigProb* dev, const SubList& list, int64_t n_max, hipStream_t s) {
+  const int G = static_cast<int>(ceil_div(n_max, kSubRows));
+  int ngroups = kSubMaxWgs / G;
+  if (ngroups < 1) ngroups = 1;
+  if (ngroups > list.count) ngroups = list.count;
+  k_subspace<B><<<static_cast<unsigned>(G * ngroups), kSubThreads, 0, s>>>(dev, list, G, ngroups);
+}
+
+template <int B>
+void launch_subspace(int b, const EigProb* dev, const SubList& list, int64_t n_max, hipStream_t s) {
+  if constexpr (B <= kSubMaxB) {
+    if (b == B)
+      launch_subspace_b<B>(dev, list, n_max, s);
+    else
+      launch_subspace<B + 1>(b, dev, list, n_max, s);
+  }
+}
 
 // Deterministic start block: entries uniform in [-1, 1) from Philox (key = seed, 1).
 __global__ void k_start_vectors(const EigProb* __restrict__ probs) {
@@ -709,459 +1254,6 @@ __global__ void k_start_vectors(const EigProb* __restrict__ probs) {
   P.X[idx] = static_cast<double>(static_cast<int64_t>(c[0]) >> 11) * (1.0 / 4503599627370496.0);
 }
 
-// Out[j, c] = sum_i A[j, i] In[i, c] for all c < b, split over workgroups (j-block of 16
-// rows, i-chunk of 256): each workgroup writes its chunk's share to AP[chunk][c][j] and
-// k_apply_sum adds the shares in chunk order (no atomics: the sum does not depend on
-// timing).  MODE 0: A = M (lower: i < j0 + 16), In = X, Out = Z.  MODE 1: A = Mt (upper:
-// i >= j0), In = Z, Out = NX.  MODE 2: A = Nsym (all i), In = X, Out = NX, and the sum also
-// forms the block's X[rows]^T NX[rows] share of the Rayleigh-Ritz matrix (into M, which is
-// free by then).  Thread (jr, kp) = (t % 16, t / 16) sums over i = kp mod 16; the 16
-// partial sums are added through LDS.  A chunk outside the operator's triangle writes
-// zeros.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_apply(const EigProb* __restrict__ probs, int nks) {
-  __shared__ double Xs[256][kEigMaxB + 1];
-  const EigProb& P = probs[blockIdx.y];
-  const int n = static_cast<int>(P.n);
-  const int b = P.b;
-  const int jb = static_cast<int>(blockIdx.x) / nks, ks = static_cast<int>(blockIdx.x) % nks;
-  const int j0 = jb * kRows;
-  if (j0 >= n || ks * 256 >= n) return;
-  gcdouble __restrict__ A = MODE == 0 ? P.M : (MODE == 1 ? P.Mt : P.Nsym);
-  const uint32_t lda = static_cast<uint32_t>(MODE == 2 ? P.n : P.npad);
-  gcdouble __restrict__ In = MODE == 1 ? P.Z : P.X;
-  const int tid = threadIdx.x;
-  const int jr = tid & (kRows - 1), kp = tid / kRows;
-  const uint32_t jrow = static_cast<uint32_t>((j0 + jr < n) ? (j0 + jr) : (n - 1));
-  int i_lo = MODE == 1 ? j0 : 0;
-  int i_hi = MODE == 0 ? ((j0 + kRows < n) ? (j0 + kRows) : n) : n;
-  i_lo = i_lo > ks * 256 ? i_lo : ks * 256;
-  i_hi = i_hi < ks * 256 + 256 ? i_hi : ks * 256 + 256;
-  double acc[kEigMaxB];
-#pragma unroll
-  for (int c = 0; c < kEigMaxB; ++c) acc[c] = 0.0;
-  if (i_lo < i_hi) {
-    const int c0 = i_lo;
-    const int cnt = i_hi - c0;
-    double mv[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int il = kp + 16 * s;
-      mv[s] = gld(A, jrow + static_cast<uint32_t>(c0 + (il < cnt ? il : 0)) * lda);
-      if (il >= cnt) mv[s] = 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < kEigMaxB; ++c) {
-      const bool ok = tid < cnt && c < b;
-      const double x = gld(In, static_cast<uint32_t>(c0 + (ok ? tid : 0)) +
-                                   static_cast<uint32_t>(ok ? c : 0) * static_cast<uint32_t>(n));
-      Xs[tid][c] = ok ? x : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int il = kp + 16 * s;
-#pragma unroll
-      for (int c = 0; c < kEigMaxB; ++c)
-        if (c < b) acc[c] = fma(mv[s], Xs[il][c], acc[c]);
-    }
-  }
-  __syncthreads();
-  auto red = reinterpret_cast<double (*)[kRows][kEigMaxB + 1]>(&Xs[0][0]);  // [kp][jr][c]
-#pragma unroll
-  for (int c = 0; c < kEigMaxB; ++c) red[kp][jr][c] = acc[c];
-  __syncthreads();
-  gdouble __restrict__ part = P.AP + static_cast<int64_t>(ks) * b * n;
-  for (int e = tid; e < kRows * b; e += 256) {
-    const int r2 = e % kRows, c = e / kRows;
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) s += red[q][r2][c];
-    if (j0 + r2 < n) gst(part, static_cast<uint32_t>(j0 + r2 + c * n), s);
-  }
-}
-
-// Out = the chunk shares of k_apply summed in chunk order, 16 rows per workgroup; MODE 2
-// also forms the block's share of the Rayleigh-Ritz matrix.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_apply_sum(const EigProb* __restrict__ probs) {
-  __shared__ double Ys[kRows][kEigMaxB + 1];
-  __shared__ double xr[kRows][kEigMaxB + 1];
-  const EigProb& P = probs[blockIdx.y];
-  const int n = static_cast<int>(P.n);
-  const int b = P.b;
-  const int j0 = static_cast<int>(blockIdx.x) * kRows;
-  if (j0 >= n) return;
-  const int nks = static_cast<int>(ceil_div(P.n, 256));
-  gdouble __restrict__ Out = MODE == 0 ? P.Z : P.NX;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kRows * b; e += 256) {
-    const int r2 = e % kRows, c = e / kRows;
-    const int j = j0 + r2;
-    double s = 0.0;
-    if (j < n) {
-      for (int ks = 0; ks < nks; ++ks)
-        s += gld(P.AP, static_cast<uint32_t>(ks * b * n + j + c * n));
-      gst(Out, static_cast<uint32_t>(j + c * n), s);
-    }
-    if (MODE == 2) {
-      Ys[r2][c] = s;
-      xr[r2][c] = (j < n) ? gld(P.X, static_cast<uint32_t>(j + c * n)) : 0.0;
-    }
-  }
-  if (MODE == 2) {
-    __syncthreads();
-    // this block's share of H, summed over the blocks in order by the Jacobi kernel
-    for (int e = tid; e < b * b; e += 256) {
-      const int i = e / b, j = e % b;
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < kRows; ++q) s += xr[q][i] * Ys[q][j];
-      P.M[static_cast<int64_t>(blockIdx.x) * b * b + e] = s;
-    }
-  }
-}
-
-// One orthonormalisation column K: X[:, K] -= X[:, :K] h twice (classical Gram-Schmidt
-// applied twice), then normalised.  x[s][c] holds rows tid + s NT.
-template <int NT, int RPT, int K>
-__device__ __forceinline__ void orth_cols(double (&x)[RPT][kEigMaxB], int b, double (*red)[32],
-                                          double* h) {
-  if constexpr (K < kEigMaxB) {
-    if (K < b) {
-      constexpr int NW = NT / 64;
-      const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-      if constexpr (K > 0) {
-        constexpr int NV = pow2_at_least<K>();
-#pragma unroll
-        for (int pass = 0; pass < 2; ++pass) {
-          double d[NV];
-#pragma unroll
-          for (int j = 0; j < NV; ++j) {
-            double p = 0.0;
-            if (j < K)
-#pragma unroll
-              for (int s = 0; s < RPT; ++s) p = fma(x[s][j], x[s][K], p);
-            d[j] = p;
-          }
-          int idx = 0;
-          sum_many<NV, 32>(d, lane, idx);
-          if ((lane & (64 / NV - 1)) == 0) red[wid][idx] = d[0];
-          __syncthreads();
-          if (tid < K) {
-            double s = 0.0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) s += red[w][tid];
-            h[tid] = s;
-          }
-          __syncthreads();
-#pragma unroll
-          for (int j = 0; j < K; ++j) {
-            const double hj = h[j];
-#pragma unroll
-            for (int s = 0; s < RPT; ++s) x[s][K] = fma(-hj, x[s][j], x[s][K]);
-          }
-        }
-      }
-      double p = 0.0;
-#pragma unroll
-      for (int s = 0; s < RPT; ++s) p = fma(x[s][K], x[s][K], p);
-      p = wave_sum(p);
-      __syncthreads();  // h of the last pass has been read
-      if (lane == 0) red[wid][0] = p;
-      __syncthreads();
-      double nrm2 = 0.0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) nrm2 += red[w][0];
-      const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-#pragma unroll
-      for (int s = 0; s < RPT; ++s) x[s][K] *= inv;
-      __syncthreads();  // red is reused by the next column
-      orth_cols<NT, RPT, K + 1>(x, b, red, h);
-    }
-  }
-}
-
-// X = orth(NX), one workgroup per problem, NT threads x 4 rows in registers (n <= 4 NT).
-template <int NT>
-__global__ __launch_bounds__(NT) void k_orth(const EigProb* __restrict__ probs) {
-  constexpr int RPT = 4;
-  __shared__ double red[NT / 64][32];
-  __shared__ double h[32];
-  const EigProb& P = probs[blockIdx.y];
-  const int64_t n = P.n;
-  const int b = P.b;
-  if (n > static_cast<int64_t>(NT) * RPT) return;  // the launcher picks NT from n
-  const int tid = threadIdx.x;
-  double x[RPT][kEigMaxB];
-#pragma unroll
-  for (int s = 0; s < RPT; ++s) {
-    const int64_t i = tid + static_cast<int64_t>(s) * NT;
-#pragma unroll
-    for (int c = 0; c < kEigMaxB; ++c) {
-      const bool ok = i < n && c < b;
-      const double v = P.NX[(ok ? i : 0) + static_cast<int64_t>(ok ? c : 0) * n];
-      x[s][c] = ok ? v : 0.0;
-    }
-  }
-  orth_cols<NT, RPT, 0>(x, b, red, h);
-#pragma unroll
-  for (int s = 0; s < RPT; ++s) {
-    const int64_t i = tid + static_cast<int64_t>(s) * NT;
-    if (i < n)
-#pragma unroll
-      for (int c = 0; c < kEigMaxB; ++c)
-        if (c < b) P.X[i + c * n] = x[s][c];
-  }
-}
-
-// ------------------------------------------------------------------ 5. Rayleigh-Ritz
-
-typedef double SmallMat[kEigMaxB + 1];
-
-// Parallel-ordering (round-robin) Jacobi on the symmetric b x b matrix H (LDS) by one
-// workgroup of 256 threads, thread t owning elements t and t + 256 of the row-major b x b
-// array.  Each round rotates floor(b/2) disjoint index pairs: the rotations are computed in
-// parallel, then applied as H <- J^T H J and Q <- Q J.  For a pair (p, q), p < q, with c, s
-// from the usual tau formula, column p becomes c col_p - s col_q and column q becomes
-// s col_p + c col_q (rows likewise); storing sn[q] = -s makes both "cs[j] col_j - sn[j]
-// col_partner".  An element is rotated away only while it is above both eps sqrt(|a_pp
-// a_qq|) and 4 eps ||H||_F (rounding keeps off-diagonal entries near eps ||H||).
-__device__ void jacobi_block(SmallMat* H, SmallMat* Q, int b, int* perm, double* cs, double* sn,
-                             int* partner, int* flag, double floor_abs) {
-  const int t = threadIdx.x;
-  const int bb = b + (b & 1);  // even number of players (one idle slot if b is odd)
-  const int nel = b * b;
-  const bool own0 = t < nel, own1 = t + 256 < nel;
-  const int i0 = t / b, j0 = t % b, i1 = (t + 256) / b, j1 = (t + 256) % b;
-  if (own0) Q[i0][j0] = i0 == j0 ? 1.0 : 0.0;
-  if (own1) Q[i1][j1] = i1 == j1 ? 1.0 : 0.0;
-  if (t < bb) perm[t] = t;
-  __syncthreads();
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    if (t == 0) *flag = 0;
-    __syncthreads();
-    for (int round = 0; round < bb - 1; ++round) {
-      if (t < bb) partner[t] = -1;
-      __syncthreads();
-      if (t < bb / 2) {
-        int p = perm[t], q = perm[bb - 1 - t];
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        if (q < b) {
-          double c = 1.0, s = 0.0;
-          const double apq = H[p][q], app = H[p][p], aqq = H[q][q];
-          if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            double tt;
-            if (fabs(tau) > 1e150) {
-              tt = 0.5 / tau;
-            } else {
-              tt = 1.0 / (fabs(tau) + sqrt(1.0 + tau * tau));
-              if (tau < 0.0) tt = -tt;
-            }
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            s = tt * c;
-            *flag = 1;
-          }
-          partner[p] = q;
-          partner[q] = p;
-          cs[p] = c;
-          sn[p] = s;
-          cs[q] = c;
-          sn[q] = -s;
-        }
-      }
-      __syncthreads();
-      // H <- J^T H J and Q <- Q J for the owned elements (reads first, then writes)
-      double h0 = 0.0, h1 = 0.0, q0 = 0.0, q1 = 0.0;
-      if (own0) {
-        const int pi = partner[i0], pj = partner[j0];
-        const double ci = pi >= 0 ? cs[i0] : 1.0, si = pi >= 0 ? sn[i0] : 0.0;
-        const double cj = pj >= 0 ? cs[j0] : 1.0, sj = pj >= 0 ? sn[j0] : 0.0;
-        const int ii = pi >= 0 ? pi : i0, jj = pj >= 0 ? pj : j0;
-        const double hij = H[i0][j0], hip = H[i0][jj], hpj = H[ii][j0], hpp = H[ii][jj];
-        h0 = ci * (cj * hij - sj * hip) - si * (cj * hpj - sj * hpp);
-        q0 = cj * Q[i0][j0] - sj * Q[i0][jj];
-      }
-      if (own1) {
-        const int pi = partner[i1], pj = partner[j1];
-        const double ci = pi >= 0 ? cs[i1] : 1.0, si = pi >= 0 ? sn[i1] : 0.0;
-        const double cj = pj >= 0 ? cs[j1] : 1.0, sj = pj >= 0 ? sn[j1] : 0.0;
-        const int ii = pi >= 0 ? pi : i1, jj = pj >= 0 ? pj : j1;
-        const double hij = H[i1][j1], hip = H[i1][jj], hpj = H[ii][j1], hpp = H[ii][jj];
-        h1 = ci * (cj * hij - sj * hip) - si * (cj * hpj - sj * hpp);
-        q1 = cj * Q[i1][j1] - sj * Q[i1][jj];
-      }
-      __syncthreads();
-      if (own0) {
-        H[i0][j0] = h0;
-        Q[i0][j0] = q0;
-      }
-      if (own1) {
-        H[i1][j1] = h1;
-        Q[i1][j1] = q1;
-      }
-      __syncthreads();
-      // keep H exactly symmetric; circle method for the next round (player 0 fixed)
-      double a0 = 0.0, a1 = 0.0;
-      if (own0) a0 = 0.5 * (H[i0][j0] + H[j0][i0]);
-      if (own1) a1 = 0.5 * (H[i1][j1] + H[j1][i1]);
-      int nxt = 0;
-      if (t < bb) nxt = t == 0 ? perm[0] : (t == 1 ? perm[bb - 1] : perm[t - 1]);
-      __syncthreads();
-      if (own0) H[i0][j0] = a0;
-      if (own1) H[i1][j1] = a1;
-      if (t < bb) perm[t] = nxt;
-      __syncthreads();
-    }
-    if (*flag == 0) break;
-    __syncthreads();
-  }
-}
-
-// Small part of Rayleigh-Ritz (one workgroup per problem): Jacobi of H, eigenvalues sorted
-// ascending; writes Qs = Q with its columns in that order and theta; clears res2.
-__global__ __launch_bounds__(256) void k_rr_small(const EigProb* __restrict__ probs) {
-  __shared__ SmallMat H[kEigMaxB];
-  __shared__ SmallMat Q[kEigMaxB];
-  __shared__ int perm[kEigMaxB + 1];
-  __shared__ double cs[kEigMaxB + 1];
-  __shared__ double sn[kEigMaxB + 1];
-  __shared__ int partner[kEigMaxB + 1];
-  __shared__ int flag;
-  __shared__ int order[kEigMaxB];
-  __shared__ double red[4];
-  const EigProb& P = probs[blockIdx.y];
-  const int b = P.b;
-  const int t = threadIdx.x;
-  // H = sum of the blocks' shares (in block order), then symmetrised
-  const int nblk = static_cast<int>(ceil_div(P.n, kRows));
-  for (int e = t; e < b * b; e += 256) {
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < nblk; k0 += 4) {
-      double x[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = P.M[static_cast<int64_t>(k0 + u < nblk ? k0 + u : 0) * b * b + e];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) s4[u] += (k0 + u < nblk) ? x[u] : 0.0;
-    }
-    H[e / b][e % b] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-  }
-  __syncthreads();
-  double f2 = 0.0;
-  double hs[2] = {0.0, 0.0};
-  for (int e = t, k = 0; e < b * b; e += 256, ++k) {
-    const int i = e / b, j = e % b;
-    hs[k] = 0.5 * (H[i][j] + H[j][i]);
-    f2 += hs[k] * hs[k];
-  }
-  __syncthreads();
-  for (int e = t, k = 0; e < b * b; e += 256, ++k) H[e / b][e % b] = hs[k];
-  f2 = wave_sum(f2);
-  if ((t & 63) == 0) red[t >> 6] = f2;
-  __syncthreads();
-  f2 = red[0] + red[1] + red[2] + red[3];
-  jacobi_block(H, Q, b, perm, cs, sn, partner, &flag, 4.0 * 2.220446049250313e-16 * sqrt(f2));
-  __syncthreads();
-  if (t < b) {
-    const double dk = H[t][t];
-    int rk = 0;
-    for (int j = 0; j < b; ++j) {
-      const double dj = H[j][j];
-      rk += (dj < dk) || (dj == dk && j < t);
-    }
-    order[rk] = t;
-    P.small[kSmallTheta + rk] = dk;
-  }
-  __syncthreads();
-  for (int e = t; e < b * b; e += 256) {
-    const int j = e / b, k = e % b;  // Qs[j][k] = Q[j][order[k]]
-    P.small[kSmallQs + e] = Q[j][order[k]];
-  }
-}
-
-// V-hat = X Qs[:, :r] (thread per row) and the squared residual norms
-// ||NX q_k - theta_k X q_k||^2, accumulated into res2[k].
-__global__ __launch_bounds__(256) void k_rr_apply(const EigProb* __restrict__ probs) {
-  __shared__ double q[kEigMaxB * kEigMaxB];
-  __shared__ double th[kEigMaxB];
-  __shared__ double red[4][RSM_MAX_R];
-  const EigProb& P = probs[blockIdx.y];
-  const int64_t n = P.n;
-  const int b = P.b, r = P.r;
-  if (static_cast<int64_t>(blockIdx.x) * 256 >= n) return;
-  const int tid = threadIdx.x, lane = tid & 63;
-  for (int e = tid; e < b * b; e += 256) q[e] = P.small[kSmallQs + e];
-  if (tid < b) th[tid] = P.small[kSmallTheta + tid];
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + tid;
-  const bool act = i < n;
-  double x[kEigMaxB], y[kEigMaxB];
-#pragma unroll
-  for (int j = 0; j < kEigMaxB; ++j) {
-    const bool ok = act && j < b;
-    const int64_t at = (ok ? i : 0) + static_cast<int64_t>(ok ? j : 0) * n;
-    const double xv = P.X[at], yv = P.NX[at];
-    x[j] = ok ? xv : 0.0;
-    y[j] = ok ? yv : 0.0;
-  }
-  __syncthreads();
-  double res[RSM_MAX_R];
-#pragma unroll
-  for (int k = 0; k < RSM_MAX_R; ++k) {
-    double v = 0.0, rs = 0.0;
-    if (k < r) {
-#pragma unroll
-      for (int j = 0; j < kEigMaxB; ++j) {
-        if (j < b) {
-          const double qj = q[j * b + k];
-          v = fma(x[j], qj, v);
-          rs = fma(y[j] - th[k] * x[j], qj, rs);
-        }
-      }
-      if (act) P.V[i + k * n] = v;
-    }
-    res[k] = rs * rs;
-  }
-  int idx = 0;
-  sum_many<RSM_MAX_R, 32>(res, lane, idx);
-  if ((lane & 3) == 0) red[tid >> 6][idx] = res[0];
-  __syncthreads();
-  // this block's squared residuals (into T, free by then), summed in block order by k_rr_finish
-  if (tid < r)
-    P.T[static_cast<int64_t>(blockIdx.x) * RSM_MAX_R + tid] =
-        (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-}
-
-__global__ void k_rr_finish(const EigProb* __restrict__ probs) {
-  const EigProb& P = probs[blockIdx.y];
-  if (threadIdx.x != 0) return;
-  const int b = P.b, r = P.r;
-  gcdouble theta = P.small + kSmallTheta;
-  const double lam_max = P.scal->lam_max;
-  const int nblk = static_cast<int>(ceil_div(P.n, 256));
-  double rmax = 0.0;
-  for (int k = 0; k < r; ++k) {
-    double s = 0.0;
-    for (int blk = 0; blk < nblk; ++blk) s += P.T[static_cast<int64_t>(blk) * RSM_MAX_R + k];
-    rmax = fmax(rmax, sqrt(s));
-  }
-  const double rel = lam_max > 0.0 ? rmax / lam_max : rmax;
-  RSM_GLOBAL rsm_info* info = P.info;
-  info->residual = rel;
-  for (int k = 0; k <= r && k < b; ++k) info->lambda[k] = theta[k];
-  uint32_t warn = 0;
-  if (info->uncovered > 0) warn |= RSM_W_RANK_DEFICIENT;
-  if (b > r && !(theta[r] > 1e-12 * lam_max)) warn |= RSM_W_RANK_DEFICIENT;
-  if (rel > 1e-6) warn |= RSM_W_NOT_CONVERGED;
-  if (P.scal->pivots > 0) warn |= RSM_W_PIVOT;
-  if (P.check_accepted && info->accepted == 0) warn |= RSM_W_NO_CONSTRAINTS;
-  atomicOr(generic(&info->warn), warn);
-  info->eig_iterations = kEigIters;
-}
 
 }  // namespace
 
@@ -1196,24 +1288,23 @@ void launch_solve_v(const EigProb* host, int nprob, EigProb* dev, hipStream_t s)
     k_inv_stage2<<<dim3(grid, np), 256, 0, s>>>(dev, bs);
   }
   k_start_vectors<<<dim3(static_cast<unsigned>(ceil_div(n_max * kEigMaxB, 256)), np), 256, 0, s>>>(dev);
-  const unsigned g_rows16 = static_cast<unsigned>(ceil_div(n_max, kRows));
-  const int nks = static_cast<int>(ceil_div(n_max, 256));
-  const unsigned g_apply = g_rows16 * static_cast<unsigned>(nks);
-  for (int it = 0; it < kEigIters; ++it) {
-    k_apply<0><<<dim3(g_apply, np), 256, 0, s>>>(dev, nks);
-    k_apply_sum<0><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
-    k_apply<1><<<dim3(g_apply, np), 256, 0, s>>>(dev, nks);
-    k_apply_sum<1><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
-    if (n_max <= 4 * 256)
-      k_orth<256><<<dim3(1, np), 256, 0, s>>>(dev);
-    else
-      k_orth<512><<<dim3(1, np), 512, 0, s>>>(dev);
+  // the subspace iteration: one launch per subspace width b (and per kLaunchMax problems)
+  for (int b = kSubMinB; b <= kSubMaxB; ++b) {
+    SubList list;
+    list.count = 0;
+    int64_t nb_n = 0;
+    for (int k = 0; k <= nprob; ++k) {
+      if (k < nprob && host[k].b == b) {
+        list.idx[list.count++] = k;
+        nb_n = host[k].n > nb_n ? host[k].n : nb_n;
+      }
+      if (list.count == kLaunchMax || (k == nprob && list.count > 0)) {
+        launch_subspace<kSubMinB>(b, dev, list, nb_n, s);
+        list.count = 0;
+        nb_n = 0;
+      }
+    }
   }
-  k_apply<2><<<dim3(g_apply, np), 256, 0, s>>>(dev, nks);
-  k_apply_sum<2><<<dim3(g_rows16, np), 256, 0, s>>>(dev);
-  k_rr_small<<<dim3(1, np), 256, 0, s>>>(dev);
-  k_rr_apply<<<dim3(static_cast<unsigned>(ceil_div(n_max, 256)), np), 256, 0, s>>>(dev);
-  k_rr_finish<<<dim3(1, np), 64, 0, s>>>(dev);
 }
 
 }  // namespace rsm

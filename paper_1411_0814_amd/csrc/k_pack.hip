@@ -180,7 +180,9 @@ __global__ void k_init_info(const ProbDesc* __restrict__ probs, IdxList list) {
     scal->lam_max = 0.0;
     scal->err_acc = 0.0;
     scal->pivots = 0;
-    scal->pad = 0;
+    scal->bar = 0;
+    scal->ticket = 0;
+    scal->stalled = 0;
   }
   if (threadIdx.x < RSM_MAX_R + 1) info->lambda[threadIdx.x] = 0.0;
 }

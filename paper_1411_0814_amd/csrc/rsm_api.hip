@@ -192,9 +192,7 @@ void set_layout(Plan& P) {
   const size_t nbv = static_cast<size_t>(P.n) * P.eig_b * sizeof(double);
   P.off_X = carve(cur, nbv);
   P.off_Z = carve(cur, nbv);
-  P.off_NX = carve(cur, nbv);
-  P.off_AP = carve(cur, static_cast<size_t>(ceil_div(P.n, 256)) * nbv);
-  P.off_small = carve(cur, kSmallDoubles * sizeof(double));
+  P.off_SP = carve(cur, static_cast<size_t>(sub_partials(P.n)) * sizeof(double));
   if (P.u_mfma) {
     P.off_ab = carve(cur, static_cast<size_t>(P.m) * (P.r * (P.r + 1) / 2 + P.r) * sizeof(double));
     P.off_abcnt = carve(cur, static_cast<size_t>(P.m) * sizeof(int32_t));
@@ -394,9 +392,7 @@ EigProb eig_desc(const Plan& P, const rsm_output& out, void* ws) {
   e.T = gptr(at<double>(ws, P.off_T));
   e.X = gptr(at<double>(ws, P.off_X));
   e.Z = gptr(at<double>(ws, P.off_Z));
-  e.NX = gptr(at<double>(ws, P.off_NX));
-  e.AP = gptr(at<double>(ws, P.off_AP));
-  e.small = gptr(at<double>(ws, P.off_small));
+  e.SP = gptr(at<double>(ws, P.off_SP));
   e.scal = gptr(at<DevScalars>(ws, P.off_scal));
   e.V = gptr(out.V);
   e.info = gptr(out.info);

@@ -25,7 +25,7 @@ constexpr int kWave = 64;                 // CDNA wavefront width
 constexpr int kCholNB = 64;               // tile of the blocked Cholesky of N
 constexpr int kEigPad = 4;                // extra vectors in the subspace iteration for V-hat
 constexpr int kEigMaxB = RSM_MAX_R + kEigPad + 1;
-constexpr int kEigIters = 3;              // inverse-iteration steps
+constexpr int kEigMaxIters = 600;         // cap of the inverse-iteration steps
 constexpr size_t kTileLdsBytes = 148 * 1024;  // LDS budget of the Y tile of the tiled Gram
 constexpr int64_t kTileTargetGroups = 256;    // tiled Gram: workgroups to aim for (one per CU)
 
@@ -51,7 +51,9 @@ struct DevScalars {
   double lam_max;       // Gershgorin bound on lambda_max(N)
   double err_acc;       // sum of squared residuals for eq.(ep)
   int32_t pivots;       // clamped Cholesky pivots
-  int32_t pad;
+  uint32_t bar;         // arrival count of the subspace iteration's group barrier
+  uint32_t ticket;      // workgroup tickets of the subspace iteration (problem 0 only)
+  uint32_t stalled;     // set when a group barrier timed out (all groups then stop)
 };
 
 // How one problem is executed and where its scratch lives in the workspace.
@@ -86,19 +88,21 @@ struct Plan {
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
          off_rows = 0;
   size_t off_N = 0, off_Nsym = 0, off_L = 0, off_M = 0, off_Mt = 0, off_T = 0, off_X = 0,
-         off_Z = 0, off_NX = 0, off_AP = 0, off_small = 0, off_ab = 0, off_abcnt = 0,
+         off_Z = 0, off_SP = 0, off_ab = 0, off_abcnt = 0,
          off_mflag = 0, off_rbits = 0, off_yrow = 0, off_B = 0, off_cmask = 0, off_Qd = 0;
   size_t off_scal = 0;
   size_t total = 0;
 };
 
-// Small per-problem arrays of the V-hat solver (doubles, in this order): the sorted
-// eigenvectors Qs of the b x b Rayleigh-Ritz matrix and the Ritz values theta.  (The
-// Rayleigh-Ritz matrix and the residuals are summed from per-workgroup partials kept in the
-// solver's free matrices, in a fixed order, so that the result does not depend on timing.)
-constexpr int kSmallQs = 0;
-constexpr int kSmallTheta = kEigMaxB * kEigMaxB;
-constexpr int kSmallDoubles = kEigMaxB * kEigMaxB + kEigMaxB;
+// Subspace iteration of the V-hat solver: rows of the iterate per workgroup, and the
+// per-workgroup partial sums it exchanges (doubles): two alternating buffers of b x b
+// matrices (Gram and Rayleigh-Ritz matrices) and one of r squared residual norms, for
+// ceil(n / kSubRows) workgroups.  The partials are summed in workgroup order, so results do
+// not depend on timing.
+constexpr int kSubRows = 16;
+__host__ __device__ constexpr int64_t sub_partials(int64_t n) {
+  return (2 * kEigMaxB * kEigMaxB + RSM_MAX_R) * ((n + kSubRows - 1) / kSubRows);
+}
 
 // Device-side description of one V-hat solve (step a6).  The solver's kernels take an array
 // of these and run every problem of a batch in the same launch (problem = blockIdx.y); each
@@ -118,10 +122,8 @@ struct EigProb {
   RSM_GLOBAL double* Mt;       // (L^{-1})^T, npad x npad, upper tiles
   RSM_GLOBAL double* T;        // recursion temporary (npad/2 x npad/2); row-sum and residual partials
   RSM_GLOBAL double* X;        // n x b iterate
-  RSM_GLOBAL double* Z;        // n x b; its first n entries hold the row sums at the start
-  RSM_GLOBAL double* NX;       // n x b
-  RSM_GLOBAL double* AP;       // thin-product partials: [ceil(n / 256)][b][n]
-  RSM_GLOBAL double* small;    // kSmallDoubles
+  RSM_GLOBAL double* Z;        // n x b: L^{-1} X
+  RSM_GLOBAL double* SP;       // sub_partials(n) doubles: the iteration's partial sums
   RSM_GLOBAL DevScalars* scal;
   RSM_GLOBAL double* V;        // output n x r
   RSM_GLOBAL rsm_info* info;
