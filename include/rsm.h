@@ -116,8 +116,9 @@ enum {
                                     2^-40 resolution (integer atomics, order-free) instead
                                     of FP64 atomics.  Needs |N_ij| < 2^23 (at most 2^23
                                     trials per column pair); a caller's N given with
-                                    RSM_N_ACCUMULATE is first rounded to that grid.  The
-                                    optional error e is not covered. */
+                                    RSM_N_ACCUMULATE is first rounded to that grid.  (The
+                                    optional error e is summed in a fixed order with or
+                                    without this flag.) */
   RSM_ROWS_FIRST = 1u << 6       /* method M2 (Section III, rows first; see the top of
                                     this file).  Then `l` is the number k of rows per
                                     sub-matrix (0 => r + 1; r < k <= min(m, RSM_MAX_L),

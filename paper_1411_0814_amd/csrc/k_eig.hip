@@ -669,17 +669,15 @@ __global__ __launch_bounds__(256) void k_inv_stage2(const EigProb* __restrict__ 
 
 // ------------------------------------------------------------------ 4-5. subspace iteration
 //
-// Inverse subspace iteration and Rayleigh-Ritz run in one launch (k_subspace).  Each problem
-// is taken by a group of G = ceil(n_max / kSubRows) workgroups; workgroup `rank` owns rows
-// 16 rank .. 16 rank + 15 of the n x b iterate (ranks past the problem's own rows only keep
-// step).  A group's workgroups meet at group barriers: device-scope release fence, an
-// arrival count, device-scope acquire; a wait that exceeds its bound stops the launch and
-// flags RSM_W_NOT_CONVERGED instead of hanging.  Workgroups take their (group, rank) from a
-// ticket counter in the order they start, so a group only waits for workgroups that have
-// started after its own first ones: the groups whose workgroups have all started always
-// finish.  Data another workgroup wrote in this launch is read after a barrier, whose
-// release (writer) and acquire (reader) fences make it visible across the XCDs' caches.
-// One iteration:
+// Inverse subspace iteration and Rayleigh-Ritz run in one launch (k_subspace), one
+// workgroup per problem: a problem's iteration needs no other workgroup, so problems of a
+// batch, and calls on other streams, run side by side with no waiting between workgroups.
+// Thread t owns rows t and n - 1 - t of the n x b iterate, and t + T and n - 1 - t - T when
+// n > 2T (T threads; NR = 2 or 4 rows per thread, one kernel instance each): a short and a
+// long row of each triangular product per pair, which balances the wavefronts' work.
+// Products stream the operator's column segments of each wavefront's rows and the matching
+// rows of the right-hand block straight into that wavefront's own LDS buffers.  One
+// iteration:
 //   Z = M X, Y = M^T Z                       (M = L^{-1}: Y = (N + mu I)^{-1} X)
 //   Y <- Y R^{-1} two or three times, R^T R the Cholesky factorisation of the b x b Gram
 //   Y^T Y, the first with a shift: shifted Cholesky QR, orthonormal to rounding even when Y
@@ -690,222 +688,325 @@ __global__ __launch_bounds__(256) void k_inv_stage2(const EigProb* __restrict__ 
 // ascending, and the residuals ||N x_k - theta_k x_k|| of the r wanted pairs.  The
 // iteration stops when max_k residual <= kSubTol lam_max, when the residual, already below
 // kSubFloor lam_max, stops halving between checks (the rounding level of the factor), or
-// after kEigMaxIters steps.  Every partial sum (products, Grams, residuals) is formed per
-// workgroup and summed in rank order, so results do not depend on timing.
+// after kEigMaxIters steps.  Every sum runs in a fixed order, so results do not depend on
+// timing.
 
-constexpr int kSubChunk = 128;                    // values of i staged per chunk
+constexpr int kSubThreads = 512;
+constexpr int kSubWaves = kSubThreads / 64;
+constexpr int kStageMax = 1184;                   // doubles of one staging buffer (see below)
 constexpr int kSubStride = kEigMaxB + 1;          // LDS row stride of b-wide rows
-constexpr int kSubThreads = 256;
+constexpr int kGramRows = 64;                     // rows per block of the Gram reductions
 constexpr double kSubTol = 1e-10;                 // converged: residual / lam_max
 constexpr double kSubFloor = 1e-8;                // below this a stalled residual stops
-constexpr long long kSubWaitTicks = 400000000LL;  // bound of one barrier wait (wall clock)
-constexpr int kSubMaxWgs = 512;                   // workgroups of one launch at most
 constexpr int kSubMinB = 2, kSubMaxB = RSM_MAX_R + kEigPad;  // subspace widths built
 constexpr double kEps = 2.220446049250313e-16;
 constexpr double kUnit = 1.1102230246251565e-16;  // unit roundoff of FP64
 
 struct SubShared {
-  double stage[kSubChunk][kSubStride];  // staged rows of the right-hand block
-  double As[kSubChunk][kSubRows + 1];   // staged slab of the operator (transposed)
-  double red[4][kSubRows][kSubStride];  // per-wavefront partial sums
-  double Yr[kSubRows][kSubStride];      // this workgroup's rows of the iterate
-  double NYr[kSubRows][kSubStride];     // its rows of N X
-  double B[kEigMaxB][kSubStride];       // b x b Gram / Rayleigh-Ritz matrix
-  double Q[kEigMaxB][kSubStride];       // rotations of the Jacobi method
+  union {
+    double stage[kSubWaves][2][kStageMax];    // each wavefront's two staging buffers
+    struct {
+      double pb[kGramRows][kSubStride];       // a block of rows of P and C (Gram)
+      double cb[kGramRows][kSubStride];
+      double part[kSubThreads];               // slice partials of the Gram entries
+    } g;
+  };
+  double wred[kSubWaves][RSM_MAX_R];          // per-wavefront residual sums
+  double B[kEigMaxB][kSubStride];             // b x b Gram / Rayleigh-Ritz matrix
+  double Q[kEigMaxB][kSubStride];             // rotations of the Jacobi method
   double cs[kEigMaxB + 1], sn[kEigMaxB + 1], th[kEigMaxB + 1], rdiag[kEigMaxB + 1];
   int partner[kEigMaxB + 1], order[kEigMaxB];
-  int stop;                             // a barrier wait failed: stop
-  int group, rank;
 };
 
-// Problems of one k_subspace launch (they share the subspace width b).
+// Problems of one k_subspace launch (they share the subspace width b and the rows per
+// thread).
 struct SubList {
   int32_t count;
   int32_t idx[kLaunchMax];
 };
 
-// The group barrier.  `arrivals` counts this workgroup's barriers times G (every workgroup
-// of a group calls it equally often), so the k-th barrier waits for k G arrivals.
-__device__ void group_barrier(RSM_GLOBAL uint32_t* ctr, RSM_GLOBAL uint32_t* stalled,
-                              uint32_t& arrivals, uint32_t G, SubShared& S) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  arrivals += G;
-  if (threadIdx.x == 0 && !S.stop) {
-    uint32_t* c = (uint32_t*)ctr;
-    uint32_t* st = (uint32_t*)stalled;
-    __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    const long long t0 = wall_clock64();
-    while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < arrivals) {
-      if (__hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-          wall_clock64() - t0 > kSubWaitTicks) {
-        __hip_atomic_store(st, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        S.stop = 1;
-        break;
+// The rows of this thread (NR of them; on[q] false where the row does not exist).
+template <int NR>
+struct SubRows {
+  int row[NR];
+  bool on[NR];
+};
+
+template <int NR>
+__device__ __forceinline__ SubRows<NR> sub_rows(int n) {
+  SubRows<NR> R;
+  const int t = threadIdx.x, h = (n + 1) / 2;
+#pragma unroll
+  for (int p = 0; p < NR / 2; ++p) {
+    const int tp = t + p * kSubThreads;
+    const bool own = tp < h;
+    R.row[2 * p] = own ? tp : 0;
+    R.row[2 * p + 1] = own ? n - 1 - tp : 0;
+    R.on[2 * p] = own;
+    R.on[2 * p + 1] = own && n - 1 - tp != tp;
+  }
+  return R;
+}
+
+// n made opaque to the optimiser at each use, so that the row addresses are formed where
+// they are used rather than kept live in registers across the whole iteration loop.
+__device__ __forceinline__ int opaque(int n) {
+  int u = __builtin_amdgcn_readfirstlane(n);
+  asm volatile("" : "+s"(u));
+  return u;
+}
+
+// Staging of the products: NR row segments of 64 rows per wavefront, K columns of the
+// operator per stage (8 with two segments, 4 with four), and the stage's K rows of the
+// right-hand block (as [column][stage row]); the doubles of one buffer.
+template <int NR>
+constexpr int stage_cols() { return NR == 2 ? 8 : 4; }
+template <int B, int NR>
+constexpr int stage_xs() { return (stage_cols<NR>() * B + 31) / 32 * 32; }
+template <int B, int NR>
+constexpr int stage_doubles() { return NR * stage_cols<NR>() * 64 + stage_xs<B, NR>(); }
+static_assert(stage_doubles<kSubMaxB, 2>() <= kStageMax &&
+              stage_doubles<kSubMaxB, 4>() <= kStageMax, "staging buffer");
+
+__device__ __forceinline__ void lds_dma_dword(const void* src, double* dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
+}
+
+// The thread's rows of A In (A n x n column-major with leading dimension lda, In n x B
+// column-major with leading dimension n) into y.  SHAPE 1: A is lower triangular (columns
+// i <= row); 2: upper (i >= row); 0: full.  Each wavefront streams the operator's column
+// segments of its own rows (64 consecutive rows per segment; the second segment runs down
+// from n - 1 - 64 w, so lane l reads it backwards) and the stage's rows of In straight into
+// its own two LDS buffers (global_load_lds_dword: lane k writes 4 bytes at base + 4 k), the
+// next stage in flight while the current one is summed; no wavefront waits for another.
+// A stage no row of a segment needs (the triangle's empty part) is neither loaded nor
+// summed.
+template <int B, int SHAPE, int NR>
+__device__ void rows_times(gcdouble __restrict__ A, uint32_t lda, gcdouble In, int n,
+                           const SubRows<NR>& R, SubShared& S, double (&y)[NR][B]) {
+  constexpr int K = stage_cols<NR>();
+  constexpr int XS = stage_xs<B, NR>();
+  constexpr int XI = XS / 32;  // instructions for the right-hand rows
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
+#pragma unroll
+    for (int c = 0; c < B; ++c) y[q][c] = 0.0;
+  if (!__any(R.on[0])) return;
+  int sb[NR];  // first row of each segment
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int t0 = 64 * w + (q >> 1) * kSubThreads;
+    sb[q] = (q & 1) ? n - t0 - 64 : t0;
+  }
+  double* const buf0 = &S.stage[w][0][0];
+  double* const buf1 = &S.stage[w][1][0];
+  auto seg_needed = [&](int q, int i_lo, int i_hi) {
+    const int rq = R.row[q];
+    const bool nd = R.on[q] && (SHAPE == 1 ? i_lo <= rq : (SHAPE == 2 ? i_hi >= rq : true));
+    return __any(nd) != 0;
+  };
+  auto issue = [&](int i0, double* dst) {
+    const int i_hi = (i0 + K - 1 < n - 1) ? (i0 + K - 1) : (n - 1);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      if (!seg_needed(q, i0, i_hi)) continue;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = (i0 + k < n) ? i0 + k : n - 1;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          int row = sb[q] + 32 * hh + (lane >> 1);
+          row = row < 0 ? 0 : (row > n - 1 ? n - 1 : row);
+          const uint64_t off =
+              (static_cast<uint64_t>(static_cast<uint32_t>(row) + static_cast<uint32_t>(i) * lda) << 3) +
+              4 * (lane & 1);
+          lds_dma_dword((const void*)(reinterpret_cast<RSM_GLOBAL const char*>(A) + off),
+                        dst + (q * K + k) * 64 + 32 * hh);
+        }
       }
-      __builtin_amdgcn_s_sleep(2);
+    }
+#pragma unroll
+    for (int u = 0; u < XI; ++u) {
+      const int d = 64 * u + lane, dd = d >> 1;
+      const int c = dd / K, kk = dd % K;
+      const int i = (i0 + kk < n) ? i0 + kk : n - 1;
+      const int cc = c < B ? c : 0;
+      const uint64_t off =
+          (static_cast<uint64_t>(static_cast<uint32_t>(i) +
+                                 static_cast<uint32_t>(cc) * static_cast<uint32_t>(n)) << 3) +
+          4 * (d & 1);
+      lds_dma_dword((const void*)(reinterpret_cast<RSM_GLOBAL const char*>(In) + off),
+                    dst + NR * K * 64 + 32 * u);
+    }
+  };
+  const int stages = (n + K - 1) / K;
+  issue(0, buf0);
+  for (int st = 0; st < stages; ++st) {
+    __builtin_amdgcn_s_waitcnt(0);  // stage st has landed; the other buffer's reads are done
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+    if (st + 1 < stages) issue((st + 1) * K, (st & 1) ? buf0 : buf1);
+    const double* cur = (st & 1) ? buf1 : buf0;
+    const double* xs = cur + NR * K * 64;
+    const int i0 = st * K;
+    const int kn = (n - i0) < K ? (n - i0) : K;
+#pragma unroll 1
+    for (int k = 0; k < kn; ++k) {
+      const int i = i0 + k;
+      double xv[B];
+#pragma unroll
+      for (int c = 0; c < B; ++c) xv[c] = xs[c * K + k];
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const int rq = R.row[q];
+        const bool nd = R.on[q] && (SHAPE == 1 ? i <= rq : (SHAPE == 2 ? i >= rq : true));
+        if (nd) {
+          const double a = cur[(q * K + k) * 64 + ((q & 1) ? 63 - lane : lane)];
+#pragma unroll
+          for (int c = 0; c < B; ++c) y[q][c] = fma(a, xv[c], y[q][c]);
+        }
+      }
     }
   }
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
 }
 
-// dst[jr][c] = sum_{lo <= i < hi} A[row_jr + i lda] In[i + c n] for c < B, row_jr = j0 + jr
-// (rows at or past n give zero rows).  Per chunk of kSubChunk values of i, the operator's
-// 16 x kSubChunk slab and the chunk's rows of In are staged in LDS (all loads of a chunk in
-// flight together); thread (jr, kp) = (t % 16, t / 16) sums i = kp mod 16 of the
-// chunk for all B columns, and the 16 partial sums of a row are added by two cross-lane
-// steps and then over the four wavefronts in order.  All threads.
+// The thread's rows into the n x B column-major array D.
+template <int B, int NR>
+__device__ __forceinline__ void put_rows(gdouble D, int n, const SubRows<NR>& R,
+                                         const double (&y)[NR][B]) {
+  const int nn = opaque(n);
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
+    if (R.on[q])
+#pragma unroll
+      for (int c = 0; c < B; ++c) D[R.row[q] + static_cast<int64_t>(c) * nn] = y[q][c];
+}
+
+// The thread's rows of the n x B column-major array D.
+template <int B, int NR>
+__device__ __forceinline__ void get_rows(gcdouble D, int n, const SubRows<NR>& R,
+                                         double (&y)[NR][B]) {
+  const int nn = opaque(n);
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
+#pragma unroll
+    for (int c = 0; c < B; ++c) y[q][c] = R.on[q] ? D[R.row[q] + static_cast<int64_t>(c) * nn] : 0.0;
+}
+
+// S.B = P^T C for the n x B column-major arrays P and C written by this workgroup (lower
+// triangle formed, upper mirrored; with C != P the two products X^T (N X) and its transpose
+// are averaged, so the result is exactly symmetric).  Blocks of kGramRows rows of P and C
+// are staged in LDS (coalesced loads down the columns); the NP = B (B + 1) / 2 entries get
+// SL slots (a power of two), and entry e (packed index) is summed by the threads
+// t = e + SL s over the block's rows j = s mod NS (NS = threads / SL), each slice keeping
+// one running sum over the blocks; the slices are added in order at the end.
 template <int B>
-__device__ void row_product(gcdouble __restrict__ A, uint32_t lda, gcdouble In, int n, int j0,
-                            int lo, int hi, SubShared& S, double (*dst)[kSubStride]) {
-  constexpr int kIn = (kSubChunk * B + kSubThreads - 1) / kSubThreads;  // In values per thread
-  constexpr int kA = kSubChunk * kSubRows / kSubThreads;                 // operator values
-  const int t = threadIdx.x, jr = t & 15, kp = t >> 4;
-  const uint32_t row = static_cast<uint32_t>(j0 + jr < n ? j0 + jr : n - 1);
-  double acc[B];
-#pragma unroll
-  for (int c = 0; c < B; ++c) acc[c] = 0.0;
-  for (int i0 = lo; i0 < hi; i0 += kSubChunk) {
-    const int cnt = (hi - i0) < kSubChunk ? (hi - i0) : kSubChunk;
-    double xv[kIn], av[kA];
-#pragma unroll
-    for (int u = 0; u < kIn; ++u) {
-      const int e = t + u * kSubThreads, il = e % kSubChunk, c = e / kSubChunk;
-      const bool ok = c < B && il < cnt;
-      xv[u] = gld(In, static_cast<uint32_t>(i0 + (ok ? il : 0)) +
-                          static_cast<uint32_t>(ok ? c : 0) * static_cast<uint32_t>(n));
-      if (!ok) xv[u] = 0.0;
+__device__ __forceinline__ void gram_of(gcdouble P, gcdouble C, int n, SubShared& S) {
+  constexpr int NP = B * (B + 1) / 2;
+  constexpr int SL = NP <= 64 ? 64 : (NP <= 128 ? 128 : 256);
+  constexpr int NS = kSubThreads / SL;
+  static_assert(NP <= SL && SL <= kSubThreads, "Gram entries exceed their slots");
+  const int t = threadIdx.x, e = t % SL, s = t / SL;
+  int c1 = 0, c2 = 0;
+  if (e < NP) {
+    c1 = static_cast<int>((sqrtf(8.0f * static_cast<float>(e) + 1.0f) - 1.0f) * 0.5f);
+    while (c1 * (c1 + 1) / 2 > e) --c1;
+    while ((c1 + 1) * (c1 + 2) / 2 <= e) ++c1;
+    c2 = e - c1 * (c1 + 1) / 2;
+  }
+  const bool sym = P == C;
+  double acc = 0.0;
+  for (int j0 = 0; j0 < n; j0 += kGramRows) {
+    __syncthreads();  // the previous block (or other use of this LDS) is done
+    for (int x = t; x < kGramRows * B; x += kSubThreads) {
+      const int jr = x % kGramRows, c = x / kGramRows;
+      const int j = j0 + jr;
+      S.g.pb[jr][c] = j < n ? P[j + static_cast<int64_t>(c) * n] : 0.0;
+      if (!sym) S.g.cb[jr][c] = j < n ? C[j + static_cast<int64_t>(c) * n] : 0.0;
     }
-#pragma unroll
-    for (int u = 0; u < kA; ++u) {
-      const int il = kp + 16 * u;
-      av[u] = gld(A, row + static_cast<uint32_t>(i0 + (il < cnt ? il : 0)) * lda);
-      if (il >= cnt) av[u] = 0.0;
-    }
-    __syncthreads();  // the previous chunk has been used
-#pragma unroll
-    for (int u = 0; u < kIn; ++u) {
-      const int e = t + u * kSubThreads, il = e % kSubChunk, c = e / kSubChunk;
-      if (c < B) S.stage[il][c] = xv[u];
-    }
-#pragma unroll
-    for (int u = 0; u < kA; ++u) S.As[kp + 16 * u][jr] = av[u];
     __syncthreads();
-#pragma unroll 2
-    for (int il = kp; il < kSubChunk; il += 16) {
-      const double a = S.As[il][jr];
-#pragma unroll
-      for (int c = 0; c < B; ++c) acc[c] = fma(a, S.stage[il][c], acc[c]);
+    if (e < NP) {
+      const double (*cb)[kSubStride] = sym ? S.g.pb : S.g.cb;
+#pragma unroll 4
+      for (int jr = s; jr < kGramRows; jr += NS) {
+        acc = fma(S.g.pb[jr][c1], cb[jr][c2], acc);
+        if (!sym) acc = fma(S.g.pb[jr][c2], cb[jr][c1], acc);
+      }
     }
   }
-#pragma unroll
-  for (int c = 0; c < B; ++c) {
-    acc[c] += __shfl_xor(acc[c], 16, 64);
-    acc[c] += __shfl_xor(acc[c], 32, 64);
-  }
-  if ((t & 63) < 16)
-#pragma unroll
-    for (int c = 0; c < B; ++c) S.red[t >> 6][jr][c] = acc[c];
   __syncthreads();
-  for (int e = t; e < kSubRows * B; e += kSubThreads) {
-    const int r2 = e % kSubRows, c = e / kSubRows;
-    const double v = (S.red[0][r2][c] + S.red[1][r2][c]) + (S.red[2][r2][c] + S.red[3][r2][c]);
-    dst[r2][c] = j0 + r2 < n ? v : 0.0;
-  }
+  S.g.part[t] = acc;
   __syncthreads();
-}
-
-// dst[c1 B + c2] = sum_jr X[jr][c1] C[jr][c2]: this workgroup's share of X^T C.
-template <int B>
-__device__ __forceinline__ void put_partial(const double (*X)[kSubStride],
-                                            const double (*C)[kSubStride], gdouble dst) {
-  for (int e = threadIdx.x; e < B * B; e += kSubThreads) {
-    const int c1 = e / B, c2 = e % B;
-    double s = 0.0;
+  if (t < NP) {
+    double v = 0.0;
 #pragma unroll
-    for (int jr = 0; jr < kSubRows; ++jr) s = fma(X[jr][c1], C[jr][c2], s);
-    dst[e] = s;
-  }
-}
-
-// dst[e / B][e % B] = sum over the gp ranks of src[rank * stride + e], in rank order (rank k
-// into running sum k mod 4, the four added pairwise at the end; 16 loads in flight).
-template <int B>
-__device__ __forceinline__ void sum_partials(gcdouble src, int64_t stride, int gp,
-                                             double (*dst)[kSubStride]) {
-  for (int e = threadIdx.x; e < B * B; e += kSubThreads) {
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-    int k = 0;
-    for (; k + 16 <= gp; k += 16) {
-      double v[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = src[(k + u) * stride + e];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) s4[u & 3] += v[u];
-    }
-    for (; k < gp; ++k) s4[k & 3] += src[k * stride + e];
-    dst[e / B][e % B] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    for (int q = 0; q < NS; ++q) v += S.g.part[q * SL + t];
+    if (!sym) v *= 0.5;
+    int a1 = static_cast<int>((sqrtf(8.0f * static_cast<float>(t) + 1.0f) - 1.0f) * 0.5f);
+    while (a1 * (a1 + 1) / 2 > t) --a1;
+    while ((a1 + 1) * (a1 + 2) / 2 <= t) ++a1;
+    const int a2 = t - a1 * (a1 + 1) / 2;
+    S.B[a1][a2] = v;
+    S.B[a2][a1] = v;
   }
   __syncthreads();
 }
 
-// Wavefront 0: Bm = L L^T, rows of Bm in registers (lane i holds row i), L written back to
-// the lower triangle of Bm (the upper one is left as it was) and rdiag[k] = 1 / l_kk.  Step k
-// reads the pivot and the finished column k of L from the owning lanes (readlane), so no
-// step waits on LDS.  A pivot that is not positive (a numerically rank-deficient Gram
-// despite the shift) is replaced by the smallest normal number, which keeps the solve
-// finite.
+// Wavefront 0: Bm = L L^T in place in LDS (lower triangle; the upper one is left as it
+// was), rdiag[k] = 1 / l_kk.  Step k: the pivot, column k scaled by the lanes below it, then
+// the trailing lower triangle updated with each lane holding up to four fixed entries (i, j),
+// i >= j.  A pivot that is not positive (a numerically rank-deficient Gram despite the
+// shift) is replaced by the smallest normal number, which keeps the solve finite.
 template <int B>
 __device__ void chol_wave(double (*Bm)[kSubStride], double* rdiag) {
+  constexpr int NL = B * (B + 1) / 2;
+  constexpr int KE = (NL + 63) / 64;
   const int lane = threadIdx.x;
-  const int i = lane < B ? lane : 0;
-  double a[B];
+  int ei[KE], ej[KE];
 #pragma unroll
-  for (int j = 0; j < B; ++j) a[j] = Bm[i][j];
-#pragma unroll
+  for (int u = 0; u < KE; ++u) {
+    const int e = lane + 64 * u;
+    int i = static_cast<int>((sqrtf(8.0f * static_cast<float>(e) + 1.0f) - 1.0f) * 0.5f);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    ei[u] = e < NL ? i : -1;
+    ej[u] = e < NL ? e - i * (i + 1) / 2 : -1;
+  }
   for (int k = 0; k < B; ++k) {
-    double d = readlane_f64(a[k], k);
+    double d = Bm[k][k];
     if (!(d > 0.0) || !isfinite(d)) d = 2.2250738585072014e-308;
     const double piv = sqrt(d), inv = 1.0 / piv;
+    wave_lds_fence();
     if (lane == k) {
-      a[k] = piv;
+      Bm[k][k] = piv;
       rdiag[k] = inv;
     }
-    if (lane > k) a[k] *= inv;
+    if (lane > k && lane < B) Bm[lane][k] *= inv;
+    wave_lds_fence();
 #pragma unroll
-    for (int j = k + 1; j < B; ++j) {
-      const double ljk = readlane_f64(a[k], j);
-      if (lane >= j) a[j] = fma(-a[k], ljk, a[j]);
-    }
+    for (int u = 0; u < KE; ++u)
+      if (ej[u] > k) Bm[ei[u]][ej[u]] = fma(-Bm[ei[u]][k], Bm[ej[u]][k], Bm[ei[u]][ej[u]]);
+    wave_lds_fence();
   }
-  if (lane < B)
-#pragma unroll
-    for (int j = 0; j < B; ++j)
-      if (j <= lane) Bm[lane][j] = a[j];
 }
 
-// Rows of the iterate times R^{-1} (R = L^T): x L^T = y by forward substitution, one row per
-// thread in registers.
+// x L^T = y (R = L^T) for one row held in registers: forward substitution with rdiag[c]
+// = 1 / l_cc.
 template <int B>
-__device__ __forceinline__ void rows_solve(double (*Yr)[kSubStride], const double (*L)[kSubStride],
-                                           const double* rdiag) {
-  const int t = threadIdx.x;
-  if (t < kSubRows) {
-    double x[B];
+__device__ __forceinline__ void row_solve(double (&y)[B], const double (*L)[kSubStride],
+                                          const double* rdiag) {
 #pragma unroll
-    for (int c = 0; c < B; ++c) x[c] = Yr[t][c];
+  for (int c = 0; c < B; ++c) {
+    double s = y[c];
 #pragma unroll
-    for (int c = 0; c < B; ++c) {
-      double s = x[c];
-#pragma unroll
-      for (int k = 0; k < c; ++k) s = fma(-x[k], L[c][k], s);
-      x[c] = s * rdiag[c];
-    }
-#pragma unroll
-    for (int c = 0; c < B; ++c) Yr[t][c] = x[c];
+    for (int k = 0; k < c; ++k) s = fma(-y[k], L[c][k], s);
+    y[c] = s * rdiag[c];
+    __builtin_amdgcn_sched_barrier(0);  // keeps the loads of L in step (register pressure)
   }
-  __syncthreads();
 }
 
 // Cyclic Jacobi with parallel (round-robin) ordering of the symmetric B x B matrix H in LDS
@@ -919,7 +1020,8 @@ __device__ __forceinline__ void rows_solve(double (*Yr)[kSubStride], const doubl
 // above both eps sqrt(|a_pp a_qq|) and 4 eps ||H||_F.  New entries are formed for the lower
 // triangle and mirrored, so H stays exactly symmetric.
 template <int B>
-__device__ void jacobi_wave(double (*H)[kSubStride], double (*Q)[kSubStride], SubShared& S) {
+__device__ void jacobi_wave(double (*H)[kSubStride], double (*Q)[kSubStride], double* cs,
+                            double* sn, int* partner) {
   constexpr int bb = B + (B & 1);
   constexpr int nr = bb - 1;
   constexpr int nl = B * (B + 1) / 2;
@@ -983,9 +1085,9 @@ __device__ void jacobi_wave(double (*H)[kSubStride], double (*Q)[kSubStride], Su
       const double cm = __shfl(c, m, 64), sm = __shfl(s, m, 64);
       if (lane < B) {
         const bool on = part < B;
-        S.partner[lane] = on ? part : lane;
-        S.cs[lane] = on ? cm : 1.0;
-        S.sn[lane] = on ? (lane < part ? sm : -sm) : 0.0;
+        partner[lane] = on ? part : lane;
+        cs[lane] = on ? cm : 1.0;
+        sn[lane] = on ? (lane < part ? sm : -sm) : 0.0;
       }
       wave_lds_fence();
       double hn[kH], qn[kQ];
@@ -994,8 +1096,8 @@ __device__ void jacobi_wave(double (*H)[kSubStride], double (*Q)[kSubStride], Su
         hn[u] = 0.0;
         if (lane + 64 * u < nl) {
           const int i = li[u], j = lj[u];
-          const int ii = S.partner[i], jj = S.partner[j];
-          const double ci = S.cs[i], si = S.sn[i], cj = S.cs[j], sj = S.sn[j];
+          const int ii = partner[i], jj = partner[j];
+          const double ci = cs[i], si = sn[i], cj = cs[j], sj = sn[j];
           hn[u] = ci * (cj * H[i][j] - sj * H[i][jj]) - si * (cj * H[ii][j] - sj * H[ii][jj]);
         }
       }
@@ -1005,7 +1107,7 @@ __device__ void jacobi_wave(double (*H)[kSubStride], double (*Q)[kSubStride], Su
         const int e = lane + 64 * u;
         if (e < B * B) {
           const int i = e / B, j = e % B;
-          qn[u] = S.cs[j] * Q[i][j] - S.sn[j] * Q[i][S.partner[j]];
+          qn[u] = cs[j] * Q[i][j] - sn[j] * Q[i][partner[j]];
         }
       }
       wave_lds_fence();
@@ -1026,10 +1128,347 @@ __device__ void jacobi_wave(double (*H)[kSubStride], double (*Q)[kSubStride], Su
   }
 }
 
-template <int B>
+template <int B, int NR>
+__device__ __forceinline__ void subspace_one(const EigProb& P, SubShared& S) {
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int n = static_cast<int>(P.n), r = P.r;
+  const SubRows<NR> R = sub_rows<NR>(n);
+  const uint32_t ld = static_cast<uint32_t>(P.npad);
+  const double lam_max = P.scal->lam_max;
+  double y[NR][B];
+  int it = 0, next_check = 2;
+  double rel = 0.0, prev_rel = 0.0;
+  bool first_check = true;
+  while (true) {
+    ++it;
+    // Z = M X, then Y = M^T Z
+    rows_times<B, 1, NR>(P.M, ld, P.X, n, R, S, y);
+    put_rows<B, NR>(P.Z, n, R, y);
+    __syncthreads();
+    rows_times<B, 2, NR>(P.Mt, ld, P.Z, n, R, S, y);
+    // shifted Cholesky QR: a second pass always, a third when the first factor's diagonal
+    // spans more than 1e4 (cond(Y) beyond about 1e4 leaves the second pass's Gram
+    // ill conditioned)
+    int passes = 3;
+    put_rows<B, NR>(P.X, n, R, y);
+    for (int pass = 0; pass < passes; ++pass) {
+      gram_of<B>(P.X, P.X, n, S);
+      if (pass == 0 && t == 0) {
+        double tr = 0.0;
+        for (int c = 0; c < B; ++c) tr += S.B[c][c];
+        const double shift = 11.0 * (static_cast<double>(n) * B + B * (B + 1.0)) * kUnit * tr;
+        for (int c = 0; c < B; ++c) S.B[c][c] += shift;
+      }
+      __syncthreads();
+      if (t < 64) chol_wave<B>(S.B, S.rdiag);
+      __syncthreads();
+      if (pass == 0) {
+        double dmin = S.B[0][0], dmax = S.B[0][0];
+        for (int c = 1; c < B; ++c) {
+          dmin = fmin(dmin, S.B[c][c]);
+          dmax = fmax(dmax, S.B[c][c]);
+        }
+        if (dmin >= 1e-4 * dmax) passes = 2;
+      }
+      // the thread's rows, re-read (they are not held across the reduction and the factor)
+      get_rows<B, NR>(P.X, n, R, y);
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (R.on[q]) row_solve<B>(y[q], S.B, S.rdiag);
+      put_rows<B, NR>(P.X, n, R, y);
+    }
+    __syncthreads();
+    if (it < next_check && it < kEigMaxIters) continue;
+    // Rayleigh-Ritz: N X (into Z), H = X^T N X
+    rows_times<B, 0, NR>(P.Nsym, static_cast<uint32_t>(n), P.X, n, R, S, y);
+    put_rows<B, NR>(P.Z, n, R, y);
+    gram_of<B>(P.X, P.Z, n, S);
+    if (t < 64) jacobi_wave<B>(S.B, S.Q, S.cs, S.sn, S.partner);
+    __syncthreads();
+    if (t < B) {
+      const double dk = S.B[t][t];
+      int rk = 0;
+      for (int j = 0; j < B; ++j) {
+        const double dj = S.B[j][j];
+        rk += (dj < dk) || (dj == dk && j < t);
+      }
+      S.order[rk] = t;
+      S.th[rk] = dk;
+    }
+    __syncthreads();
+    // Ritz vectors (ascending) into the thread's rows of X, and per wavefront the squared
+    // residuals ||N x_k - theta_k x_k||^2 of the r wanted pairs over its rows
+    get_rows<B, NR>(P.X, n, R, y);
+    __syncthreads();  // every row read before any is overwritten
+#pragma unroll 1
+    for (int k = 0; k < B; ++k) {
+      const int ok = S.order[k];
+      const int nn = opaque(n);
+      double d2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        if (R.on[q]) {
+          const int rq = R.row[q];
+          double xv = 0.0, zv = 0.0;
+#pragma unroll
+          for (int c = 0; c < B; ++c) {
+            const double qc = S.Q[c][ok];
+            xv = fma(y[q][c], qc, xv);
+            zv = fma(P.Z[rq + static_cast<int64_t>(c) * nn], qc, zv);
+          }
+          P.X[rq + static_cast<int64_t>(k) * nn] = xv;
+          const double d = zv - S.th[k] * xv;
+          d2 = fma(d, d, d2);
+        }
+      }
+      if (k < r) {
+        const double v = wave_sum(d2);
+        if (lane == 0) S.wred[wid][k] = v;
+      }
+    }
+    __syncthreads();
+    if (t < r) {
+      double s2 = 0.0;
+      for (int w = 0; w < kSubThreads / 64; ++w) s2 += S.wred[w][t];
+      S.cs[t] = sqrt(s2);
+    }
+    __syncthreads();
+    double rmax = 0.0;
+    for (int k = 0; k < r; ++k) rmax = fmax(rmax, S.cs[k]);
+    rel = lam_max > 0.0 ? rmax / lam_max : rmax;
+    __syncthreads();
+    const bool stalled = !first_check && rel <= kSubFloor && rel > 0.5 * prev_rel;
+    if (rel <= kSubTol || stalled || it >= kEigMaxIters) break;
+    first_check = false;
+    prev_rel = rel;
+    next_check = it + 1 + it / 4;
+  }
+  // V-hat = the r leading (smallest) Ritz vectors, from the thread's rows of X
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
+    if (R.on[q])
+      for (int c = 0; c < r; ++c)
+        P.V[R.row[q] + static_cast<int64_t>(c) * n] = P.X[R.row[q] + static_cast<int64_t>(c) * n];
+  if (t == 0) {
+    RSM_GLOBAL rsm_info* info = P.info;
+    uint32_t warn = 0;
+    info->residual = rel;
+    for (int k = 0; k <= r && k < B; ++k) info->lambda[k] = S.th[k];
+    if (B > r && !(S.th[r] > 1e-12 * lam_max)) warn |= RSM_W_RANK_DEFICIENT;
+    if (rel > 1e-6) warn |= RSM_W_NOT_CONVERGED;
+    if (info->uncovered > 0) warn |= RSM_W_RANK_DEFICIENT;
+    if (P.scal->pivots > 0) warn |= RSM_W_PIVOT;
+    if (P.check_accepted && info->accepted == 0) warn |= RSM_W_NO_CONSTRAINTS;
+    atomicOr(generic(&info->warn), warn);
+    info->eig_iterations = it;
+  }
+}
+
+// The iteration of problem P with its subspace width as a compile-time constant.
+template <int B, int NR>
+__device__ __forceinline__ void subspace_dispatch(int b, const EigProb& P, SubShared& S) {
+  if constexpr (B <= kSubMaxB) {
+    if (b == B)
+      subspace_one<B, NR>(P, S);
+    else
+      subspace_dispatch<B + 1, NR>(b, P, S);
+  }
+}
+
+// One workgroup per problem of `list`, whatever their subspace widths.
+template <int NR>
 __global__ __launch_bounds__(kSubThreads) void k_subspace(const EigProb* __restrict__ probs,
-                                                          SubList list, int G, int ngroups) {
+                                                          SubList list) {
   __shared__ SubShared S;
+  const EigProb& P = probs[list.idx[blockIdx.x]];
+  subspace_dispatch<kSubMinB, NR>(P.b, P, S);
+}
+
+// Group form of the same iteration, for launches of at most kGroupMaxProblems problems: one
+// group of G = ceil(n_max / 16) workgroups takes the problems in turn, workgroup `rank`
+// owning rows 16 rank .. 16 rank + 15 of the iterate, so a single large problem is spread
+// over up to 128 CUs.  The workgroups meet at group barriers (device-scope release fence,
+// an arrival count, device-scope acquire) and take their rank from a ticket counter in the
+// order they start, so the group only waits for workgroups that have started.  A wait can
+// only fail to end if the waiting workgroups of this and other concurrent group launches
+// fill every workgroup slot of the device (two per CU): at G <= 64 (n <= 1024) that takes
+// more than seven such launches at once, at n = 2048 more than three; the wait is bounded
+// (about 4 s of wall clock), after which the launch stops and flags RSM_W_NOT_CONVERGED.
+// Partial sums are formed per workgroup and summed in rank order, so results do not depend
+// on timing.
+constexpr int kGrpChunk = 128;                    // values of i staged per chunk
+constexpr int kGrpThreads = 256;
+constexpr long long kSubWaitTicks = 400000000LL;  // bound of one barrier wait (wall clock)
+constexpr int kGroupMaxProblems = 4;              // launches up to this size use the group form
+
+struct GrpShared {
+  double stage[kGrpChunk][kSubStride];  // staged rows of the right-hand block
+  double As[kGrpChunk][kSubRows + 1];   // staged slab of the operator (transposed)
+  double red[4][kSubRows][kSubStride];  // per-wavefront partial sums
+  double Yr[kSubRows][kSubStride];      // this workgroup's rows of the iterate
+  double NYr[kSubRows][kSubStride];     // its rows of N X
+  double B[kEigMaxB][kSubStride];       // b x b Gram / Rayleigh-Ritz matrix
+  double Q[kEigMaxB][kSubStride];       // rotations of the Jacobi method
+  double cs[kEigMaxB + 1], sn[kEigMaxB + 1], th[kEigMaxB + 1], rdiag[kEigMaxB + 1];
+  int partner[kEigMaxB + 1], order[kEigMaxB];
+  int stop;                             // a barrier wait failed: stop
+  int group, rank;
+};
+
+
+// The group barrier.  `arrivals` counts this workgroup's barriers times G (every workgroup
+// of a group calls it equally often), so the k-th barrier waits for k G arrivals.
+__device__ void group_barrier(RSM_GLOBAL uint32_t* ctr, RSM_GLOBAL uint32_t* stalled,
+                              uint32_t& arrivals, uint32_t G, GrpShared& S) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  arrivals += G;
+  if (threadIdx.x == 0 && !S.stop) {
+    uint32_t* c = (uint32_t*)ctr;
+    uint32_t* st = (uint32_t*)stalled;
+    __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = wall_clock64();
+    while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < arrivals) {
+      if (__hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+          wall_clock64() - t0 > kSubWaitTicks) {
+        __hip_atomic_store(st, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        S.stop = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// dst[jr][c] = sum_{lo <= i < hi} A[row_jr + i lda] In[i + c n] for c < B, row_jr = j0 + jr
+// (rows at or past n give zero rows).  Per chunk of kGrpChunk values of i, the operator's
+// 16 x kGrpChunk slab and the chunk's rows of In are staged in LDS (all loads of a chunk in
+// flight together); thread (jr, kp) = (t % 16, t / 16) sums i = kp mod 16 of the
+// chunk for all B columns, and the 16 partial sums of a row are added by two cross-lane
+// steps and then over the four wavefronts in order.  All threads.
+template <int B>
+__device__ void row_product(gcdouble __restrict__ A, uint32_t lda, gcdouble In, int n, int j0,
+                            int lo, int hi, GrpShared& S, double (*dst)[kSubStride]) {
+  constexpr int kIn = (kGrpChunk * B + kGrpThreads - 1) / kGrpThreads;  // In values per thread
+  constexpr int kA = kGrpChunk * kSubRows / kGrpThreads;                 // operator values
+  const int t = threadIdx.x, jr = t & 15, kp = t >> 4;
+  const uint32_t row = static_cast<uint32_t>(j0 + jr < n ? j0 + jr : n - 1);
+  double acc[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) acc[c] = 0.0;
+  for (int i0 = lo; i0 < hi; i0 += kGrpChunk) {
+    const int cnt = (hi - i0) < kGrpChunk ? (hi - i0) : kGrpChunk;
+    double xv[kIn], av[kA];
+#pragma unroll
+    for (int u = 0; u < kIn; ++u) {
+      const int e = t + u * kGrpThreads, il = e % kGrpChunk, c = e / kGrpChunk;
+      const bool ok = c < B && il < cnt;
+      xv[u] = gld(In, static_cast<uint32_t>(i0 + (ok ? il : 0)) +
+                          static_cast<uint32_t>(ok ? c : 0) * static_cast<uint32_t>(n));
+      if (!ok) xv[u] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kA; ++u) {
+      const int il = kp + 16 * u;
+      av[u] = gld(A, row + static_cast<uint32_t>(i0 + (il < cnt ? il : 0)) * lda);
+      if (il >= cnt) av[u] = 0.0;
+    }
+    __syncthreads();  // the previous chunk has been used
+#pragma unroll
+    for (int u = 0; u < kIn; ++u) {
+      const int e = t + u * kGrpThreads, il = e % kGrpChunk, c = e / kGrpChunk;
+      if (c < B) S.stage[il][c] = xv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kA; ++u) S.As[kp + 16 * u][jr] = av[u];
+    __syncthreads();
+#pragma unroll 2
+    for (int il = kp; il < kGrpChunk; il += 16) {
+      const double a = S.As[il][jr];
+#pragma unroll
+      for (int c = 0; c < B; ++c) acc[c] = fma(a, S.stage[il][c], acc[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    acc[c] += __shfl_xor(acc[c], 16, 64);
+    acc[c] += __shfl_xor(acc[c], 32, 64);
+  }
+  if ((t & 63) < 16)
+#pragma unroll
+    for (int c = 0; c < B; ++c) S.red[t >> 6][jr][c] = acc[c];
+  __syncthreads();
+  for (int e = t; e < kSubRows * B; e += kGrpThreads) {
+    const int r2 = e % kSubRows, c = e / kSubRows;
+    const double v = (S.red[0][r2][c] + S.red[1][r2][c]) + (S.red[2][r2][c] + S.red[3][r2][c]);
+    dst[r2][c] = j0 + r2 < n ? v : 0.0;
+  }
+  __syncthreads();
+}
+
+// dst[c1 B + c2] = sum_jr X[jr][c1] C[jr][c2]: this workgroup's share of X^T C.
+template <int B>
+__device__ __forceinline__ void put_partial(const double (*X)[kSubStride],
+                                            const double (*C)[kSubStride], gdouble dst) {
+  for (int e = threadIdx.x; e < B * B; e += kGrpThreads) {
+    const int c1 = e / B, c2 = e % B;
+    double s = 0.0;
+#pragma unroll
+    for (int jr = 0; jr < kSubRows; ++jr) s = fma(X[jr][c1], C[jr][c2], s);
+    dst[e] = s;
+  }
+}
+
+// dst[e / B][e % B] = sum over the gp ranks of src[rank * stride + e], in rank order (rank k
+// into running sum k mod 4, the four added pairwise at the end; 16 loads in flight).
+template <int B>
+__device__ __forceinline__ void sum_partials(gcdouble src, int64_t stride, int gp,
+                                             double (*dst)[kSubStride]) {
+  for (int e = threadIdx.x; e < B * B; e += kGrpThreads) {
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 16 <= gp; k += 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = src[(k + u) * stride + e];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s4[u & 3] += v[u];
+    }
+    for (; k < gp; ++k) s4[k & 3] += src[k * stride + e];
+    dst[e / B][e % B] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+  }
+  __syncthreads();
+}
+
+// Rows of the iterate times R^{-1} (R = L^T): x L^T = y by forward substitution, one row per
+// thread in registers.
+template <int B>
+__device__ __forceinline__ void rows_solve(double (*Yr)[kSubStride], const double (*L)[kSubStride],
+                                           const double* rdiag) {
+  const int t = threadIdx.x;
+  if (t < kSubRows) {
+    double x[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) x[c] = Yr[t][c];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      double s = x[c];
+#pragma unroll
+      for (int k = 0; k < c; ++k) s = fma(-x[k], L[c][k], s);
+      x[c] = s * rdiag[c];
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) Yr[t][c] = x[c];
+  }
+  __syncthreads();
+}
+
+template <int B>
+__global__ __launch_bounds__(kGrpThreads) void k_subspace_group(const EigProb* __restrict__ probs,
+                                                          SubList list, int G, int ngroups) {
+  __shared__ GrpShared S;
   const int t = threadIdx.x;
   const EigProb& P0 = probs[list.idx[0]];
   if (t == 0) {
@@ -1063,7 +1502,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subspace(const EigProb* __restr
       // Z = M X (rows j0.., i <= j0 + 15), then Y = M^T Z (i >= j0)
       if (act) {
         row_product<B>(P.M, ld, P.X, n, j0, 0, (j0 + kSubRows < n ? j0 + kSubRows : n), S, S.Yr);
-        for (int e = t; e < kSubRows * B; e += kSubThreads) {
+        for (int e = t; e < kSubRows * B; e += kGrpThreads) {
           const int r2 = e % kSubRows, c = e / kSubRows;
           if (j0 + r2 < n) P.Z[(j0 + r2) + static_cast<int64_t>(c) * n] = S.Yr[r2][c];
         }
@@ -1102,7 +1541,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subspace(const EigProb* __restr
       }
       if (S.stop) break;
       if (act)
-        for (int e = t; e < kSubRows * B; e += kSubThreads) {
+        for (int e = t; e < kSubRows * B; e += kGrpThreads) {
           const int r2 = e % kSubRows, c = e / kSubRows;
           if (j0 + r2 < n) P.X[(j0 + r2) + static_cast<int64_t>(c) * n] = S.Yr[r2][c];
         }
@@ -1118,20 +1557,20 @@ __global__ __launch_bounds__(kSubThreads) void k_subspace(const EigProb* __restr
       group_barrier(ctr, stalled, arrivals, G, S);
       if (S.stop) break;
       sum_partials<B>(hbuf, mstride, gp, S.B);
-      double hs[(B * B + kSubThreads - 1) / kSubThreads];
+      double hs[(B * B + kGrpThreads - 1) / kGrpThreads];
 #pragma unroll
-      for (int k = 0; k < (B * B + kSubThreads - 1) / kSubThreads; ++k) {
-        const int e = t + k * kSubThreads;
+      for (int k = 0; k < (B * B + kGrpThreads - 1) / kGrpThreads; ++k) {
+        const int e = t + k * kGrpThreads;
         hs[k] = e < B * B ? 0.5 * (S.B[e / B][e % B] + S.B[e % B][e / B]) : 0.0;
       }
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < (B * B + kSubThreads - 1) / kSubThreads; ++k) {
-        const int e = t + k * kSubThreads;
+      for (int k = 0; k < (B * B + kGrpThreads - 1) / kGrpThreads; ++k) {
+        const int e = t + k * kGrpThreads;
         if (e < B * B) S.B[e / B][e % B] = hs[k];
       }
       __syncthreads();
-      if (t < 64) jacobi_wave<B>(S.B, S.Q, S);
+      if (t < 64) jacobi_wave<B>(S.B, S.Q, S.cs, S.sn, S.partner);
       __syncthreads();
       if (t < B) {
         const double dk = S.B[t][t];
@@ -1146,7 +1585,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subspace(const EigProb* __restr
       __syncthreads();
       // Ritz vectors (ascending) in this workgroup's rows, and the residual terms; thread
       // (row, k) forms entry k of the row's rotated X and N X
-      for (int e = t; e < kSubRows * B; e += kSubThreads) {
+      for (int e = t; e < kSubRows * B; e += kGrpThreads) {
         const int r2 = e % kSubRows, k = e / kSubRows;
         const int ok = S.order[k];
         double xv = 0.0, yv = 0.0;
@@ -1161,7 +1600,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subspace(const EigProb* __restr
         S.red[0][r2][k] = (j0 + r2 < n && k < r) ? rk * rk : 0.0;
       }
       __syncthreads();
-      for (int e = t; e < kSubRows * B; e += kSubThreads) {
+      for (int e = t; e < kSubRows * B; e += kGrpThreads) {
         const int r2 = e % kSubRows, k = e / kSubRows;
         S.Yr[r2][k] = S.red[1][r2][k];
         S.NYr[r2][k] = S.red[2][r2][k];
@@ -1174,7 +1613,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subspace(const EigProb* __restr
           for (int jr = 0; jr < kSubRows; ++jr) s += S.red[0][jr][t];
           sp_res[rank * RSM_MAX_R + t] = s;
         }
-        for (int e = t; e < kSubRows * B; e += kSubThreads) {
+        for (int e = t; e < kSubRows * B; e += kGrpThreads) {
           const int r2 = e % kSubRows, c = e / kSubRows;
           if (j0 + r2 < n) P.X[(j0 + r2) + static_cast<int64_t>(c) * n] = S.Yr[r2][c];
         }
@@ -1199,7 +1638,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subspace(const EigProb* __restr
     }
     // V-hat = the r leading (smallest) Ritz vectors
     if (act && !S.stop)
-      for (int e = t; e < kSubRows * r; e += kSubThreads) {
+      for (int e = t; e < kSubRows * r; e += kGrpThreads) {
         const int r2 = e % kSubRows, c = e / kSubRows;
         if (j0 + r2 < n) P.V[(j0 + r2) + static_cast<int64_t>(c) * n] = S.Yr[r2][c];
       }
@@ -1226,21 +1665,14 @@ __global__ __launch_bounds__(kSubThreads) void k_subspace(const EigProb* __restr
 }
 
 template <int B>
-void launch_subspace_b(const EigProb* dev, const SubList& list, int64_t n_max, hipStream_t s) {
-  const int G = static_cast<int>(ceil_div(n_max, kSubRows));
-  int ngroups = kSubMaxWgs / G;
-  if (ngroups < 1) ngroups = 1;
-  if (ngroups > list.count) ngroups = list.count;
-  k_subspace<B><<<static_cast<unsigned>(G * ngroups), kSubThreads, 0, s>>>(dev, list, G, ngroups);
-}
-
-template <int B>
-void launch_subspace(int b, const EigProb* dev, const SubList& list, int64_t n_max, hipStream_t s) {
+void launch_group(int b, const EigProb* dev, const SubList& list, int64_t n_max, hipStream_t s) {
   if constexpr (B <= kSubMaxB) {
-    if (b == B)
-      launch_subspace_b<B>(dev, list, n_max, s);
-    else
-      launch_subspace<B + 1>(b, dev, list, n_max, s);
+    if (b != B) {
+      launch_group<B + 1>(b, dev, list, n_max, s);
+      return;
+    }
+    const int G = static_cast<int>(ceil_div(n_max, kSubRows));
+    k_subspace_group<B><<<static_cast<unsigned>(G), kGrpThreads, 0, s>>>(dev, list, G, 1);
   }
 }
 
@@ -1288,20 +1720,37 @@ void launch_solve_v(const EigProb* host, int nprob, EigProb* dev, hipStream_t s)
     k_inv_stage2<<<dim3(grid, np), 256, 0, s>>>(dev, bs);
   }
   k_start_vectors<<<dim3(static_cast<unsigned>(ceil_div(n_max * kEigMaxB, 256)), np), 256, 0, s>>>(dev);
-  // the subspace iteration: one launch per subspace width b (and per kLaunchMax problems)
+  // the subspace iteration.  When at most kGroupMaxProblems problems need it, those that are
+  // not deterministic take the group form, one launch per subspace width (one group of
+  // ceil(n / 16) <= 128 workgroups taking the launch's problems in turn).  Every other
+  // problem - all of a larger call, and deterministic ones always, so that their result
+  // never depends on the rest of a batch - takes one workgroup of its own: one launch per
+  // rows per thread (and per kLaunchMax problems), all widths together.
+  const bool small = nprob <= kGroupMaxProblems;
+  auto grouped = [&](int k) { return small && !host[k].deterministic; };
   for (int b = kSubMinB; b <= kSubMaxB; ++b) {
     SubList list;
     list.count = 0;
     int64_t nb_n = 0;
-    for (int k = 0; k <= nprob; ++k) {
-      if (k < nprob && host[k].b == b) {
+    for (int k = 0; k < nprob; ++k)
+      if (grouped(k) && host[k].b == b) {
         list.idx[list.count++] = k;
         nb_n = host[k].n > nb_n ? host[k].n : nb_n;
       }
+    if (list.count) launch_group<kSubMinB>(b, dev, list, nb_n, s);
+  }
+  for (int four = 0; four < 2; ++four) {
+    SubList list;
+    list.count = 0;
+    for (int k = 0; k <= nprob; ++k) {
+      if (k < nprob && !grouped(k) && (host[k].n > 2 * kSubThreads) == (four != 0))
+        list.idx[list.count++] = k;
       if (list.count == kLaunchMax || (k == nprob && list.count > 0)) {
-        launch_subspace<kSubMinB>(b, dev, list, nb_n, s);
+        if (four)
+          k_subspace<4><<<static_cast<unsigned>(list.count), kSubThreads, 0, s>>>(dev, list);
+        else
+          k_subspace<2><<<static_cast<unsigned>(list.count), kSubThreads, 0, s>>>(dev, list);
         list.count = 0;
-        nb_n = 0;
       }
     }
   }

@@ -178,7 +178,6 @@ __global__ void k_init_info(const ProbDesc* __restrict__ probs, IdxList list) {
     info->e = __builtin_nan("");
     scal->mu = 0.0;
     scal->lam_max = 0.0;
-    scal->err_acc = 0.0;
     scal->pivots = 0;
     scal->bar = 0;
     scal->ticket = 0;

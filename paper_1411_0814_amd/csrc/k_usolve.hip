@@ -123,18 +123,22 @@ __global__ __launch_bounds__(256) void k_usolve(const ProbDesc* __restrict__ pro
   const bool wave_active = w < mw;
   // rows past m (last wavefront only) read row m - 1: valid address, zero weight
   const int64_t iy = active ? i : (m - 1);
+  constexpr int kUnroll = u_unroll<R>();
+  static_assert(kUChunk % kUnroll == 0, "column groups tile a chunk");
   for (int64_t j0 = 0; j0 < n; j0 += kUChunk) {
     const int jn = static_cast<int>((n - j0) < kUChunk ? (n - j0) : kUChunk);
+    // the last group of kUnroll columns can run past jn: its slots hold zeros, since a zero
+    // weight times whatever LDS held before (possibly a NaN) would not be zero
+    const int jpad = (jn + kUnroll - 1) / kUnroll * kUnroll;
     __syncthreads();
-    for (int e = tid; e < jn * R; e += 256) {
+    for (int e = tid; e < jpad * R; e += 256) {
       const int jj = e / R, a = e % R;
-      Vs[e] = V[(j0 + jj) + static_cast<int64_t>(a) * n];
+      Vs[e] = jj < jn ? V[(j0 + jj) + static_cast<int64_t>(a) * n] : 0.0;
     }
     __syncthreads();
     if (wave_active) {
       // groups of kUnroll columns: all loads of a group first, then the products; the
       // mask bit is a 0/1 weight, so there is no divergent branch
-      constexpr int kUnroll = u_unroll<R>();
       for (int jj = 0; jj < jn; jj += kUnroll) {
         uint64_t word[kUnroll];
         double y[kUnroll];
@@ -396,15 +400,25 @@ __global__ __launch_bounds__(256) void k_error(const ProbDesc* __restrict__ prob
       }
     }
   }
+  // one partial per workgroup, summed in a fixed order: e is reproducible bit for bit
+  __shared__ double wsum[4];
   acc = wave_sum(acc);
-  if ((tid & 63) == 0) atomic_add_f64((double*)&P.scal->err_acc, acc);
+  if ((tid & 63) == 0) wsum[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) P.errp[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
 }
 
+// e = sqrt(sum / known): each lane sums a strided share of the partials in order, then a
+// fixed butterfly over the wavefront.
 __global__ void k_error_finalize(const ProbDesc* __restrict__ probs, IdxList list) {
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t parts = ceil_div(P.m, int64_t(256));
+  double acc = 0.0;
+  for (int64_t q = threadIdx.x; q < parts; q += 64) acc += P.errp[q];
+  acc = wave_sum(acc);
   if (threadIdx.x == 0) {
     const double k = static_cast<double>(P.info->known);
-    P.info->e = k > 0.0 ? sqrt(P.scal->err_acc / k) : 0.0;
+    P.info->e = k > 0.0 ? sqrt(acc / k) : 0.0;
   }
 }
 

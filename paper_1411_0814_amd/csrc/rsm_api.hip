@@ -197,6 +197,9 @@ void set_layout(Plan& P) {
     P.off_ab = carve(cur, static_cast<size_t>(P.m) * (P.r * (P.r + 1) / 2 + P.r) * sizeof(double));
     P.off_abcnt = carve(cur, static_cast<size_t>(P.m) * sizeof(int32_t));
   }
+  P.off_errp = (P.flags & RSM_COMPUTE_ERROR)
+                   ? carve(cur, static_cast<size_t>(ceil_div(P.m, 256)) * sizeof(double))
+                   : ~size_t(0);
   P.off_rbits = P.off_yrow = P.off_B = P.off_cmask = P.off_Qd = ~size_t(0);
   if (P.rows_first) {
     P.off_rbits = carve(cur, static_cast<size_t>(P.m) * P.nw * sizeof(uint64_t));
@@ -356,6 +359,7 @@ ProbDesc prob_desc(const Plan& P, const rsm_input& in, const rsm_output& out, vo
   d.scal = gptr(at<DevScalars>(ws, P.off_scal));
   d.ab = P.u_mfma ? gptr(at<double>(ws, P.off_ab)) : nullptr;
   d.abcnt = P.u_mfma ? gptr(at<int32_t>(ws, P.off_abcnt)) : nullptr;
+  d.errp = (P.flags & RSM_COMPUTE_ERROR) ? gptr(at<double>(ws, P.off_errp)) : nullptr;
   d.rows_first = P.rows_first ? 1 : 0;
   d.nw = static_cast<int32_t>(P.nw);
   if (P.rows_first) {
@@ -383,6 +387,8 @@ EigProb eig_desc(const Plan& P, const rsm_output& out, void* ws) {
   e.b = P.eig_b;
   e.r = P.r;
   e.check_accepted = (P.flags & RSM_FINALIZE_ONLY) ? 0 : 1;
+  e.deterministic = (P.flags & RSM_DETERMINISTIC) ? 1 : 0;
+  e.pad_ = 0;
   e.seed = P.seed ^ 0x9E3779B97F4A7C15ull;
   e.N = gptr(out.N ? out.N : at<double>(ws, P.off_N));
   e.Nsym = gptr(at<double>(ws, P.off_Nsym));

@@ -49,12 +49,20 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct DevScalars {
   double mu;            // shift of the factorisation
   double lam_max;       // Gershgorin bound on lambda_max(N)
-  double err_acc;       // sum of squared residuals for eq.(ep)
   int32_t pivots;       // clamped Cholesky pivots
-  uint32_t bar;         // arrival count of the subspace iteration's group barrier
-  uint32_t ticket;      // workgroup tickets of the subspace iteration (problem 0 only)
-  uint32_t stalled;     // set when a group barrier timed out (all groups then stop)
+  uint32_t bar;         // arrival count of the group solver's barrier
+  uint32_t ticket;      // workgroup tickets of the group solver (first problem of a launch)
+  uint32_t stalled;     // set when a group barrier wait timed out (the launch then stops)
 };
+
+// Group form of the V-hat solver's subspace iteration: rows of the iterate per workgroup,
+// and the per-workgroup partial sums it exchanges (doubles): two alternating buffers of
+// b x b matrices and one of r squared residual norms, for ceil(n / kSubRows) workgroups,
+// summed in workgroup order.
+constexpr int kSubRows = 16;
+__host__ __device__ constexpr int64_t sub_partials(int64_t n) {
+  return (2 * kEigMaxB * kEigMaxB + RSM_MAX_R) * ((n + kSubRows - 1) / kSubRows);
+}
 
 // How one problem is executed and where its scratch lives in the workspace.
 struct Plan {
@@ -88,21 +96,12 @@ struct Plan {
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
          off_rows = 0;
   size_t off_N = 0, off_Nsym = 0, off_L = 0, off_M = 0, off_Mt = 0, off_T = 0, off_X = 0,
-         off_Z = 0, off_SP = 0, off_ab = 0, off_abcnt = 0,
+         off_Z = 0, off_SP = 0, off_ab = 0, off_abcnt = 0, off_errp = 0,
          off_mflag = 0, off_rbits = 0, off_yrow = 0, off_B = 0, off_cmask = 0, off_Qd = 0;
   size_t off_scal = 0;
   size_t total = 0;
 };
 
-// Subspace iteration of the V-hat solver: rows of the iterate per workgroup, and the
-// per-workgroup partial sums it exchanges (doubles): two alternating buffers of b x b
-// matrices (Gram and Rayleigh-Ritz matrices) and one of r squared residual norms, for
-// ceil(n / kSubRows) workgroups.  The partials are summed in workgroup order, so results do
-// not depend on timing.
-constexpr int kSubRows = 16;
-__host__ __device__ constexpr int64_t sub_partials(int64_t n) {
-  return (2 * kEigMaxB * kEigMaxB + RSM_MAX_R) * ((n + kSubRows - 1) / kSubRows);
-}
 
 // Device-side description of one V-hat solve (step a6).  The solver's kernels take an array
 // of these and run every problem of a batch in the same launch (problem = blockIdx.y); each
@@ -114,6 +113,8 @@ struct EigProb {
   int32_t b;             // subspace width
   int32_t r;             // target rank
   int32_t check_accepted;  // flag "no accepted trial" (off when only finalising a given N)
+  int32_t deterministic;   // RSM_DETERMINISTIC: the solve's form may not depend on the batch
+  int32_t pad_;
   uint64_t seed;         // start-vector stream
   RSM_GLOBAL const double* N;  // accumulated N (lower triangle, column-major n x n)
   RSM_GLOBAL double* Nsym;     // N with both triangles
@@ -122,8 +123,8 @@ struct EigProb {
   RSM_GLOBAL double* Mt;       // (L^{-1})^T, npad x npad, upper tiles
   RSM_GLOBAL double* T;        // recursion temporary (npad/2 x npad/2); row-sum and residual partials
   RSM_GLOBAL double* X;        // n x b iterate
-  RSM_GLOBAL double* Z;        // n x b: L^{-1} X
-  RSM_GLOBAL double* SP;       // sub_partials(n) doubles: the iteration's partial sums
+  RSM_GLOBAL double* Z;        // n x b: L^{-1} X, then N X
+  RSM_GLOBAL double* SP;       // sub_partials(n) doubles (group form of the iteration)
   RSM_GLOBAL DevScalars* scal;
   RSM_GLOBAL double* V;        // output n x r
   RSM_GLOBAL rsm_info* info;
@@ -165,6 +166,7 @@ struct ProbDesc {
   RSM_GLOBAL int32_t* mflag;   // per trial: minor vector left to the Jacobi pass (I)
   RSM_GLOBAL double* ab;       // U-hat normal equations on MFMA: (r(r+1)/2 + r) x m, ld m
   RSM_GLOBAL int32_t* abcnt;   // known entries per row (m)
+  RSM_GLOBAL double* errp;     // error of eq.(ep): one partial sum per 256 rows
   // method M2 (rows first)
   int32_t rows_first;
   int32_t nw;                  // 64-column words per row of rbits

@@ -33,6 +33,7 @@ class Job:
     start: float = math.nan
     done: float = math.nan
     result: object = None
+    kept: object = None     # (V-hat, sampled rows of U-hat, info bytes) when sampled
 
 
 def poisson_trace(n_items: int, qps: float, seconds: float, seed: int) -> list[Job]:
@@ -100,9 +101,14 @@ class Server:
     def _footprint(self, it: PoolItem) -> int:
         return footprint(it)
 
-    def run(self, jobs: list[Job], time_limit: float | None = None) -> dict:
+    def run(self, jobs: list[Job], time_limit: float | None = None,
+            sample: dict | None = None) -> dict:
         """Serve `jobs` (sorted by arrival) in real time; returns latency / throughput
-        statistics.  Stops admitting new work after time_limit seconds (if given)."""
+        statistics.  Stops admitting new work after time_limit seconds (if given).
+        `sample` maps request ids to a device index tensor of rows: for those requests the
+        result's V-hat, those rows of U-hat and the raw info record are kept in `job.kept`
+        (the rest of the result, its workspace included, is released as for every other
+        request)."""
         torch = self.torch
         pending = deque(sorted(jobs, key=lambda j: j.arrival))
         waiting: deque[Job] = deque()
@@ -126,6 +132,13 @@ class Server:
                     t = time.perf_counter() - t0
                     for j in group:
                         j.done = t
+                        if sample is not None and j.rid in sample:
+                            # on the request's stream: U-hat's memory returns to that
+                            # stream's pool when the result is dropped below, and the next
+                            # work there is ordered after this copy
+                            with torch.cuda.stream(self.streams[si]):
+                                j.kept = (j.result.V, j.result.U[sample[j.rid]],
+                                          j.result.info_raw)
                         if not self.keep:
                             j.result = None
                     used -= nbytes

@@ -68,3 +68,36 @@ def test_solver_converges_by_residual(name):
         assert info["eig_iterations"] == 2       # one step shrinks the rest by ~1e-7
     else:
         assert info["eig_iterations"] > 3
+
+
+def test_batched_solves_one_workgroup_per_problem():
+    # six problems of the same subspace width in one call take the one-workgroup-per-problem
+    # form of the iteration; each must match its own eigh like the single calls above
+    import torch
+    from paper_1411_0814_amd import Request, _lib, decompose_batched
+    reqs, refs = [], []
+    rng = np.random.default_rng(11)
+    for k, name in enumerate(["gap_0.99", "bulk_edge", "near_zero"] * 2):
+        n, _, lam_fn = CASES[name]
+        n -= 37 * k                          # uneven sizes
+        r = 8                                # one subspace width for the whole call
+        lam = lam_fn(n, r)
+        N = _spd(n, lam, seed=100 + k)
+        m = 500
+        Y = torch.from_numpy(rng.standard_normal((n, m))).cuda().T
+        W = torch.from_numpy(rng.random((n, m)) < 0.8).cuda().T
+        Nt = torch.from_numpy(np.ascontiguousarray(N.T)).cuda()
+        reqs.append(Request(Y=Y, W=W, r=r, num_submatrices=0, seed=1, gram="f64", N=Nt,
+                            flags=_lib.FINALIZE_ONLY))
+        refs.append((N, r, name))
+    out = decompose_batched(reqs)
+    torch.cuda.synchronize()
+    for res, (N, r, name) in zip(out, refs):
+        V, info = res.V.cpu().numpy(), res.info()
+        E = np.linalg.eigh(N)[1]
+        theta = metrics.principal_angle_max(V, E[:, :r])
+        print(f"[eig batched] {name} n={N.shape[0]}: theta {theta:.2e} iterations "
+              f"{info['eig_iterations']} residual {info['residual']:.2e}", flush=True)
+        assert "not_converged" not in info["warnings"]
+        assert theta <= 1e-6
+        assert np.abs(V.T @ V - np.eye(r)).max() <= 1e-12

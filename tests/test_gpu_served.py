@@ -84,3 +84,29 @@ def test_served_mix_of_column_and_row_sampling_bitwise_alone():
         torch.cuda.synchronize()
         assert torch.equal(alone.V, j.result.V)
         assert torch.equal(alone.U, j.result.U)
+
+
+def test_sampled_results_kept_while_the_rest_is_released():
+    # every request sampled, results otherwise dropped at completion (their memory goes back
+    # to the streams' pools and is reused by the next batches): the kept V-hat and rows of
+    # U-hat still equal the same request run alone
+    import torch
+    from paper_1411_0814_amd import decompose, serve
+    pool = _pool()
+    jobs = serve.poisson_trace(len(pool), qps=3000.0, seconds=0.03, seed=5)
+    rows = [torch.arange(0, it.Y.shape[0], 7, device="cuda") for it in pool]
+    sample = {j.rid: rows[j.item] for j in jobs}
+    srv = serve.Server(pool, batching=True, max_inflight=3)
+    srv.budget = 2 * max(it.footprint for it in pool)
+    stats = srv.run(jobs, sample=sample)
+    torch.cuda.synchronize()
+    assert stats["completed"] == len(jobs) and stats["batches"] >= 3
+    for j in jobs:
+        assert j.result is None and j.kept is not None
+        it = pool[j.item]
+        alone = decompose(it.Y, it.W, it.r, it.num_submatrices, j.seed, l=it.l)
+        Va, Ua = alone.V.cpu().numpy(), alone.U[rows[j.item]].cpu().numpy()
+        Vm, Um = j.kept[0].cpu().numpy(), j.kept[1].cpu().numpy()
+        Wr = it.W[rows[j.item]].cpu().numpy()
+        assert metrics.principal_angle_max(Vm, Va) <= 1e-4
+        assert metrics.rel_rms_known(Wr, Um, Vm, Ua, Va) <= 1e-5
