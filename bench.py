@@ -49,7 +49,7 @@ def parse():
                          "summarised beside it")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--served-seconds", type=float, default=60.0)
-    ap.add_argument("--served-budget-gib", type=float, default=16.0)
+    ap.add_argument("--served-budget-gib", type=float, default=128.0)
     ap.add_argument("--served-sample", type=float, default=0.05,
                     help="fraction of served requests compared with the same request alone")
     ap.add_argument("--parity-problems", type=int, default=64,
@@ -496,6 +496,18 @@ def run_rows_first(args, torch, p, Y, W, stream, steps=10, warmup=2):
 
 # ------------------------------------------------------------------ C3: batched
 
+# The FP32 Gram's error in a trial's minor vectors grows as eps32 ||G_t|| / gap(G_t), and
+# that gap closes as the trial's qualifying rows approach its l columns.  Problems whose
+# expected qualifying rows per trial, m rho^l, fall below this many per column take the
+# FP64 Gram (24 of the 256 problems of the mixed batch).
+FP64_GRAM_BELOW_ROWS_PER_COLUMN = 4
+
+
+def batch_gram(spec: dict) -> str:
+    rows = spec["m"] * spec["rho"] ** spec["l"]
+    return "f64" if rows < FP64_GRAM_BELOW_ROWS_PER_COLUMN * spec["l"] else "f32"
+
+
 def _batch_setup(args, torch):
     """The mixed batch: 256 problems of uneven sizes drawn on the device, and requests."""
     import synth
@@ -507,7 +519,7 @@ def _batch_setup(args, torch):
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     reqs = [Request(Y=Y, W=W, r=sp["r"], num_submatrices=sp["num_submatrices"],
-                    seed=sp["seed_rsm"], l=sp["l"], gram="f32")
+                    seed=sp["seed_rsm"], l=sp["l"], gram=batch_gram(sp))
             for sp, (Y, W) in zip(specs, inputs)]
     return specs, inputs, reqs, t_gen
 
@@ -626,6 +638,7 @@ def run_batched(args, torch):
     warn = [res[k].info() for k in range(len(reqs))]
     out = {
         "problems": len(reqs),
+        "fp64_gram_problems": sum(q.gram == "f64" for q in reqs),
         "batched": {"decompositions_per_s": round(len(reqs) / t_batch, 1),
                     "ms_per_batch": round(t_batch * 1e3, 3),
                     "ms_per_batch_p50": round(float(np.percentile(times, 50)) * 1e3, 3),
@@ -967,7 +980,9 @@ def main_suite(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batched {bout['problems']} problems in one call: m U[4096,65536], "
                                "n U[128,1024], r U{2..16}, rho U[0.6,0.9], l=r+1, I=4n, no noise",
-                   "gram": "f32", "eig_solves": "f64", "step": "one batched call"},
+                   "gram": f"f32; f64 where m rho^l < {FP64_GRAM_BELOW_ROWS_PER_COLUMN} l "
+                           f"({bout['fp64_gram_problems']} problems)",
+                   "eig_solves": "f64", "step": "one batched call"},
         "latency_ms": {"p50": bout["batched"]["ms_per_batch_p50"],
                        "p99": bout["batched"]["ms_per_batch_p99"],
                        "of": "one batched call (all 256 problems)"},
@@ -1063,8 +1078,37 @@ def main_table1(args):
         "rows": rows,
         "paper_hardware": "Matlab, FP64, one core of an Intel i5-3470 at 3.2 GHz",
         "all_e_within_1e-3": all(r["e_within_1e-3"] for r in rows),
+        "fig1": fig1_slopes(rows),
     }
     print(json.dumps(line), flush=True)
+
+
+def fig1_slopes(rows):
+    """Time against m (n fixed) and against n (m fixed) over the Table I rows that vary one
+    of them, both divided by their smallest values and fitted by a straight line, as the
+    paper's Fig. 1 does (a slope below 1: time grows more slowly than the size); with the
+    log-log exponent and the same fits of the paper's printed one-core times."""
+    def fit(xs, ts):
+        x = np.asarray(xs, float) / min(xs)
+        t = np.asarray(ts, float) / min(ts)
+        slope = float(np.polyfit(x, t, 1)[0])
+        expo = float(np.polyfit(np.log(x), np.log(t), 1)[0])
+        return round(slope, 3), round(expo, 3)
+    out = {}
+    for name, key, other in (("time_vs_m", "m", "n"), ("time_vs_n", "n", "m")):
+        ref = max(r[other] for r in rows)
+        sel = [r for r in rows if r[other] == ref and r["rho"] == 0.2 and r["sigma"] == 0.2]
+        sel.sort(key=lambda r: r[key])
+        if len(sel) < 2:
+            continue
+        xs = [r[key] for r in sel]
+        g_slope, g_exp = fit(xs, [r["gpu_ms"] for r in sel])
+        p_slope, p_exp = fit(xs, [r["paper_matlab_s"] for r in sel])
+        out[name] = {key: xs, f"fixed_{other}": ref, "gpu_ms": [r["gpu_ms"] for r in sel],
+                     "gpu_slope": g_slope, "gpu_loglog_exponent": g_exp,
+                     "paper_matlab_s": [r["paper_matlab_s"] for r in sel],
+                     "paper_slope": p_slope, "paper_loglog_exponent": p_exp}
+    return out
 
 
 def main_single(args):

@@ -330,7 +330,9 @@ __device__ __forceinline__ void lds_dma4(const void* src, float* dst) {
 
 // DB: two chunk buffers; the loads of chunk k + 1 are issued right after the barrier that
 // publishes chunk k and land while chunk k is summed (one barrier per chunk).
-template <int L, int NT, bool DB>
+// TA: the type of the sums.  With double, every product of two FP32 values is exact and
+// only the FP64 additions round: the FP64 Gram of FP32 data.
+template <int L, int NT, bool DB, typename TA>
 __global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ probs,
                                                  IdxList list) {
   constexpr int NG = L * (L + 1) / 2;
@@ -365,9 +367,9 @@ __global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ pr
     valid &= (c >= 0);
     mc[a] = c < 0 ? 0 : c;
   }
-  float acc[NG];
+  TA acc[NG];
 #pragma unroll
-  for (int g = 0; g < NG; ++g) acc[g] = 0.0f;
+  for (int g = 0; g < NG; ++g) acc[g] = TA(0);
   int count = 0;
   const int rot = (tid * 13) & (kDmaRows - 1);
   const int colk = lane >> 4, rowk = lane & 15;
@@ -413,9 +415,9 @@ __global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ pr
       while (q) {
         const int i = (__ffs(q) - 1 + rot) & (kDmaRows - 1);
         q &= q - 1;
-        float y[L];
+        TA y[L];
 #pragma unroll
-        for (int a = 0; a < L; ++a) y[a] = tile[mc[a] * kDmaRows + i];
+        for (int a = 0; a < L; ++a) y[a] = static_cast<TA>(tile[mc[a] * kDmaRows + i]);
         int g = 0;
 #pragma unroll
         for (int a = 0; a < L; ++a)
@@ -425,7 +427,7 @@ __global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ pr
     }
   }
   if (active) {
-    RSM_GLOBAL float* dst = static_cast<RSM_GLOBAL float*>(P.part) + static_cast<int64_t>(split) * NG * I + t;
+    RSM_GLOBAL TA* dst = static_cast<RSM_GLOBAL TA*>(P.part) + static_cast<int64_t>(split) * NG * I + t;
 #pragma unroll
     for (int g = 0; g < NG; ++g) dst[static_cast<int64_t>(g) * I] = acc[g];
     P.prow[static_cast<int64_t>(split) * I + t] = count;
@@ -594,7 +596,7 @@ void run_tile_nt(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipS
   k_gram_tile<L, T, NT><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
 }
 
-template <int L, int NT, bool DB>
+template <int L, int NT, bool DB, typename TA = float>
 void run_dma(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
   size_t lds = 0;
   int wgs = 0;
@@ -606,12 +608,12 @@ void run_dma(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStrea
   }
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_dma<L, NT, DB>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_dma<L, NT, DB, TA>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 156 * 1024);
     attr_set = true;
   }
   const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
-  k_gram_dma<L, NT, DB><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
+  k_gram_dma<L, NT, DB, TA><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
 }
 
 // Largest trial count per workgroup of the double-buffered kernel: 1024 threads leave 128
@@ -650,6 +652,24 @@ void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStre
     }
   }
   run_tile_nt<L, T, 256>(d, g, h, s);
+}
+
+// FP32 Y, FP64 sums: the double-buffered direct-to-LDS kernel with FP64 accumulators
+// (l(l+1) registers): 512 trials per workgroup while they fit two wavefronts per SIMD.
+template <int L>
+constexpr bool mixed_has_512() {
+  return L <= 14;
+}
+
+template <int L>
+void run_mixed(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  if constexpr (mixed_has_512<L>()) {
+    if (h[0]->gram_threads == 512) {
+      run_dma<L, 512, true, double>(d, g, h, s);
+      return;
+    }
+  }
+  run_dma<L, 256, true, double>(d, g, h, s);
 }
 
 template <int L>
@@ -693,6 +713,8 @@ void dispatch_types(const ProbDesc* d, const IdxList& g, const Plan* const* h, h
   } else if (P.prec == RSM_GRAM_F64) {
     if (P.y_dtype == RSM_F64 && P.tiled)
       run_tile<L, double>(d, g, h, s);
+    else if (P.y_dtype == RSM_F32 && P.tiled)
+      run_mixed<L>(d, g, h, s);
     else if (P.y_dtype == RSM_F32)
       run_plain<L, float, double>(d, g, h, s);
     else
@@ -716,6 +738,15 @@ int gram_threads_built(int l, int prec, int y_dtype, int kernel, int* out) {
     return 1;
   }
   const bool f64 = prec == RSM_GRAM_F64;
+  if (f64 && y_dtype == RSM_F32) {  // FP64 sums of FP32 data: direct-to-LDS staging only
+    if (kernel != RSM_GRAM_KERNEL_DMA2) return 0;
+    out[0] = 256;
+    if (l <= 14) {
+      out[1] = 512;
+      return 2;
+    }
+    return 1;
+  }
   if (f64 != (y_dtype == RSM_F64)) return 0;
   if (kernel == RSM_GRAM_KERNEL_DMA) {
     if (f64) return 0;
@@ -742,8 +773,8 @@ int gram_threads_built(int l, int prec, int y_dtype, int kernel, int* out) {
 
 bool gram_tiled_ok(const Plan& P) {
   if (!P.tiled) return false;
-  const bool f64 = P.prec == RSM_GRAM_F64;
-  if (f64 != (P.y_dtype == RSM_F64)) return false;
+  const bool f64 = P.y_dtype == RSM_F64;
+  if (f64 && P.prec != RSM_GRAM_F64) return false;  // FP64 data has no FP32 Gram kernel
   const size_t elem = f64 ? 8 : 4;
   const size_t stride = f64 ? TileStride<double>::kValue : TileStride<float>::kValue;
   return static_cast<size_t>(ceil_div(P.n, 64) * 64) * stride * elem <= kTileLdsBytes;

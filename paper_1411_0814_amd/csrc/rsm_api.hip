@@ -113,13 +113,14 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
   return RSM_OK;
 }
 
-// Staging of the tiled kernels when the tile table does not say otherwise: FP32 loads
+// Staging of the tiled kernels when the tile table does not say otherwise: FP32 data loads
 // straight into LDS with two chunk buffers (no staging registers, loads overlapping the
-// sums); FP64 and split-BF16 stage through registers.
+// sums), with FP32 or FP64 sums; FP64 data and split-BF16 stage through registers.
 int builtin_gram_kernel(int l, int prec, int y_dtype) {
   (void)l;
-  return (prec == RSM_GRAM_F32 && y_dtype == RSM_F32) ? RSM_GRAM_KERNEL_DMA2
-                                                      : RSM_GRAM_KERNEL_REGS;
+  return ((prec == RSM_GRAM_F32 || prec == RSM_GRAM_F64) && y_dtype == RSM_F32)
+             ? RSM_GRAM_KERNEL_DMA2
+             : RSM_GRAM_KERNEL_REGS;
 }
 
 int default_gram_kernel(const Plan& P) { return builtin_gram_kernel(P.l, P.prec, P.y_dtype); }
@@ -137,7 +138,10 @@ bool threads_built(int l, int prec, int y_dtype, int kernel, int threads) {
 int default_gram_threads(const Plan& P, int kernel) {
   if (P.prec == RSM_GRAM_BF16X2) return kBfTrialsPerGroup;
   if (kernel == RSM_GRAM_KERNEL_DMA) return 256;
-  if (kernel == RSM_GRAM_KERNEL_DMA2) return P.l <= 12 ? 1024 : 512;
+  if (kernel == RSM_GRAM_KERNEL_DMA2) {
+    if (P.prec == RSM_GRAM_F64) return P.l <= 14 ? 512 : 256;  // FP64 sums of FP32 data
+    return P.l <= 12 ? 1024 : 512;
+  }
   return tile_threads(P.l, P.prec == RSM_GRAM_F64 ? 8 : 4);
 }
 

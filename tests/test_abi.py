@@ -272,7 +272,11 @@ def test_tune_threads_lists_built_kernels():
     assert _lib.tune_threads(12, _lib.GRAM_F32, F32) == [256]
     assert _lib.tune_threads(6, _lib.GRAM_F64, F64) == [256, 512]
     assert _lib.tune_threads(7, _lib.GRAM_F64, F64) == [256]
-    assert _lib.tune_threads(6, _lib.GRAM_F64, F32) == []        # per-trial streamer
+    assert _lib.tune_threads(6, _lib.GRAM_F64, F32) == []        # REGS: no FP64 sums of FP32
+    # FP64 sums of FP32 data: double-buffered direct-to-LDS only, 512 trials up to l = 14
+    assert _lib.tune_threads(14, _lib.GRAM_F64, F32, DB) == [256, 512]
+    assert _lib.tune_threads(15, _lib.GRAM_F64, F32, DB) == [256]
+    assert _lib.tune_threads(6, _lib.GRAM_F64, F32, DMA) == []
     assert _lib.tune_threads(16, _lib.GRAM_BF16X2, F32) == [64]
     assert _lib.tune_threads(17, _lib.GRAM_BF16X2, F32) == []
 
@@ -283,7 +287,8 @@ def test_tune_table_roundtrip_and_validation(empty_tune_table):
             _entry(l=16, gram_prec=_lib.GRAM_BF16X2, gram_threads=64, gram_wgs=64),
             _entry(l=17, gram_threads=512, gram_kernel=_lib.GRAM_KERNEL_DMA),
             _entry(l=17, gram_threads=512),          # FP32 stages straight into LDS by default
-            _entry(l=9, gram_threads=1024)]
+            _entry(l=9, gram_threads=1024),
+            _entry(l=14, gram_prec=_lib.GRAM_F64, gram_threads=512)]
     _lib.tune_set(good)
     assert _lib.tune_get() == good
     bad = [_entry(l=1), _entry(l=_lib.MAX_L + 1), _entry(gram_threads=384),
@@ -295,7 +300,9 @@ def test_tune_table_roundtrip_and_validation(empty_tune_table):
                   gram_kernel=_lib.GRAM_KERNEL_DMA),
            _entry(gram_wgs=-1), _entry(gram_wgs=(1 << 20) + 1),
            _entry(batched=2), _entry(y_dtype=7), _entry(gram_prec=3),
-           _entry(gram_prec=_lib.GRAM_F64, gram_threads=256)]     # F64 Gram of F32 Y: streamer
+           # FP64 sums of FP32 Y: straight-to-LDS only, 256 trials above l = 14
+           _entry(l=15, gram_prec=_lib.GRAM_F64, gram_threads=512),
+           _entry(gram_prec=_lib.GRAM_F64, gram_threads=256, gram_kernel=_lib.GRAM_KERNEL_REGS)]
     for e in bad:
         with pytest.raises(_lib.RSMError) as ei:
             _lib.tune_set(good[:1] + [e])

@@ -50,8 +50,10 @@ def test_split_bf16_parity(m, n, r, rho, extra):
     V, U = res.V.cpu().numpy(), res.U.cpu().numpy()
     theta = metrics.principal_angle_max(V, ora.V)
     rms = metrics.rel_rms_known(p.W, U, V, ora.U, ora.V)
+    print(f"[bf16x2 {m}x{n} r{r}] gram rel {worst:.2e} theta {theta:.2e} rms {rms:.2e}",
+          flush=True)
     assert theta <= 1e-4, theta
-    assert rms <= 1e-4, rms
+    assert rms <= 1e-5, rms
 
 
 def test_split_bf16_close_to_fp32():

@@ -119,6 +119,23 @@ def test_fp32_gram_parity_medium():
     print(f"fp32 medium: theta={theta:.3e} rms={rms:.3e}")
 
 
+@pytest.mark.parametrize("gram", ["f64", "f32"])
+def test_low_row_regime_of_table1(gram):
+    """The regime of the paper's own workloads (Table I): rho = 0.2, l = 4, r = 3, noise 0.2,
+    25 n trials, so a trial keeps about m rho^4 = 52 of m = 32768 rows (a reduced 32768 x
+    256 shape of its first row)."""
+    dt = np.float32 if gram == "f32" else np.float64
+    p = synth.paper_synthetic(32768, 256, 3, 0.2, 0.2, 71, factor_dtype=dt, y_dtype=dt,
+                              num_submatrices=25 * 256, l=4, seed_rsm=72, gram=gram)
+    res, info = _run(p, gram, taps=True)
+    ora = rsm.rsm(p.Y, p.W, p.r, p.num_submatrices, seed=p.seed_rsm, l=p.l, with_e=False)
+    mean_rows = info["rows_total"] / p.num_submatrices
+    assert 30 < mean_rows < 80, mean_rows
+    theta, rms = _compare_full(p, res, info, ora, u=2.0**-24 if gram == "f32" else 2.0**-53)
+    print(f"low-row regime {gram}: mean rows {mean_rows:.1f} theta={theta:.3e} rms={rms:.3e}",
+          flush=True)
+
+
 def test_ragged_row_major_fp64():
     """m, n not multiples of 64; row-major Y and W (repacked by the library)."""
     import torch

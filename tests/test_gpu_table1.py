@@ -1,6 +1,7 @@
-"""The paper's printed numbers (Table I, §V-A): on two of its synthetic workloads the GPU
-path's error e of eq.(ep) equals the e the paper prints for RSM, within the sampling
-spread of e over a different random instance (1e-3), and lies below the noise level."""
+"""The paper's printed numbers (Table I, §V-A): on each of its ten synthetic workloads the
+GPU path's error e of eq.(ep) equals the e the paper prints for RSM within 5e-4 (the
+spread of e over a different random instance of the same workload; the instances here are
+not the paper's), and lies below the noise level."""
 import csv
 import os
 
@@ -18,7 +19,7 @@ def _golden():
         return [row for row in csv.DictReader(line for line in f if not line.startswith("#"))]
 
 
-@pytest.mark.parametrize("row", [0, 9])
+@pytest.mark.parametrize("row", list(range(10)))
 def test_table1_error_matches_paper(row):
     from paper_1411_0814_amd import _lib, decompose
     gold = _golden()[row]
@@ -29,5 +30,6 @@ def test_table1_error_matches_paper(row):
     info = res.info()
     assert not info["warnings"], info["warnings"]
     e = info["e"]
-    assert abs(e - float(gold["e_rsm"])) <= 1e-3, (e, gold["e_rsm"])
+    print(f"[table1 {row}] e {e:.5f} paper {float(gold['e_rsm']):.5f}", flush=True)
+    assert abs(e - float(gold["e_rsm"])) <= 5e-4, (e, gold["e_rsm"])
     assert e < float(gold["sigma"])

@@ -27,28 +27,32 @@ CASES = [(3, "f32", 256, 1, REGS), (6, "f32", 256, 8192, REGS), (9, "f32", 512, 
          (6, "f64", 512, 1, REGS), (3, "f32", 512, 1, DMA), (9, "f32", 256, 8192, DMA),
          (13, "f32", 512, 64, DMA), (17, "f32", 256, 4096, DMA), (17, "f32", 512, 1, DMA),
          (3, "f32", 1024, 1, DMA2), (9, "f32", 1024, 8192, DMA2), (12, "f32", 512, 64, DMA2),
-         (17, "f32", 512, 4096, DMA2)]
+         (17, "f32", 512, 4096, DMA2),
+         # "f64/f32": FP64 sums of FP32 data
+         (4, "f64/f32", 512, 1, DMA2), (14, "f64/f32", 512, 4096, DMA2),
+         (17, "f64/f32", 256, 64, DMA2)]
 
 
 @pytest.mark.parametrize("l,prec,threads,wgs,kernel", CASES)
 def test_tuned_gram_shapes_exact_rows_and_bounded_gram(l, prec, threads, wgs, kernel):
     from paper_1411_0814_amd import _lib, decompose
-    dt = np.float32 if prec == "f32" else np.float64
+    dt = np.float64 if prec == "f64" else np.float32
+    gram = prec.split("/")[0]
     r = l - 1
     p = synth.paper_synthetic(5003, 160, r, 0.9, 1e-3, 60 + l, factor_dtype=dt, y_dtype=dt,
-                              num_submatrices=700, seed_rsm=l, gram=prec)
-    _lib.tune_set([{"l": l, "gram_prec": _lib.GRAM_MODES[prec],
-                    "y_dtype": _lib.F32 if prec == "f32" else _lib.F64, "batched": 0,
+                              num_submatrices=700, seed_rsm=l, gram=gram)
+    _lib.tune_set([{"l": l, "gram_prec": _lib.GRAM_MODES[gram],
+                    "y_dtype": _lib.F64 if prec == "f64" else _lib.F32, "batched": 0,
                     "gram_threads": threads, "gram_wgs": wgs, "gram_kernel": kernel}])
     Y, W = to_device(p)
-    res = decompose(Y, W, p.r, p.num_submatrices, p.seed_rsm, l=l, gram=prec, taps=True)
+    res = decompose(Y, W, p.r, p.num_submatrices, p.seed_rsm, l=l, gram=gram, taps=True)
     cols = res.taps["cols"].cpu().numpy()
     rows = res.taps["rows"].cpu().numpy()
     G = res.taps["gram"].cpu().numpy()
     ora = rsm.rsm(p.Y, p.W, p.r, p.num_submatrices, seed=p.seed_rsm, l=l, with_e=False)
     assert np.array_equal(cols, ora.subsets)
     assert np.array_equal(rows, ora.rows)
-    u = 2.0 ** -24 if prec == "f32" else 2.0 ** -53
+    u = 2.0 ** -24 if gram == "f32" else 2.0 ** -53
     Y64 = np.asarray(p.Y, dtype=np.float64)
     for t in np.linspace(0, len(cols) - 1, 60).astype(int):
         R = rsm.qualifying_rows(p.W, cols[t])
