@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--plain-gram", action="store_true",
                     help="per-trial column-streaming Gram kernel instead of the tiled one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched: omit the one-at-a-time leg (for profiling runs)")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in Gram tile shapes (no autotuning before timing)")
@@ -116,11 +118,12 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n, "launches": 3}), flush=True)
 
 
-def traffic_from_profile(kernel_src):
-    """HBM bytes per launch of the Gram kernel from the committed rocprofv3 counter summary,
-    or None when the kernel source has changed since the counters were taken."""
+def traffic_from_profile(kernel_src, profile="k_gram_dma_paper_scale_counters.md",
+                         key="hbm_bytes_per_launch"):
+    """HBM bytes of the Gram step from a committed rocprofv3 counter summary, or None when
+    the kernel source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_gram_tile_paper_scale_counters.md")
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -134,7 +137,7 @@ def traffic_from_profile(kernel_src):
     if vals.get("kernel_source_sha256") != sha:
         return None
     try:
-        return int(vals["hbm_bytes_per_launch"])
+        return int(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -591,9 +594,13 @@ def _batch_gram_roofline(reqs, stream, torch, ws):
     achieved = b_alg / (span_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": "gram (row qualification + Gram), every problem of the batch",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profile(
+                os.path.join(ROOT, "paper_1411_0814_amd", "csrc", "k_gram.hip"),
+                "k_gram_dma_batched256_counters.md", "hbm_bytes_per_call"),
             "bytes_alg_per_launch": int(b_alg), "launch_ms": round(span_ms, 4),
-            "note": "the step's launches (one per l) back to back; bytes and time summed"}
+            "note": "the step's launches (one per l and precision) back to back; bytes and "
+                    "time summed over them; traffic from the committed counters"}
 
 
 def run_batched(args, torch):
@@ -615,24 +622,25 @@ def run_batched(args, torch):
     progress(f"batched: {np.mean(times) * 1e3:.2f} ms per batch of {len(reqs)}")
     tune.clear()
     # plain: one at a time on one stream, one workspace sized for the largest problem
+    plain_reqs = [] if args.no_plain else reqs
     ws1_need = max(workspace_bytes([q]) for q in reqs)
     ws1 = torch.empty(ws1_need + 256, dtype=torch.uint8, device="cuda")
     ws1 = ws1[(-ws1.data_ptr()) % 256:][:ws1_need]
-    for q in reqs[:8]:
+    for q in plain_reqs[:8]:
         decompose(q.Y, q.W, q.r, q.num_submatrices, q.seed, l=q.l, gram=q.gram,
                   stream=stream, workspace=ws1)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in reqs]
+           for _ in plain_reqs]
     t0 = time.perf_counter()
-    for q, (a, b) in zip(reqs, evs):
+    for q, (a, b) in zip(plain_reqs, evs):
         a.record(stream)
         decompose(q.Y, q.W, q.r, q.num_submatrices, q.seed, l=q.l, gram=q.gram,
                   stream=stream, workspace=ws1)
         b.record(stream)
     torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    lat_plain = [a.elapsed_time(b) for a, b in evs]
+    t_plain = max(time.perf_counter() - t0, 1e-9)
+    lat_plain = [a.elapsed_time(b) for a, b in evs] or [float("nan")]
     del ws1
     t_batch = float(np.mean(times))
     warn = [res[k].info() for k in range(len(reqs))]
@@ -644,11 +652,11 @@ def run_batched(args, torch):
                     "ms_per_batch_p50": round(float(np.percentile(times, 50)) * 1e3, 3),
                     "ms_per_batch_p99": round(float(np.percentile(times, 99)) * 1e3, 3),
                     "steps": args.steps, "warmup": args.warmup},
-        "plain": {"decompositions_per_s": round(len(reqs) / t_plain, 1),
+        "plain": {"decompositions_per_s": round(len(plain_reqs) / t_plain, 1),
                   "ms_total": round(t_plain * 1e3, 3),
                   "latency_ms": {"p50": round(float(np.percentile(lat_plain, 50)), 4),
                                  "p99": round(float(np.percentile(lat_plain, 99)), 4)}},
-        "speedup": round(t_plain / t_batch, 2),
+        "speedup": round(t_plain / t_batch, 2) if plain_reqs else None,
         "gen_s": round(t_gen, 2),
         "builtin_tiles": {"decompositions_per_s": round(len(reqs) / float(np.mean(t_builtin)), 1),
                           "ms_per_batch": round(float(np.mean(t_builtin)) * 1e3, 3)},
