@@ -771,9 +771,13 @@ def run_served(args, torch, batch, saturation):
         rng = np.random.default_rng(17)
         picked = rng.random(len(trace)) < args.served_sample
         sample = {j.rid: dev_rows[j.item] for j, s in zip(trace, picked) if s}
+        # memory cached for earlier streams goes back to the device first (the runtime
+        # allocates kernel scratch for each new queue from what is free)
+        torch.cuda.empty_cache()
         srv = serve.Server(pool, budget_bytes=budget, batching=True, max_inflight=3)
         st_b = srv.run(trace, sample=sample)
         torch.cuda.synchronize()
+        del srv
         progress(f"served {frac}x: continuous batching done ({len(trace)} requests)")
         # alone vs in the mix; requests the library flags as having no unique V-hat (no
         # accepted trial, an uncovered column or no eigen-gap) are counted apart
@@ -804,6 +808,7 @@ def run_served(args, torch, batch, saturation):
             j.kept = None
         progress(f"served {frac}x: {n_cmp} sampled requests compared alone")
         trace_p = serve.poisson_trace(len(pool), qps, args.served_seconds, seed=11)
+        torch.cuda.empty_cache()
         st_p = serve.Server(pool, budget_bytes=budget, batching=False, max_inflight=1).run(
             trace_p, time_limit=args.served_seconds)
         torch.cuda.synchronize()

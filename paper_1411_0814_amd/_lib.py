@@ -101,6 +101,7 @@ class TuneEntry(C.Structure):
 
 
 GRAM_KERNEL_REGS, GRAM_KERNEL_DMA, GRAM_KERNEL_DMA2 = 1, 2, 3
+GRAM_KERNEL_GATHER, GRAM_KERNEL_AUTO = 4, 5
 
 
 EXPORTS = ["rsm_abi_version", "rsm_status_string", "rsm_workspace_bytes", "rsm_decompose",

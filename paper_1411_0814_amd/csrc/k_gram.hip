@@ -324,9 +324,27 @@ __global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ p
 
 constexpr int kDmaRows = 16;
 
-__device__ __forceinline__ void lds_dma4(const void* src, float* dst) {
+__device__ __forceinline__ void lds_dma4(const void* src, void* dst) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
 }
+
+// Staging every column of a chunk pays for all n columns whatever a trial keeps: per trial
+// and 64-row word about 64 n 4 / NT bytes (the chunk, shared by the workgroup's NT trials).
+// Loading a trial's qualifying values straight from Y pays about a cache line per value:
+// 64 f l 64 bytes, f = rho^l the expected fraction of qualifying rows, rho the mask's
+// density (its ones counted while packing it).  A problem gathers when that is the smaller:
+// f l 16 NT < n.  The choice depends only on the problem, so a deterministic problem takes
+// the same path alone and in any batch.
+__device__ __forceinline__ bool gram_gathers(const ProbDesc& P, int nt) {
+  const double known = static_cast<double>(P.scal->mask_ones);
+  const double rho = known / (static_cast<double>(P.m) * static_cast<double>(P.n));
+  const double f = rho > 0.0 ? exp(static_cast<double>(P.l) * log(rho)) : 0.0;
+  return f * P.l * 16.0 * nt < static_cast<double>(P.n);
+}
+
+// Launch modes of the two FP32-data kernels: every problem of the launch, or only the
+// problems gram_gathers gives to that kernel (both kernels run with kModeAuto).
+constexpr int kModeAll = 0, kModeAuto = 1;
 
 // DB: two chunk buffers; the loads of chunk k + 1 are issued right after the barrier that
 // publishes chunk k and land while chunk k is summed (one barrier per chunk).
@@ -334,12 +352,13 @@ __device__ __forceinline__ void lds_dma4(const void* src, float* dst) {
 // only the FP64 additions round: the FP64 Gram of FP32 data.
 template <int L, int NT, bool DB, typename TA>
 __global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ probs,
-                                                 IdxList list) {
+                                                 IdxList list, int mode) {
   constexpr int NG = L * (L + 1) / 2;
   constexpr int NW = NT / 64;
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
   const int groups = P.gram_groups, splits = P.splits;
   if (static_cast<int>(blockIdx.x) >= groups * splits) return;  // past this problem's work
+  if (mode == kModeAuto && gram_gathers(P, NT)) return;           // k_gram_gather takes it
   const int64_t m = P.m, I = P.I, ldy = P.ldy, mw32 = 2 * P.mw;
   const int n = static_cast<int>(P.n);
   const int n4 = (n + 3) & ~3, n64 = (n + 63) & ~63;
@@ -423,6 +442,141 @@ __global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ pr
         for (int a = 0; a < L; ++a)
 #pragma unroll
           for (int b = 0; b <= a; ++b) acc[g++] += y[a] * y[b];
+      }
+    }
+  }
+  if (active) {
+    RSM_GLOBAL TA* dst = static_cast<RSM_GLOBAL TA*>(P.part) + static_cast<int64_t>(split) * NG * I + t;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) dst[static_cast<int64_t>(g) * I] = acc[g];
+    P.prow[static_cast<int64_t>(split) * I + t] = count;
+  }
+}
+
+// ------------------------------------------------------------------ gathering
+//
+// For problems whose trials keep few rows: only the mask words travel into LDS (per 64-row
+// word, the lo and hi 32-bit halves of every column's word as two planes, two buffers, the
+// next word's loads in flight while the current one is used); each thread ANDs its trial's
+// l words and loads the l values of each qualifying row straight from Y, the loads of the
+// next qualifying row issued before the current row's products.  Same work split, partial
+// sums and row counts as k_gram_dma.
+
+// One qualifying row's products, summed in TA.
+template <int L, typename TA>
+__device__ __forceinline__ void sum_row(const float (&y)[L], TA (&acc)[L * (L + 1) / 2]) {
+  TA v[L];
+#pragma unroll
+  for (int a = 0; a < L; ++a) v[a] = static_cast<TA>(y[a]);
+  int g = 0;
+#pragma unroll
+  for (int a = 0; a < L; ++a)
+#pragma unroll
+    for (int b = 0; b <= a; ++b) acc[g++] += v[a] * v[b];
+}
+
+template <int L, int NT, typename TA>
+__global__ __launch_bounds__(NT) void k_gram_gather(const ProbDesc* __restrict__ probs,
+                                                    IdxList list, int mode) {
+  constexpr int NG = L * (L + 1) / 2;
+  constexpr int NW = NT / 64;
+  // the pipelined loop holds a second row of values (l registers); kept only where the
+  // registers of NT / 256 wavefronts per SIMD leave room for it (an estimate: the sums,
+  // 5 l for the columns and the two rows, 48 for the rest)
+  constexpr int kRegs = 512 / (NT / 256);
+  constexpr bool kPipe = NG * static_cast<int>(sizeof(TA) / 4) + 5 * L + 48 <= kRegs;
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int groups = P.gram_groups, splits = P.splits;
+  if (static_cast<int>(blockIdx.x) >= groups * splits) return;  // past this problem's work
+  if (mode == kModeAuto && !gram_gathers(P, NT)) return;          // k_gram_dma takes it
+  const int64_t I = P.I, ldy = P.ldy, mw = P.mw, mw32 = 2 * P.mw;
+  const int n = static_cast<int>(P.n);
+  const int n64 = (n + 63) & ~63;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  // per buffer: lo words [n64], hi words [n64]
+  uint32_t* const buf0 = reinterpret_cast<uint32_t*>(smem_raw);
+  int group, split;
+  tile_work(groups, splits, group, split);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t t = static_cast<int64_t>(group) * NT + tid;
+  const bool active = t < I;
+  const int64_t w0 = static_cast<int64_t>(split) * P.words_per_split;
+  const int64_t w1 = (w0 + P.words_per_split < mw) ? (w0 + P.words_per_split) : mw;
+  auto Y = static_cast<RSM_GLOBAL const float*>(P.ycm);
+  auto wbits32 = reinterpret_cast<RSM_GLOBAL const uint32_t*>(P.wbits);
+
+  int mc[L];
+  bool valid = active;
+#pragma unroll
+  for (int a = 0; a < L; ++a) {
+    int c = active ? P.cols[t * L + a] : 0;
+    valid &= (c >= 0);
+    mc[a] = c < 0 ? 0 : c;
+  }
+  RSM_GLOBAL const float* col[L];
+#pragma unroll
+  for (int a = 0; a < L; ++a) col[a] = Y + static_cast<int64_t>(mc[a]) * ldy;
+  TA acc[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) acc[g] = TA(0);
+  int count = 0;
+
+  auto issue = [&](int64_t w, uint32_t* dst) {
+    for (int g = wu; g < n64 / 64; g += NW) {
+      const int c = (64 * g + lane < n) ? (64 * g + lane) : (n - 1);
+      RSM_GLOBAL const uint32_t* src = wbits32 + static_cast<int64_t>(c) * mw32 + 2 * w;
+      lds_dma4((const void*)src, dst + g * 64);
+      lds_dma4((const void*)(src + 1), dst + n64 + g * 64);
+    }
+  };
+  const int buf_words = 2 * n64;
+  if (w0 < w1) issue(w0, buf0);
+  for (int64_t w = w0; w < w1; ++w) {
+    const uint32_t* cur = buf0 + ((w - w0) & 1) * buf_words;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();  // word w is in `cur`; every wave is done with the other buffer
+    if (w + 1 < w1) issue(w + 1, buf0 + ((w + 1 - w0) & 1) * buf_words);
+    if (!valid) continue;
+    uint32_t lo = 0xffffffffu, hi = 0xffffffffu;
+#pragma unroll
+    for (int a = 0; a < L; ++a) {
+      lo &= cur[mc[a]];
+      hi &= cur[n64 + mc[a]];
+    }
+    uint64_t q = (static_cast<uint64_t>(hi) << 32) | lo;
+    count += __popcll(q);
+    if (!q) continue;
+    if constexpr (kPipe) {
+      // software pipeline over the qualifying rows: the next row's values are loaded while
+      // the current row's products are summed
+      int64_t row = w * 64 + (__ffsll(static_cast<unsigned long long>(q)) - 1);
+      q &= q - 1;
+      float y[L];
+#pragma unroll
+      for (int a = 0; a < L; ++a) y[a] = col[a][row];
+      while (true) {
+        const bool more = q != 0;
+        float yn[L];
+        if (more) {
+          const int64_t rn = w * 64 + (__ffsll(static_cast<unsigned long long>(q)) - 1);
+          q &= q - 1;
+#pragma unroll
+          for (int a = 0; a < L; ++a) yn[a] = col[a][rn];
+        }
+        sum_row<L, TA>(y, acc);
+        if (!more) break;
+#pragma unroll
+        for (int a = 0; a < L; ++a) y[a] = yn[a];
+      }
+    } else {
+      while (q) {
+        const int64_t row = w * 64 + (__ffsll(static_cast<unsigned long long>(q)) - 1);
+        q &= q - 1;
+        float y[L];
+#pragma unroll
+        for (int a = 0; a < L; ++a) y[a] = col[a][row];
+        sum_row<L, TA>(y, acc);
       }
     }
   }
@@ -597,7 +751,8 @@ void run_tile_nt(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipS
 }
 
 template <int L, int NT, bool DB, typename TA = float>
-void run_dma(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+void run_dma(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s,
+             int mode = kModeAll) {
   size_t lds = 0;
   int wgs = 0;
   for (int k = 0; k < g.count; ++k) {
@@ -613,7 +768,33 @@ void run_dma(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStrea
     attr_set = true;
   }
   const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
-  k_gram_dma<L, NT, DB, TA><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
+  k_gram_dma<L, NT, DB, TA><<<dim3(grid, g.count), NT, lds, s>>>(d, g, mode);
+}
+
+template <int L, int NT, typename TA>
+void run_gather(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s,
+                int mode) {
+  size_t lds = 0;
+  int wgs = 0;
+  for (int k = 0; k < g.count; ++k) {
+    const size_t n64 = (static_cast<size_t>(h[k]->n) + 63) & ~size_t(63);
+    lds = std::max(lds, 2 * 2 * n64 * sizeof(uint32_t));
+    wgs = std::max(wgs, h[k]->gram_wgs);
+  }
+  const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
+  k_gram_gather<L, NT, TA><<<dim3(grid, g.count), NT, lds, s>>>(d, g, mode);
+}
+
+// The straight-to-LDS kernels of FP32 data with sums of type TA: kernel DMA2 stages every
+// problem, GATHER gathers every problem, AUTO runs both, each taking the problems
+// gram_gathers gives it.
+template <int L, int NT, typename TA>
+void run_fp32_data(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+  const int kern = h[0]->gram_kernel;
+  if (kern != RSM_GRAM_KERNEL_GATHER)
+    run_dma<L, NT, true, TA>(d, g, h, s, kern == RSM_GRAM_KERNEL_AUTO ? kModeAuto : kModeAll);
+  if (kern != RSM_GRAM_KERNEL_DMA2)
+    run_gather<L, NT, TA>(d, g, h, s, kern == RSM_GRAM_KERNEL_AUTO ? kModeAuto : kModeAll);
 }
 
 // Largest trial count per workgroup of the double-buffered kernel: 1024 threads leave 128
@@ -634,14 +815,16 @@ void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStre
         run_dma<L, 256, false>(d, g, h, s);
       return;
     }
-    if (h[0]->gram_kernel == RSM_GRAM_KERNEL_DMA2) {
+    const int kern = h[0]->gram_kernel;
+    if (kern == RSM_GRAM_KERNEL_DMA2 || kern == RSM_GRAM_KERNEL_GATHER ||
+        kern == RSM_GRAM_KERNEL_AUTO) {
       if constexpr (dma_has_1024<L>()) {
         if (h[0]->gram_threads == 1024) {
-          run_dma<L, 1024, true>(d, g, h, s);
+          run_fp32_data<L, 1024, float>(d, g, h, s);
           return;
         }
       }
-      run_dma<L, 512, true>(d, g, h, s);
+      run_fp32_data<L, 512, float>(d, g, h, s);
       return;
     }
   }
@@ -665,11 +848,11 @@ template <int L>
 void run_mixed(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
   if constexpr (mixed_has_512<L>()) {
     if (h[0]->gram_threads == 512) {
-      run_dma<L, 512, true, double>(d, g, h, s);
+      run_fp32_data<L, 512, double>(d, g, h, s);
       return;
     }
   }
-  run_dma<L, 256, true, double>(d, g, h, s);
+  run_fp32_data<L, 256, double>(d, g, h, s);
 }
 
 template <int L>
@@ -738,8 +921,10 @@ int gram_threads_built(int l, int prec, int y_dtype, int kernel, int* out) {
     return 1;
   }
   const bool f64 = prec == RSM_GRAM_F64;
-  if (f64 && y_dtype == RSM_F32) {  // FP64 sums of FP32 data: direct-to-LDS staging only
-    if (kernel != RSM_GRAM_KERNEL_DMA2) return 0;
+  const bool fp32_data_kernel = kernel == RSM_GRAM_KERNEL_DMA2 ||
+                                kernel == RSM_GRAM_KERNEL_GATHER || kernel == RSM_GRAM_KERNEL_AUTO;
+  if (f64 && y_dtype == RSM_F32) {  // FP64 sums of FP32 data: the straight-to-LDS kernels only
+    if (!fp32_data_kernel) return 0;
     out[0] = 256;
     if (l <= 14) {
       out[1] = 512;
@@ -754,7 +939,7 @@ int gram_threads_built(int l, int prec, int y_dtype, int kernel, int* out) {
     out[1] = 512;
     return 2;
   }
-  if (kernel == RSM_GRAM_KERNEL_DMA2) {
+  if (fp32_data_kernel) {
     if (f64) return 0;
     out[0] = 512;
     if (l <= 12) {

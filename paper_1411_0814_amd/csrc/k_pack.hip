@@ -14,11 +14,13 @@ namespace rsm {
 namespace {
 
 // Column-major W: one thread per (column, 64-row word) of problem list.idx[blockIdx.y].
+// Each wavefront adds the ones of its words to the problem's count of known entries.
 __global__ void k_pack_mask_colmajor(const ProbDesc* __restrict__ probs, IdxList list) {
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
   const int64_t m = P.m, n = P.n, mw = P.mw;
-  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (gid >= n * mw) return;
+  const int64_t gid0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool in = gid0 < n * mw;
+  const int64_t gid = in ? gid0 : 0;
   const int64_t j = gid / mw;
   const int64_t w = gid - j * mw;
   const int64_t i0 = w * 64;
@@ -52,7 +54,10 @@ __global__ void k_pack_mask_colmajor(const ProbDesc* __restrict__ probs, IdxList
 #pragma unroll
     for (int k = 0; k < 64; ++k) word |= static_cast<uint64_t>(k < cnt && x[k] != 0) << k;
   }
-  P.wbits[j * mw + w] = word;
+  if (in) P.wbits[j * mw + w] = word;
+  const unsigned long long ones =
+      wave_sum<unsigned long long>(in ? static_cast<unsigned long long>(__popcll(word)) : 0ull);
+  if ((threadIdx.x & 63) == 0 && ones) atomicAdd(&P.scal->mask_ones, ones);
 }
 
 // Row-major W: a 64-row x 64-column byte tile through LDS, one thread per output word.
@@ -71,13 +76,16 @@ __global__ __launch_bounds__(256) void k_pack_mask_rowmajor(const ProbDesc* __re
     tile[rr][cc] = (i < m && j < n) ? (P.W[i * P.ldw + j] != 0) : 0;
   }
   __syncthreads();
-  if (threadIdx.x < 64) {
+  if (threadIdx.x < 64) {  // the first wavefront, whole
     const int64_t j = j0 + threadIdx.x;
+    uint64_t word = 0;
     if (j < n) {
-      uint64_t word = 0;
       for (int rr = 0; rr < 64; ++rr) word |= static_cast<uint64_t>(tile[rr][threadIdx.x]) << rr;
       P.wbits[j * mw + w] = word;
     }
+    const unsigned long long ones =
+        wave_sum<unsigned long long>(static_cast<unsigned long long>(__popcll(word)));
+    if (threadIdx.x == 0 && ones) atomicAdd(&P.scal->mask_ones, ones);
   }
 }
 
@@ -182,6 +190,7 @@ __global__ void k_init_info(const ProbDesc* __restrict__ probs, IdxList list) {
     scal->bar = 0;
     scal->ticket = 0;
     scal->stalled = 0;
+    scal->mask_ones = 0;
   }
   if (threadIdx.x < RSM_MAX_R + 1) info->lambda[threadIdx.x] = 0.0;
 }

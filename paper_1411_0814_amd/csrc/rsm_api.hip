@@ -115,11 +115,13 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
 
 // Staging of the tiled kernels when the tile table does not say otherwise: FP32 data loads
 // straight into LDS with two chunk buffers (no staging registers, loads overlapping the
-// sums), with FP32 or FP64 sums; FP64 data and split-BF16 stage through registers.
+// sums), or for problems whose trials keep few rows only the mask words, the values
+// gathered from Y (chosen per problem on the device), with FP32 or FP64 sums; FP64 data and
+// split-BF16 stage through registers.
 int builtin_gram_kernel(int l, int prec, int y_dtype) {
   (void)l;
   return ((prec == RSM_GRAM_F32 || prec == RSM_GRAM_F64) && y_dtype == RSM_F32)
-             ? RSM_GRAM_KERNEL_DMA2
+             ? RSM_GRAM_KERNEL_AUTO
              : RSM_GRAM_KERNEL_REGS;
 }
 
@@ -138,7 +140,8 @@ bool threads_built(int l, int prec, int y_dtype, int kernel, int threads) {
 int default_gram_threads(const Plan& P, int kernel) {
   if (P.prec == RSM_GRAM_BF16X2) return kBfTrialsPerGroup;
   if (kernel == RSM_GRAM_KERNEL_DMA) return 256;
-  if (kernel == RSM_GRAM_KERNEL_DMA2) {
+  if (kernel == RSM_GRAM_KERNEL_DMA2 || kernel == RSM_GRAM_KERNEL_GATHER ||
+      kernel == RSM_GRAM_KERNEL_AUTO) {
     if (P.prec == RSM_GRAM_F64) return P.l <= 14 ? 512 : 256;  // FP64 sums of FP32 data
     return P.l <= 12 ? 1024 : 512;
   }
@@ -594,7 +597,7 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
                return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0 && !P.rows_first; },
              [](const Plan& P) {
                return ((((int64_t(P.l) * 4 + P.y_dtype) * 4 + P.prec) * 2 + (P.tiled ? 1 : 0)) *
-                       4 + P.gram_kernel) * 1024 + P.gram_threads;
+                       8 + P.gram_kernel) * 2048 + P.gram_threads;
              },
              [&](const IdxList& g, const Plan* const* h) {
                mark_all(outputs, g, RSM_STEP_GRAM, 0, s);
@@ -677,7 +680,7 @@ int32_t rsm_tune_set(const rsm_tune_entry* entries, int32_t count) {
     if (e.l < 2 || e.l > RSM_MAX_L || e.gram_prec < RSM_GRAM_F64 ||
         e.gram_prec > RSM_GRAM_BF16X2 || (e.y_dtype != RSM_F32 && e.y_dtype != RSM_F64) ||
         (e.batched != 0 && e.batched != 1) || e.gram_wgs < 0 || e.gram_wgs > (1 << 20) ||
-        e.gram_threads < 0 || e.gram_kernel < 0 || e.gram_kernel > RSM_GRAM_KERNEL_DMA2)
+        e.gram_threads < 0 || e.gram_kernel < 0 || e.gram_kernel > RSM_GRAM_KERNEL_AUTO)
       return RSM_E_ARG;
     int built[8];
     if (e.gram_kernel && !gram_threads_built(e.l, e.gram_prec, e.y_dtype, e.gram_kernel, built))
@@ -706,7 +709,7 @@ int32_t rsm_tune_threads(int32_t l, int32_t gram_prec, int32_t y_dtype, int32_t 
                          int32_t* threads, int32_t cap, int32_t* count) {
   using namespace rsm;
   if (!count || cap < 0 || (cap > 0 && !threads) || l < 2 || l > RSM_MAX_L ||
-      gram_kernel < RSM_GRAM_KERNEL_REGS || gram_kernel > RSM_GRAM_KERNEL_DMA2)
+      gram_kernel < RSM_GRAM_KERNEL_REGS || gram_kernel > RSM_GRAM_KERNEL_AUTO)
     return RSM_E_ARG;
   int built[8];
   const int nb = gram_threads_built(l, gram_prec, y_dtype, gram_kernel, built);

@@ -53,6 +53,7 @@ struct DevScalars {
   uint32_t bar;         // arrival count of the group solver's barrier
   uint32_t ticket;      // workgroup tickets of the group solver (first problem of a launch)
   uint32_t stalled;     // set when a group barrier wait timed out (the launch then stops)
+  unsigned long long mask_ones;  // known entries of W (counted while packing the mask)
 };
 
 // Group form of the V-hat solver's subspace iteration: rows of the iterate per workgroup,

@@ -7,6 +7,9 @@ launches every admitted group as one batched library call on one of several stre
 Requests that arrive while batches run are admitted as soon as memory and a stream free
 up, so their work overlaps on the device with the batches still running.  Inputs (Y, W)
 stay resident for the whole run; each request's factors stay on the device in its result.
+Each stream owns one workspace arena, grown to the largest group it has run and reused by
+every later group on that stream, so the caching allocator does not accumulate one
+workspace per batch (memory that the runtime may need itself, e.g. for kernel scratch).
 
 `batching=False, max_inflight=1` serves the same trace first-in first-out one request at
 a time through the single-problem call: the plain baseline.
@@ -20,7 +23,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Request, _lib, _problem, decompose, decompose_batched
+from . import Request, _lib, _problem, decompose, decompose_batched, workspace_bytes
 
 
 @dataclass
@@ -88,6 +91,7 @@ class Server:
         self.keep = keep_results
         self.device = pool[0].Y.device
         self.streams = [torch.cuda.Stream(self.device) for _ in range(self.max_inflight)]
+        self.arenas = [None] * self.max_inflight   # per stream: uint8 tensor, 256-aligned
         for it in pool:
             it.footprint = self._footprint(it)
             if it.footprint > self.budget:
@@ -100,6 +104,21 @@ class Server:
 
     def _footprint(self, it: PoolItem) -> int:
         return footprint(it)
+
+    def _arena(self, si: int, nbytes: int):
+        """The stream's workspace arena, grown (by a quarter beyond the need) when a group
+        needs more; allocated on that stream, and only replaced between its groups."""
+        torch = self.torch
+        a = self.arenas[si]
+        if a is None or a.numel() < nbytes:
+            self.arenas[si] = None
+            with torch.cuda.stream(self.streams[si]):
+                buf = torch.empty(nbytes + nbytes // 4 + 256, dtype=torch.uint8,
+                                  device=self.device)
+            off = (-buf.data_ptr()) % 256
+            a = buf[off:]
+            self.arenas[si] = a
+        return a
 
     def run(self, jobs: list[Job], time_limit: float | None = None,
             sample: dict | None = None) -> dict:
@@ -161,10 +180,13 @@ class Server:
                 with torch.cuda.stream(st):
                     reqs = [self._request(j) for j in group]
                     if self.batching:
-                        results = decompose_batched(reqs, stream=st)
+                        ws = self._arena(si, workspace_bytes(reqs))
+                        results = decompose_batched(reqs, stream=st, workspace=ws)
                     else:
+                        ws = self._arena(si, max(workspace_bytes([q]) for q in reqs))
                         results = [decompose(q.Y, q.W, q.r, q.num_submatrices, q.seed, l=q.l,
-                                             gram=q.gram, flags=q.flags, stream=st)
+                                             gram=q.gram, flags=q.flags, stream=st,
+                                             workspace=ws)
                                    for q in reqs]
                     ev = torch.cuda.Event()
                     ev.record(st)

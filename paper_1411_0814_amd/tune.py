@@ -98,7 +98,8 @@ def autotune(requests, *, wgs=WGS_CANDIDATES, reps: int = 3, stream=None,
     report = []
     for (l, prec, ydt), members in sorted(groups.items()):
         shapes = [(kern, nt) for kern in (_lib.GRAM_KERNEL_REGS, _lib.GRAM_KERNEL_DMA,
-                                          _lib.GRAM_KERNEL_DMA2)
+                                          _lib.GRAM_KERNEL_DMA2, _lib.GRAM_KERNEL_GATHER,
+                                          _lib.GRAM_KERNEL_AUTO)
                   for nt in _lib.tune_threads(l, prec, ydt, kern)]
         if not shapes:
             continue                                 # per-trial streamer: nothing to tune

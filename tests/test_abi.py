@@ -277,6 +277,12 @@ def test_tune_threads_lists_built_kernels():
     assert _lib.tune_threads(14, _lib.GRAM_F64, F32, DB) == [256, 512]
     assert _lib.tune_threads(15, _lib.GRAM_F64, F32, DB) == [256]
     assert _lib.tune_threads(6, _lib.GRAM_F64, F32, DMA) == []
+    for kern in (_lib.GRAM_KERNEL_GATHER, _lib.GRAM_KERNEL_AUTO):  # as the two-buffer kernel
+        assert _lib.tune_threads(12, _lib.GRAM_F32, F32, kern) == [512, 1024]
+        assert _lib.tune_threads(13, _lib.GRAM_F32, F32, kern) == [512]
+        assert _lib.tune_threads(14, _lib.GRAM_F64, F32, kern) == [256, 512]
+        assert _lib.tune_threads(6, _lib.GRAM_F64, F64, kern) == []
+        assert _lib.tune_threads(9, _lib.GRAM_BF16X2, F32, kern) == []
     assert _lib.tune_threads(16, _lib.GRAM_BF16X2, F32) == [64]
     assert _lib.tune_threads(17, _lib.GRAM_BF16X2, F32) == []
 
@@ -294,7 +300,7 @@ def test_tune_table_roundtrip_and_validation(empty_tune_table):
     bad = [_entry(l=1), _entry(l=_lib.MAX_L + 1), _entry(gram_threads=384),
            _entry(l=12, gram_threads=512, gram_kernel=_lib.GRAM_KERNEL_REGS),
            _entry(l=13, gram_threads=1024),          # built-in kernel at l = 13: 512 only
-           _entry(gram_kernel=4), _entry(gram_kernel=-1),
+           _entry(gram_kernel=6), _entry(gram_kernel=-1),
            _entry(l=13, gram_threads=1024, gram_kernel=_lib.GRAM_KERNEL_DMA2),
            _entry(l=6, gram_prec=_lib.GRAM_F64, y_dtype=_lib.F64, gram_threads=0,
                   gram_kernel=_lib.GRAM_KERNEL_DMA),

@@ -136,6 +136,21 @@ def test_low_row_regime_of_table1(gram):
           flush=True)
 
 
+@pytest.mark.parametrize("gram", ["f32", "f64"])
+def test_few_qualifying_rows_gathered(gram):
+    """FP32 data whose trials keep about 22 of 30011 rows (rho = 0.3, l = 6): the built-in
+    kernel choice gathers the qualifying values from Y instead of staging every column; FP32
+    and FP64 sums."""
+    p = synth.paper_synthetic(30011, 301, 5, 0.3, 1e-2, 73, factor_dtype=np.float32,
+                              y_dtype=np.float32, relative_sigma=True, num_submatrices=2000,
+                              l=6, seed_rsm=74, gram=gram)
+    res, info = _run(p, gram, taps=True)
+    ora = rsm.rsm(p.Y, p.W, p.r, p.num_submatrices, seed=p.seed_rsm, l=p.l, with_e=False)
+    theta, rms = _compare_full(p, res, info, ora, u=2.0**-24 if gram == "f32" else 2.0**-53)
+    print(f"gathered {gram}: mean rows {info['rows_total'] / p.num_submatrices:.1f} "
+          f"theta={theta:.3e} rms={rms:.3e}", flush=True)
+
+
 def test_ragged_row_major_fp64():
     """m, n not multiples of 64; row-major Y and W (repacked by the library)."""
     import torch

@@ -19,7 +19,7 @@ def _empty_table():
     _lib.tune_set([])
 
 
-REGS, DMA, DMA2 = 1, 2, 3
+REGS, DMA, DMA2, GATHER, AUTO = 1, 2, 3, 4, 5
 # (l, Y/Gram type, trials per workgroup, workgroup target, staging): both staging kernels,
 # both thread counts, a single row split and many row splits
 CASES = [(3, "f32", 256, 1, REGS), (6, "f32", 256, 8192, REGS), (9, "f32", 512, 8192, REGS),
@@ -30,7 +30,11 @@ CASES = [(3, "f32", 256, 1, REGS), (6, "f32", 256, 8192, REGS), (9, "f32", 512, 
          (17, "f32", 512, 4096, DMA2),
          # "f64/f32": FP64 sums of FP32 data
          (4, "f64/f32", 512, 1, DMA2), (14, "f64/f32", 512, 4096, DMA2),
-         (17, "f64/f32", 256, 64, DMA2)]
+         (17, "f64/f32", 256, 64, DMA2),
+         # gathering the qualifying values (forced), and the per-problem choice
+         (3, "f32", 1024, 1, GATHER), (12, "f32", 512, 4096, GATHER), (17, "f32", 512, 64, GATHER),
+         (5, "f64/f32", 512, 8192, GATHER), (16, "f64/f32", 256, 1, GATHER),
+         (9, "f32", 1024, 2048, AUTO), (15, "f64/f32", 256, 2048, AUTO)]
 
 
 @pytest.mark.parametrize("l,prec,threads,wgs,kernel", CASES)
