@@ -335,8 +335,11 @@ __device__ __forceinline__ void lds_dma4(const void* src, void* dst) {
 // density (its ones counted while packing it).  A problem gathers when that is the smaller:
 // f l 16 NT < n.  The choice depends only on the problem, so a deterministic problem takes
 // the same path alone and in any batch.
+// Called by whole wavefronts (lane k reads partial count k; their sum is exact).
 __device__ __forceinline__ bool gram_gathers(const ProbDesc& P, int nt) {
-  const double known = static_cast<double>(P.scal->mask_ones);
+  static_assert(kMaskOnesParts == 64, "one partial count per lane");
+  const unsigned long long part = P.scal->mask_ones[threadIdx.x & 63];
+  const double known = static_cast<double>(wave_sum<unsigned long long>(part));
   const double rho = known / (static_cast<double>(P.m) * static_cast<double>(P.n));
   const double f = rho > 0.0 ? exp(static_cast<double>(P.l) * log(rho)) : 0.0;
   return f * P.l * 16.0 * nt < static_cast<double>(P.n);

@@ -14,10 +14,14 @@ namespace rsm {
 namespace {
 
 // Column-major W: one thread per (column, 64-row word) of problem list.idx[blockIdx.y].
-// Each wavefront adds the ones of its words to the problem's count of known entries.
-__global__ void k_pack_mask_colmajor(const ProbDesc* __restrict__ probs, IdxList list) {
+// Each workgroup adds the ones of its words to one of the problem's partial counts of known
+// entries.
+__global__ __launch_bounds__(256) void k_pack_mask_colmajor(const ProbDesc* __restrict__ probs,
+                                                            IdxList list) {
+  __shared__ unsigned long long wave_ones[4];
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
   const int64_t m = P.m, n = P.n, mw = P.mw;
+  if (static_cast<int64_t>(blockIdx.x) * blockDim.x >= n * mw) return;  // whole workgroup
   const int64_t gid0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const bool in = gid0 < n * mw;
   const int64_t gid = in ? gid0 : 0;
@@ -57,7 +61,12 @@ __global__ void k_pack_mask_colmajor(const ProbDesc* __restrict__ probs, IdxList
   if (in) P.wbits[j * mw + w] = word;
   const unsigned long long ones =
       wave_sum<unsigned long long>(in ? static_cast<unsigned long long>(__popcll(word)) : 0ull);
-  if ((threadIdx.x & 63) == 0 && ones) atomicAdd(&P.scal->mask_ones, ones);
+  if ((threadIdx.x & 63) == 0) wave_ones[threadIdx.x >> 6] = ones;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long tot = wave_ones[0] + wave_ones[1] + wave_ones[2] + wave_ones[3];
+    if (tot) atomicAdd(&P.scal->mask_ones[blockIdx.x % kMaskOnesParts], tot);
+  }
 }
 
 // Row-major W: a 64-row x 64-column byte tile through LDS, one thread per output word.
@@ -85,7 +94,8 @@ __global__ __launch_bounds__(256) void k_pack_mask_rowmajor(const ProbDesc* __re
     }
     const unsigned long long ones =
         wave_sum<unsigned long long>(static_cast<unsigned long long>(__popcll(word)));
-    if (threadIdx.x == 0 && ones) atomicAdd(&P.scal->mask_ones, ones);
+    if (threadIdx.x == 0 && ones)
+      atomicAdd(&P.scal->mask_ones[(blockIdx.x + blockIdx.y) % kMaskOnesParts], ones);
   }
 }
 
@@ -190,8 +200,8 @@ __global__ void k_init_info(const ProbDesc* __restrict__ probs, IdxList list) {
     scal->bar = 0;
     scal->ticket = 0;
     scal->stalled = 0;
-    scal->mask_ones = 0;
   }
+  for (int k = threadIdx.x; k < kMaskOnesParts; k += blockDim.x) scal->mask_ones[k] = 0;
   if (threadIdx.x < RSM_MAX_R + 1) info->lambda[threadIdx.x] = 0.0;
 }
 

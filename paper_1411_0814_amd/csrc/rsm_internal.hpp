@@ -45,6 +45,8 @@ __host__ __device__ constexpr int tile_threads(int l, int elem_bytes) {
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+constexpr int kMaskOnesParts = 64;
+
 // Scalars the device passes between steps of one problem (lives in the workspace).
 struct DevScalars {
   double mu;            // shift of the factorisation
@@ -53,7 +55,9 @@ struct DevScalars {
   uint32_t bar;         // arrival count of the group solver's barrier
   uint32_t ticket;      // workgroup tickets of the group solver (first problem of a launch)
   uint32_t stalled;     // set when a group barrier wait timed out (the launch then stops)
-  unsigned long long mask_ones;  // known entries of W (counted while packing the mask)
+  // known entries of W, counted while packing the mask: 64 partial counts (workgroup k of
+  // the packing adds to entry k mod 64, so that no single address takes every atomic)
+  unsigned long long mask_ones[kMaskOnesParts];
 };
 
 // Group form of the V-hat solver's subspace iteration: rows of the iterate per workgroup,
