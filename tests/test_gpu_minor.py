@@ -55,6 +55,19 @@ def test_inverse_iteration_matches_jacobi_and_oracle(l, dt, noise):
     assert err_inv <= ((1e-9 if noise < 0.1 else 1e-7) if dt == np.float64 else 1e-4), err_inv
     Va, Ua = a.V.cpu().numpy(), a.U.cpu().numpy()
     assert metrics.principal_angle_max(Va, b.V.cpu().numpy()) <= 1e-5
+    theta = metrics.principal_angle_max(Va, ora.V)
     if noise < 0.1:
-        assert metrics.principal_angle_max(Va, ora.V) <= 1e-4
+        assert theta <= 1e-4
         assert metrics.rel_rms_known(p.W, Ua, Va, ora.U, ora.V) <= 1e-5
+    else:
+        # heavy noise leaves a small gap between the r-th and (r+1)-th eigenvalues of N, so
+        # V-hat moves with N's differences: Davis-Kahan's sin-theta theorem bounds the angle
+        # by ||N_gpu - N_oracle||_2 (plus the V-hat solver's residual, 1e-10 lam_max) over
+        # that gap, here with a factor 2 of slack
+        lam = np.linalg.eigvalsh(ora.N)
+        gap = lam[r] - lam[r - 1]
+        dN = np.linalg.norm(Na - ora.N, 2)
+        bound = 2.0 * (dN + 1e-9 * lam[-1]) / gap
+        print(f"[minor l={l} noise={noise}] theta {theta:.2e} sin-theta bound {bound:.2e} "
+              f"(gap {gap:.3g}, ||dN|| {dN:.2e})", flush=True)
+        assert np.sin(theta) <= bound, (theta, bound)
