@@ -227,12 +227,21 @@ __device__ __forceinline__ void unpack_pair(int e, int& a, int& b) {
   b = e - a * (a + 1) / 2;
 }
 
+// A workgroup barrier that orders LDS only: the global loads of the next stage stay in
+// flight across it (__syncthreads also waits for every outstanding global load).  The
+// kernel shares nothing but LDS between its threads.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Workgroup: 128 consecutive rows (4 wavefronts x 2 tiles of 16).  Per stage of 32 columns
 // the workgroup writes K's and V's rows for those columns to LDS ([K | 0 | V | 0] per
 // column, the B operands); each lane loads the mask bit and Y value of its (row, column)
 // position of every k-step (the A operands: the bit as 0/1 for the A part, bit times y for
-// the b part) before the staging, so the loads overlap it.  Rows past m and columns past n
-// have weight 0.
+// the b part), the next stage's issued while the current stage's K is staged.  Rows past m
+// and columns past n have weight 0.
 template <int R, typename TY>
 __global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ probs, IdxList list) {
   using S = UfShape<R>;
@@ -289,13 +298,17 @@ __global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ prob
   };
   load_stage(0, wreg, yreg);
   for (int64_t c0 = 0; c0 < n; c0 += kUfCols) {
-    __syncthreads();  // the previous stage's B operands are consumed
+    lds_barrier();  // the previous stage's B operands are consumed
     for (int e = tid; e < kUfCols * R; e += 256) {
       const int c = e / R, a = e - c * R;
       const int64_t j = c0 + c;
       Vc[e] = j < n ? V[j + static_cast<int64_t>(a) * n] : 0.0;
     }
-    __syncthreads();
+    lds_barrier();
+    // the next stage's A operands: issued after this stage's V-hat loads have landed
+    // (loads complete in order, so a wait on those would wait on these too), to land while
+    // K is staged and the products run
+    if (c0 + kUfCols < n) load_stage(c0 + kUfCols, wnext, ynext);
     for (int e = tid; e < kUfCols * T * 16; e += 256) {
       const int c = e / (T * 16), q = e - c * (T * 16);
       double val = 0.0;
@@ -306,18 +319,18 @@ __global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ prob
       }
       Kc[c * LD + q] = val;
     }
-    __syncthreads();
-    if (c0 + kUfCols < n) load_stage(c0 + kUfCols, wnext, ynext);
+    lds_barrier();
 #pragma unroll
     for (int ks = 0; ks < kUfCols / 4; ++ks) {
-      const bool jok = c0 + 4 * ks + lk < n;
+      // the mask bit as a 0/1 weight, formed without branches
+      const uint32_t jok = (c0 + 4 * ks + lk < n) ? 1u : 0u;
       double aw[kUfTiles], awy[kUfTiles];
 #pragma unroll
       for (int t = 0; t < kUfTiles; ++t) {
-        const bool known = jok && rok[t] && ((wreg[ks][t] >> (ic[t] & 31)) & 1u);
-        aw[t] = known ? 1.0 : 0.0;
-        awy[t] = known ? static_cast<double>(yreg[ks][t]) : 0.0;
-        cnt[t] += known ? 1 : 0;
+        const uint32_t kn = (wreg[ks][t] >> (ic[t] & 31)) & jok & (rok[t] ? 1u : 0u);
+        aw[t] = static_cast<double>(kn);
+        awy[t] = kn ? static_cast<double>(yreg[ks][t]) : 0.0;
+        cnt[t] += static_cast<int>(kn);
       }
       const double* brow = Kc + (4 * ks + lk) * LD + li;
 #pragma unroll
