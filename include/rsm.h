@@ -109,8 +109,9 @@ enum {
   RSM_N_ACCUMULATE = 1u << 2,    /* add this call's trials onto the N passed in out->N
                                     instead of starting from zero (resume / sharding) */
   RSM_COMPUTE_ERROR = 1u << 3,   /* fill rsm_info.e (eq.(ep)) with an extra pass over Y */
-  RSM_PLAIN_GRAM = 1u << 4,      /* use the per-trial column-streaming Gram kernel
-                                    (the unblocked baseline) instead of the tiled one */
+  RSM_PLAIN_GRAM = 1u << 4,      /* use the per-trial column-streaming Gram kernel alone
+                                    (the unblocked baseline) instead of the tiled or the
+                                    gathering one */
   RSM_DETERMINISTIC = 1u << 5,   /* bitwise-reproducible results, whatever else shares the
                                     launches: N is accumulated in 64-bit fixed point with
                                     2^-40 resolution (integer atomics, order-free) instead

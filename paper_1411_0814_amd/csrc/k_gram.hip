@@ -34,9 +34,30 @@ namespace {
 
 // ------------------------------------------------------------------ per-trial streamer
 
+// Staging every column of a chunk pays for all n columns whatever a trial keeps: per trial
+// and 64-row word about 64 n 4 / NT bytes (the chunk, shared by the workgroup's NT trials).
+// Loading a trial's qualifying values straight from Y pays about a cache line per value:
+// 64 f l 64 bytes, f = rho^l the expected fraction of qualifying rows, rho the mask's
+// density (its ones counted while packing it).  A problem gathers when that is the smaller:
+// f l 16 NT < n.  The choice depends only on the problem, so a deterministic problem takes
+// the same path alone and in any batch.
+// Called by whole wavefronts (lane k reads partial count k; their sum is exact).
+__device__ __forceinline__ bool gram_gathers(const ProbDesc& P, int nt) {
+  static_assert(kMaskOnesParts == 64, "one partial count per lane");
+  const unsigned long long part = P.scal->mask_ones[threadIdx.x & 63];
+  const double known = static_cast<double>(wave_sum<unsigned long long>(part));
+  const double rho = known / (static_cast<double>(P.m) * static_cast<double>(P.n));
+  const double f = rho > 0.0 ? exp(static_cast<double>(P.l) * log(rho)) : 0.0;
+  return f * P.l * 16.0 * nt < static_cast<double>(P.n);
+}
+
+// Launch modes of the two FP32-data kernels: every problem of the launch, or only the
+// problems gram_gathers gives to that kernel (both kernels run with kModeAuto).
+constexpr int kModeAll = 0, kModeAuto = 1;
+
 template <int L, typename TY, typename TA>
 __global__ __launch_bounds__(256) void k_gram_plain(const ProbDesc* __restrict__ probs,
-                                                    IdxList list) {
+                                                    IdxList list, int mode) {
   constexpr int NG = L * (L + 1) / 2;
   const ProbDesc& P = probs[list.idx[blockIdx.z]];
   const int64_t I = P.I, mw = P.mw, ldy = P.ldy;
@@ -44,6 +65,7 @@ __global__ __launch_bounds__(256) void k_gram_plain(const ProbDesc* __restrict__
   const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int split = blockIdx.y;
   if (t >= I || split >= P.splits) return;  // wave-uniform
+  if (mode == kModeAuto && gram_gathers(P, kGatherPlainThreads)) return;  // gathered instead
   const int64_t w0 = static_cast<int64_t>(split) * P.words_per_split;
   const int64_t w1 = (w0 + P.words_per_split < mw) ? (w0 + P.words_per_split) : mw;
   auto Y = static_cast<RSM_GLOBAL const TY*>(P.ycm);
@@ -236,15 +258,17 @@ __device__ __forceinline__ void tile_work(int groups, int splits, int& group, in
   }
 }
 
+
 template <int L, typename T, int NT>
 __global__ __launch_bounds__(NT) void k_gram_tile(const ProbDesc* __restrict__ probs,
-                                                  IdxList list) {
+                                                  IdxList list, int mode) {
   constexpr int NG = L * (L + 1) / 2;
   using S = ChunkStager<T, NT>;
   constexpr int kS = S::kS;
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
   const int groups = P.gram_groups, splits = P.splits;
   if (static_cast<int>(blockIdx.x) >= groups * splits) return;  // past this problem's work
+  if (mode == kModeAuto && gram_gathers(P, NT)) return;           // k_gram_gather takes it
   const int64_t m = P.m, I = P.I;
   const int n = static_cast<int>(P.n);
   const int n_pad = static_cast<int>(ceil_div(n, NT / S::kVPC) * (NT / S::kVPC));
@@ -328,26 +352,6 @@ __device__ __forceinline__ void lds_dma4(const void* src, void* dst) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
 }
 
-// Staging every column of a chunk pays for all n columns whatever a trial keeps: per trial
-// and 64-row word about 64 n 4 / NT bytes (the chunk, shared by the workgroup's NT trials).
-// Loading a trial's qualifying values straight from Y pays about a cache line per value:
-// 64 f l 64 bytes, f = rho^l the expected fraction of qualifying rows, rho the mask's
-// density (its ones counted while packing it).  A problem gathers when that is the smaller:
-// f l 16 NT < n.  The choice depends only on the problem, so a deterministic problem takes
-// the same path alone and in any batch.
-// Called by whole wavefronts (lane k reads partial count k; their sum is exact).
-__device__ __forceinline__ bool gram_gathers(const ProbDesc& P, int nt) {
-  static_assert(kMaskOnesParts == 64, "one partial count per lane");
-  const unsigned long long part = P.scal->mask_ones[threadIdx.x & 63];
-  const double known = static_cast<double>(wave_sum<unsigned long long>(part));
-  const double rho = known / (static_cast<double>(P.m) * static_cast<double>(P.n));
-  const double f = rho > 0.0 ? exp(static_cast<double>(P.l) * log(rho)) : 0.0;
-  return f * P.l * 16.0 * nt < static_cast<double>(P.n);
-}
-
-// Launch modes of the two FP32-data kernels: every problem of the launch, or only the
-// problems gram_gathers gives to that kernel (both kernels run with kModeAuto).
-constexpr int kModeAll = 0, kModeAuto = 1;
 
 // DB: two chunk buffers; the loads of chunk k + 1 are issued right after the barrier that
 // publishes chunk k and land while chunk k is summed (one barrier per chunk).
@@ -466,8 +470,8 @@ __global__ __launch_bounds__(NT) void k_gram_dma(const ProbDesc* __restrict__ pr
 // sums and row counts as k_gram_dma.
 
 // One qualifying row's products, summed in TA.
-template <int L, typename TA>
-__device__ __forceinline__ void sum_row(const float (&y)[L], TA (&acc)[L * (L + 1) / 2]) {
+template <int L, typename TA, typename TY>
+__device__ __forceinline__ void sum_row(const TY (&y)[L], TA (&acc)[L * (L + 1) / 2]) {
   TA v[L];
 #pragma unroll
   for (int a = 0; a < L; ++a) v[a] = static_cast<TA>(y[a]);
@@ -478,20 +482,22 @@ __device__ __forceinline__ void sum_row(const float (&y)[L], TA (&acc)[L * (L + 
     for (int b = 0; b <= a; ++b) acc[g++] += v[a] * v[b];
 }
 
-template <int L, int NT, typename TA>
+template <int L, int NT, typename TA, typename TY>
 __global__ __launch_bounds__(NT) void k_gram_gather(const ProbDesc* __restrict__ probs,
                                                     IdxList list, int mode) {
   constexpr int NG = L * (L + 1) / 2;
   constexpr int NW = NT / 64;
-  // the pipelined loop holds a second row of values (l registers); kept only where the
-  // registers of NT / 256 wavefronts per SIMD leave room for it (an estimate: the sums,
-  // 5 l for the columns and the two rows, 48 for the rest)
+  // the pipelined loop holds a second row of values; kept only where the registers of
+  // NT / 256 wavefronts per SIMD leave room for it (an estimate: the sums, the column
+  // addresses and indices, the two rows, 48 for the rest)
   constexpr int kRegs = 512 / (NT / 256);
-  constexpr bool kPipe = NG * static_cast<int>(sizeof(TA) / 4) + 5 * L + 48 <= kRegs;
+  constexpr int kYRegs = static_cast<int>(sizeof(TY) / 4);
+  constexpr bool kPipe =
+      NG * static_cast<int>(sizeof(TA) / 4) + 3 * L + 2 * kYRegs * L + 48 <= kRegs;
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
   const int groups = P.gram_groups, splits = P.splits;
   if (static_cast<int>(blockIdx.x) >= groups * splits) return;  // past this problem's work
-  if (mode == kModeAuto && !gram_gathers(P, NT)) return;          // k_gram_dma takes it
+  if (mode == kModeAuto && !gram_gathers(P, NT)) return;          // the staging kernel takes it
   const int64_t I = P.I, ldy = P.ldy, mw = P.mw, mw32 = 2 * P.mw;
   const int n = static_cast<int>(P.n);
   const int n64 = (n + 63) & ~63;
@@ -506,7 +512,7 @@ __global__ __launch_bounds__(NT) void k_gram_gather(const ProbDesc* __restrict__
   const bool active = t < I;
   const int64_t w0 = static_cast<int64_t>(split) * P.words_per_split;
   const int64_t w1 = (w0 + P.words_per_split < mw) ? (w0 + P.words_per_split) : mw;
-  auto Y = static_cast<RSM_GLOBAL const float*>(P.ycm);
+  auto Y = static_cast<RSM_GLOBAL const TY*>(P.ycm);
   auto wbits32 = reinterpret_cast<RSM_GLOBAL const uint32_t*>(P.wbits);
 
   int mc[L];
@@ -517,7 +523,7 @@ __global__ __launch_bounds__(NT) void k_gram_gather(const ProbDesc* __restrict__
     valid &= (c >= 0);
     mc[a] = c < 0 ? 0 : c;
   }
-  RSM_GLOBAL const float* col[L];
+  RSM_GLOBAL const TY* col[L];
 #pragma unroll
   for (int a = 0; a < L; ++a) col[a] = Y + static_cast<int64_t>(mc[a]) * ldy;
   TA acc[NG];
@@ -555,19 +561,19 @@ __global__ __launch_bounds__(NT) void k_gram_gather(const ProbDesc* __restrict__
       // the current row's products are summed
       int64_t row = w * 64 + (__ffsll(static_cast<unsigned long long>(q)) - 1);
       q &= q - 1;
-      float y[L];
+      TY y[L];
 #pragma unroll
       for (int a = 0; a < L; ++a) y[a] = col[a][row];
       while (true) {
         const bool more = q != 0;
-        float yn[L];
+        TY yn[L];
         if (more) {
           const int64_t rn = w * 64 + (__ffsll(static_cast<unsigned long long>(q)) - 1);
           q &= q - 1;
 #pragma unroll
           for (int a = 0; a < L; ++a) yn[a] = col[a][rn];
         }
-        sum_row<L, TA>(y, acc);
+        sum_row<L, TA, TY>(y, acc);
         if (!more) break;
 #pragma unroll
         for (int a = 0; a < L; ++a) y[a] = yn[a];
@@ -576,10 +582,10 @@ __global__ __launch_bounds__(NT) void k_gram_gather(const ProbDesc* __restrict__
       while (q) {
         const int64_t row = w * 64 + (__ffsll(static_cast<unsigned long long>(q)) - 1);
         q &= q - 1;
-        float y[L];
+        TY y[L];
 #pragma unroll
         for (int a = 0; a < L; ++a) y[a] = col[a][row];
-        sum_row<L, TA>(y, acc);
+        sum_row<L, TA, TY>(y, acc);
       }
     }
   }
@@ -735,7 +741,8 @@ constexpr bool tile_has_512() {
 }
 
 template <int L, typename T, int NT>
-void run_tile_nt(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
+void run_tile_nt(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s,
+                 int mode = kModeAll) {
   size_t lds = 0;
   int wgs = 0;
   for (int k = 0; k < g.count; ++k) {
@@ -750,7 +757,7 @@ void run_tile_nt(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipS
     attr_set = true;
   }
   const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
-  k_gram_tile<L, T, NT><<<dim3(grid, g.count), NT, lds, s>>>(d, g);
+  k_gram_tile<L, T, NT><<<dim3(grid, g.count), NT, lds, s>>>(d, g, mode);
 }
 
 template <int L, int NT, bool DB, typename TA = float>
@@ -774,7 +781,7 @@ void run_dma(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStrea
   k_gram_dma<L, NT, DB, TA><<<dim3(grid, g.count), NT, lds, s>>>(d, g, mode);
 }
 
-template <int L, int NT, typename TA>
+template <int L, int NT, typename TA, typename TY = float>
 void run_gather(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s,
                 int mode) {
   size_t lds = 0;
@@ -785,7 +792,7 @@ void run_gather(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipSt
     wgs = std::max(wgs, h[k]->gram_wgs);
   }
   const unsigned grid = static_cast<unsigned>(ceil_div(wgs, 8) * 8);
-  k_gram_gather<L, NT, TA><<<dim3(grid, g.count), NT, lds, s>>>(d, g, mode);
+  k_gram_gather<L, NT, TA, TY><<<dim3(grid, g.count), NT, lds, s>>>(d, g, mode);
 }
 
 // The straight-to-LDS kernels of FP32 data with sums of type TA: kernel DMA2 stages every
@@ -831,13 +838,21 @@ void run_tile(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStre
       return;
     }
   }
+  // FP64 data: the register-staged kernel (REGS), the gathering one (GATHER), or both,
+  // each taking the problems gram_gathers gives it (AUTO)
+  const int kern = h[0]->gram_kernel;
+  const int mode = kern == RSM_GRAM_KERNEL_AUTO ? kModeAuto : kModeAll;
   if constexpr (tile_has_512<L, T>()) {
     if (h[0]->gram_threads == 512) {
-      run_tile_nt<L, T, 512>(d, g, h, s);
+      if (kern != RSM_GRAM_KERNEL_GATHER) run_tile_nt<L, T, 512>(d, g, h, s, mode);
+      if constexpr (sizeof(T) == 8)
+        if (kern != RSM_GRAM_KERNEL_REGS) run_gather<L, 512, double, double>(d, g, h, s, mode);
       return;
     }
   }
-  run_tile_nt<L, T, 256>(d, g, h, s);
+  if (kern != RSM_GRAM_KERNEL_GATHER) run_tile_nt<L, T, 256>(d, g, h, s, mode);
+  if constexpr (sizeof(T) == 8)
+    if (kern != RSM_GRAM_KERNEL_REGS) run_gather<L, 256, double, double>(d, g, h, s, mode);
 }
 
 // FP32 Y, FP64 sums: the double-buffered direct-to-LDS kernel with FP64 accumulators
@@ -887,8 +902,11 @@ void run_plain(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStr
     I = std::max(I, h[k]->I);
     splits = std::max(splits, h[k]->splits);
   }
+  // AUTO: the gathering kernel takes the problems whose trials keep few rows
+  const bool pair = h[0]->gram_kernel == RSM_GRAM_KERNEL_AUTO;
   const dim3 grid(static_cast<unsigned>(ceil_div(I, 4)), static_cast<unsigned>(splits), g.count);
-  k_gram_plain<L, TY, TA><<<grid, 256, 0, s>>>(d, g);
+  k_gram_plain<L, TY, TA><<<grid, 256, 0, s>>>(d, g, pair ? kModeAuto : kModeAll);
+  if (pair) run_gather<L, kGatherPlainThreads, TA, TY>(d, g, h, s, kModeAuto);
 }
 
 template <int L>
@@ -936,6 +954,14 @@ int gram_threads_built(int l, int prec, int y_dtype, int kernel, int* out) {
     return 1;
   }
   if (f64 != (y_dtype == RSM_F64)) return 0;
+  if (f64 && (kernel == RSM_GRAM_KERNEL_GATHER || kernel == RSM_GRAM_KERNEL_AUTO)) {
+    out[0] = 256;  // FP64 data: as the register-staged kernel it pairs with
+    if (l <= 6) {
+      out[1] = 512;
+      return 2;
+    }
+    return 1;
+  }
   if (kernel == RSM_GRAM_KERNEL_DMA) {
     if (f64) return 0;
     out[0] = 256;

@@ -107,7 +107,9 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
     P.gram_kernel = default_gram_kernel(P);
     set_gram_shape(P, default_gram_threads(P, P.gram_kernel), 0);
   } else {
-    P.gram_kernel = 0;
+    // the per-trial streamer, paired with the gathering kernel (each takes the problems the
+    // mask's density gives it) unless the caller asked for the streamer alone
+    P.gram_kernel = (p.flags & RSM_PLAIN_GRAM) ? 0 : RSM_GRAM_KERNEL_AUTO;
     set_gram_shape(P, 0, 0);
   }
   return RSM_OK;
@@ -115,14 +117,13 @@ int32_t make_plan(const rsm_problem& p, Plan& P) {
 
 // Staging of the tiled kernels when the tile table does not say otherwise: FP32 data loads
 // straight into LDS with two chunk buffers (no staging registers, loads overlapping the
-// sums), or for problems whose trials keep few rows only the mask words, the values
-// gathered from Y (chosen per problem on the device), with FP32 or FP64 sums; FP64 data and
-// split-BF16 stage through registers.
+// sums), FP64 data through registers; for problems whose trials keep few rows, only the
+// mask words are staged and the values gathered from Y (chosen per problem on the device).
+// Split-BF16 stages through registers.
 int builtin_gram_kernel(int l, int prec, int y_dtype) {
   (void)l;
-  return ((prec == RSM_GRAM_F32 || prec == RSM_GRAM_F64) && y_dtype == RSM_F32)
-             ? RSM_GRAM_KERNEL_AUTO
-             : RSM_GRAM_KERNEL_REGS;
+  if (prec == RSM_GRAM_BF16X2) return RSM_GRAM_KERNEL_REGS;
+  return RSM_GRAM_KERNEL_AUTO;
 }
 
 int default_gram_kernel(const Plan& P) { return builtin_gram_kernel(P.l, P.prec, P.y_dtype); }
@@ -140,6 +141,9 @@ bool threads_built(int l, int prec, int y_dtype, int kernel, int threads) {
 int default_gram_threads(const Plan& P, int kernel) {
   if (P.prec == RSM_GRAM_BF16X2) return kBfTrialsPerGroup;
   if (kernel == RSM_GRAM_KERNEL_DMA) return 256;
+  if ((kernel == RSM_GRAM_KERNEL_GATHER || kernel == RSM_GRAM_KERNEL_AUTO) &&
+      P.y_dtype == RSM_F64)
+    return tile_threads(P.l, 8);  // FP64 data: as the register-staged kernel it pairs with
   if (kernel == RSM_GRAM_KERNEL_DMA2 || kernel == RSM_GRAM_KERNEL_GATHER ||
       kernel == RSM_GRAM_KERNEL_AUTO) {
     if (P.prec == RSM_GRAM_F64) return P.l <= 14 ? 512 : 256;  // FP64 sums of FP32 data
@@ -164,6 +168,14 @@ void set_gram_shape(Plan& P, int threads, int64_t splits_hint) {
   } else {
     P.gram_threads = 0;
     if (P.I > 0 && P.I < 8192) splits = ceil_div(8192, P.I);
+    // the gathering kernel paired with the streamer takes its trials in groups, with
+    // row splits for about four workgroups per CU (at most 16: the partial sums of every
+    // split are written and reduced)
+    if (P.gram_kernel == RSM_GRAM_KERNEL_AUTO) {
+      groups = ceil_div(P.I > 0 ? P.I : 1, kGatherPlainThreads);
+      const int64_t want = std::min<int64_t>(16, ceil_div(4 * kTileTargetGroups, groups));
+      splits = std::max<int64_t>(splits, want);
+    }
   }
   if (splits > P.mw) splits = P.mw;
   P.words_per_split = ceil_div(P.mw, splits);

@@ -47,6 +47,10 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr int kMaskOnesParts = 64;
 
+// Trials per workgroup of the gathering Gram kernel when it pairs with the per-trial
+// streamer (problems whose n-column tile does not fit LDS).
+constexpr int kGatherPlainThreads = 256;
+
 // Scalars the device passes between steps of one problem (lives in the workspace).
 struct DevScalars {
   double mu;            // shift of the factorisation

@@ -281,7 +281,8 @@ def test_tune_threads_lists_built_kernels():
         assert _lib.tune_threads(12, _lib.GRAM_F32, F32, kern) == [512, 1024]
         assert _lib.tune_threads(13, _lib.GRAM_F32, F32, kern) == [512]
         assert _lib.tune_threads(14, _lib.GRAM_F64, F32, kern) == [256, 512]
-        assert _lib.tune_threads(6, _lib.GRAM_F64, F64, kern) == []
+        assert _lib.tune_threads(6, _lib.GRAM_F64, F64, kern) == [256, 512]   # FP64 data
+        assert _lib.tune_threads(7, _lib.GRAM_F64, F64, kern) == [256]
         assert _lib.tune_threads(9, _lib.GRAM_BF16X2, F32, kern) == []
     assert _lib.tune_threads(16, _lib.GRAM_BF16X2, F32) == [64]
     assert _lib.tune_threads(17, _lib.GRAM_BF16X2, F32) == []

@@ -34,7 +34,8 @@ CASES = [(3, "f32", 256, 1, REGS), (6, "f32", 256, 8192, REGS), (9, "f32", 512, 
          # gathering the qualifying values (forced), and the per-problem choice
          (3, "f32", 1024, 1, GATHER), (12, "f32", 512, 4096, GATHER), (17, "f32", 512, 64, GATHER),
          (5, "f64/f32", 512, 8192, GATHER), (16, "f64/f32", 256, 1, GATHER),
-         (9, "f32", 1024, 2048, AUTO), (15, "f64/f32", 256, 2048, AUTO)]
+         (9, "f32", 1024, 2048, AUTO), (15, "f64/f32", 256, 2048, AUTO),
+         (4, "f64", 256, 2048, GATHER), (6, "f64", 512, 1, AUTO), (11, "f64", 256, 64, GATHER)]
 
 
 @pytest.mark.parametrize("l,prec,threads,wgs,kernel", CASES)
