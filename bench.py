@@ -565,27 +565,34 @@ def _time_batch(reqs, steps, warmup, stream, torch, ws):
 
 
 def _batch_gram_roofline(reqs, stream, torch, ws):
-    """One fused call with step events on every problem: the gather + Gram step of the batch
-    (its launches run back to back) from the first problem's start to the last one's end,
-    and the algorithmic bytes of every problem's trials."""
+    """One fused call with step events on one problem per Gram launch: the gather + Gram step
+    of the batch (its launches run back to back) from the first launch's start to the last
+    one's end, and the algorithmic bytes of every problem's trials."""
     from dataclasses import replace
 
     from paper_1411_0814_amd import _lib, decompose_batched
     nev = 2 * len(_lib.STEPS)
     gi = _lib.STEPS.index("gram")
-    evs = []
-    for _ in reqs:
+    # the library records a problem's step events around its launch group, and the Gram
+    # step launches once per (l, precision) in this batch: one problem per group carries
+    # events (recording 2 x 7 events for every problem would itself stretch the step)
+    first = {}
+    for k, q in enumerate(reqs):
+        first.setdefault((q.l, q.gram), k)
+    marked = sorted(first.values())
+    evs = {}
+    for k in marked:
         e = [torch.cuda.Event(enable_timing=True) for _ in range(nev)]
         for x in e:
             x.record(stream)
-        evs.append(e)
+        evs[k] = e
     ref = torch.cuda.Event(enable_timing=True)
     ref.record(stream)
-    res = decompose_batched([replace(q, events=e) for q, e in zip(reqs, evs)], stream=stream,
-                            workspace=ws)
+    res = decompose_batched([replace(q, events=evs[k]) if k in evs else q
+                             for k, q in enumerate(reqs)], stream=stream, workspace=ws)
     torch.cuda.synchronize()
-    starts = [ref.elapsed_time(e[2 * gi]) for e in evs]
-    ends = [ref.elapsed_time(e[2 * gi + 1]) for e in evs]
+    starts = [ref.elapsed_time(e[2 * gi]) for e in evs.values()]
+    ends = [ref.elapsed_time(e[2 * gi + 1]) for e in evs.values()]
     span_ms = max(ends) - min(starts)
     b_alg = 0
     for q, r in zip(reqs, res):
@@ -599,8 +606,9 @@ def _batch_gram_roofline(reqs, stream, torch, ws):
                 os.path.join(ROOT, "paper_1411_0814_amd", "csrc", "k_gram.hip"),
                 "k_gram_dma_batched256_counters.md", "hbm_bytes_per_call"),
             "bytes_alg_per_launch": int(b_alg), "launch_ms": round(span_ms, 4),
-            "note": "the step's launches (one per l and precision) back to back; bytes and "
-                    "time summed over them; traffic from the committed counters"}
+            "note": "the step's launches (one per l and precision) back to back, timed between "
+                    "the step events of one problem per launch; bytes summed over the batch; "
+                    "traffic from the committed counters"}
 
 
 def run_batched(args, torch):
