@@ -325,11 +325,12 @@ typedef struct {
 #define RSM_GRAM_KERNEL_DMA 2   /* tiled Gram loading Y straight into LDS (FP32 Y and Gram) */
 #define RSM_GRAM_KERNEL_DMA2 3  /* the same with two chunk buffers (loads overlap the sums);
                                    FP32 Y with FP32 or FP64 sums */
-#define RSM_GRAM_KERNEL_GATHER 4 /* FP32 Y: only the mask words staged in LDS, each trial's
+#define RSM_GRAM_KERNEL_GATHER 4 /* only the mask words staged in LDS, each trial's
                                     qualifying values loaded straight from Y (for trials
                                     that keep few rows) */
-#define RSM_GRAM_KERNEL_AUTO 5  /* FP32 Y: GATHER or DMA2 per problem, by the mask's density
-                                   (the built-in choice for FP32 Y) */
+#define RSM_GRAM_KERNEL_AUTO 5  /* GATHER or the staging kernel (DMA2 for FP32 Y, REGS for
+                                   FP64 Y) per problem, by the mask's density: the built-in
+                                   choice for every precision but split-BF16 */
 
 /* Replaces the table with `count` entries (0 clears it; later duplicates of a key win).
  * RSM_E_ARG, and the table unchanged, for an entry outside the ranges above, a kernel not
