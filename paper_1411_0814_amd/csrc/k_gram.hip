@@ -40,8 +40,8 @@ namespace {
 // 64 f l 64 bytes, f = rho^l the expected fraction of qualifying rows, rho the mask's
 // density (its ones counted while packing it).  A problem gathers when that is the smaller:
 // f l 16 NT < n.  The choice depends only on the problem, so a deterministic problem takes
-// the same path alone and in any batch.
-// Called by whole wavefronts (lane k reads partial count k; their sum is exact).
+// the same path alone and in any batch.  Called by whole wavefronts (lane k reads partial
+// count k; their sum is exact).
 __device__ __forceinline__ bool gram_gathers(const ProbDesc& P, int nt) {
   static_assert(kMaskOnesParts == 64, "one partial count per lane");
   const unsigned long long part = P.scal->mask_ones[threadIdx.x & 63];
@@ -51,8 +51,10 @@ __device__ __forceinline__ bool gram_gathers(const ProbDesc& P, int nt) {
   return f * P.l * 16.0 * nt < static_cast<double>(P.n);
 }
 
-// Launch modes of the two FP32-data kernels: every problem of the launch, or only the
-// problems gram_gathers gives to that kernel (both kernels run with kModeAuto).
+// Launch modes of the gathering kernel and of the kernel it pairs with (staging through
+// LDS, through registers, or the per-trial streamer): every problem of the launch, or only
+// the problems gram_gathers gives to that kernel (both kernels of a pair run with
+// kModeAuto).
 constexpr int kModeAll = 0, kModeAuto = 1;
 
 template <int L, typename TY, typename TA>

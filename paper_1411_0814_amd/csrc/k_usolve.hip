@@ -205,19 +205,27 @@ __global__ __launch_bounds__(256) void k_usolve_ab(const ProbDesc* __restrict__ 
 // register i / 4.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kUfTiles = 2;                  // 16-row tiles per wavefront
-constexpr int kUfRows = 4 * 16 * kUfTiles;   // rows per workgroup (4 wavefronts)
-constexpr int kUfCols = 32;                  // columns per LDS stage (8 k-steps of 4)
+constexpr int kUfWaves = 4;                          // wavefronts per workgroup
+constexpr int kUfThreads = 64 * kUfWaves;
+constexpr int kUfCols = 16;                          // columns per LDS stage (4 k-steps)
 
 template <int R>
 struct UfShape {
   static constexpr int kNA = R * (R + 1) / 2;
-  static constexpr int kTA = (kNA + 15) / 16;   // 16-wide output tiles of A entries
+  static constexpr int kTA = uform_tiles_a(R);  // 16-wide output tiles of A entries
   static constexpr int kT = kTA + 1;            // and one of b (r <= 16)
-  // doubles per staged column: 16 mod 32, so that the 4 k-rows of a B fragment (128 bytes
-  // each) fall on alternate halves of the LDS banks
-  static constexpr int kStride = kT * 16 + ((kT % 2 == 0) ? 16 : 0);
+  static constexpr int kStride = uform_stride(R);
+  static_assert(kStride == kT * 16 + ((kT % 2 == 0) ? 16 : 0), "row layout");
+  static_assert((kUfCols * kStride * 8) % (4 * kUfThreads) == 0, "a stage is whole rounds");
 };
+
+// 16-row tiles per wavefront: four while the accumulators of four tiles and FP32 Y values
+// leave room for two wavefronts per SIMD (each right-operand value then feeds four
+// products), else two; and the rows of a workgroup.
+template <int R, typename TY>
+constexpr int uf_tiles() { return (UfShape<R>::kT <= 4 && sizeof(TY) == 4) ? 4 : 2; }
+template <int R, typename TY>
+constexpr int uf_rows() { return kUfWaves * 16 * uf_tiles<R, TY>(); }
 
 // Row pair (a, b), b <= a, of packed entry e < r(r+1)/2.
 __device__ __forceinline__ void unpack_pair(int e, int& a, int& b) {
@@ -227,35 +235,63 @@ __device__ __forceinline__ void unpack_pair(int e, int& a, int& b) {
   b = e - a * (a + 1) / 2;
 }
 
-// A workgroup barrier that orders LDS only: the global loads of the next stage stay in
-// flight across it (__syncthreads also waits for every outstanding global load).  The
-// kernel shares nothing but LDS between its threads.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+// The right operand of the product, once per problem: row j of kext (j < ceil(n/32)*32) is
+// [v_ja v_jb (a >= b) | 0 | v_j | 0], zero for j >= n.
+template <int R>
+__global__ __launch_bounds__(256) void k_ukext(const ProbDesc* __restrict__ probs, IdxList list) {
+  using S = UfShape<R>;
+  constexpr int NA = S::kNA, TA = S::kTA, LD = S::kStride;
+  const ProbDesc& P = probs[list.idx[blockIdx.y]];
+  const int64_t n = P.n, rows = ceil_div(n, 32) * 32;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= rows * LD) return;
+  const int64_t j = e / LD;
+  const int q = static_cast<int>(e - j * LD);
+  RSM_GLOBAL const double* __restrict__ V = P.V;
+  double val = 0.0;
+  if (j < n) {
+    if (q < NA) {
+      int a, b;
+      unpack_pair(q, a, b);
+      val = V[j + static_cast<int64_t>(a) * n] * V[j + static_cast<int64_t>(b) * n];
+    } else if (q >= TA * 16 && q - TA * 16 < R) {
+      val = V[j + static_cast<int64_t>(q - TA * 16) * n];
+    }
+  }
+  P.kext[e] = val;
 }
 
-// Workgroup: 128 consecutive rows (4 wavefronts x 2 tiles of 16).  Per stage of 32 columns
-// the workgroup writes K's and V's rows for those columns to LDS ([K | 0 | V | 0] per
-// column, the B operands); each lane loads the mask bit and Y value of its (row, column)
-// position of every k-step (the A operands: the bit as 0/1 for the A part, bit times y for
-// the b part), the next stage's issued while the current stage's K is staged.  Rows past m
-// and columns past n have weight 0.
+__device__ __forceinline__ void lds_dma_dword(const void* src, void* dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
+}
+
+// Workgroup: kRows consecutive rows (kUfWaves wavefronts x kTiles tiles of 16).  The
+// right operand's rows for a stage of kUfCols columns travel from kext straight into one of
+// two LDS buffers (global_load_lds_dword: lane k of a wavefront writes 4 bytes at base + 4 k;
+// the workgroup moves 4 bytes per thread per round), and each lane loads the mask bit and Y value of its (row, column)
+// position of every k-step (the left operand: the bit as 0/1 for the A part, bit times y for
+// the b part).  Stage s + 1's loads are issued right after the barrier that publishes stage
+// s and land while stage s runs on the matrix cores: one barrier per stage.  Rows past m and
+// columns past n have weight 0.
 template <int R, typename TY>
-__global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ probs, IdxList list) {
+__global__ __launch_bounds__(kUfThreads) void k_uform(const ProbDesc* __restrict__ probs,
+                                                      IdxList list) {
   using S = UfShape<R>;
-  constexpr int NA = S::kNA, TA = S::kTA, T = S::kT, LD = S::kStride;
-  __shared__ double Kc[kUfCols * LD];
-  __shared__ double Vc[kUfCols * R];
+  constexpr int NA = S::kNA, TA = S::kTA, T = S::kT, LD = S::kStride, C = kUfCols;
+  constexpr int kUfTiles = uf_tiles<R, TY>(), kUfRows = uf_rows<R, TY>();
+  constexpr int KS = C / 4;                               // k-steps of 4 columns per stage
+  constexpr int kRound = 4 * kUfThreads;                  // bytes the workgroup moves per round
+  constexpr int kRounds = C * LD * 8 / kRound;            // rounds of a stage
+  __shared__ __align__(16) double Kb[2 * C * LD];
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
   const int64_t m = P.m, n = P.n, ldy = P.ldy, mw32 = 2 * P.mw;
   const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kUfRows;
   if (row0 >= m) return;
   auto Y = static_cast<RSM_GLOBAL const TY*>(P.ycm);
   auto wbits = reinterpret_cast<RSM_GLOBAL const uint32_t*>(P.wbits);
-  RSM_GLOBAL const double* __restrict__ V = P.V;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  auto kext = reinterpret_cast<RSM_GLOBAL const char*>(P.kext);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lk = lane >> 4;
   int64_t ic[kUfTiles];
   bool rok[kUfTiles];
@@ -271,22 +307,19 @@ __global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ prob
 #pragma unroll
     for (int q = 0; q < T; ++q) acc[t][q] = f64x4{0.0, 0.0, 0.0, 0.0};
   int cnt[kUfTiles] = {};
-  // (a, b) of the packed A entry in each column slot q of a staged row, once per workgroup
-  __shared__ int8_t pa[T * 16], pb[T * 16];
-  for (int q = tid; q < T * 16; q += 256) {
-    int a = -1, b = -1;
-    if (q < NA) unpack_pair(q, a, b);
-    pa[q] = static_cast<int8_t>(a);
-    pb[q] = static_cast<int8_t>(b);
-  }
-  // A operands of a stage: mask words and Y values of (row ic[t], column c0 + 4 ks + lk);
-  // the next stage's are loaded while the current one runs on the matrix cores
-  uint32_t wreg[kUfCols / 4][kUfTiles], wnext[kUfCols / 4][kUfTiles];
-  TY yreg[kUfCols / 4][kUfTiles], ynext[kUfCols / 4][kUfTiles];
-  auto load_stage = [&](int64_t cs, uint32_t (&wr)[kUfCols / 4][kUfTiles],
-                        TY (&yr)[kUfCols / 4][kUfTiles]) {
+  // right operand of stage st into `dst` (rows st*C .. st*C + C - 1 of kext, all present)
+  auto issue_k = [&](int64_t st, double* dst) {
+    const char* src = kext + st * (C * LD * 8) + 4 * tid;
+    char* d = reinterpret_cast<char*>(dst) + 256 * wv;
 #pragma unroll
-    for (int ks = 0; ks < kUfCols / 4; ++ks) {
+    for (int u = 0; u < kRounds; ++u) lds_dma_dword(src + kRound * u, d + kRound * u);
+  };
+  // left operand of a stage: mask words and Y values of (row ic[t], column cs + 4 ks + lk)
+  uint32_t wreg[KS][kUfTiles], wnext[KS][kUfTiles];
+  TY yreg[KS][kUfTiles], ynext[KS][kUfTiles];
+  auto load_stage = [&](int64_t cs, uint32_t (&wr)[KS][kUfTiles], TY (&yr)[KS][kUfTiles]) {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
       const int64_t j = cs + 4 * ks + lk;
       const int64_t jc = j < n ? j : n - 1;
 #pragma unroll
@@ -296,32 +329,20 @@ __global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ prob
       }
     }
   };
+  const int64_t stages = ceil_div(n, C);
+  issue_k(0, Kb);
   load_stage(0, wreg, yreg);
-  for (int64_t c0 = 0; c0 < n; c0 += kUfCols) {
-    lds_barrier();  // the previous stage's B operands are consumed
-    for (int e = tid; e < kUfCols * R; e += 256) {
-      const int c = e / R, a = e - c * R;
-      const int64_t j = c0 + c;
-      Vc[e] = j < n ? V[j + static_cast<int64_t>(a) * n] : 0.0;
+  for (int64_t st = 0; st < stages; ++st) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();  // stage st is in its buffer; every wave is done with the other one
+    const double* cur = Kb + (st & 1) * (C * LD);
+    if (st + 1 < stages) {
+      issue_k(st + 1, Kb + ((st + 1) & 1) * (C * LD));
+      load_stage((st + 1) * C, wnext, ynext);
     }
-    lds_barrier();
-    // the next stage's A operands: issued after this stage's V-hat loads have landed
-    // (loads complete in order, so a wait on those would wait on these too), to land while
-    // K is staged and the products run
-    if (c0 + kUfCols < n) load_stage(c0 + kUfCols, wnext, ynext);
-    for (int e = tid; e < kUfCols * T * 16; e += 256) {
-      const int c = e / (T * 16), q = e - c * (T * 16);
-      double val = 0.0;
-      if (q < NA) {
-        val = Vc[c * R + pa[q]] * Vc[c * R + pb[q]];
-      } else if (q >= TA * 16 && q - TA * 16 < R) {
-        val = Vc[c * R + (q - TA * 16)];
-      }
-      Kc[c * LD + q] = val;
-    }
-    lds_barrier();
+    const int64_t c0 = st * C;
 #pragma unroll
-    for (int ks = 0; ks < kUfCols / 4; ++ks) {
+    for (int ks = 0; ks < KS; ++ks) {
       // the mask bit as a 0/1 weight, formed without branches
       const uint32_t jok = (c0 + 4 * ks + lk < n) ? 1u : 0u;
       double aw[kUfTiles], awy[kUfTiles];
@@ -332,7 +353,7 @@ __global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ prob
         awy[t] = kn ? static_cast<double>(yreg[ks][t]) : 0.0;
         cnt[t] += static_cast<int>(kn);
       }
-      const double* brow = Kc + (4 * ks + lk) * LD + li;
+      const double* brow = cur + (4 * ks + lk) * LD + li;
 #pragma unroll
       for (int q = 0; q < T; ++q) {
         const double b = brow[q * 16];
@@ -342,7 +363,7 @@ __global__ __launch_bounds__(256) void k_uform(const ProbDesc* __restrict__ prob
       }
     }
 #pragma unroll
-    for (int ks = 0; ks < kUfCols / 4; ++ks)
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int t = 0; t < kUfTiles; ++t) {
         wreg[ks][t] = wnext[ks][t];
@@ -436,16 +457,19 @@ __global__ void k_error_finalize(const ProbDesc* __restrict__ probs, IdxList lis
 }
 
 template <int R>
-void run_usolve(const ProbDesc* d, const IdxList& g, int64_t m, int y_dtype, bool mfma,
-                hipStream_t s) {
+void run_usolve(const ProbDesc* d, const IdxList& g, int64_t m, int64_t n, int y_dtype,
+                bool mfma, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(ceil_div(m, 256)), g.count);
   if constexpr (R >= kUMfmaMinR) {
     if (mfma) {
-      const dim3 gf(static_cast<unsigned>(ceil_div(m, kUfRows)), g.count);
+      const int64_t kext = ceil_div(n, 32) * 32 * UfShape<R>::kStride;
+      k_ukext<R><<<dim3(static_cast<unsigned>(ceil_div(kext, 256)), g.count), 256, 0, s>>>(d, g);
       if (y_dtype == RSM_F32)
-        k_uform<R, float><<<gf, 256, 0, s>>>(d, g);
+        k_uform<R, float><<<dim3(static_cast<unsigned>(ceil_div(m, uf_rows<R, float>())), g.count),
+                            kUfThreads, 0, s>>>(d, g);
       else
-        k_uform<R, double><<<gf, 256, 0, s>>>(d, g);
+        k_uform<R, double><<<dim3(static_cast<unsigned>(ceil_div(m, uf_rows<R, double>())), g.count),
+                             kUfThreads, 0, s>>>(d, g);
       k_usolve_ab<R><<<grid, 256, 0, s>>>(d, g);
       return;
     }
@@ -474,12 +498,15 @@ void run_error(const ProbDesc* d, const IdxList& g, int64_t m, int y_dtype, hipS
 // The group shares r, the element type of Y and the way A_i and b_i are formed.
 void launch_solve_u(const ProbDesc* d, const IdxList& g, const Plan* const* h, hipStream_t s) {
   if (!g.count) return;
-  int64_t m = 0;
-  for (int k = 0; k < g.count; ++k) m = std::max(m, h[k]->m);
+  int64_t m = 0, n = 0;
+  for (int k = 0; k < g.count; ++k) {
+    m = std::max(m, h[k]->m);
+    n = std::max(n, h[k]->n);
+  }
   switch (h[0]->r) {
 #define RSM_U_CASE(RR) \
   case RR:             \
-    run_usolve<RR>(d, g, m, h[0]->y_dtype, h[0]->u_mfma, s); \
+    run_usolve<RR>(d, g, m, n, h[0]->y_dtype, h[0]->u_mfma, s); \
     break;
     RSM_R_CASES(RSM_U_CASE)
 #undef RSM_U_CASE

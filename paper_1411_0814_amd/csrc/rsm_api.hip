@@ -1,5 +1,6 @@
 // The C ABI of librsm (include/rsm.h): argument validation, the execution plan and
 // workspace layout of each problem, and the launch sequence of steps a0..a7.
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -215,6 +216,8 @@ void set_layout(Plan& P) {
   if (P.u_mfma) {
     P.off_ab = carve(cur, static_cast<size_t>(P.m) * (P.r * (P.r + 1) / 2 + P.r) * sizeof(double));
     P.off_abcnt = carve(cur, static_cast<size_t>(P.m) * sizeof(int32_t));
+    P.off_kext = carve(cur, static_cast<size_t>(ceil_div(P.n, 32) * 32) * uform_stride(P.r) *
+                                sizeof(double));
   }
   P.off_errp = (P.flags & RSM_COMPUTE_ERROR)
                    ? carve(cur, static_cast<size_t>(ceil_div(P.m, 256)) * sizeof(double))
@@ -378,6 +381,7 @@ ProbDesc prob_desc(const Plan& P, const rsm_input& in, const rsm_output& out, vo
   d.scal = gptr(at<DevScalars>(ws, P.off_scal));
   d.ab = P.u_mfma ? gptr(at<double>(ws, P.off_ab)) : nullptr;
   d.abcnt = P.u_mfma ? gptr(at<int32_t>(ws, P.off_abcnt)) : nullptr;
+  d.kext = P.u_mfma ? gptr(at<double>(ws, P.off_kext)) : nullptr;
   d.errp = (P.flags & RSM_COMPUTE_ERROR) ? gptr(at<double>(ws, P.off_errp)) : nullptr;
   d.rows_first = P.rows_first ? 1 : 0;
   d.nw = static_cast<int32_t>(P.nw);
@@ -447,6 +451,99 @@ void for_groups(const std::vector<Plan>& plans, Take take, Key key, Fn fn) {
 
 void mark_all(const rsm_output* outs, const IdxList& g, int step, int end, hipStream_t s) {
   for (int k = 0; k < g.count; ++k) mark(outs[g.idx[k]], step, end, s);
+}
+
+// The launch groups of one step touch disjoint problems, so they may run side by side: on
+// up to kForkLanes streams, the caller's and library streams of the same device (default
+// priority, created once per device), forked from and joined back into the caller's stream
+// by events, so that the caller's stream orders the steps as before.  The last, longest
+// workgroups of one launch then overlap the next launch instead of leaving CUs idle.
+// g_fork_mu is held while a step's lanes are forked, fed and joined.  Only calls of at
+// least kForkMinProblems problems fork: a smaller call has few, short launches per step,
+// and a server that overlaps several such calls on streams of its own gets its overlap
+// from them (lanes shared by its streams would queue one call's launches behind
+// another's).
+constexpr int kForkLanes = 4;
+constexpr int kForkMinProblems = 64;
+constexpr int kForkDevices = 64;
+
+struct ForkLanes {
+  hipStream_t aux[kForkLanes - 1] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kForkLanes - 1] = {};
+  int state = 0;  // 0: not made yet, 1: ready, -1: could not be made (groups run in order)
+};
+std::mutex g_fork_mu;
+ForkLanes g_fork[kForkDevices];
+
+// The lanes of the device of stream s (caller holds g_fork_mu); null when s is not on the
+// current device or the lanes could not be made.
+ForkLanes* fork_lanes(hipStream_t s) {
+  int cur = -1, dev = -1;
+  if (hipGetDevice(&cur) != hipSuccess || hipStreamGetDevice(s, &dev) != hipSuccess ||
+      dev != cur || dev < 0 || dev >= kForkDevices)
+    return nullptr;
+  ForkLanes& L = g_fork[dev];
+  if (L.state == 0) {
+    bool ok = hipEventCreateWithFlags(&L.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; ok && i < kForkLanes - 1; ++i)
+      ok = hipStreamCreateWithFlags(&L.aux[i], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&L.join[i], hipEventDisableTiming) == hipSuccess;
+    L.state = ok ? 1 : -1;
+  }
+  return L.state == 1 ? &L : nullptr;
+}
+
+// for_groups with the groups spread over the fork lanes: largest estimated work first, each
+// on the lane with the least work so far.  fn(g, h, stream) enqueues one group.
+template <typename Take, typename Key, typename Work, typename Fn>
+void for_groups_forked(const std::vector<Plan>& plans, Take take, Key key, Work work, Fn fn,
+                       hipStream_t s) {
+  struct Group {
+    IdxList g;
+    const Plan* h[kLaunchMax];
+    double work;
+  };
+  std::vector<Group> gs;
+  for_groups(plans, take, key, [&](const IdxList& g, const Plan* const* h) {
+    gs.emplace_back();
+    Group& x = gs.back();
+    x.g = g;
+    x.work = 0.0;
+    for (int k = 0; k < g.count; ++k) {
+      x.h[k] = h[k];
+      x.work += work(*h[k]);
+    }
+  });
+  if (gs.size() <= 1 || plans.size() < static_cast<size_t>(kForkMinProblems)) {
+    for (const Group& x : gs) fn(x.g, x.h, s);
+    return;
+  }
+  std::lock_guard<std::mutex> lock(g_fork_mu);
+  ForkLanes* L = fork_lanes(s);
+  if (!L) {
+    for (const Group& x : gs) fn(x.g, x.h, s);
+    return;
+  }
+  const int lanes = std::min<int>(kForkLanes, static_cast<int>(gs.size()));
+  (void)hipEventRecord(L->fork, s);
+  for (int i = 0; i + 1 < lanes; ++i) (void)hipStreamWaitEvent(L->aux[i], L->fork, 0);
+  std::vector<int> order(gs.size());
+  for (size_t i = 0; i < gs.size(); ++i) order[i] = static_cast<int>(i);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return gs[a].work > gs[b].work; });
+  double load[kForkLanes] = {};
+  for (int i : order) {
+    int lane = 0;
+    for (int q = 1; q < lanes; ++q)
+      if (load[q] < load[lane]) lane = q;
+    load[lane] += gs[i].work;
+    fn(gs[i].g, gs[i].h, lane == 0 ? s : L->aux[lane - 1]);
+  }
+  for (int i = 0; i + 1 < lanes; ++i) {
+    (void)hipEventRecord(L->join[i], L->aux[i]);
+    (void)hipStreamWaitEvent(s, L->join[i], 0);
+  }
 }
 
 }  // namespace
@@ -604,18 +701,20 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
     launch_subsets(dprob, g, h, s);
     mark_all(outputs, g, RSM_STEP_SUBSETS, 1, s);
   });
-  // a2 + a3: one launch per (l, element type, precision, kernel, trials per workgroup)
-  for_groups(plans, [](const Plan& P) {
+  // a2 + a3: one launch per (l, element type, precision, kernel, trials per workgroup),
+  // the launches side by side on the fork lanes
+  for_groups_forked(plans, [](const Plan& P) {
                return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0 && !P.rows_first; },
              [](const Plan& P) {
                return ((((int64_t(P.l) * 4 + P.y_dtype) * 4 + P.prec) * 2 + (P.tiled ? 1 : 0)) *
                        8 + P.gram_kernel) * 2048 + P.gram_threads;
              },
-             [&](const IdxList& g, const Plan* const* h) {
-               mark_all(outputs, g, RSM_STEP_GRAM, 0, s);
-               launch_gram(dprob, g, h, s);
-               mark_all(outputs, g, RSM_STEP_GRAM, 1, s);
-             });
+             [](const Plan& P) { return double(P.m) * double(P.I) * P.l; },
+             [&](const IdxList& g, const Plan* const* h, hipStream_t ls) {
+               mark_all(outputs, g, RSM_STEP_GRAM, 0, ls);
+               launch_gram(dprob, g, h, ls);
+               mark_all(outputs, g, RSM_STEP_GRAM, 1, ls);
+             }, s);
   // method M2: a2 + a3 for all rows-first problems in shared launches (per element type)
   for_groups(plans, [](const Plan& P) {
                return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0 && P.rows_first; },
@@ -633,13 +732,14 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
              one_key, [&](const IdxList& g, const Plan* const* h) {
                launch_n_fixed(dprob, g, h, true, s);
              });
-  for_groups(plans, [&](const Plan& P) { return front(P) && !P.rows_first; },
+  for_groups_forked(plans, [&](const Plan& P) { return front(P) && !P.rows_first; },
              [](const Plan& P) { return int64_t(P.l); },
-             [&](const IdxList& g, const Plan* const* h) {
-               mark_all(outputs, g, RSM_STEP_MINOR, 0, s);
-               launch_minor(dprob, g, h, s);
-               mark_all(outputs, g, RSM_STEP_MINOR, 1, s);
-             });
+             [](const Plan& P) { return double(P.I) * P.l * P.l * P.l; },
+             [&](const IdxList& g, const Plan* const* h, hipStream_t ls) {
+               mark_all(outputs, g, RSM_STEP_MINOR, 0, ls);
+               launch_minor(dprob, g, h, ls);
+               mark_all(outputs, g, RSM_STEP_MINOR, 1, ls);
+             }, s);
   for_groups(plans, [&](const Plan& P) { return front(P) && P.rows_first; },
              [](const Plan& P) { return int64_t(P.l); },
              [&](const IdxList& g, const Plan* const* h) {
@@ -664,15 +764,17 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
     launch_solve_v(eig.data(), static_cast<int>(eig.size()), deig, s);
     for (int32_t k : who) mark(outputs[k], RSM_STEP_EIG, 1, s);
   }
-  // a7 (and the optional error): one launch per (r, element type)
+  // a7 (and the optional error): one launch per (r, element type); a7's side by side
   auto back = [](const Plan& P) { return !(P.flags & RSM_ACCUMULATE_ONLY); };
   auto ukey = [](const Plan& P) { return int64_t(P.r) * 4 + P.y_dtype; };
   auto ukey_v = [](const Plan& P) { return (int64_t(P.r) * 4 + P.y_dtype) * 2 + (P.u_mfma ? 1 : 0); };
-  for_groups(plans, back, ukey_v, [&](const IdxList& g, const Plan* const* h) {
-    mark_all(outputs, g, RSM_STEP_USOLVE, 0, s);
-    launch_solve_u(dprob, g, h, s);
-    mark_all(outputs, g, RSM_STEP_USOLVE, 1, s);
-  });
+  for_groups_forked(plans, back, ukey_v,
+                    [](const Plan& P) { return double(P.m) * double(P.n) * P.r * P.r; },
+                    [&](const IdxList& g, const Plan* const* h, hipStream_t ls) {
+                      mark_all(outputs, g, RSM_STEP_USOLVE, 0, ls);
+                      launch_solve_u(dprob, g, h, ls);
+                      mark_all(outputs, g, RSM_STEP_USOLVE, 1, ls);
+                    }, s);
   for_groups(plans, [](const Plan& P) {
                return !(P.flags & RSM_ACCUMULATE_ONLY) && (P.flags & RSM_COMPUTE_ERROR);
              }, ukey,

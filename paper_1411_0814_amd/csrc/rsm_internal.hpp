@@ -36,6 +36,15 @@ constexpr int kBfTrialsPerGroup = 64;
 // (one dense product over all columns, 0/1 mask weights) instead of one thread per row.
 constexpr int kUMfmaMinR = 6;
 
+// Row of the matrix-core U-hat product's right operand, one per column j of Y:
+// [v_ja v_jb for a >= b (r(r+1)/2 entries) | zeros to a multiple of 16 | v_j (r entries) |
+// zeros], stored with this many doubles per row.  The stride is 16 mod 32 doubles, so the
+// four rows a matrix-core fragment reads from LDS fall on alternate halves of the banks.
+__host__ __device__ constexpr int uform_tiles_a(int r) { return (r * (r + 1) / 2 + 15) / 16; }
+__host__ __device__ constexpr int uform_stride(int r) {
+  return (uform_tiles_a(r) + 1) * 16 + (((uform_tiles_a(r) + 1) % 2 == 0) ? 16 : 0);
+}
+
 // Threads (= trials) per workgroup of the tiled Gram kernel: as many as the register file
 // allows with l(l+1)/2 accumulators plus the prefetched next tile held per thread.
 __host__ __device__ constexpr int tile_threads(int l, int elem_bytes) {
@@ -105,7 +114,7 @@ struct Plan {
   size_t off_wbits = 0, off_ypack = 0, off_cols = 0, off_part = 0, off_prow = 0, off_G = 0,
          off_rows = 0;
   size_t off_N = 0, off_Nsym = 0, off_L = 0, off_M = 0, off_Mt = 0, off_T = 0, off_X = 0,
-         off_Z = 0, off_SP = 0, off_ab = 0, off_abcnt = 0, off_errp = 0,
+         off_Z = 0, off_SP = 0, off_ab = 0, off_abcnt = 0, off_kext = 0, off_errp = 0,
          off_mflag = 0, off_rbits = 0, off_yrow = 0, off_B = 0, off_cmask = 0, off_Qd = 0;
   size_t off_scal = 0;
   size_t total = 0;
@@ -175,6 +184,7 @@ struct ProbDesc {
   RSM_GLOBAL int32_t* mflag;   // per trial: minor vector left to the Jacobi pass (I)
   RSM_GLOBAL double* ab;       // U-hat normal equations on MFMA: (r(r+1)/2 + r) x m, ld m
   RSM_GLOBAL int32_t* abcnt;   // known entries per row (m)
+  RSM_GLOBAL double* kext;     // its right operand: ceil(n/32)*32 rows of uform_stride(r)
   RSM_GLOBAL double* errp;     // error of eq.(ep): one partial sum per 256 rows
   // method M2 (rows first)
   int32_t rows_first;

@@ -94,3 +94,33 @@ def test_served_mix_equals_alone_bitwise():
         a = decompose(it.Y, it.W, it.r, it.num_submatrices, j.seed, l=it.l, flags=it.flags)
         assert _same(a.V.cpu().numpy(), j.result.V.cpu().numpy()), j.rid
         assert _same(a.U.cpu().numpy(), j.result.U.cpu().numpy()), j.rid
+
+
+def test_large_batch_on_side_by_side_lanes_equals_alone_bitwise():
+    """A call of 72 problems runs each step's launch groups (one per l for the Gram and
+    minor steps, one per r for U-hat) side by side on several streams, joined back into
+    the caller's stream before the next step: every problem's N, V-hat and U-hat are still
+    bitwise those of the problem run alone."""
+    import torch
+    from paper_1411_0814_amd import Request, _lib, decompose, decompose_batched
+    det = _lib.DETERMINISTIC | _lib.N_ACCUMULATE
+    ranks = [2, 3, 5, 6, 8, 9]
+    reqs, alone = [], []
+    for k in range(72):
+        r = ranks[k % len(ranks)]
+        m, n = 900 + 37 * k, 40 + (k % 5) * 6
+        p = synth.paper_synthetic(m, n, r, 0.85, 1e-3, 900 + k, factor_dtype=np.float32,
+                                  y_dtype=np.float32, num_submatrices=4 * n, seed_rsm=k)
+        Y, W = to_device(p)
+        N1 = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+        alone.append((decompose(Y, W, r, p.num_submatrices, p.seed_rsm, l=p.l, N=N1,
+                                flags=det), N1))
+        reqs.append(Request(Y=Y, W=W, r=r, num_submatrices=p.num_submatrices,
+                            seed=p.seed_rsm, l=p.l, flags=det,
+                            N=torch.zeros(n, n, dtype=torch.float64, device="cuda")))
+    out = decompose_batched(reqs)
+    torch.cuda.synchronize()
+    for k, ((r1, N1), rb, q) in enumerate(zip(alone, out, reqs)):
+        assert _same(N1.cpu().numpy(), q.N.cpu().numpy()), k
+        assert _same(r1.V.cpu().numpy(), rb.V.cpu().numpy()), k
+        assert _same(r1.U.cpu().numpy(), rb.U.cpu().numpy()), k
