@@ -120,7 +120,7 @@ enum {
                                     RSM_N_ACCUMULATE is first rounded to that grid.  (The
                                     optional error e is summed in a fixed order with or
                                     without this flag.) */
-  RSM_ROWS_FIRST = 1u << 6       /* method M2 (Section III, rows first; see the top of
+  RSM_ROWS_FIRST = 1u << 6,      /* method M2 (Section III, rows first; see the top of
                                     this file).  Then `l` is the number k of rows per
                                     sub-matrix (0 => r + 1; r < k <= min(m, RSM_MAX_L),
                                     m <= 2^31 - 1), `nvec` must be 0 (every trial gives
@@ -134,6 +134,17 @@ enum {
                                     The workspace then also holds the row bit-planes,
                                     a row-major copy of a column-major Y, and I x n x r
                                     doubles for the rows of every trial's Q_t. */
+  RSM_SERIAL_STEPS = 1u << 7     /* rsm_decompose_batched: run each step's launch groups
+                                    one after another on the caller's stream.  Without it
+                                    a call of at least 64 problems runs the groups of its
+                                    Gram, minor-vector and U-hat steps side by side on
+                                    streams of the library (made once per device, default
+                                    priority), joined back into the caller's stream before
+                                    the next step.  For callers that overlap several calls
+                                    on streams of their own (lanes shared by those calls
+                                    would queue one call's launches behind another's).  Set
+                                    on any problem of a call, it holds for the whole call;
+                                    results do not depend on it. */
 };
 
 typedef struct rsm_problem {

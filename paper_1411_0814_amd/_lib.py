@@ -48,6 +48,7 @@ COMPUTE_ERROR = 1 << 3
 PLAIN_GRAM = 1 << 4
 DETERMINISTIC = 1 << 5
 ROWS_FIRST = 1 << 6         # method M2: k-row subsets, qualifying columns
+SERIAL_STEPS = 1 << 7       # a step's launch groups in order on the caller's stream
 
 STEPS = ["pack", "subsets", "gram", "minor", "eig", "usolve", "error"]
 

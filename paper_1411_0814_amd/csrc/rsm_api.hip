@@ -14,7 +14,7 @@ namespace {
 
 constexpr uint32_t kKnownFlags = RSM_ACCUMULATE_ONLY | RSM_FINALIZE_ONLY | RSM_N_ACCUMULATE |
                                  RSM_COMPUTE_ERROR | RSM_PLAIN_GRAM | RSM_DETERMINISTIC |
-                                 RSM_ROWS_FIRST;
+                                 RSM_ROWS_FIRST | RSM_SERIAL_STEPS;
 constexpr size_t kAlign = 256;
 
 size_t carve(size_t& cursor, size_t bytes) {
@@ -459,10 +459,10 @@ void mark_all(const rsm_output* outs, const IdxList& g, int step, int end, hipSt
 // by events, so that the caller's stream orders the steps as before.  The last, longest
 // workgroups of one launch then overlap the next launch instead of leaving CUs idle.
 // g_fork_mu is held while a step's lanes are forked, fed and joined.  Only calls of at
-// least kForkMinProblems problems fork: a smaller call has few, short launches per step,
-// and a server that overlaps several such calls on streams of its own gets its overlap
-// from them (lanes shared by its streams would queue one call's launches behind
-// another's).
+// least kForkMinProblems problems fork (a smaller call has few, short launches per step),
+// and none with RSM_SERIAL_STEPS: a caller that overlaps several calls on streams of its
+// own gets its overlap from them, and lanes shared by its streams would queue one call's
+// launches behind another's.
 constexpr int kForkLanes = 4;
 constexpr int kForkMinProblems = 64;
 constexpr int kForkDevices = 64;
@@ -497,8 +497,8 @@ ForkLanes* fork_lanes(hipStream_t s) {
 // for_groups with the groups spread over the fork lanes: largest estimated work first, each
 // on the lane with the least work so far.  fn(g, h, stream) enqueues one group.
 template <typename Take, typename Key, typename Work, typename Fn>
-void for_groups_forked(const std::vector<Plan>& plans, Take take, Key key, Work work, Fn fn,
-                       hipStream_t s) {
+void for_groups_forked(const std::vector<Plan>& plans, bool may_fork, Take take, Key key,
+                       Work work, Fn fn, hipStream_t s) {
   struct Group {
     IdxList g;
     const Plan* h[kLaunchMax];
@@ -515,7 +515,7 @@ void for_groups_forked(const std::vector<Plan>& plans, Take take, Key key, Work 
       x.work += work(*h[k]);
     }
   });
-  if (gs.size() <= 1 || plans.size() < static_cast<size_t>(kForkMinProblems)) {
+  if (gs.size() <= 1 || !may_fork) {
     for (const Group& x : gs) fn(x.g, x.h, s);
     return;
   }
@@ -684,6 +684,9 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   for (int32_t k = 0; k < nprob; ++k) hp[k] = prob_desc(plans[k], inputs[k], outputs[k], ws + base[k]);
   put_prob_descs(hp.data(), nprob, dprob, s);
 
+  // the launch groups of a step side by side (large calls, unless a problem asks otherwise)
+  bool fork = nprob >= kForkMinProblems;
+  for (const Plan& P : plans) fork = fork && !(P.flags & RSM_SERIAL_STEPS);
   auto all = [](const Plan&) { return true; };
   auto front = [](const Plan& P) { return !(P.flags & RSM_FINALIZE_ONLY); };
   auto one_key = [](const Plan&) { return int64_t(0); };
@@ -703,7 +706,7 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   });
   // a2 + a3: one launch per (l, element type, precision, kernel, trials per workgroup),
   // the launches side by side on the fork lanes
-  for_groups_forked(plans, [](const Plan& P) {
+  for_groups_forked(plans, fork, [](const Plan& P) {
                return !(P.flags & RSM_FINALIZE_ONLY) && P.I > 0 && !P.rows_first; },
              [](const Plan& P) {
                return ((((int64_t(P.l) * 4 + P.y_dtype) * 4 + P.prec) * 2 + (P.tiled ? 1 : 0)) *
@@ -732,7 +735,7 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
              one_key, [&](const IdxList& g, const Plan* const* h) {
                launch_n_fixed(dprob, g, h, true, s);
              });
-  for_groups_forked(plans, [&](const Plan& P) { return front(P) && !P.rows_first; },
+  for_groups_forked(plans, fork, [&](const Plan& P) { return front(P) && !P.rows_first; },
              [](const Plan& P) { return int64_t(P.l); },
              [](const Plan& P) { return double(P.I) * P.l * P.l * P.l; },
              [&](const IdxList& g, const Plan* const* h, hipStream_t ls) {
@@ -768,7 +771,7 @@ int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
   auto back = [](const Plan& P) { return !(P.flags & RSM_ACCUMULATE_ONLY); };
   auto ukey = [](const Plan& P) { return int64_t(P.r) * 4 + P.y_dtype; };
   auto ukey_v = [](const Plan& P) { return (int64_t(P.r) * 4 + P.y_dtype) * 2 + (P.u_mfma ? 1 : 0); };
-  for_groups_forked(plans, back, ukey_v,
+  for_groups_forked(plans, fork, back, ukey_v,
                     [](const Plan& P) { return double(P.m) * double(P.n) * P.r * P.r; },
                     [&](const IdxList& g, const Plan* const* h, hipStream_t ls) {
                       mark_all(outputs, g, RSM_STEP_USOLVE, 0, ls);

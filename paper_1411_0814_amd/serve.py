@@ -10,6 +10,10 @@ stay resident for the whole run; each request's factors stay on the device in it
 Each stream owns one workspace arena, grown to the largest group it has run and reused by
 every later group on that stream, so the caching allocator does not accumulate one
 workspace per batch (memory that the runtime may need itself, e.g. for kernel scratch).
+A group admitted while other groups run asks the library to keep its steps' launch groups
+in order on its own stream (SERIAL_STEPS): the overlap then comes from the server's
+streams, which the library's own side-by-side lanes would otherwise queue behind each
+other.  A group admitted onto an idle device may spread its steps over those lanes.
 
 `batching=False, max_inflight=1` serves the same trace first-in first-out one request at
 a time through the single-problem call: the plain baseline.
@@ -19,7 +23,7 @@ from __future__ import annotations
 import math
 import time
 from collections import deque
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -179,6 +183,8 @@ class Server:
                 st = self.streams[si]
                 with torch.cuda.stream(st):
                     reqs = [self._request(j) for j in group]
+                    if inflight:
+                        reqs[0] = replace(reqs[0], flags=reqs[0].flags | _lib.SERIAL_STEPS)
                     if self.batching:
                         ws = self._arena(si, workspace_bytes(reqs))
                         results = decompose_batched(reqs, stream=st, workspace=ws)

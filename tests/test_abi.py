@@ -107,6 +107,14 @@ def test_split_bf16_accepted_for_fp32():
     assert code == _lib.OK and nbytes > 0
 
 
+def test_serial_steps_flag_accepted_and_changes_no_workspace():
+    # a call-level scheduling choice: the same plan and workspace as without it
+    code, base = _ws(_prob())
+    code2, serial = _ws(_prob(flags=_lib.SERIAL_STEPS))
+    assert code == code2 == _lib.OK and serial == base
+    assert _ws(_prob(flags=1 << 8))[0] == _lib.E_ARG
+
+
 def test_workspace_bytes_valid_and_monotone():
     code, small = _ws(_prob())
     assert code == _lib.OK and small > 0

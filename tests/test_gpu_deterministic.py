@@ -124,3 +124,12 @@ def test_large_batch_on_side_by_side_lanes_equals_alone_bitwise():
         assert _same(N1.cpu().numpy(), q.N.cpu().numpy()), k
         assert _same(r1.V.cpu().numpy(), rb.V.cpu().numpy()), k
         assert _same(r1.U.cpu().numpy(), rb.U.cpu().numpy()), k
+    # the same call with its launch groups in order on the caller's stream
+    from dataclasses import replace
+    reqs_s = [replace(q, N=torch.zeros_like(q.N)) for q in reqs]
+    reqs_s[5] = replace(reqs_s[5], flags=det | _lib.SERIAL_STEPS)
+    out_s = decompose_batched(reqs_s)
+    torch.cuda.synchronize()
+    for k, ((r1, N1), rs, q) in enumerate(zip(alone, out_s, reqs_s)):
+        assert _same(N1.cpu().numpy(), q.N.cpu().numpy()), k
+        assert _same(r1.U.cpu().numpy(), rs.U.cpu().numpy()), k
