@@ -566,8 +566,9 @@ def _time_batch(reqs, steps, warmup, stream, torch, ws):
 
 def _batch_gram_roofline(reqs, stream, torch, ws):
     """One fused call with step events on one problem per Gram launch: the gather + Gram step
-    of the batch (its launches run back to back) from the first launch's start to the last
-    one's end, and the algorithmic bytes of every problem's trials."""
+    of the batch (its launches run side by side on the library's lanes) from the first
+    launch's start to the last one's end, and the algorithmic bytes of every problem's
+    trials."""
     from dataclasses import replace
 
     from paper_1411_0814_amd import _lib, decompose_batched
@@ -606,9 +607,10 @@ def _batch_gram_roofline(reqs, stream, torch, ws):
                 os.path.join(ROOT, "paper_1411_0814_amd", "csrc", "k_gram.hip"),
                 "k_gram_dma_batched256_counters.md", "hbm_bytes_per_call"),
             "bytes_alg_per_launch": int(b_alg), "launch_ms": round(span_ms, 4),
-            "note": "the step's launches (one per l and precision) back to back, timed between "
-                    "the step events of one problem per launch; bytes summed over the batch; "
-                    "traffic from the committed counters"}
+            "note": "the step's launches (one per l and precision, side by side on four "
+                    "streams) from the earliest start to the latest end of the step events of "
+                    "one problem per launch; bytes summed over the batch; traffic from the "
+                    "committed counters"}
 
 
 def run_batched(args, torch):
