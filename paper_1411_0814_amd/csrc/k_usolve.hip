@@ -7,8 +7,9 @@
 //    chunks of columns and read as a broadcast.  Used for small r.
 //  - k_uform: for all rows at once, [A | b] = W~ [K | V] as one dense product on the FP64
 //    matrix cores, where row j of K holds the products v_ja v_jb (a >= b) of V-hat's row j
-//    and W~ is the 0/1 mask (for the A part) or the mask times Y (for the b part).  The
-//    r(r+1)/2 + r results per row go to the workspace; k_usolve_ab solves them.
+//    and W~ is the 0/1 mask (for the A part) or the mask times Y (for the b part); k_ukext
+//    writes [K | V] once per problem.  The r(r+1)/2 + r results per row go to the
+//    workspace; k_usolve_ab solves them.
 // A_i is factorised by Cholesky in registers, one thread per row.  Rows with fewer than r
 // known entries (or a singular A_i) get u_i = 0 and are counted as underdetermined.
 //
@@ -265,12 +266,12 @@ __device__ __forceinline__ void lds_dma_dword(const void* src, void* dst) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
 }
 
-// Workgroup: kRows consecutive rows (kUfWaves wavefronts x kTiles tiles of 16).  The
+// Workgroup: uf_rows consecutive rows (kUfWaves wavefronts x uf_tiles tiles of 16).  The
 // right operand's rows for a stage of kUfCols columns travel from kext straight into one of
 // two LDS buffers (global_load_lds_dword: lane k of a wavefront writes 4 bytes at base + 4 k;
-// the workgroup moves 4 bytes per thread per round), and each lane loads the mask bit and Y value of its (row, column)
-// position of every k-step (the left operand: the bit as 0/1 for the A part, bit times y for
-// the b part).  Stage s + 1's loads are issued right after the barrier that publishes stage
+// the workgroup moves 4 bytes per thread per round), and each lane loads the mask bit and
+// Y value of its (row, column) position of every k-step (the left operand: the bit as 0/1
+// for the A part, bit times y for the b part).  Stage s + 1's loads are issued right after the barrier that publishes stage
 // s and land while stage s runs on the matrix cores: one barrier per stage.  Rows past m and
 // columns past n have weight 0.
 template <int R, typename TY>
