@@ -35,8 +35,9 @@ constexpr int u_unroll() {
 
 // Cholesky of A (packed lower triangle, row-major: entry (a, b), b <= a, at a(a+1)/2 + b)
 // in place, then A u = b by two triangular solves; u_i = 0 unless the row has at least r
-// known entries and every pivot is positive.  Writes U's row, and adds the wavefront's
-// underdetermined rows and known entries to the problem's info.
+// known entries and every pivot is positive.  The diagonal slots keep 1 / l_jj, so each
+// column costs one FP64 division and the rest are multiplications.  Writes U's row, and
+// adds the wavefront's underdetermined rows and known entries to the problem's info.
 template <int R>
 __device__ __forceinline__ void solve_row(const ProbDesc& P, double (&A)[R * (R + 1) / 2],
                                           const double (&bv)[R], int cnt, bool active,
@@ -50,14 +51,14 @@ __device__ __forceinline__ void solve_row(const ProbDesc& P, double (&A)[R * (R 
 #pragma unroll
       for (int p = 0; p < j; ++p) d -= A[j * (j + 1) / 2 + p] * A[j * (j + 1) / 2 + p];
       ok &= (d > 0.0);
-      const double ljj = sqrt(d > 0.0 ? d : 1.0);
-      A[j * (j + 1) / 2 + j] = ljj;
+      const double rl = 1.0 / sqrt(d > 0.0 ? d : 1.0);
+      A[j * (j + 1) / 2 + j] = rl;
 #pragma unroll
       for (int ii = j + 1; ii < R; ++ii) {
         double s = A[ii * (ii + 1) / 2 + j];
 #pragma unroll
         for (int p = 0; p < j; ++p) s -= A[ii * (ii + 1) / 2 + p] * A[j * (j + 1) / 2 + p];
-        A[ii * (ii + 1) / 2 + j] = s / ljj;
+        A[ii * (ii + 1) / 2 + j] = s * rl;
       }
     }
   }
@@ -71,7 +72,7 @@ __device__ __forceinline__ void solve_row(const ProbDesc& P, double (&A)[R * (R 
       double s = bv[a];
 #pragma unroll
       for (int p = 0; p < a; ++p) s -= A[a * (a + 1) / 2 + p] * u[p];
-      u[a] = s / A[a * (a + 1) / 2 + a];
+      u[a] = s * A[a * (a + 1) / 2 + a];
     }
     // backward: L^T u = z
 #pragma unroll
@@ -79,7 +80,7 @@ __device__ __forceinline__ void solve_row(const ProbDesc& P, double (&A)[R * (R 
       double s = u[a];
 #pragma unroll
       for (int p = a + 1; p < R; ++p) s -= A[p * (p + 1) / 2 + a] * u[p];
-      u[a] = s / A[a * (a + 1) / 2 + a];
+      u[a] = s * A[a * (a + 1) / 2 + a];
     }
   }
   RSM_GLOBAL double* __restrict__ U = P.U;
@@ -179,14 +180,22 @@ __global__ __launch_bounds__(256) void k_usolve(const ProbDesc* __restrict__ pro
   solve_row<R>(P, A, bv, cnt, active, i);
 }
 
-// Solve of the normal equations that k_uform wrote: one thread per row.
+// Solve of the normal equations that k_uform wrote: one thread per row.  From r = 14 the
+// r(r+1)/2 + r values of a row fill the register file (one wavefront per SIMD), and a
+// workgroup is one wavefront, so that it fits wherever one SIMD's registers are free
+// while the U-hat launches of other ranks run beside it.
 template <int R>
-__global__ __launch_bounds__(256) void k_usolve_ab(const ProbDesc* __restrict__ probs, IdxList list) {
+constexpr int usolve_ab_threads() { return R >= 14 ? 64 : 256; }
+
+template <int R>
+__global__ __launch_bounds__(usolve_ab_threads<R>()) void k_usolve_ab(
+    const ProbDesc* __restrict__ probs, IdxList list) {
   constexpr int NA = R * (R + 1) / 2;
+  constexpr int NT = usolve_ab_threads<R>();
   const ProbDesc& P = probs[list.idx[blockIdx.y]];
   const int64_t m = P.m;
-  if (static_cast<int64_t>(blockIdx.x) * 256 >= m) return;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (static_cast<int64_t>(blockIdx.x) * NT >= m) return;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
   const bool active = i < m;
   const int64_t ic = active ? i : m - 1;
   RSM_GLOBAL const double* __restrict__ ab = P.ab;
@@ -471,7 +480,8 @@ void run_usolve(const ProbDesc* d, const IdxList& g, int64_t m, int64_t n, int y
       else
         k_uform<R, double><<<dim3(static_cast<unsigned>(ceil_div(m, uf_rows<R, double>())), g.count),
                              kUfThreads, 0, s>>>(d, g);
-      k_usolve_ab<R><<<grid, 256, 0, s>>>(d, g);
+      constexpr int nt = usolve_ab_threads<R>();
+      k_usolve_ab<R><<<dim3(static_cast<unsigned>(ceil_div(m, nt)), g.count), nt, 0, s>>>(d, g);
       return;
     }
   }
