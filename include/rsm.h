@@ -271,7 +271,11 @@ int32_t rsm_decompose_noalloc(const rsm_problem* p, const rsm_input* in, const r
  * for all problems together), each launch's extent set by its largest problem.
  * problems/inputs/outputs are host arrays of nprob entries; each problem's results equal
  * those of rsm_decompose on it alone, up to the order of floating-point accumulation
- * into N.  workspace: rsm_workspace_bytes(problems, nprob) bytes. */
+ * into N.  workspace: rsm_workspace_bytes(problems, nprob) bytes.  A call of 64 or more
+ * problems runs the launch groups of its Gram, minor-vector and U-hat steps side by side
+ * on the caller's stream and three streams of the library, joined back into the caller's
+ * stream before the next step (see RSM_SERIAL_STEPS); everything the call enqueues is
+ * still ordered after the caller's earlier work on hip_stream and before its later work. */
 int32_t rsm_decompose_batched(int32_t nprob, const rsm_problem* problems,
                               const rsm_input* inputs, const rsm_output* outputs,
                               void* workspace, size_t ws_bytes, void* hip_stream);
