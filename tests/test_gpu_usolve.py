@@ -12,7 +12,7 @@ from tests.gpu_util import to_device
 pytestmark = pytest.mark.gpu
 
 # (m, n, r, rho, dtype): m not a multiple of the 128- or 256-row workgroup, n not a multiple of the
-# 16- or 32-column stage; every 7th row is thinned to r - 2 known entries (underdetermined)
+# 16-column stage; every 7th row is thinned to r - 2 known entries (underdetermined)
 CASES = [(3001, 203, 2, 0.7, np.float32), (2999, 150, 5, 0.8, np.float64),
          (3001, 203, 6, 0.8, np.float32), (4097, 97, 8, 0.75, np.float32),
          (3001, 99, 9, 0.8, np.float64), (3001, 130, 12, 0.85, np.float64),
